@@ -1,0 +1,42 @@
+"""Diagnostics reported by the paper's tables.
+
+* ``rel_l2``: ||a - b||_2 / ||b||_2 (Fig. convergence_BD caption).
+* ``extrema``: min/max of theta' and w (Table tbl:straka).
+* ``front_location``: the density-current front is where the -0.5 K contour
+  of theta' meets the ground (Table tbl:straka caption). Read here as the
+  largest x >= 0 on the bottom wall row where theta' <= -0.5 K, linearly
+  interpolated between that node and the next one in x.
+"""
+
+import numpy as np
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def extrema(state, n_active):
+    th = state[:n_active, 2]
+    w = state[:n_active, 1]
+    return dict(theta_min=float(th.min()), theta_max=float(th.max()),
+                w_min=float(w.min()), w_max=float(w.max()))
+
+
+def front_location(xy, theta, bottom_nodes, level=-0.5) -> float:
+    x = xy[bottom_nodes, 0]
+    th = theta[bottom_nodes]
+    order = np.argsort(x)
+    x, th = x[order], th[order]
+    sel = x >= 0.0
+    x, th = x[sel], th[sel]
+    cold = np.nonzero(th <= level)[0]
+    if cold.size == 0:
+        return 0.0
+    i = cold[-1]
+    if i + 1 >= x.size:
+        return float(x[i])
+    # linear interpolation of the crossing between node i and node i+1
+    f = (level - th[i]) / (th[i + 1] - th[i])
+    return float(x[i] + f * (x[i + 1] - x[i]))

@@ -1,0 +1,165 @@
+"""Pins of the oracle's right-hand sides, ghost closure, time stepping and
+diagnostics (Sections 5.2, 6.1, 6.2, 6.4)."""
+
+import csv
+import os
+
+import numpy as np
+import pytest
+import sympy as sp
+
+import oracle as O
+from oracle.pipeline import build_ns, build_advection
+from workloads import advection_config, density_current_config, channel
+from workloads.configs import _ns_config
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ns800():
+    cfg = density_current_config("hexagonal", 800.0)
+    model, idx, W, Ww = build_ns(cfg)
+    return cfg, model
+
+
+def test_hydrostatic_rest_is_exactly_steady(ns800):
+    """The perturbation form builds in hydrostatic balance (Section 6.2): the
+    state at rest has zero tendency, exactly."""
+    cfg, model = ns800
+    z = np.zeros_like(cfg["state0"])
+    out, s = O.ns_rhs(model, z)
+    assert np.all(out == 0.0) and np.all(s == 0.0)
+
+
+def test_ghost_closure_enforces_boundary_conditions(ns800):
+    """Section 5.2 / Section 6.4: after the closure the boundary rows satisfy
+    du/dz = dtheta/dz = 0, dpi/dz = g theta / (c_p theta_bar (theta_bar +
+    theta)), w = 0 and d2w/dz2 = 0, with the ghost values included."""
+    cfg, model = ns800
+    nd = cfg["nodes"]
+    rng = np.random.default_rng(0)
+    st = rng.standard_normal(cfg["state0"].shape) * np.array([10, 10, 5, 1e-3])
+    s = O.ghost_closure(model, st)
+    c = cfg["consts"]
+    for wl in range(2):
+        nodes = nd.wall_nodes[wl]
+        rows = model.idx[nodes]
+        assert np.all(s[nodes, 1] == 0.0)
+        for f, W, target in ((0, model.wall_dz[wl], 0.0), (2, model.wall_dz[wl], 0.0),
+                             (1, model.wall_dzz[wl], 0.0)):
+            r = O.apply_dm(rows, W, s[:, f])
+            scale = O.apply_dm(rows, np.abs(W), np.abs(s[:, f]))
+            assert np.all(np.abs(r - target) <= 1e-12 * scale)
+        th = s[nodes, 2]
+        bc = c["g"] * th / (c["c_p"] * c["theta_bar"] * (c["theta_bar"] + th))
+        r = O.apply_dm(rows, model.wall_dz[wl], s[:, 3])
+        scale = O.apply_dm(rows, np.abs(model.wall_dz[wl]), np.abs(s[:, 3])) + np.abs(bc)
+        assert np.all(np.abs(r - bc) <= 1e-12 * scale)
+
+
+def _manufactured(nd):
+    """Smooth x-periodic fields and the exact PDE right-hand side of Eqs.
+    uEq..piEq (mu = 1, no hyperviscosity), differentiated by sympy."""
+    x, z = sp.symbols("x z")
+    L, H = nd.period_x, 6400.0
+    k = 2 * sp.pi / L
+    u = 12 * sp.sin(k * x + 0.3) * sp.cos(sp.pi * z / H) + 3
+    w = 8 * sp.cos(2 * k * x) * sp.sin(sp.pi * z / H)
+    th = 6 * sp.cos(k * x - 0.5) * sp.cos(2 * sp.pi * z / H)
+    pi = 1e-3 * sp.sin(3 * k * x) * sp.cos(sp.pi * z / H)
+    cp, cv, Rd, g, tb, mu = 1004.0, 717.0, 287.0, 9.81, 300.0, 1.0
+    pib = 1 - g * z / (cp * tb)
+    D = sp.diff
+    lap = lambda f: D(f, x, 2) + D(f, z, 2)                                   # noqa: E731
+    du = -u * D(u, x) - w * D(u, z) - cp * (tb + th) * D(pi, x) + mu * lap(u)
+    dw = -u * D(w, x) - w * D(w, z) - cp * (tb + th) * D(pi, z) + g * th / tb + mu * lap(w)
+    dth = -u * D(th, x) - w * D(th, z) + mu * lap(th)
+    dpi = -u * D(pi, x) - w * (D(pib, z) + D(pi, z)) - (Rd / cv) * (pib + pi) * (D(u, x) + D(w, z))
+    F = [sp.lambdify((x, z), e, "numpy") for e in (u, w, th, pi)]
+    R = [sp.lambdify((x, z), e, "numpy") for e in (du, dw, dth, dpi)]
+    X, Z = nd.xy[:, 0], nd.xy[:, 1]
+    state = np.stack([np.broadcast_to(f(X, Z), X.shape) for f in F], axis=1).astype(float)
+    exact = np.stack([np.broadcast_to(r(X, Z), X.shape) for r in R], axis=1).astype(float)
+    return state, exact
+
+
+def test_manufactured_rhs_converges():
+    """Eqs. uEq..piEq on a manufactured smooth state, away from the walls:
+    the oracle's tendency approaches the exact one as h shrinks (every term
+    enters; a dropped term or wrong sign leaves an O(1) error)."""
+    errs, hs = [], []
+    for nx, nz in ((64, 9), (128, 17)):
+        nd = channel("hexagonal", nx, nz, -25600.0, 51200.0, 6400.0)
+        cfg = _ns_config(nd, "mms", 1.0, "rk4")
+        cfg["consts"] = dict(cfg["consts"], mu=1.0)
+        cfg["hv_coeff"] = 0.0
+        model, *_ = build_ns(cfg)
+        state, exact = _manufactured(nd)
+        na = nd.n_active
+        out, _ = O.ns_rhs(model, state)
+        # rows whose stencils do not reach the ghost rows (the manufactured
+        # fields do not satisfy the wall conditions)
+        rows = np.arange(na) // nx
+        inner = (rows >= 3) & (rows <= nz - 4)
+        rel = [np.abs(out[:na][inner, f] - exact[:na][inner, f]).max() / np.abs(exact[:na, f]).max()
+               for f in range(4)]
+        errs.append(rel)
+        hs.append(nd.h)
+    errs = np.array(errs)
+    assert np.all(errs[-1] < 2e-3), errs
+    order = np.log(errs[0] / errs[1]) / np.log(hs[0] / hs[1])
+    assert np.all(order > 2.5), order
+
+
+def test_rk_orders():
+    """RK4 is 4th order and the 3-stage scheme 3rd order on y' = lambda y."""
+    lam = -1.3 + 0.7j
+    f = lambda t, y: lam * y                                                 # noqa: E731
+    for step, p in ((O.rk4_step, 4), (O.wsrk3_step, 3)):
+        errs = []
+        for n in (20, 40):
+            y = np.array([1.0 + 0j])
+            for i in range(n):
+                y = step(f, i / n, y, 1.0 / n)
+            errs.append(abs(y[0] - np.exp(lam)))
+        assert abs(np.log2(errs[0] / errs[1]) - p) < 0.25
+
+
+def test_front_location_interpolates():
+    xy = np.array([[-100.0, 0], [0.0, 0], [100.0, 0], [200.0, 0], [300.0, 0]])
+    th = np.array([-3.0, -2.0, -1.0, 0.0, 0.0])
+    assert O.front_location(xy, th, np.arange(5)) == pytest.approx(150.0)
+
+
+def test_bell_return_improves_with_resolution():
+    """Section 6.1 / scalar-transport workload: the reversing flow brings the
+    cosine bell back at T; the return error shrinks under refinement."""
+    errs = []
+    for n in (24, 40):
+        cfg = advection_config(n)
+        model, idx, W, status = build_advection(cfg)
+        assert status.sum() == 0
+        y, _ = O.integrate(model, cfg["psi0"], 0.0, cfg["dt"], 2000, "rk4")
+        errs.append(O.rel_l2(y, cfg["psi0"]))
+    assert errs[1] < 0.85 * errs[0] and errs[1] < 0.9, errs
+
+
+@pytest.mark.slow
+def test_density_current_400m_against_table():
+    """Table tbl:straka, hexagonal 400 m: the oracle's run to 900 s lands
+    within 10% of the printed extrema and 3% of the front (RK4, this
+    build's hyperviscosity reading)."""
+    with open(os.path.join(GOLDEN, "straka_table.csv")) as f:
+        rows = [r for r in csv.reader(f) if r and not r[0].startswith("#")][1:]
+    ref = {(r[0], float(r[1])): [float(v) for v in r[2:]] for r in rows}["hexagonal", 400.0]
+    cfg = density_current_config("hexagonal", 400.0)
+    model, *_ = build_ns(cfg)
+    y, _ = O.integrate(lambda t, y: O.ns_rhs(model, y)[0], cfg["state0"], 0.0, cfg["dt"], 900, "rk4")
+    s = O.ghost_closure(model, y)
+    e = O.extrema(s, cfg["nodes"].n_active)
+    got = [e["theta_min"], e["theta_max"], e["w_min"], e["w_max"]]
+    front = O.front_location(cfg["nodes"].xy, s[:, 2], cfg["nodes"].wall_nodes[0])
+    for g, r in zip(got, ref[:4]):
+        assert abs(g - r) <= 0.1 * abs(r) + 0.1, (got, ref)
+    assert abs(front - ref[4]) <= 0.03 * ref[4]

@@ -1,0 +1,92 @@
+"""The five workload shapes (scalar transport, density current at 100 m, batched
+weights on 1M scattered nodes, density current at 25 m with ensembles, coarse
+400 m density current) as plain dictionaries of method parameters and inputs.
+
+Method parameters follow the paper's problem statement: PHS order m (odd),
+polynomial degree l, stencil size n, operators, hyperviscosity power k and
+coefficient, viscosity mu, time step (Section 6.3 time-step table) and the
+Runge-Kutta tableau.
+"""
+
+import numpy as np
+
+from .nodes import unit_square_cartesian, straka_nodes, channel, jittered_square
+from .fields import NS_CONSTANTS, cosine_bell, swirl_velocity, straka_state, smooth_ns_state
+
+# Nominal magnitude of the grid-scale symbol of a unit-spacing Laplacian cubed
+# ((2 pi^2)^3 rounded); used only to turn a damping rate into a coefficient.
+SIGMA_REF = 8000.0
+# Hyperviscosity strength for the Navier-Stokes workloads: the grid-scale
+# mode is damped at rate NS_HV_C / dt. The paper's scaling rule is garbled;
+# 2^-2 is the smallest power of two that keeps the 400 m density current
+# stable to 900 s with RK4 at the paper's time step.
+NS_HV_C = 0.25
+
+# Section 6.3 time-step table: node spacing (m) -> dt (s).
+DT_TABLE = {800.0: 2.0, 400.0: 1.0, 200.0: 0.5, 100.0: 0.25, 50.0: 0.125, 25.0: 0.0625}
+
+
+def advection_config(n_side: int = 64):
+    """Scalar transport: Cartesian n_side^2 on [0,1]^2, r^5 + degree-4
+    polynomials (15 terms), 37-node stencils, Dx, Dy and Laplacian-cubed
+    hyperviscosity (HV PHS order 7), RK4 with dt = 2.5e-3 to T = 5."""
+    nodes = unit_square_cartesian(n_side)
+    U, V = swirl_velocity(nodes.xy)
+    h = nodes.h
+    return dict(
+        name=f"advection-cartesian-{n_side}x{n_side}",
+        nodes=nodes, m=5, l=4, n=37, hv_k=3, hv_m=7,
+        hv_coeff=2.0 ** -6 * h ** 6,
+        U=U, V=V, vel_period=5.0,
+        psi0=cosine_bell(nodes.xy),
+        dt=2.5e-3, t_end=5.0, tableau="rk4",
+    )
+
+
+def density_current_config(layout: str = "hexagonal", h: float = 100.0, seed: int = 0,
+                           tableau: str = "rk4"):
+    """Straka density current (Section 6.4): r^7 + degree-4 polynomials, n=37,
+    operators Dx, Dz, Laplacian and Laplacian-cubed (+ Dz, Dzz at walls),
+    mu = 75 m^2/s, dt from the Section 6.3 table, run to t = 900 s."""
+    nodes = straka_nodes(layout, h, seed=seed)
+    dt = DT_TABLE[float(h)]
+    return _ns_config(nodes, f"density-current-{layout}-{int(h)}m", dt, tableau)
+
+
+def scale_config(nx: int = 2048, nz: int = 256, tableau: str = "rk4"):
+    """Density current on a 2048 x 256 hexagonal-row channel at 25 m column
+    spacing (rows at 6400/255 m), 524,288 active nodes plus 2 x 2048 ghosts."""
+    nodes = channel("hexagonal", nx, nz, -25600.0, 51200.0, 6400.0)
+    return _ns_config(nodes, f"density-current-hexagonal-{nx}x{nz}", 0.0625, tableau)
+
+
+def _ns_config(nodes, name, dt, tableau):
+    c = dict(NS_CONSTANTS)
+    h = nodes.h
+    return dict(
+        name=name, nodes=nodes, m=7, l=4, n=37, hv_k=3, hv_m=7,
+        hv_coeff=NS_HV_C * h ** 6 / (SIGMA_REF * dt),
+        consts=c, dt=dt, t_end=900.0, tableau=tableau,
+        state0=straka_state(nodes, c=c),
+    )
+
+
+def weights_config(n_side: int = 1024, seed: int = 0):
+    """Batched weights on n_side^2 jittered-Cartesian nodes in [0,1]^2:
+    per-node degree l ~ U{3,4,5}, PHS order m = 2l-3, stencil size n = 2M+1
+    (interior) or 2M+19 (within 3h of an edge), M = (l+1)(l+2)/2;
+    operators Dx, Dy and Laplacian^k with k = (m-1)/2."""
+    nodes = jittered_square(n_side, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    l = rng.integers(3, 6, nodes.n_active).astype(np.int32)
+    M = (l + 1) * (l + 2) // 2
+    x, y = nodes.xy[:, 0], nodes.xy[:, 1]
+    edge = np.minimum(np.minimum(x, 1.0 - x), np.minimum(y, 1.0 - y)) < 3.0 * nodes.h
+    n = np.where(edge, 2 * M + 19, 2 * M + 1).astype(np.int32)
+    m = (2 * l - 3).astype(np.int32)
+    return dict(name=f"weights-scattered-{n_side}x{n_side}", nodes=nodes,
+                l_per=l, m_per=m, n_per=n, n_max=int(n.max()))
+
+
+def smooth_state_for(nodes, seed: int = 2, dtype=np.float64):
+    return smooth_ns_state(nodes, seed=seed, dtype=dtype)

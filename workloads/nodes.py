@@ -1,0 +1,128 @@
+"""Node sets (Section 5.1: Cartesian, hexagonal, quasi-uniform scattered) and
+the ghost-node rows of Section 5.2, for the paper's test domains.
+
+Ordering convention used everywhere: active nodes (those that carry a stencil
+and prognostic values) come first, row by row from the bottom wall upwards,
+then the ghost rows (bottom ghost row, then top ghost row). Ghost node ``g`` of
+a wall sits in the ghost row next to boundary node ``g`` of the same wall.
+"""
+
+from dataclasses import dataclass, field
+import numpy as np
+
+KIND_INTERIOR = 0
+KIND_WALL = 1
+KIND_GHOST = 2
+
+
+@dataclass
+class NodeSet:
+    xy: np.ndarray                  # (n_total, 2) float64, [x, z]
+    n_active: int                   # nodes 0..n_active-1 have stencils
+    period_x: float                 # x period (0.0: not periodic)
+    h: float                        # nominal node spacing
+    layout: str
+    nx: int = 0
+    nz: int = 0
+    wall_nodes: np.ndarray = field(default_factory=lambda: np.zeros((0, 0), np.int32))
+    ghost_nodes: np.ndarray = field(default_factory=lambda: np.zeros((0, 0), np.int32))
+    height: float = 0.0
+
+    @property
+    def n_total(self) -> int:
+        return int(self.xy.shape[0])
+
+    def kinds(self) -> np.ndarray:
+        k = np.zeros(self.n_total, np.int8)
+        k[self.n_active:] = KIND_GHOST
+        if self.wall_nodes.size:
+            k[self.wall_nodes.ravel()] = KIND_WALL
+        return k
+
+
+def unit_square_cartesian(n_side: int = 64) -> NodeSet:
+    """n_side x n_side Cartesian lattice on [0,1]^2 with x_i = i/(n_side-1);
+    node index = j*n_side + i. No ghosts, no periodicity (one-sided stencils
+    at the edges)."""
+    t = np.arange(n_side, dtype=np.float64) / (n_side - 1)
+    X, Y = np.meshgrid(t, t, indexing="xy")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1).copy()
+    return NodeSet(xy=xy, n_active=xy.shape[0], period_x=0.0, h=1.0 / (n_side - 1),
+                   layout="cartesian", nx=n_side, nz=n_side)
+
+
+def channel(layout: str, nx: int, nz: int, x_left: float, length: float, height: float,
+            seed: int = 0, jitter: float = 0.2) -> NodeSet:
+    """x-periodic channel [x_left, x_left+length) x [0, height] with walls at
+    z=0 and z=height and one ghost row outside each wall.
+
+    * ``cartesian``: nx columns at spacing hx = length/nx, nz rows at
+      dz = height/(nz-1).
+    * ``hexagonal``: as Cartesian but odd rows are shifted by hx/2.
+    * ``scattered``: hexagonal positions jittered by U[-jitter*hx, jitter*hx]
+      in x and z for interior rows, and in x only for wall rows (PCG64 stream
+      seeded with ``seed``).
+
+    Ghost node g of a wall is placed straight outside boundary node g (same
+    x, one row spacing dz beyond the wall), so every layout gets one ghost per
+    boundary node (Section 5.2). On the hexagonal lattice the shifted
+    continuation row would not do: a stencil that is symmetric in x weighs
+    the two ghosts at -hx/2 and +hx/2 equally, so the alternating ghost mode
+    is invisible to every boundary row and W_G is singular.
+    """
+    if layout not in ("cartesian", "hexagonal", "scattered"):
+        raise ValueError(layout)
+    hx = length / nx
+    dz = height / (nz - 1)
+    shifted = layout in ("hexagonal", "scattered")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = []
+    for r in range(nz):
+        x = x_left + (np.arange(nx, dtype=np.float64) + (0.5 if (shifted and r % 2) else 0.0)) * hx
+        z = np.full(nx, height if r == nz - 1 else r * dz)
+        if layout == "scattered":
+            x = x + rng.uniform(-jitter * hx, jitter * hx, nx)
+            if 0 < r < nz - 1:
+                z = z + rng.uniform(-jitter * hx, jitter * hx, nx)
+            x = x_left + np.mod(x - x_left, length)
+        pts.append(np.stack([x, z], axis=1))
+    bottom, top = pts[0], pts[nz - 1]
+    pts.append(np.stack([bottom[:, 0], np.full(nx, -dz)], axis=1))
+    pts.append(np.stack([top[:, 0], np.full(nx, height + dz)], axis=1))
+    xy = np.concatenate(pts, axis=0)
+    n_active = nx * nz
+    wall = np.stack([np.arange(nx), (nz - 1) * nx + np.arange(nx)]).astype(np.int32)
+    ghost = np.stack([n_active + np.arange(nx), n_active + nx + np.arange(nx)]).astype(np.int32)
+    return NodeSet(xy=xy, n_active=n_active, period_x=length, h=hx, layout=layout,
+                   nx=nx, nz=nz, wall_nodes=wall, ghost_nodes=ghost, height=height)
+
+
+def straka_nodes(layout: str, h: float, seed: int = 0) -> NodeSet:
+    """Density-current domain [-25.6, 25.6] x [0, 6.4] km (Section 6.4) at node
+    spacing h metres. Cartesian rows are h apart; hexagonal and scattered rows
+    are about h*sqrt(3)/2 apart, the row count rounded so the walls are rows."""
+    length, height = 51200.0, 6400.0
+    nx = int(round(length / h))
+    if layout == "cartesian":
+        nz = int(round(height / h)) + 1
+    else:
+        nz = int(round(height / (h * np.sqrt(3.0) / 2.0))) + 1
+    return channel(layout, nx, nz, -25600.0, length, height, seed=seed)
+
+
+def jittered_square(n_side: int = 1024, seed: int = 0, jitter: float = 0.2) -> NodeSet:
+    """n_side^2 quasi-uniform scattered nodes in [0,1]^2: a Cartesian lattice
+    with spacing h = 1/(n_side-1), interior nodes jittered by U[-jitter*h,
+    jitter*h]^2, edge nodes jittered along their edge only, corners fixed."""
+    h = 1.0 / (n_side - 1)
+    base = unit_square_cartesian(n_side)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = rng.uniform(-jitter * h, jitter * h, size=base.xy.shape)
+    x, y = base.xy[:, 0], base.xy[:, 1]
+    on_x_edge = (x == 0.0) | (x == 1.0)
+    on_y_edge = (y == 0.0) | (y == 1.0)
+    d[on_x_edge, 0] = 0.0
+    d[on_y_edge, 1] = 0.0
+    xy = base.xy + d
+    return NodeSet(xy=xy, n_active=xy.shape[0], period_x=0.0, h=h, layout="scattered",
+                   nx=n_side, nz=n_side)
