@@ -1,0 +1,222 @@
+"""Benchmark of the RBF-FD hot path on one MI355X.
+
+Workload: the density current on a 2048 x 256 hexagonal-row channel at 25 m
+column spacing (524,288 active nodes + 2 x 2,048 ghost nodes), r^7 +
+degree-4 polynomials, n = 37, operators Dx, Dz, Lap, Lap^3, RK4 with
+dt = 1/16 s. Setup (untimed for the headline, reported separately): stencil
+search + batched weights (A1-A4) and model creation. Timed region: K RK4
+steps, each 4 stages of ghost closure (B1) + fused gather-stencil RHS and
+stage update (B2-B4), with HIP events around every fused RHS launch.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64|bf16]
+
+Prints one JSON line. value = node updates per second (one node, one RHS
+evaluation) of the FP32-field path; roofline = the fused RHS kernel's
+algorithmic bytes per launch over its measured average duration.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "RHS node-updates/s & % HBM peak, FP32 vs FP64 at stated rel-L2; stencils/s"
+
+
+def field_bytes_per_node_stage(tableau, fb, F=4, E=1):
+    """Field traffic per node and stage, averaged over the tableau's stages:
+    RK4 stage 1 reads y_n and writes y_1 and the accumulator; stages 2-3 read
+    y_s, y_n and the accumulator and write y_s+1 and the accumulator;
+    stage 4 reads y_3 and the accumulator and writes y_n+1."""
+    v = F * E * fb
+    if tableau == "rk4":
+        return v * (3 + 5 + 5 + 3) / 4.0
+    return v * (2 + 3 + 3) / 3.0
+
+
+def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup):
+    import torch
+    nd = cfg["nodes"]
+    model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
+    dt_t = torch.float64 if fdt == R.F64 else torch.float32
+    state = P.to_dev(cfg["state0"], dt_t).reshape(model.state_shape()).contiguous()
+    t = R.rbffd_step(ctx, model, state, 0.0, cfg["dt"], warmup, R.RK4)
+    # timed region: K steps with events around every fused RHS launch
+    model.profile(True)
+    model.profile_read()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record()
+    t = R.rbffd_step(ctx, model, state, t, cfg["dt"], steps, R.RK4)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    total_ms = ev0.elapsed_time(ev1)
+    k_ms, launches = model.profile_read()
+    model.profile(False)
+    # graph replay of the same steps, for reference
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    t = R.rbffd_step(ctx, model, state, t, cfg["dt"], steps, R.RK4)
+    torch.cuda.synchronize()
+    graph_s = time.perf_counter() - g0
+    fb = 8 if fdt == R.F64 else 4
+    per_node = model.bytes_per_node() + field_bytes_per_node_stage("rk4", fb)
+    bytes_launch = per_node * nd.n_active
+    k_avg_s = k_ms / launches / 1e3
+    updates = nd.n_active * 4 * steps
+    res = dict(node_updates_per_s=updates / (total_ms / 1e3), ms_per_step=total_ms / steps,
+               wall_s=wall, graph_ms_per_step=graph_s * 1e3 / steps,
+               kernel_avg_ms=k_ms / launches, kernel_launches=launches,
+               bytes_per_node=per_node, bytes_per_launch=bytes_launch,
+               kernel_gbs=bytes_launch / k_avg_s / 1e9,
+               finite=bool(torch.isfinite(state).all().item()))
+    del model
+    return res
+
+
+def weights_leg(R, ctx, cfg, precision):
+    """One rbffd_weights launch over a node set; returns stencils/s."""
+    import torch
+    from paper_1509_02615_amd import pipeline as P
+    nd = cfg["nodes"]
+    xy = P.to_dev(nd.xy, torch.float64)
+    n_per = P.to_dev(cfg["n_per"], torch.int32)
+    m_per = P.to_dev(cfg["m_per"], torch.int32)
+    l_per = P.to_dev(cfg["l_per"], torch.int32)
+    ops = [(R.DX, 0, 0), (R.DZ, 0, 0), (R.HYPERLAP, 0, 0)]
+    idx = R.rbffd_knn(ctx, xy, cfg["n_max"], 0.0, n_per=n_per)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    _, W, status, rc = R.rbffd_weights(ctx, xy, ops, cfg["n_max"], n_per=n_per, m_per=m_per, l_per=l_per,
+                                       idx_in=idx, precision=precision)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    bad = int((status != 0).sum().item())
+    return dict(stencils=nd.n_active, ms=ms, stencils_per_s=nd.n_active / (ms / 1e3), singular=bad)
+
+
+def cpu_baseline(cfg, min_seconds=10.0):
+    """The oracle's RHS on a bounded sample: one 2048-node row of the same
+    channel (row 128), stencils and weights from the oracle (untimed), then
+    repeated evaluations of Eqs. uEq..piEq for at least min_seconds."""
+    import oracle as O
+    nd = cfg["nodes"]
+    rows = np.arange(128 * nd.nx, 129 * nd.nx)
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0), (O.HYPERLAP, 3, 7)]
+    idx = O.knn(nd.xy, rows, cfg["n"], nd.period_x)
+    Wo, _ = O.all_weights(nd.xy, idx, rows, cfg["m"], cfg["l"], ops, nd.period_x)
+    state = cfg["state0"].astype(np.float64)
+    is_wall = np.zeros(len(rows), bool)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        O.ns_tendency(state, rows, idx, Wo[0], Wo[1], Wo[2], Wo[3], nd.xy[rows, 1], is_wall,
+                      cfg["consts"], cfg["hv_coeff"])
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds:
+            break
+    return dict(value=len(rows) * reps / el, unit="node-updates/s", cores=1, kind="oracle",
+                sample=f"one 2048-node row of the 2048x256 channel, {reps} FP64 RHS evaluations "
+                       f"in {el:.1f} s (numpy, single thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and weight legs")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the multi-GPU path is not built (see the sharding notes); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1509_02615_amd import rbffd as R
+    from paper_1509_02615_amd import pipeline as P
+    from workloads import scale_config, weights_config
+
+    torch.cuda.set_device(0)
+    ctx = R.Context(0)
+    cfg = scale_config()
+    nd = cfg["nodes"]
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    log(f"[bench] workload {cfg['name']}: {nd.n_active} active + {nd.n_total - nd.n_active} ghost nodes")
+
+    # A1-A4 on the same node set (setup of the timed region)
+    xy = P.to_dev(nd.xy, torch.float64)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    xy, idx, W, Ww, (st_a, st_w) = P.ns_weights(ctx, cfg, xy=xy)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - s0
+    n_stencils = nd.n_active + nd.wall_nodes.size
+    assert int(st_a.abs().sum()) == 0 and int(st_w.abs().sum()) == 0
+    log(f"[bench] search + weights for {n_stencils} stencils: {setup_s:.3f} s")
+
+    fdt = {"fp32": R.F32, "fp64": R.F64, "bf16": R.F32}[args.precision]
+    wdt = {"fp32": R.F32, "fp64": R.F64, "bf16": R.BF16}[args.precision]
+    main_leg = run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, args.steps, args.warmup)
+    log(f"[bench] {args.precision}: {main_leg}")
+
+    extras = {}
+    if not args.no_extras:
+        for name, (f2, w2) in {"fp64": (R.F64, R.F64), "fp32": (R.F32, R.F32), "bf16": (R.F32, R.BF16)}.items():
+            if name == args.precision:
+                continue
+            extras[name] = run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, f2, w2, args.steps, args.warmup)
+            log(f"[bench] {name}: {extras[name]}")
+        wcfg = weights_config(1024)
+        extras["weights_mixed_1M_fp64"] = weights_leg(R, ctx, wcfg, R.SOLVE_FP64)
+        log(f"[bench] weights fp64: {extras['weights_mixed_1M_fp64']}")
+    extras["weights_scale_setup"] = dict(stencils=n_stencils, seconds=setup_s,
+                                         stencils_per_s=n_stencils / setup_s,
+                                         note="search + FP64 weights incl. host sync, 4+2 operators")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg)
+        log(f"[bench] cpu baseline: {cpu}")
+
+    k = main_leg
+    achieved = k["kernel_gbs"]
+    line = {
+        "metric": METRIC,
+        "value": k["node_updates_per_s"],
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": k["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "f32 (bf16 weights)"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{cfg['name']}: density current, 524,288 active + 4,096 ghost nodes, "
+                               f"r^7 + degree-4 polynomials, n=37, RK4 dt=1/16 s, E=1",
+                   "stages_per_step": 4, "precision": args.precision},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "ns_stage_kernel", "bytes_per_launch": k["bytes_per_launch"],
+                     "kernel_avg_ms": k["kernel_avg_ms"]},
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * rbffd.h -- C ABI of the MI355X (gfx950) RBF-FD library.
+ *
+ * The library computes, on one GPU, the data-parallel hot path of the
+ * polyharmonic-spline + polynomial RBF-FD method (Barnett, Flyer & Wicker,
+ * arXiv 1509.02615):
+ *   A1  stencil search: the n nodes nearest each centre           (Section 6, App. A)
+ *   A2-A4 batched weights: one saddle-point solve per stencil    (Section 3, Eq. weights;
+ *                                                                 Section 5.3, Eq. eqn:laplacian)
+ *   B1  ghost-node closure per Runge-Kutta stage                 (Section 5.2, Eq. bcEqn;
+ *                                                                 BCs of Section 6.4)
+ *   B2-B3 fused gather-stencil products + PDE right-hand side   (Section 6.1; Eqs. uEq-piEq)
+ *   B4  Runge-Kutta stages fused into the right-hand side        (Section 6: RK4)
+ *
+ * Conventions (every entry point):
+ *   - Every array argument is a DEVICE pointer on the context's device,
+ *     owned by the caller, unless stated otherwise. Scalars are by value.
+ *   - All work is enqueued on the context's HIP stream; an entry point returns
+ *     once the work is enqueued, except where it says it synchronises.
+ *   - Return value: RBFFD_OK (0) or a negative rbffd_status code. Nothing is
+ *     thrown across the ABI. On RBFFD_EINVAL nothing has been written.
+ *     rbffd_last_error() gives a message for the last failing call.
+ *   - A context (and the models created from it) is used by one host thread
+ *     at a time.
+ *   - Node coordinates are (x, z) pairs in FP64, [n_nodes][2] row-major.
+ *   - Field arrays ("state") are [n_nodes][E][F] row-major: node-major, then
+ *     ensemble member, then field. F = 1 (psi) for transport, F = 4
+ *     (u, w, theta', pi') for Navier-Stokes. The element type is the model's
+ *     field dtype.
+ */
+#ifndef RBFFD_H
+#define RBFFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbffd_ctx rbffd_ctx;     /* opaque, library-owned */
+typedef struct rbffd_model rbffd_model; /* opaque, library-owned */
+
+typedef enum {
+  RBFFD_OK = 0,
+  RBFFD_EINVAL = -1,     /* bad argument; nothing written                         */
+  RBFFD_ENOMEM = -2,     /* device or host allocation failed                      */
+  RBFFD_EDEVICE = -3,    /* HIP runtime error                                     */
+  RBFFD_ESINGULAR = -4,  /* some stencil systems are singular (see status[])      */
+  RBFFD_ENONFINITE = -5  /* a state value became Inf/NaN during rbffd_step        */
+} rbffd_status;
+
+/* Differential operators L (Section 3: "the operator L"). */
+typedef enum {
+  RBFFD_DX = 1,        /* d/dx                                                   */
+  RBFFD_DZ = 2,        /* d/dz (the second coordinate; d/dy in the unit square)  */
+  RBFFD_LAP = 3,       /* Laplacian                                              */
+  RBFFD_HYPERLAP = 4,  /* Laplacian^k, k = rbffd_op.k (Section 5.3)              */
+  RBFFD_DZZ = 5        /* d2/dz2 (wall closure of w, Section 6.4)                */
+} rbffd_op_kind;
+
+typedef struct {
+  int32_t kind;       /* rbffd_op_kind                                              */
+  int32_t k;          /* power for RBFFD_HYPERLAP; 0 = (m_eff - 1)/2, the largest power
+                         for which Laplacian^k r^m stays continuous (m >= 2k+1)        */
+  int32_t phs_order;  /* PHS order m used for this operator; 0 = the stencil's m.
+                         Operators of equal order share one factorisation.           */
+  int32_t reserved;   /* must be 0                                                   */
+} rbffd_op;
+
+/* Node set and per-stencil method parameters (Section 3: node set, stencil
+ * size n, PHS order m (odd, phi = r^m), polynomial degree l). */
+typedef struct {
+  int64_t n_nodes;          /* N: nodes searched as neighbours                         */
+  const double *xy;         /* [N][2] FP64 (x, z)                                      */
+  double period_x;          /* x period for the minimum image; 0 = not periodic.
+                               With a period all x must lie in one interval of that
+                               length.                                                  */
+  int64_t n_centers;        /* Nc: number of stencils                                  */
+  const int32_t *centers;   /* [Nc] centre node indices, or NULL = 0..Nc-1             */
+  int32_t n_max;            /* stencil row length of idx/w (1..120)                    */
+  const int32_t *n_per;     /* [Nc] stencil size per centre (<= n_max), or NULL = n_max */
+  int32_t m_uniform;        /* odd PHS order, 1 <= m <= 15, used when m_per is NULL     */
+  const int32_t *m_per;     /* [Nc] or NULL                                            */
+  int32_t l_uniform;        /* polynomial degree 0..6, used when l_per is NULL          */
+  const int32_t *l_per;     /* [Nc] or NULL                                            */
+  const int32_t *idx_in;    /* [Nc][n_max] given stencils (skip the search), or NULL    */
+} rbffd_stencils;
+
+enum { RBFFD_SOLVE_FP64 = 0, RBFFD_SOLVE_FP32_IR = 1 };
+enum { RBFFD_F64 = 0, RBFFD_F32 = 1, RBFFD_BF16 = 2 };
+enum { RBFFD_PHYS_ADVECTION = 1, RBFFD_PHYS_NS = 2 };
+enum { RBFFD_RK4 = 0, RBFFD_WSRK3 = 1 };
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t
+ * (NULL = the null stream) that every call of this context is ordered on. */
+int rbffd_create(rbffd_ctx **out, int device, void *hip_stream);
+int rbffd_destroy(rbffd_ctx *ctx);
+/* Message of the last failing call on this context (never NULL). */
+const char *rbffd_last_error(rbffd_ctx *ctx);
+/* Block until all work enqueued on the context's stream has finished. */
+int rbffd_sync(rbffd_ctx *ctx);
+
+/* ---- A1: stencil search ------------------------------------------------- */
+
+/* For each centre c: the n_c nodes with the smallest key (d^2, j), in that
+ * order, where d^2 = dx*dx + dz*dz is evaluated in IEEE FP64 with two
+ * rounded products and a rounded sum (no fused multiply-add) and dx is the
+ * minimum image for a periodic x (shifted by one period when |dx| > period/2).
+ * Section 6 uses the n = 37 nearest nodes (a complete symmetric set on
+ * Cartesian and hexagonal lattices, Appendix A).
+ * Output idx [Nc][n_max] int32, entries past n_c set to -1. Uses m/l only for
+ * validation. Synchronises once (grid set-up). EINVAL if n_c > N. */
+int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx);
+
+/* ---- A1-A4: batched weights -------------------------------------------- */
+
+/* One row of each differentiation matrix per centre (Section 3, Eq. weights):
+ * with phi(r) = r^m and all monomials of degree <= l, solve
+ *     [Phi P; P^T 0] [w; v] = [L phi(|x - x_j|) at x_c ; L p(x_c)]
+ * and keep w. The system is formed in a frame centred at x_c and scaled by
+ * the largest centre-to-node distance, solved by LU with partial pivoting in
+ * FP64 (or an FP32 factorisation when precision = RBFFD_SOLVE_FP32_IR) plus
+ * iterative refinement with double-double residuals, then rescaled.
+ * Runs the A1 search first unless st->idx_in is given (then idx is a copy).
+ * Outputs: idx [Nc][n_max] (may be NULL when idx_in is given),
+ *          w [n_ops][Nc][n_max] FP64 (zero past n_c),
+ *          status [Nc] (NULL allowed): 0 ok, 1 singular (smallest pivot below
+ *          1e-13 max|A|, or refinement did not converge).
+ * Returns RBFFD_ESINGULAR (after writing everything) when any status is 1;
+ * synchronises to read the status count. EINVAL: even m, l > 6, n_c < M,
+ * K = n_c + M > 128, Laplacian^k with m < 2k+1, n_ops outside 1..8. */
+int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
+                  int precision, int32_t *idx, double *w, int32_t *status);
+
+/* ---- B1-B4: right-hand side model -------------------------------------- */
+
+typedef struct {
+  int32_t physics;        /* RBFFD_PHYS_ADVECTION or RBFFD_PHYS_NS                      */
+  int32_t field_dtype;    /* RBFFD_F64 or RBFFD_F32 (state element type)                */
+  int32_t weight_dtype;   /* RBFFD_F64, RBFFD_F32 or RBFFD_BF16 for the first-derivative
+                             and Laplacian weights; hyperviscosity and closure weights
+                             stay FP64. F32/BF16 need field_dtype F32.                   */
+  int32_t n;              /* stencil length (row length of idx and w)                    */
+  int64_t n_total;        /* N: all nodes including ghosts                               */
+  int64_t n_active;       /* nodes 0..n_active-1 carry stencils and prognostic values;
+                             n_active..N-1 are ghost nodes                               */
+  int32_t ensemble;       /* E >= 1 members sharing the weights                          */
+  int32_t reserved0;
+  const int32_t *idx;     /* [n_active][n] stencils (indices < N)                        */
+  const double *w;        /* [n_ops][n_active][n] weights. Transport: Dx, Dz, Lap^k.
+                             Navier-Stokes: Dx, Dz, Lap, Lap^k.                         */
+  const double *xy;       /* [N][2] node coordinates (z gives pi-bar(z))                 */
+  double hv_coeff;        /* coefficient of the Lap^k term added to every field's
+                             tendency (sign included; +gamma for k = 3)                 */
+  /* transport (Section 6.1, flux form): velocity (U, V)(x) * cos(pi t / vel_period) */
+  const double *vel_u;    /* [n_total] U at the nodes (read at stencil neighbours)       */
+  const double *vel_v;    /* [n_total] V at the nodes                                    */
+  double vel_period;
+  /* Navier-Stokes constants (Section 6.2, 6.4) */
+  double c_p, c_v, R_d, g, theta_bar, mu;
+  /* ghost closure (Section 5.2), Navier-Stokes only */
+  int32_t n_walls;        /* 0 or 2 (bottom, top)                                        */
+  int32_t n_wall;         /* boundary nodes per wall = ghost nodes per wall              */
+  const int32_t *wall_nodes;   /* [n_walls][n_wall] active indices of boundary nodes     */
+  const int32_t *ghost_nodes;  /* [n_walls][n_wall] ghost indices; ghost g pairs with
+                                  boundary node g (W_G rows/columns in this order)       */
+  const double *wall_dz;  /* [n_walls][n_wall][n] Dz weights of the boundary rows        */
+  const double *wall_dzz; /* [n_walls][n_wall][n] Dzz weights of the boundary rows       */
+} rbffd_model_desc;
+
+/* Build a model: repack stencils and weights into the library's slot-major
+ * layout, mark wall nodes, and factor and invert each wall's ghost block W_G
+ * (Section 5.2) once on the host, keeping the inverse to rounding accuracy
+ * in a cyclic band. Synchronises. The caller's arrays may be freed after.
+ * EINVAL: inconsistent sizes, a wall stencil that reaches the other wall's
+ * ghosts; ESINGULAR: a singular W_G. */
+int rbffd_model_create(rbffd_ctx *ctx, const rbffd_model_desc *desc, rbffd_model **out);
+int rbffd_model_destroy(rbffd_model *model);
+
+/* B1 alone: set w = 0 on the wall nodes and fill the ghost rows of `state`
+ * ([N][E][F]) from W_G u_G = bc - W_I u_I - W_B u_B for u, theta' (bc 0),
+ * pi' (bc = g theta'/(c_p theta_bar (theta_bar + theta'))) with the Dz rows
+ * and w (bc 0) with the Dzz rows. No-op for transport models. */
+int rbffd_ghost(rbffd_ctx *ctx, rbffd_model *model, void *state);
+
+/* B1-B3: one right-hand-side evaluation at time t. Runs the closure on
+ * `state` (its wall-w and ghost entries are overwritten), then writes
+ * tendency [N][E][F] for the active nodes (ghost rows and wall dw/dt set 0). */
+int rbffd_rhs(rbffd_ctx *ctx, rbffd_model *model, double t, void *state, void *tendency);
+
+/* B1-B4: advance `state` in place by n_steps steps of size dt with the
+ * tableau (RBFFD_RK4: classical RK4; RBFFD_WSRK3: y1 = y + dt/3 f(y),
+ * y2 = y + dt/2 f(y1), y + dt f(y2)). Each stage is closure -> fused
+ * RHS + stage update; one step is captured once as a HIP graph and replayed.
+ * *t (host) is advanced. Synchronises at the end to check for non-finite
+ * values: returns RBFFD_ENONFINITE and names the first bad step in
+ * rbffd_last_error. */
+int rbffd_step(rbffd_ctx *ctx, rbffd_model *model, void *state, double *t, double dt,
+               int64_t n_steps, int tableau);
+
+/* Bytes of the slot-major stencil stream (indices + weights of every
+ * operator) plus per-node constants that the fused right-hand-side kernel
+ * reads per node and evaluation; field traffic is not included. */
+int64_t rbffd_model_bytes_per_node(rbffd_model *model);
+
+/* Kernel timing for measurement: while enabled (enable != 0), rbffd_rhs and
+ * rbffd_step launch every stage without graph replay and record a pair of
+ * HIP events on the context stream around each fused right-hand-side
+ * kernel. rbffd_model_profile_read synchronises and returns the summed
+ * kernel time (ms) and the number of launches since the last read or
+ * enable, then resets both. */
+int rbffd_model_profile(rbffd_model *model, int enable);
+int rbffd_model_profile_read(rbffd_model *model, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBFFD_H */

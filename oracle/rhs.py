@@ -134,26 +134,36 @@ def ghost_closure(model: NSModel, state: np.ndarray) -> np.ndarray:
     return s
 
 
+def ns_tendency(s, rows, idx, w_dx, w_dz, w_lap, w_hv, z, is_wall, consts, hv_coeff):
+    """Eqs. uEq..piEq at the nodes ``rows`` of a closed state ``s`` [n_total][4]
+    (ghost rows filled), given those rows' stencils and weights."""
+    c = consts
+    u, w, th, pi = (s[rows, f] for f in range(4))
+    D = lambda W: apply_dm(idx, W, s)                    # noqa: E731  [rows][4]
+    dx, dz, lap, hv = D(w_dx), D(w_dz), D(w_lap), D(w_hv)
+    pibar = 1.0 - c["g"] * z / (c["c_p"] * c["theta_bar"])
+    dpibar = -c["g"] / (c["c_p"] * c["theta_bar"])
+    out = np.zeros((len(rows), 4))
+    cp_th = c["c_p"] * (c["theta_bar"] + th)
+    out[:, 0] = -u * dx[:, 0] - w * dz[:, 0] - cp_th * dx[:, 3] + c["mu"] * lap[:, 0]
+    out[:, 1] = -u * dx[:, 1] - w * dz[:, 1] - cp_th * dz[:, 3] \
+        + c["g"] * th / c["theta_bar"] + c["mu"] * lap[:, 1]
+    out[:, 2] = -u * dx[:, 2] - w * dz[:, 2] + c["mu"] * lap[:, 2]
+    out[:, 3] = -u * dx[:, 3] - w * (dpibar + dz[:, 3]) \
+        - (c["R_d"] / c["c_v"]) * (pibar + pi) * (dx[:, 0] + dz[:, 1])
+    out += hv_coeff * hv
+    out[is_wall, 1] = 0.0
+    return out
+
+
 def ns_rhs(model: NSModel, state: np.ndarray):
     """Tendency [n_total][4] of Eqs. uEq..piEq (zero on ghost rows) and the
     closed state (ghost rows filled) it was evaluated on."""
-    c = model.consts
     s = ghost_closure(model, state)
     na = model.n_active
-    u, w, th, pi = (s[:na, f] for f in range(4))
-    D = lambda W: apply_dm(model.idx, W, s)              # noqa: E731  [n_active][4]
-    dx, dz, lap, hv = D(model.w_dx), D(model.w_dz), D(model.w_lap), D(model.w_hv)
-    z = model.z[:na]
-    pibar = 1.0 - c["g"] * z / (c["c_p"] * c["theta_bar"])
-    dpibar = -c["g"] / (c["c_p"] * c["theta_bar"])
+    is_wall = np.zeros(na, bool)
+    is_wall[model.wall_nodes.ravel()] = True
     out = np.zeros_like(s)
-    cp_th = c["c_p"] * (c["theta_bar"] + th)
-    out[:na, 0] = -u * dx[:, 0] - w * dz[:, 0] - cp_th * dx[:, 3] + c["mu"] * lap[:, 0]
-    out[:na, 1] = -u * dx[:, 1] - w * dz[:, 1] - cp_th * dz[:, 3] \
-        + c["g"] * th / c["theta_bar"] + c["mu"] * lap[:, 1]
-    out[:na, 2] = -u * dx[:, 2] - w * dz[:, 2] + c["mu"] * lap[:, 2]
-    out[:na, 3] = -u * dx[:, 3] - w * (dpibar + dz[:, 3]) \
-        - (c["R_d"] / c["c_v"]) * (pibar + pi) * (dx[:, 0] + dz[:, 1])
-    out[:na] += model.hv_coeff * hv
-    out[model.wall_nodes.ravel(), 1] = 0.0
+    out[:na] = ns_tendency(s, np.arange(na), model.idx, model.w_dx, model.w_dz, model.w_lap,
+                           model.w_hv, model.z[:na], is_wall, model.consts, model.hv_coeff)
     return out, s

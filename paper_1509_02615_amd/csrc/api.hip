@@ -1,0 +1,181 @@
+// extern "C" entry points of librbffd: argument checks and dispatch.
+#include <cstdarg>
+#include <new>
+
+#include "common.hpp"
+
+int rbffd_fail(rbffd_ctx *ctx, int code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return code;
+}
+
+extern "C" {
+
+int rbffd_create(rbffd_ctx **out, int device, void *hip_stream) {
+  if (!out) return RBFFD_EINVAL;
+  *out = nullptr;
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev)
+    return RBFFD_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return RBFFD_EDEVICE;
+  auto *ctx = new (std::nothrow) rbffd_ctx();
+  if (!ctx) return RBFFD_ENOMEM;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
+  *out = ctx;
+  return RBFFD_OK;
+}
+
+int rbffd_destroy(rbffd_ctx *ctx) {
+  delete ctx;
+  return RBFFD_OK;
+}
+
+const char *rbffd_last_error(rbffd_ctx *ctx) {
+  return ctx ? ctx->last_error.c_str() : "null context";
+}
+
+int rbffd_sync(rbffd_ctx *ctx) {
+  if (!ctx) return RBFFD_EINVAL;
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return RBFFD_OK;
+}
+
+static int check_stencils(rbffd_ctx *ctx, const rbffd_stencils *st) {
+  if (!st) return rbffd_fail(ctx, RBFFD_EINVAL, "null stencil description");
+  if (st->n_nodes <= 0 || st->n_nodes >= (int64_t(1) << 31) || !st->xy)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "bad node set (n_nodes=%lld)", (long long)st->n_nodes);
+  if (st->n_centers <= 0 || st->n_centers >= (int64_t(1) << 31))
+    return rbffd_fail(ctx, RBFFD_EINVAL, "bad n_centers=%lld", (long long)st->n_centers);
+  if (st->n_max < 1 || st->n_max > 120)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "n_max=%d outside 1..120", st->n_max);
+  if (st->n_max > st->n_nodes)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "stencil larger than the node set");
+  if (!(st->period_x >= 0.0)) return rbffd_fail(ctx, RBFFD_EINVAL, "negative period");
+  return RBFFD_OK;
+}
+
+int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx) {
+  if (!ctx) return RBFFD_EINVAL;
+  int rc = check_stencils(ctx, st);
+  if (rc) return rc;
+  if (!idx) return rbffd_fail(ctx, RBFFD_EINVAL, "null idx");
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return knn_run(ctx, st, idx);
+}
+
+int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
+                  int precision, int32_t *idx, double *w, int32_t *status) {
+  if (!ctx) return RBFFD_EINVAL;
+  int rc = check_stencils(ctx, st);
+  if (rc) return rc;
+  if (!ops || n_ops < 1 || n_ops > 8) return rbffd_fail(ctx, RBFFD_EINVAL, "n_ops=%d outside 1..8", n_ops);
+  if (!w) return rbffd_fail(ctx, RBFFD_EINVAL, "null w");
+  if (!st->idx_in && !idx) return rbffd_fail(ctx, RBFFD_EINVAL, "need idx output or idx_in");
+  if (precision != RBFFD_SOLVE_FP64 && precision != RBFFD_SOLVE_FP32_IR)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "bad precision %d", precision);
+  // Uniform parameters are checked here; per-centre ones are checked on the
+  // device (a bad entry gives status 2 and EINVAL).
+  if (!st->m_per && (st->m_uniform < 1 || st->m_uniform > 15 || st->m_uniform % 2 == 0))
+    return rbffd_fail(ctx, RBFFD_EINVAL, "PHS order m=%d must be odd in 1..15", st->m_uniform);
+  if (!st->l_per && (st->l_uniform < 0 || st->l_uniform > 6))
+    return rbffd_fail(ctx, RBFFD_EINVAL, "degree l=%d outside 0..6", st->l_uniform);
+  for (int i = 0; i < n_ops; ++i) {
+    const rbffd_op &o = ops[i];
+    if (o.kind < RBFFD_DX || o.kind > RBFFD_DZZ || o.reserved != 0 || o.k < 0 || o.k > 7 ||
+        o.phs_order < 0 || o.phs_order > 15 || (o.phs_order && o.phs_order % 2 == 0))
+      return rbffd_fail(ctx, RBFFD_EINVAL, "bad operator %d (kind %d k %d order %d)", i, o.kind,
+                        o.k, o.phs_order);
+    if (o.kind == RBFFD_HYPERLAP && o.k > 0) {
+      int m = o.phs_order ? o.phs_order : (st->m_per ? 15 : st->m_uniform);
+      if (m < 2 * o.k + 1)
+        return rbffd_fail(ctx, RBFFD_EINVAL, "Laplacian^%d of r^%d is not continuous", o.k, m);
+    }
+  }
+  if (!st->n_per && !st->l_per) {
+    int M = (st->l_uniform + 1) * (st->l_uniform + 2) / 2;
+    if (st->n_max < M)
+      return rbffd_fail(ctx, RBFFD_EINVAL, "stencil size %d below the %d polynomial terms", st->n_max, M);
+    if (st->n_max + M > 128)
+      return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d above 128", st->n_max + M);
+  }
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  const int32_t *use_idx = st->idx_in;
+  if (!use_idx) {
+    rc = knn_run(ctx, st, idx);
+    if (rc) return rc;
+    use_idx = idx;
+  } else if (idx) {
+    RBFFD_HIP(ctx, hipMemcpyAsync(idx, st->idx_in, sizeof(int32_t) * st->n_centers * st->n_max,
+                                  hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  int32_t n_bad = 0;
+  rc = weights_run(ctx, st, ops, n_ops, precision, use_idx, w, status, &n_bad);
+  if (rc) return rc;
+  if (n_bad < 0) return rbffd_fail(ctx, RBFFD_EINVAL, "%d stencils have invalid m, l or n", -n_bad);
+  if (n_bad > 0) return rbffd_fail(ctx, RBFFD_ESINGULAR, "%d singular stencil systems", n_bad);
+  return RBFFD_OK;
+}
+
+int rbffd_model_create(rbffd_ctx *ctx, const rbffd_model_desc *desc, rbffd_model **out) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!desc || !out) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  *out = nullptr;
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return model_create_impl(ctx, desc, out);
+}
+
+int rbffd_model_destroy(rbffd_model *model) { return model_destroy_impl(model); }
+
+int rbffd_ghost(rbffd_ctx *ctx, rbffd_model *model, void *state) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!model || !state) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return model_ghost(ctx, model, state);
+}
+
+int rbffd_rhs(rbffd_ctx *ctx, rbffd_model *model, double t, void *state, void *tendency) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!model || !state || !tendency) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return model_rhs(ctx, model, t, state, tendency);
+}
+
+int rbffd_step(rbffd_ctx *ctx, rbffd_model *model, void *state, double *t, double dt,
+               int64_t n_steps, int tableau) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!model || !state || !t) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  if (n_steps < 0 || n_steps >= (int64_t(1) << 31))
+    return rbffd_fail(ctx, RBFFD_EINVAL, "bad n_steps");
+  if (tableau != RBFFD_RK4 && tableau != RBFFD_WSRK3)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "bad tableau %d", tableau);
+  if (!(dt > 0.0)) return rbffd_fail(ctx, RBFFD_EINVAL, "dt must be positive");
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return model_step(ctx, model, state, t, dt, n_steps, tableau);
+}
+
+int64_t rbffd_model_bytes_per_node(rbffd_model *model) {
+  return model ? model_bytes_per_node(model) : 0;
+}
+
+int rbffd_model_profile(rbffd_model *model, int enable) {
+  if (!model) return RBFFD_EINVAL;
+  return model_profile(model, enable);
+}
+
+int rbffd_model_profile_read(rbffd_model *model, double *total_ms, int64_t *launches) {
+  if (!model || !total_ms || !launches) return RBFFD_EINVAL;
+  return model_profile_read(model, total_ms, launches);
+}
+
+}  // extern "C"

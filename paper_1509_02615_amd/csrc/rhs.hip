@@ -1,0 +1,545 @@
+// B1-B4: ghost closure, fused gather-stencil right-hand side, RK stages.
+//
+// The right-hand side is a memory-bound ELL product: for every node i and
+// slot k the kernel streams the slot-major record (index + weights of
+// every operator) once, coalesced across the wavefront, gathers the
+// neighbour's fields (all four fields of a node are one 16- or 32-byte
+// vector, so a gather is one load) and accumulates every derivative the
+// equations need. The pointwise physics and the Runge-Kutta stage update are
+// fused into the epilogue, so one launch per stage reads each stream once.
+//
+// Navier-Stokes (Eqs. uEq, wEq, thetaEq, piEq): 15 dot products per node --
+// Dx and Dz of u, w, theta', pi'; Lap of u, w, theta' (mu Lap); Lap^k of all
+// four (hyperviscosity, Section 5.3). Transport (Section 6.1, flux form):
+// the velocity shape is folded into one weight per slot, 2 dot products.
+//
+// Reduced precision: FP32 fields use centre-subtracted sums
+// sum_k w_k (f_j - f_i), which equal sum_k w_k f_j because derivative
+// weights sum to zero (they reproduce constants, Section 3); hyperviscosity
+// weights stay FP64 and accumulate in FP64 (their sums cancel strongly).
+//
+// Launch geometry: 256-thread blocks, thread = (node, member); block ids are
+// remapped so that each of the 8 XCDs (which take block ids round-robin)
+// works on one contiguous node range and its L2 sees neighbouring gathers.
+#include <climits>
+#include <cmath>
+
+#include "model.hpp"
+
+namespace {
+
+constexpr int RHS_BLOCK = 256;
+
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  const int64_t full = (nb / 8) * 8;
+  if (b >= full) return b;
+  return (b % 8) * (nb / 8) + b / 8;
+}
+
+template <class FT> struct F4 {
+  FT v[4];
+};
+
+__device__ __forceinline__ F4<float> load4(const float *p) {
+  float4 q = *reinterpret_cast<const float4 *>(p);
+  return F4<float>{{q.x, q.y, q.z, q.w}};
+}
+__device__ __forceinline__ F4<double> load4(const double *p) {
+  double2 a = reinterpret_cast<const double2 *>(p)[0];
+  double2 b = reinterpret_cast<const double2 *>(p)[1];
+  return F4<double>{{a.x, a.y, b.x, b.y}};
+}
+__device__ __forceinline__ void store4(float *p, const double *v) {
+  *reinterpret_cast<float4 *>(p) = make_float4(static_cast<float>(v[0]), static_cast<float>(v[1]),
+                                               static_cast<float>(v[2]), static_cast<float>(v[3]));
+}
+__device__ __forceinline__ void store4(double *p, const double *v) {
+  reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+}
+
+__device__ __forceinline__ float bf16f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+
+struct NSArgs {
+  const void *ys;     // fields the derivatives are taken of  [N][E][4]
+  const void *yn;     // base of the stage update (y_n)
+  void *out;          // tendency or next stage
+  void *acc;          // RK4 accumulator
+  const int *idx_t;
+  const void *rec;
+  const double *hv_t;
+  const uint8_t *kind;
+  const double *pibar;
+  int64_t Na;
+  int n, E;
+  double c_p, rcv, g, theta_bar, mu, hv, dpibar;
+  double ca, cb;
+  int mode;      // 0: out = f; 1: out = yn + ca f; 2: out = acc + ca f
+  int acc_mode;  // 0: none; 1: acc = yn + cb f; 2: acc += cb f
+  DevMisc *misc;
+  int check;     // record the step of the first non-finite output
+};
+
+template <class FT, int WDT>
+__global__ __launch_bounds__(RHS_BLOCK) void ns_stage_kernel(NSArgs a) {
+  const int64_t t = xcd_block() * RHS_BLOCK + threadIdx.x;
+  if (t >= a.Na * a.E) return;
+  const int E = a.E;
+  const int64_t i = E == 1 ? t : t / E;
+  const int e = static_cast<int>(t - i * E);
+  const FT *ys = static_cast<const FT *>(a.ys);
+  const F4<FT> own = load4(ys + (i * E + e) * 4);
+  FT sdx[4] = {0, 0, 0, 0}, sdz[4] = {0, 0, 0, 0}, slp[3] = {0, 0, 0};
+  double shv[4] = {0.0, 0.0, 0.0, 0.0};
+  const int n = a.n;
+  const int64_t Na = a.Na;
+#pragma unroll 2
+  for (int k = 0; k < n; ++k) {
+    const int64_t s = static_cast<int64_t>(k) * Na + i;
+    int j;
+    FT wdx, wdz, wlp;
+    double whv;
+    if constexpr (WDT == RBFFD_F64) {
+      const RecF64 r = static_cast<const RecF64 *>(a.rec)[s];
+      j = a.idx_t[s];
+      wdx = r.dx;
+      wdz = r.dz;
+      wlp = r.lap;
+      whv = r.hv;
+    } else if constexpr (WDT == RBFFD_F32) {
+      const RecF32 r = static_cast<const RecF32 *>(a.rec)[s];
+      j = r.idx;
+      wdx = r.dx;
+      wdz = r.dz;
+      wlp = r.lap;
+      whv = a.hv_t[s];
+    } else {
+      const RecBF16 r = static_cast<const RecBF16 *>(a.rec)[s];
+      j = r.idx;
+      wdx = bf16f(r.dx);
+      wdz = bf16f(r.dz);
+      wlp = bf16f(r.lap);
+      whv = a.hv_t[s];
+    }
+    const F4<FT> f = load4(ys + (static_cast<int64_t>(j) * E + e) * 4);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const FT d = f.v[c] - own.v[c];
+      sdx[c] = fma(wdx, d, sdx[c]);
+      sdz[c] = fma(wdz, d, sdz[c]);
+      if (c < 3) slp[c] = fma(wlp, d, slp[c]);
+      shv[c] = fma(whv, static_cast<double>(d), shv[c]);
+    }
+  }
+  // Eqs. uEq..piEq (perturbation form), evaluated in FP64
+  const double u = own.v[0], w = own.v[1], th = own.v[2], pi = own.v[3];
+  const double cp_th = a.c_p * (a.theta_bar + th);
+  double f[4];
+  f[0] = -u * sdx[0] - w * sdz[0] - cp_th * sdx[3] + a.mu * slp[0] + a.hv * shv[0];
+  f[1] = -u * sdx[1] - w * sdz[1] - cp_th * sdz[3] + a.g * th / a.theta_bar + a.mu * slp[1] + a.hv * shv[1];
+  f[2] = -u * sdx[2] - w * sdz[2] + a.mu * slp[2] + a.hv * shv[2];
+  f[3] = -u * sdx[3] - w * (a.dpibar + static_cast<double>(sdz[3])) -
+         a.rcv * (a.pibar[i] + pi) * (static_cast<double>(sdx[0]) + static_cast<double>(sdz[1])) + a.hv * shv[3];
+  if (a.kind[i] == 1) f[1] = 0.0;  // w stays 0 on the walls
+  const int64_t o = (i * E + e) * 4;
+  double r[4];
+  if (a.mode == 0) {
+    for (int c = 0; c < 4; ++c) r[c] = f[c];
+  } else {
+    const F4<FT> b = load4(static_cast<const FT *>(a.mode == 1 ? a.yn : a.acc) + o);
+    for (int c = 0; c < 4; ++c) r[c] = static_cast<double>(b.v[c]) + a.ca * f[c];
+    if (a.acc_mode) {
+      const F4<FT> base = load4(static_cast<const FT *>(a.acc_mode == 1 ? a.yn : a.acc) + o);
+      double q[4];
+      for (int c = 0; c < 4; ++c) q[c] = static_cast<double>(base.v[c]) + a.cb * f[c];
+      store4(static_cast<FT *>(a.acc) + o, q);
+    }
+  }
+  store4(static_cast<FT *>(a.out) + o, r);
+  if (a.check) {
+    bool fin = isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]) && isfinite(r[3]);
+    if (!fin) atomicMin(&a.misc->nonfinite_step, a.misc->step_ctr);
+  }
+}
+
+struct AdvArgs {
+  const void *ys, *yn;
+  void *out, *acc;
+  const int *idx_t;
+  const RecAdv *rec;
+  int64_t Na;
+  int n, E;
+  double hv, omega;     // velocity factor cos(omega * t)
+  double t_fixed;       // stage time when misc == nullptr
+  double t_off, dt;     // stage time = t0 + step_ctr * dt + t_off
+  double ca, cb;
+  int mode, acc_mode;
+  DevMisc *misc;
+  int check;
+};
+
+template <class FT>
+__global__ __launch_bounds__(RHS_BLOCK) void adv_stage_kernel(AdvArgs a) {
+  const int64_t t = xcd_block() * RHS_BLOCK + threadIdx.x;
+  if (t >= a.Na * a.E) return;
+  const int E = a.E;
+  const int64_t i = E == 1 ? t : t / E;
+  const int e = static_cast<int>(t - i * E);
+  const FT *ys = static_cast<const FT *>(a.ys);
+  double sa = 0.0, sh = 0.0;
+  const int64_t Na = a.Na;
+#pragma unroll 4
+  for (int k = 0; k < a.n; ++k) {
+    const int64_t s = static_cast<int64_t>(k) * Na + i;
+    const int j = a.idx_t[s];
+    const RecAdv r = a.rec[s];
+    const double v = ys[static_cast<int64_t>(j) * E + e];
+    sa = fma(r.adv, v, sa);
+    sh = fma(r.hv, v, sh);
+  }
+  double ts = a.t_fixed;
+  if (a.misc) ts = (a.misc->t0 + static_cast<double>(a.misc->step_ctr) * a.dt) + a.t_off;
+  const double f = -cos(a.omega * ts) * sa + a.hv * sh;
+  const int64_t o = i * E + e;
+  double r;
+  if (a.mode == 0) {
+    r = f;
+  } else {
+    const FT *b = static_cast<const FT *>(a.mode == 1 ? a.yn : a.acc);
+    r = static_cast<double>(b[o]) + a.ca * f;
+    if (a.acc_mode) {
+      const FT *base = static_cast<const FT *>(a.acc_mode == 1 ? a.yn : a.acc);
+      static_cast<FT *>(a.acc)[o] = static_cast<FT>(static_cast<double>(base[o]) + a.cb * f);
+    }
+  }
+  static_cast<FT *>(a.out)[o] = static_cast<FT>(r);
+  if (a.check && !isfinite(r)) atomicMin(&a.misc->nonfinite_step, a.misc->step_ctr);
+}
+
+struct GArgs {
+  void *y;  // [N][E][4]
+  const int *wall_nodes, *ghost_nodes, *wall_idx, *gstart;
+  const double2 *wall_w;
+  const double *ginv;
+  double *gres;
+  const uint8_t *kind;
+  int nb, n, E, band, n_walls;
+  double bc_scale, theta_bar;  // dpi/dz = bc_scale * th / (theta_bar + th)
+};
+
+// B1 part 1: boundary-row residuals r = bc - (W_I u_I + W_B u_B), w_B := 0.
+template <class FT>
+__global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_kernel(GArgs a) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * RHS_BLOCK + threadIdx.x;
+  const int E = a.E;
+  if (t >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
+  const int64_t wb = t / E;  // wall * nb + b
+  const int e = static_cast<int>(t - wb * E);
+  FT *y = static_cast<FT *>(a.y);
+  const int node = a.wall_nodes[wb];
+  double ru = 0.0, rw = 0.0, rt = 0.0, rp = 0.0;
+  for (int k = 0; k < a.n; ++k) {
+    const int64_t s = wb * a.n + k;
+    const int j = a.wall_idx[s];
+    const uint8_t kj = a.kind[j];
+    if (kj == 2) continue;  // ghost entries form W_G
+    const double2 ww = a.wall_w[s];
+    const F4<FT> f = load4(y + (static_cast<int64_t>(j) * E + e) * 4);
+    ru = fma(-ww.x, static_cast<double>(f.v[0]), ru);
+    rt = fma(-ww.x, static_cast<double>(f.v[2]), rt);
+    rp = fma(-ww.x, static_cast<double>(f.v[3]), rp);
+    if (kj != 1) rw = fma(-ww.y, static_cast<double>(f.v[1]), rw);  // wall w is 0
+  }
+  const double thb = static_cast<double>(y[(static_cast<int64_t>(node) * E + e) * 4 + 2]);
+  rp += a.bc_scale * thb / (a.theta_bar + thb);
+  y[(static_cast<int64_t>(node) * E + e) * 4 + 1] = FT(0);
+  double *g = a.gres + (wb * E + e) * 4;
+  g[0] = ru;
+  g[1] = rw;
+  g[2] = rt;
+  g[3] = rp;
+}
+
+// B1 part 2: ghost values u_G = W_G^-1 r through the banded inverse.
+template <class FT>
+__global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_kernel(GArgs a) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * RHS_BLOCK + threadIdx.x;
+  const int E = a.E;
+  if (t >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
+  const int64_t wg = t / E;  // wall * nb + ghost position
+  const int e = static_cast<int>(t - wg * E);
+  const int wl = static_cast<int>(wg / a.nb), gp = static_cast<int>(wg - static_cast<int64_t>(wl) * a.nb);
+  double v[4];
+  for (int f = 0; f < 4; ++f) {
+    const int op = f == 1 ? 1 : 0;
+    const int64_t row = (static_cast<int64_t>(wl) * 2 + op) * a.nb + gp;
+    const double *z = a.ginv + row * a.band;
+    int p = a.gstart[row];
+    const double *r = a.gres + (static_cast<int64_t>(wl) * a.nb * E + e) * 4 + f;
+    double s = 0.0;
+    for (int q = 0; q < a.band; ++q) {
+      s = fma(z[q], r[static_cast<int64_t>(p) * E * 4], s);
+      if (++p == a.nb) p = 0;
+    }
+    v[f] = s;
+  }
+  store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.ghost_nodes[wg]) * E + e) * 4, v);
+}
+
+__global__ void misc_init_kernel(DevMisc *m, double t0) {
+  m->nonfinite_step = INT_MAX;
+  m->step_ctr = 0;
+  m->t0 = t0;
+}
+
+__global__ void tick_kernel(DevMisc *m) { m->step_ctr += 1; }
+
+// ---- host-side launchers ----------------------------------------------------
+
+int launch_ghost(rbffd_ctx *ctx, rbffd_model *m, void *y) {
+  if (m->physics != RBFFD_PHYS_NS || m->n_walls == 0) return RBFFD_OK;
+  GArgs g{};
+  g.y = y;
+  g.wall_nodes = m->wall_nodes.as<int>();
+  g.ghost_nodes = m->ghost_nodes.as<int>();
+  g.wall_idx = m->wall_idx.as<int>();
+  g.gstart = m->gstart.as<int>();
+  g.wall_w = m->wall_w.as<double2>();
+  g.ginv = m->ginv.as<double>();
+  g.gres = m->gres.as<double>();
+  g.kind = m->kind.as<uint8_t>();
+  g.nb = m->nb;
+  g.n = m->n;
+  g.E = m->E;
+  g.band = m->band;
+  g.n_walls = m->n_walls;
+  g.bc_scale = m->g / (m->c_p * m->theta_bar);
+  g.theta_bar = m->theta_bar;
+  const int64_t cnt = static_cast<int64_t>(m->n_walls) * m->nb * m->E;
+  if (m->fdt == RBFFD_F64) {
+    ghost_resid_kernel<double><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(g);
+    ghost_apply_kernel<double><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(g);
+  } else {
+    ghost_resid_kernel<float><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(g);
+    ghost_apply_kernel<float><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(g);
+  }
+  RBFFD_HIP(ctx, hipGetLastError());
+  return RBFFD_OK;
+}
+
+struct StageSpec {
+  const void *ys, *yn;
+  void *out;
+  double ca, cb, t_off;
+  int mode, acc_mode, check;
+};
+
+int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_fixed, bool use_misc, double dt) {
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (m->profile) {
+    RBFFD_HIP(ctx, hipEventCreate(&ev0));
+    RBFFD_HIP(ctx, hipEventCreate(&ev1));
+    m->prof_events.push_back({ev0, ev1});
+    RBFFD_HIP(ctx, hipEventRecord(ev0, ctx->stream));
+  }
+  const int64_t cnt = m->Na * m->E;
+  const unsigned grid = grid_for(cnt, RHS_BLOCK);
+  DevMisc *misc = m->dev_misc.as<DevMisc>();
+  if (m->physics == RBFFD_PHYS_NS) {
+    NSArgs a{};
+    a.ys = sp.ys;
+    a.yn = sp.yn;
+    a.out = sp.out;
+    a.acc = m->acc.p;
+    a.idx_t = m->idx_t.as<int>();
+    a.rec = m->rec.p;
+    a.hv_t = m->hv_t.as<double>();
+    a.kind = m->kind.as<uint8_t>();
+    a.pibar = m->pibar.as<double>();
+    a.Na = m->Na;
+    a.n = m->n;
+    a.E = m->E;
+    a.c_p = m->c_p;
+    a.rcv = m->R_d / m->c_v;
+    a.g = m->g;
+    a.theta_bar = m->theta_bar;
+    a.mu = m->mu;
+    a.hv = m->hv_coeff;
+    a.dpibar = -m->g / (m->c_p * m->theta_bar);
+    a.ca = sp.ca;
+    a.cb = sp.cb;
+    a.mode = sp.mode;
+    a.acc_mode = sp.acc_mode;
+    a.misc = misc;
+    a.check = sp.check;
+    if (m->fdt == RBFFD_F64)
+      ns_stage_kernel<double, RBFFD_F64><<<grid, RHS_BLOCK, 0, ctx->stream>>>(a);
+    else if (m->wdt == RBFFD_F32)
+      ns_stage_kernel<float, RBFFD_F32><<<grid, RHS_BLOCK, 0, ctx->stream>>>(a);
+    else
+      ns_stage_kernel<float, RBFFD_BF16><<<grid, RHS_BLOCK, 0, ctx->stream>>>(a);
+  } else {
+    AdvArgs a{};
+    a.ys = sp.ys;
+    a.yn = sp.yn;
+    a.out = sp.out;
+    a.acc = m->acc.p;
+    a.idx_t = m->idx_t.as<int>();
+    a.rec = m->rec.as<RecAdv>();
+    a.Na = m->Na;
+    a.n = m->n;
+    a.E = m->E;
+    a.hv = m->hv_coeff;
+    a.omega = M_PI / m->vel_period;
+    a.t_fixed = t_fixed;
+    a.t_off = sp.t_off;
+    a.dt = dt;
+    a.ca = sp.ca;
+    a.cb = sp.cb;
+    a.mode = sp.mode;
+    a.acc_mode = sp.acc_mode;
+    a.misc = use_misc ? misc : nullptr;
+    a.check = sp.check;
+    if (m->fdt == RBFFD_F64)
+      adv_stage_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(a);
+    else
+      adv_stage_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(a);
+  }
+  RBFFD_HIP(ctx, hipGetLastError());
+  if (ev1) RBFFD_HIP(ctx, hipEventRecord(ev1, ctx->stream));
+  return RBFFD_OK;
+}
+
+// Zero the ghost rows of a tendency / state buffer (fill kernel, graph-safe).
+__global__ void zero_rows_kernel(void *p, int64_t first_byte, int64_t n_bytes) {
+  int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n_bytes / 4) static_cast<uint32_t *>(p)[first_byte / 4 + t] = 0u;
+}
+
+// One full time step, as a sequence of launches on the context stream.
+int enqueue_step(rbffd_ctx *ctx, rbffd_model *m, void *y, double dt, int tableau) {
+  int rc;
+  void *ya = m->ya.p, *yb = m->yb.p;
+  if (tableau == RBFFD_RK4) {
+    const StageSpec st[4] = {
+        {y, y, ya, 0.5 * dt, dt / 6.0, 0.0, 1, 1, 0},
+        {ya, y, yb, 0.5 * dt, dt / 3.0, 0.5 * dt, 1, 2, 0},
+        {yb, y, ya, dt, dt / 3.0, 0.5 * dt, 1, 2, 0},
+        {ya, nullptr, y, dt / 6.0, 0.0, dt, 2, 0, 1},
+    };
+    for (const StageSpec &sp : st) {
+      if ((rc = launch_ghost(ctx, m, const_cast<void *>(sp.ys)))) return rc;
+      if ((rc = launch_stage(ctx, m, sp, 0.0, true, dt))) return rc;
+    }
+  } else {
+    const StageSpec st[3] = {
+        {y, y, ya, dt / 3.0, 0.0, 0.0, 1, 0, 0},
+        {ya, y, yb, dt / 2.0, 0.0, dt / 3.0, 1, 0, 0},
+        {yb, y, y, dt, 0.0, dt / 2.0, 1, 0, 1},
+    };
+    for (const StageSpec &sp : st) {
+      if ((rc = launch_ghost(ctx, m, const_cast<void *>(sp.ys)))) return rc;
+      if ((rc = launch_stage(ctx, m, sp, 0.0, true, dt))) return rc;
+    }
+  }
+  tick_kernel<<<1, 1, 0, ctx->stream>>>(m->dev_misc.as<DevMisc>());
+  RBFFD_HIP(ctx, hipGetLastError());
+  return RBFFD_OK;
+}
+
+}  // namespace
+
+int model_ghost(rbffd_ctx *ctx, rbffd_model *m, void *state) { return launch_ghost(ctx, m, state); }
+
+int model_rhs(rbffd_ctx *ctx, rbffd_model *m, double t, void *state, void *tendency) {
+  int rc = launch_ghost(ctx, m, state);
+  if (rc) return rc;
+  StageSpec sp{state, state, tendency, 0.0, 0.0, 0.0, 0, 0, 0};
+  rc = launch_stage(ctx, m, sp, t, false, 0.0);
+  if (rc) return rc;
+  if (m->N > m->Na) {
+    const int64_t row = static_cast<int64_t>(m->E) * m->F * m->field_bytes();
+    const int64_t first = m->Na * row, bytes = (m->N - m->Na) * row;
+    zero_rows_kernel<<<grid_for(bytes / 4, 256), 256, 0, ctx->stream>>>(tendency, first, bytes);
+    RBFFD_HIP(ctx, hipGetLastError());
+  }
+  return RBFFD_OK;
+}
+
+int model_step(rbffd_ctx *ctx, rbffd_model *m, void *state, double *t, double dt, int64_t n_steps, int tableau) {
+  if (n_steps == 0) return RBFFD_OK;
+  hipStream_t s = ctx->stream;
+  misc_init_kernel<<<1, 1, 0, s>>>(m->dev_misc.as<DevMisc>(), *t);
+  RBFFD_HIP(ctx, hipGetLastError());
+  if (m->profile) {
+    for (int64_t k = 0; k < n_steps; ++k) {
+      int rc = enqueue_step(ctx, m, state, dt, tableau);
+      if (rc) return rc;
+    }
+  } else if (!m->exec || m->graph_state != state || m->graph_dt != dt || m->graph_tableau != tableau) {
+    if (m->exec) {
+      RBFFD_HIP(ctx, hipGraphExecDestroy(m->exec));
+      m->exec = nullptr;
+    }
+    if (m->graph) {
+      RBFFD_HIP(ctx, hipGraphDestroy(m->graph));
+      m->graph = nullptr;
+    }
+    hipStream_t cs = s;
+    bool own_stream = false;
+    if (cs == nullptr) {  // the null stream cannot be captured
+      RBFFD_HIP(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      own_stream = true;
+    }
+    hipStream_t saved = ctx->stream;
+    ctx->stream = cs;
+    RBFFD_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_step(ctx, m, state, dt, tableau);
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(cs, &graph);
+    ctx->stream = saved;
+    if (own_stream) (void)hipStreamDestroy(cs);
+    if (rc) return rc;
+    if (ec != hipSuccess) return rbffd_fail(ctx, RBFFD_EDEVICE, "graph capture: %s", hipGetErrorString(ec));
+    m->graph = graph;
+    RBFFD_HIP(ctx, hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));
+    m->graph_state = state;
+    m->graph_dt = dt;
+    m->graph_tableau = tableau;
+  }
+  if (!m->profile)
+    for (int64_t k = 0; k < n_steps; ++k) RBFFD_HIP(ctx, hipGraphLaunch(m->exec, s));
+  DevMisc h{};
+  RBFFD_HIP(ctx, hipMemcpyAsync(&h, m->dev_misc.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  RBFFD_HIP(ctx, hipStreamSynchronize(s));
+  const double t0 = *t;
+  *t = t0 + static_cast<double>(n_steps) * dt;
+  if (h.nonfinite_step != INT_MAX)
+    return rbffd_fail(ctx, RBFFD_ENONFINITE, "non-finite state at step %d of this call", h.nonfinite_step + 1);
+  return RBFFD_OK;
+}
+
+int model_profile(rbffd_model *m, int enable) {
+  m->profile = enable ? 1 : 0;
+  return RBFFD_OK;
+}
+
+int model_profile_read(rbffd_model *m, double *total_ms, int64_t *launches) {
+  rbffd_ctx *ctx = m->ctx;
+  RBFFD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double sum = 0.0;
+  for (auto &p : m->prof_events) {
+    float ms = 0.0f;
+    RBFFD_HIP(ctx, hipEventElapsedTime(&ms, p.first, p.second));
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = static_cast<int64_t>(m->prof_events.size());
+  for (auto &p : m->prof_events) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  m->prof_events.clear();
+  return RBFFD_OK;
+}

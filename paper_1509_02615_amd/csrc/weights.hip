@@ -1,0 +1,554 @@
+// A2-A4: batched RBF-FD weights, one saddle-point solve per stencil.
+//
+// Section 3, Eq. (weights): for phi(r) = r^m (m odd) and the monomials of
+// degree <= l, the weights of operator L at centre x_c are the first n
+// entries of the solution of
+//     [Phi P; P^T 0] [w; v] = [L phi(|x - x_j|) at x_c ; L p_q(x_c)].
+// The repeated solve over all N centres is the O(n^3 N) preprocessing cost
+// the paper names; stencils are independent, so one workgroup solves one
+// stencil and a launch covers them all (mixed n, m, l in one launch).
+//
+// Per workgroup:
+//  1. offsets of the stencil nodes from the centre (minimum image in x),
+//     scaled by rho = the largest offset length;
+//  2. assembly of [A | B] in LDS (column-major), A = [Phi P; P^T 0] of size
+//     K = n + M, B = one right-hand side per operator of this PHS order
+//     (Section 5.3, Eq. eqn:laplacian for Laplacian^k of r^m);
+//  3. LU with partial pivoting of [A | B] (FP64, or FP32 for the
+//     mixed-precision variant);
+//  4. back substitution, then iterative refinement: residual b - A x with A
+//     and b regenerated from the offsets and accumulated in double-double,
+//     correction through the same factors, until the correction is at
+//     rounding level;
+//  5. rescaling by rho^-q (q = derivative order) and the padded row write.
+//
+// FP64 matrix cores on gfx950 have the same peak as the FP64 vector ALUs,
+// so the factorisation is written on the vector ALUs.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace {
+
+constexpr int W_THREADS = 256;
+constexpr int MAX_OPS = 8;
+
+struct WOp {
+  int kind, k, order;
+};
+
+struct WArgs {
+  const double *xy;
+  double period;
+  const int *centers;
+  int n_centers;
+  int n_nodes;
+  const int *n_per;
+  int n_max;
+  const int *m_per;
+  int m_uni;
+  const int *l_per;
+  int l_uni;
+  const int *idx;
+  WOp ops[MAX_OPS];
+  int n_ops;
+  double *w;
+  int *status;
+  int k_cap;
+  int max_iter;
+};
+
+__device__ __forceinline__ int n_terms(int l) { return (l + 1) * (l + 2) / 2; }
+
+// Graded monomial order: q -> (a, b) of x^a z^b, degree d = a + b.
+__device__ __forceinline__ void mono(int q, int &a, int &b) {
+  int d = 0;
+  while ((d + 1) * (d + 2) / 2 <= q) ++d;
+  b = q - d * (d + 1) / 2;
+  a = d - b;
+}
+
+__device__ __forceinline__ double ipow(double x, int p) {
+  double r = 1.0;
+  for (int i = 0; i < (p < 0 ? -p : p); ++i) r *= x;
+  return p < 0 ? 1.0 / r : r;
+}
+
+__device__ __forceinline__ double fact(int n) {
+  double r = 1.0;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+
+// L applied to |x - x_j|^m at the centre, node offset (x, z).
+__device__ double phs_rhs(int kind, int m, int k, double x, double z) {
+#pragma clang fp contract(off)
+  double r2 = x * x + z * z;
+  if (r2 == 0.0) return 0.0;
+  double r = sqrt(r2);
+  switch (kind) {
+    case RBFFD_DX: return -m * ipow(r, m - 2) * x;
+    case RBFFD_DZ: return -m * ipow(r, m - 2) * z;
+    case RBFFD_LAP: return static_cast<double>(m * m) * ipow(r, m - 2);
+    case RBFFD_HYPERLAP: {
+      double c = 1.0;
+      for (int i = 0; i < k; ++i) c *= static_cast<double>((m - 2 * i) * (m - 2 * i));
+      return c * ipow(r, m - 2 * k);
+    }
+    case RBFFD_DZZ: {
+      double a = m * ipow(r, m - 2);
+      double b = (m >= 4) ? m * (m - 2) * ipow(r, m - 4) * z * z : m * (m - 2) * z * z / r;
+      return a + b;
+    }
+  }
+  return 0.0;
+}
+
+// L(x^a z^b) at the origin.
+__device__ double poly_rhs(int kind, int k, int a, int b) {
+  switch (kind) {
+    case RBFFD_DX: return (a == 1 && b == 0) ? 1.0 : 0.0;
+    case RBFFD_DZ: return (a == 0 && b == 1) ? 1.0 : 0.0;
+    case RBFFD_LAP: return ((a == 2 && b == 0) || (a == 0 && b == 2)) ? 2.0 : 0.0;
+    case RBFFD_DZZ: return (a == 0 && b == 2) ? 2.0 : 0.0;
+    case RBFFD_HYPERLAP: {
+      if (a + b != 2 * k || (a & 1) || (b & 1)) return 0.0;
+      double c = fact(k) / (fact(a / 2) * fact(k - a / 2));
+      return c * fact(a) * fact(b);
+    }
+  }
+  return 0.0;
+}
+
+// Entry (i, j) of [Phi P; P^T 0] for scaled offsets (xi, ze).
+__device__ __forceinline__ double sys_entry(int i, int j, int n, int m, const double *xi,
+                                            const double *ze) {
+#pragma clang fp contract(off)
+  if (i < n && j < n) {
+    double dx = xi[i] - xi[j], dz = ze[i] - ze[j];
+    return ipow(sqrt(dx * dx + dz * dz), m);
+  }
+  if (i < n) {
+    int a, b;
+    mono(j - n, a, b);
+    return ipow(xi[i], a) * ipow(ze[i], b);
+  }
+  if (j < n) {
+    int a, b;
+    mono(i - n, a, b);
+    return ipow(xi[j], a) * ipow(ze[j], b);
+  }
+  return 0.0;
+}
+
+__device__ __forceinline__ double rhs_entry(int i, int n, int m, const WOp &op, int k_eff,
+                                            const double *xi, const double *ze) {
+  if (i < n) return phs_rhs(op.kind, m, k_eff, xi[i], ze[i]);
+  int a, b;
+  mono(i - n, a, b);
+  return poly_rhs(op.kind, k_eff, a, b);
+}
+
+// b_i - sum_j A_ij x_j accumulated in double-double (exact products by
+// fma, error-free sums), rounded once at the end.
+__device__ double dd_residual(int i, int K, int n, int m, const double *xi, const double *ze,
+                              const double *x, double b) {
+#pragma clang fp contract(off)
+  double s = b, e = 0.0;
+  for (int j = 0; j < K; ++j) {
+    const double aij = sys_entry(i, j, n, m, xi, ze);
+    const double p = aij * x[j];
+    const double pe = fma(aij, x[j], -p);
+    const double s1 = s - p;
+    const double bb = s1 - s;
+    const double te = (s - (s1 - bb)) + (-p - bb);
+    s = s1;
+    e += te - pe;
+  }
+  return s + e;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
+  extern __shared__ double smem[];
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int kc = a.k_cap;
+  // LDS carve-up
+  double *xs = smem;                       // [8][kc] solution
+  double *rs = xs + MAX_OPS * kc;          // [8][kc] residual / correction
+  double *xi = rs + MAX_OPS * kc;          // [128]
+  double *ze = xi + 128;                   // [128]
+  __shared__ double s_red[4];
+  __shared__ int s_piv[128];
+  __shared__ int s_flag, s_pivrow;
+  __shared__ double s_pmin, s_amax;
+  T *A = reinterpret_cast<T *>(ze + 128);  // [kc + 8 columns][kc], column-major
+
+  const int c = a.centers ? a.centers[q] : q;
+  const int n = a.n_per ? a.n_per[q] : a.n_max;
+  const int m = a.m_per ? a.m_per[q] : a.m_uni;
+  const int l = a.l_per ? a.l_per[q] : a.l_uni;
+  const int M = n_terms(l);
+  const int K = n + M;
+  double *wrow = a.w + static_cast<int64_t>(q) * a.n_max;
+  const int64_t op_stride = static_cast<int64_t>(a.n_centers) * a.n_max;
+
+  // validity (uniform for the block)
+  bool bad = (c < 0 || c >= a.n_nodes || n < 1 || n > a.n_max || m < 1 || m > 15 || (m & 1) == 0 ||
+              l < 0 || l > 6 || n < M || K > kc);
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+  if (!bad) {
+    for (int t = tid; t < n; t += W_THREADS) {
+      int j = a.idx[static_cast<int64_t>(q) * a.n_max + t];
+      if (j < 0 || j >= a.n_nodes) s_flag = 2;
+    }
+  }
+  __syncthreads();
+  if (bad || s_flag) {
+    for (int o = 0; o < a.n_ops; ++o)
+      for (int t = tid; t < a.n_max; t += W_THREADS) wrow[o * op_stride + t] = 0.0;
+    if (tid == 0 && a.status) a.status[q] = 2;
+    return;
+  }
+
+  // 1. offsets from the centre, then scale by rho
+  const double xc = a.xy[2 * c], zc = a.xy[2 * c + 1];
+  for (int t = tid; t < n; t += W_THREADS) {
+    int j = a.idx[static_cast<int64_t>(q) * a.n_max + t];
+    double dx = a.xy[2 * j] - xc;
+    if (a.period > 0.0) {
+      double half = 0.5 * a.period;
+      if (dx > half)
+        dx -= a.period;
+      else if (dx < -half)
+        dx += a.period;
+    }
+    xi[t] = dx;
+    ze[t] = a.xy[2 * j + 1] - zc;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double v = 0.0;
+    for (int t = tid; t < n; t += 64) {
+#pragma clang fp contract(off)
+      double d2 = xi[t] * xi[t] + ze[t] * ze[t];
+      v = fmax(v, d2);
+    }
+    v = wave_max(v);
+    if (tid == 0) s_red[0] = sqrt(v);
+  }
+  __syncthreads();
+  const double rho = s_red[0];
+  if (!(rho > 0.0)) {
+    for (int o = 0; o < a.n_ops; ++o)
+      for (int t = tid; t < a.n_max; t += W_THREADS) wrow[o * op_stride + t] = 0.0;
+    if (tid == 0 && a.status) a.status[q] = 1;
+    return;
+  }
+  for (int t = tid; t < n; t += W_THREADS) {
+    xi[t] = xi[t] / rho;
+    ze[t] = ze[t] / rho;
+  }
+  __syncthreads();
+
+  int status = 0;
+  unsigned done = 0;
+  // operators grouped by PHS order: one factorisation per group
+  while (done != (1u << a.n_ops) - 1u) {
+    int first = 0;
+    while (done & (1u << first)) ++first;
+    const int mg = a.ops[first].order ? a.ops[first].order : m;
+    int gl[MAX_OPS], ng = 0;
+    for (int o = 0; o < a.n_ops; ++o) {
+      int mo = a.ops[o].order ? a.ops[o].order : m;
+      if (!(done & (1u << o)) && mo == mg) {
+        gl[ng++] = o;
+        done |= 1u << o;
+      }
+    }
+    int kg[MAX_OPS];
+    bool group_bad = false;
+    for (int g = 0; g < ng; ++g) {
+      const WOp &op = a.ops[gl[g]];
+      kg[g] = (op.kind == RBFFD_HYPERLAP && op.k == 0) ? (mg - 1) / 2 : op.k;
+      if (op.kind == RBFFD_HYPERLAP && mg < 2 * kg[g] + 1) group_bad = true;
+    }
+    if (group_bad) {
+      status = 2;
+      for (int g = 0; g < ng; ++g)
+        for (int t = tid; t < a.n_max; t += W_THREADS) wrow[gl[g] * op_stride + t] = 0.0;
+      continue;
+    }
+    const int Kt = K + ng;  // columns of [A | B]
+
+    // 2. assembly, column-major: element (i, j) at j*kc + i
+    for (int t = tid; t < K * K; t += W_THREADS) {
+      int i = t % K, j = t / K;
+      A[j * kc + i] = static_cast<T>(sys_entry(i, j, n, mg, xi, ze));
+    }
+    for (int t = tid; t < K * ng; t += W_THREADS) {
+      int i = t % K, g = t / K;
+      A[(K + g) * kc + i] = static_cast<T>(rhs_entry(i, n, mg, a.ops[gl[g]], kg[g], xi, ze));
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double v = 0.0;
+      for (int t = tid; t < K * K; t += 64) v = fmax(v, fabs(static_cast<double>(A[(t / K) * kc + t % K])));
+      v = wave_max(v);
+      if (tid == 0) {
+        s_amax = v;
+        s_pmin = INFINITY;
+      }
+    }
+    __syncthreads();
+
+    // 3. LU with partial pivoting of [A | B]
+    for (int k = 0; k < K; ++k) {
+      if (tid < 64) {
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + tid; i < K; i += 64) {
+          double v = fabs(static_cast<double>(A[k * kc + i]));
+          if (v > best) {
+            best = v;
+            bi = i;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          double ob = __shfl_xor(best, off, 64);
+          int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (tid == 0) {
+          s_pivrow = bi;
+          s_piv[k] = bi;
+          s_pmin = fmin(s_pmin, best);
+        }
+      }
+      __syncthreads();
+      const int p = s_pivrow;
+      if (p != k) {
+        for (int j = tid; j < Kt; j += W_THREADS) {
+          T tmp = A[j * kc + k];
+          A[j * kc + k] = A[j * kc + p];
+          A[j * kc + p] = tmp;
+        }
+        __syncthreads();
+      }
+      const T piv = A[k * kc + k];
+      const int rows = K - k - 1;
+      for (int i = k + 1 + tid; i < K; i += W_THREADS)
+        A[k * kc + i] = (piv != T(0)) ? A[k * kc + i] / piv : T(0);
+      __syncthreads();
+      const int cols = Kt - k - 1;
+      if (rows > 0 && cols > 0) {
+        const int total = rows * cols;
+        int ri = tid % rows, cj = tid / rows;
+        const int dq = W_THREADS / rows, dr = W_THREADS % rows;
+        for (int t = tid; t < total; t += W_THREADS) {
+          const int i = k + 1 + ri, j = k + 1 + cj;
+          A[j * kc + i] = fma(-A[k * kc + i], A[j * kc + k], A[j * kc + i]);
+          ri += dr;
+          cj += dq;
+          if (ri >= rows) {
+            ri -= rows;
+            cj += 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // 4. back substitution U x = y (y = transformed right-hand sides)
+    for (int t = tid; t < K * ng; t += W_THREADS) xs[(t / K) * kc + t % K] = A[(K + t / K) * kc + t % K];
+    __syncthreads();
+    for (int k = K - 1; k >= 0; --k) {
+      if (tid < ng) xs[tid * kc + k] = xs[tid * kc + k] / static_cast<double>(A[k * kc + k]);
+      __syncthreads();
+      for (int t = tid; t < k * ng; t += W_THREADS) {
+        int i = t % k, g = t / k;
+        xs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), xs[g * kc + k], xs[g * kc + i]);
+      }
+      __syncthreads();
+    }
+
+    // 5. iterative refinement with double-double residuals
+    bool converged = false;
+    for (int it = 0; it < a.max_iter && !converged; ++it) {
+      for (int t = tid; t < K * ng; t += W_THREADS) {
+        const int i = t % K, g = t / K;
+        rs[g * kc + i] = dd_residual(i, K, n, mg, xi, ze, xs + g * kc,
+                                     rhs_entry(i, n, mg, a.ops[gl[g]], kg[g], xi, ze));
+      }
+      __syncthreads();
+      if (tid < ng) {  // row interchanges, in factorisation order
+        for (int k = 0; k < K; ++k) {
+          int p = s_piv[k];
+          if (p != k) {
+            double tmp = rs[tid * kc + k];
+            rs[tid * kc + k] = rs[tid * kc + p];
+            rs[tid * kc + p] = tmp;
+          }
+        }
+      }
+      __syncthreads();
+      for (int k = 0; k < K - 1; ++k) {  // unit lower triangle
+        for (int t = tid; t < (K - k - 1) * ng; t += W_THREADS) {
+          int i = k + 1 + t % (K - k - 1), g = t / (K - k - 1);
+          rs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), rs[g * kc + k], rs[g * kc + i]);
+        }
+        __syncthreads();
+      }
+      for (int k = K - 1; k >= 0; --k) {  // upper triangle
+        if (tid < ng) rs[tid * kc + k] = rs[tid * kc + k] / static_cast<double>(A[k * kc + k]);
+        __syncthreads();
+        for (int t = tid; t < k * ng; t += W_THREADS) {
+          int i = t % k, g = t / k;
+          rs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), rs[g * kc + k], rs[g * kc + i]);
+        }
+        __syncthreads();
+      }
+      // x += d; converged when |d| <= 2^-48 |x| (max norms over the group)
+      if (tid < 64) {
+        double dmax = 0.0, xmax = 0.0;
+        for (int t = tid; t < K * ng; t += 64) {
+          int i = t % K, g = t / K;
+          double d = rs[g * kc + i];
+          double xn = xs[g * kc + i] + d;
+          xs[g * kc + i] = xn;
+          dmax = fmax(dmax, fabs(d));
+          xmax = fmax(xmax, fabs(xn));
+        }
+        dmax = wave_max(dmax);
+        xmax = wave_max(xmax);
+        if (tid == 0) s_red[1] = (dmax <= 0x1p-48 * xmax) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      converged = s_red[1] != 0.0;
+      __syncthreads();
+    }
+
+    // 6. status and rescaled output
+    bool finite = true;
+    if (tid < 64) {
+      double v = 0.0;
+      for (int t = tid; t < K * ng; t += 64) v = fmax(v, fabs(xs[(t / K) * kc + t % K]));
+      v = wave_max(v);
+      if (tid == 0) s_red[2] = v;
+    }
+    __syncthreads();
+    finite = isfinite(s_red[2]);
+    if (!(s_pmin >= 1e-13 * s_amax) || !converged || !finite) status = status ? status : 1;
+    for (int g = 0; g < ng; ++g) {
+      const WOp &op = a.ops[gl[g]];
+      const int qd = (op.kind == RBFFD_DX || op.kind == RBFFD_DZ) ? 1
+                     : (op.kind == RBFFD_HYPERLAP)                ? 2 * kg[g]
+                                                                  : 2;
+      const double scale = 1.0 / ipow(rho, qd);
+      for (int t = tid; t < a.n_max; t += W_THREADS)
+        wrow[gl[g] * op_stride + t] = (t < n && finite) ? xs[g * kc + t] * scale : 0.0;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && a.status) a.status[q] = status;
+}
+
+// Per-stencil system size K = n + M and a count of invalid parameter sets.
+__global__ void ksize_kernel(const int *n_per, int n_max, const int *l_per, int l_uni, int nc,
+                             int *kmax, int *n_invalid) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  int n = n_per ? n_per[q] : n_max;
+  int l = l_per ? l_per[q] : l_uni;
+  if (l < 0 || l > 6 || n < 1 || n > n_max) {
+    atomicAdd(n_invalid, 1);
+    return;
+  }
+  atomicMax(kmax, n + n_terms(l));
+}
+
+__global__ void count_status_kernel(const int *status, int nc, int *counts) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  int s = status[q];
+  if (s == 1) atomicAdd(&counts[0], 1);
+  if (s == 2) atomicAdd(&counts[1], 1);
+}
+
+}  // namespace
+
+int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops, int precision,
+                const int32_t *idx, double *w, int32_t *status, int32_t *n_bad) {
+  hipStream_t s = ctx->stream;
+  const int nc = static_cast<int>(st->n_centers);
+  DevBuf d_k;
+  RBFFD_HIP(ctx, d_k.alloc(4 * sizeof(int)));
+  RBFFD_HIP(ctx, hipMemsetAsync(d_k.p, 0, 4 * sizeof(int), s));
+  ksize_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
+                                                 d_k.as<int>(), d_k.as<int>() + 1);
+  RBFFD_HIP(ctx, hipGetLastError());
+  int hk[2];
+  RBFFD_HIP(ctx, hipMemcpyAsync(hk, d_k.p, sizeof(hk), hipMemcpyDeviceToHost, s));
+  RBFFD_HIP(ctx, hipStreamSynchronize(s));
+  if (hk[1] > 0) return rbffd_fail(ctx, RBFFD_EINVAL, "%d stencils with invalid n or l", hk[1]);
+  const int kc = hk[0];
+  if (kc > 128) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d above 128", kc);
+
+  DevBuf d_status;
+  int32_t *st_out = status;
+  if (!st_out) {
+    RBFFD_HIP(ctx, d_status.alloc(sizeof(int32_t) * nc));
+    st_out = d_status.as<int32_t>();
+  }
+  WArgs a{};
+  a.xy = st->xy;
+  a.period = st->period_x;
+  a.centers = st->centers;
+  a.n_centers = nc;
+  a.n_nodes = static_cast<int>(st->n_nodes);
+  a.n_per = st->n_per;
+  a.n_max = st->n_max;
+  a.m_per = st->m_per;
+  a.m_uni = st->m_uniform;
+  a.l_per = st->l_per;
+  a.l_uni = st->l_uniform;
+  a.idx = idx;
+  for (int i = 0; i < n_ops; ++i) a.ops[i] = WOp{ops[i].kind, ops[i].k, ops[i].phs_order};
+  a.n_ops = n_ops;
+  a.w = w;
+  a.status = st_out;
+  a.k_cap = kc;
+  const size_t head = sizeof(double) * (2 * MAX_OPS * kc + 256);
+  if (precision == RBFFD_SOLVE_FP64) {
+    a.max_iter = 3;
+    size_t lds = head + sizeof(double) * static_cast<size_t>(kc) * (kc + MAX_OPS);
+    if (lds > 156 * 1024) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d too large for LDS", kc);
+    RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<double>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    weights_kernel<double><<<nc, W_THREADS, lds, s>>>(a);
+  } else {
+    a.max_iter = 30;
+    size_t lds = head + sizeof(float) * static_cast<size_t>(kc) * (kc + MAX_OPS);
+    RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<float>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    weights_kernel<float><<<nc, W_THREADS, lds, s>>>(a);
+  }
+  RBFFD_HIP(ctx, hipGetLastError());
+  RBFFD_HIP(ctx, hipMemsetAsync(d_k.p, 0, 4 * sizeof(int), s));
+  count_status_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, nc, d_k.as<int>());
+  RBFFD_HIP(ctx, hipGetLastError());
+  RBFFD_HIP(ctx, hipMemcpyAsync(hk, d_k.p, sizeof(hk), hipMemcpyDeviceToHost, s));
+  RBFFD_HIP(ctx, hipStreamSynchronize(s));
+  *n_bad = hk[1] > 0 ? -hk[1] : hk[0];
+  return RBFFD_OK;
+}

@@ -1,0 +1,70 @@
+"""The hot path for the paper's workloads, chained through the C ABI:
+node set -> rbffd_knn/rbffd_weights (A1-A4) -> rbffd_model_create ->
+rbffd_rhs / rbffd_step (B1-B4). Inputs come from the ``workloads`` package;
+every arithmetic step runs in the library's kernels."""
+
+import numpy as np
+import torch
+
+from . import rbffd as R
+
+
+def to_dev(a, dtype=None, device="cuda"):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(device)
+
+
+def ns_ops(cfg):
+    return [(R.DX, 0, 0), (R.DZ, 0, 0), (R.LAP, 0, 0), (R.HYPERLAP, cfg["hv_k"], cfg["hv_m"])]
+
+
+def advection_ops(cfg):
+    return [(R.DX, 0, 0), (R.DZ, 0, 0), (R.HYPERLAP, cfg["hv_k"], cfg["hv_m"])]
+
+
+def ns_weights(ctx, cfg, xy=None):
+    """Stencils and weights of a channel workload: (xy, idx, W, Wwall, status)."""
+    nd = cfg["nodes"]
+    if xy is None:
+        xy = to_dev(nd.xy, torch.float64)
+    idx, W, status, _ = R.rbffd_weights(ctx, xy, ns_ops(cfg), cfg["n"], cfg["m"], cfg["l"],
+                                        period_x=nd.period_x, n_centers=nd.n_active)
+    # the wall rows repeat the (deterministic) search for the wall centres
+    wall = to_dev(nd.wall_nodes.ravel(), torch.int32)
+    _, Ww, wstatus, _ = R.rbffd_weights(ctx, xy, [(R.DZ, 0, 0), (R.DZZ, 0, 0)], cfg["n"], cfg["m"], cfg["l"],
+                                        period_x=nd.period_x, centers=wall)
+    return xy, idx, W, Ww, (status, wstatus)
+
+
+def ns_model(ctx, cfg, idx, W, Ww, xy=None, field_dtype=R.F64, weight_dtype=R.F64, ensemble=1,
+             hv_coeff=None):
+    nd = cfg["nodes"]
+    if xy is None:
+        xy = to_dev(nd.xy, torch.float64)
+    nb = nd.wall_nodes.shape[1]
+    n = idx.shape[1]
+    return R.Model(ctx, R.PHYS_NS, idx, W, xy, nd.n_active, field_dtype=field_dtype,
+                   weight_dtype=weight_dtype, ensemble=ensemble,
+                   hv_coeff=cfg["hv_coeff"] if hv_coeff is None else hv_coeff, consts=cfg["consts"],
+                   wall_nodes=to_dev(nd.wall_nodes, torch.int32), ghost_nodes=to_dev(nd.ghost_nodes, torch.int32),
+                   wall_dz=Ww[0].reshape(2, nb, n).contiguous(), wall_dzz=Ww[1].reshape(2, nb, n).contiguous())
+
+
+def advection_model(ctx, cfg, idx, W, xy=None, field_dtype=R.F64, ensemble=1):
+    nd = cfg["nodes"]
+    if xy is None:
+        xy = to_dev(nd.xy, torch.float64)
+    return R.Model(ctx, R.PHYS_ADVECTION, idx, W, xy, nd.n_active, field_dtype=field_dtype,
+                   ensemble=ensemble, hv_coeff=cfg["hv_coeff"], vel_u=to_dev(cfg["U"], torch.float64),
+                   vel_v=to_dev(cfg["V"], torch.float64), vel_period=cfg["vel_period"])
+
+
+def advection_weights(ctx, cfg, xy=None):
+    nd = cfg["nodes"]
+    if xy is None:
+        xy = to_dev(nd.xy, torch.float64)
+    idx, W, status, _ = R.rbffd_weights(ctx, xy, advection_ops(cfg), cfg["n"], cfg["m"], cfg["l"],
+                                        period_x=nd.period_x, n_centers=nd.n_active)
+    return xy, idx, W, status

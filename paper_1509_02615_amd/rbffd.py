@@ -1,0 +1,247 @@
+"""Thin Python binding of librbffd (include/rbffd.h): argument marshalling only.
+
+Every function takes torch tensors that live on the context's GPU, checks
+their dtype, shape and contiguity, and passes raw device pointers to the
+C ABI. All arithmetic happens in the library's HIP kernels; if the library
+is missing this module raises at import time.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbffd.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1509_02615_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EDEVICE, ESINGULAR, ENONFINITE = 0, -1, -2, -3, -4, -5
+DX, DZ, LAP, HYPERLAP, DZZ = 1, 2, 3, 4, 5
+SOLVE_FP64, SOLVE_FP32_IR = 0, 1
+F64, F32, BF16 = 0, 1, 2
+PHYS_ADVECTION, PHYS_NS = 1, 2
+RK4, WSRK3 = 0, 1
+
+_vp = ctypes.c_void_p
+_i32, _i64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+class Op(ctypes.Structure):
+    _fields_ = [("kind", _i32), ("k", _i32), ("phs_order", _i32), ("reserved", _i32)]
+
+
+class Stencils(ctypes.Structure):
+    _fields_ = [("n_nodes", _i64), ("xy", _vp), ("period_x", _f64), ("n_centers", _i64),
+                ("centers", _vp), ("n_max", _i32), ("n_per", _vp), ("m_uniform", _i32),
+                ("m_per", _vp), ("l_uniform", _i32), ("l_per", _vp), ("idx_in", _vp)]
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("physics", _i32), ("field_dtype", _i32), ("weight_dtype", _i32), ("n", _i32),
+                ("n_total", _i64), ("n_active", _i64), ("ensemble", _i32), ("reserved0", _i32),
+                ("idx", _vp), ("w", _vp), ("xy", _vp), ("hv_coeff", _f64),
+                ("vel_u", _vp), ("vel_v", _vp), ("vel_period", _f64),
+                ("c_p", _f64), ("c_v", _f64), ("R_d", _f64), ("g", _f64), ("theta_bar", _f64),
+                ("mu", _f64), ("n_walls", _i32), ("n_wall", _i32), ("wall_nodes", _vp),
+                ("ghost_nodes", _vp), ("wall_dz", _vp), ("wall_dzz", _vp)]
+
+
+_lib.rbffd_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _vp]
+_lib.rbffd_destroy.argtypes = [_vp]
+_lib.rbffd_last_error.argtypes = [_vp]
+_lib.rbffd_last_error.restype = ctypes.c_char_p
+_lib.rbffd_sync.argtypes = [_vp]
+_lib.rbffd_knn.argtypes = [_vp, ctypes.POINTER(Stencils), _vp]
+_lib.rbffd_weights.argtypes = [_vp, ctypes.POINTER(Stencils), ctypes.POINTER(Op), ctypes.c_int,
+                               ctypes.c_int, _vp, _vp, _vp]
+_lib.rbffd_model_create.argtypes = [_vp, ctypes.POINTER(ModelDesc), ctypes.POINTER(_vp)]
+_lib.rbffd_model_destroy.argtypes = [_vp]
+_lib.rbffd_ghost.argtypes = [_vp, _vp, _vp]
+_lib.rbffd_rhs.argtypes = [_vp, _vp, _f64, _vp, _vp]
+_lib.rbffd_step.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_f64), _f64, _i64, ctypes.c_int]
+_lib.rbffd_model_bytes_per_node.argtypes = [_vp]
+_lib.rbffd_model_bytes_per_node.restype = _i64
+_lib.rbffd_model_profile.argtypes = [_vp, ctypes.c_int]
+_lib.rbffd_model_profile_read.argtypes = [_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
+
+EXPORTS = ["rbffd_create", "rbffd_destroy", "rbffd_last_error", "rbffd_sync", "rbffd_knn",
+           "rbffd_weights", "rbffd_model_create", "rbffd_model_destroy", "rbffd_ghost",
+           "rbffd_rhs", "rbffd_step", "rbffd_model_bytes_per_node", "rbffd_model_profile",
+           "rbffd_model_profile_read"]
+
+
+class RbffdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rbffd error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t, dtype, shape=None, name="array"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+class Context:
+    """rbffd_create on ``device`` ordered on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.device = device
+        h = _vp()
+        rc = _lib.rbffd_create(ctypes.byref(h), device, _vp(stream.cuda_stream))
+        if rc != OK:
+            raise RbffdError(rc, "rbffd_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.rbffd_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def check(self, rc, allow=()):
+        if rc != OK and rc not in allow:
+            raise RbffdError(rc, _lib.rbffd_last_error(self.h).decode())
+        return rc
+
+    def sync(self):
+        self.check(_lib.rbffd_sync(self.h))
+
+
+def _stencils(xy, n_max, period_x, centers, n_per, m, l, m_per, l_per, idx_in, n_centers=None):
+    N = xy.shape[0]
+    nc = centers.shape[0] if centers is not None else (
+        n_per.shape[0] if n_per is not None else (idx_in.shape[0] if idx_in is not None else (
+            n_centers if n_centers is not None else N)))
+    st = Stencils(n_nodes=N, xy=_ptr(xy, torch.float64, (N, 2), "xy"), period_x=float(period_x),
+                  n_centers=nc, centers=_ptr(centers, torch.int32, (nc,), "centers"),
+                  n_max=int(n_max), n_per=_ptr(n_per, torch.int32, (nc,), "n_per"),
+                  m_uniform=int(m), m_per=_ptr(m_per, torch.int32, (nc,), "m_per"),
+                  l_uniform=int(l), l_per=_ptr(l_per, torch.int32, (nc,), "l_per"),
+                  idx_in=_ptr(idx_in, torch.int32, (nc, n_max), "idx_in"))
+    return st, nc
+
+
+def rbffd_knn(ctx: Context, xy, n_max, period_x=0.0, centers=None, n_per=None, out=None, n_centers=None):
+    """A1: int32 [Nc][n_max] nearest-node stencils (see rbffd.h). Without
+    ``centers`` the centres are nodes 0..n_centers-1 (default: all)."""
+    st, nc = _stencils(xy, n_max, period_x, centers, n_per, 1, 0, None, None, None, n_centers)
+    if out is None:
+        out = torch.empty((nc, n_max), dtype=torch.int32, device=xy.device)
+    ctx.check(_lib.rbffd_knn(ctx.h, ctypes.byref(st), _ptr(out, torch.int32, (nc, n_max), "idx")))
+    return out
+
+
+def rbffd_weights(ctx: Context, xy, ops, n_max, m=0, l=0, period_x=0.0, centers=None, n_per=None,
+                  m_per=None, l_per=None, idx_in=None, precision=SOLVE_FP64, out=None, n_centers=None):
+    """A1-A4: returns (idx [Nc][n_max], w [n_ops][Nc][n_max] FP64, status [Nc], rc).
+    ops: list of (kind, k, phs_order). rc is OK or ESINGULAR."""
+    st, nc = _stencils(xy, n_max, period_x, centers, n_per, m, l, m_per, l_per, idx_in, n_centers)
+    dev = xy.device
+    op_arr = (Op * len(ops))(*[Op(kind, k, order, 0) for (kind, k, order) in ops])
+    if out is None:
+        idx = idx_in if idx_in is not None else torch.empty((nc, n_max), dtype=torch.int32, device=dev)
+        w = torch.empty((len(ops), nc, n_max), dtype=torch.float64, device=dev)
+        status = torch.empty((nc,), dtype=torch.int32, device=dev)
+    else:
+        idx, w, status = out
+    idx_out = None if idx_in is not None else _ptr(idx, torch.int32, (nc, n_max), "idx")
+    rc = ctx.check(_lib.rbffd_weights(ctx.h, ctypes.byref(st), op_arr, len(ops), int(precision), idx_out,
+                                      _ptr(w, torch.float64, (len(ops), nc, n_max), "w"),
+                                      _ptr(status, torch.int32, (nc,), "status")), allow=(ESINGULAR,))
+    return idx, w, status, rc
+
+
+class Model:
+    """rbffd_model_create / rbffd_ghost / rbffd_rhs / rbffd_step."""
+
+    def __init__(self, ctx: Context, physics, idx, w, xy, n_active, field_dtype=F64, weight_dtype=F64,
+                 ensemble=1, hv_coeff=0.0, vel_u=None, vel_v=None, vel_period=1.0, consts=None,
+                 wall_nodes=None, ghost_nodes=None, wall_dz=None, wall_dzz=None):
+        self.ctx = ctx
+        N = xy.shape[0]
+        na, n = idx.shape
+        self.N, self.Na, self.n, self.E = N, na, n, ensemble
+        self.F = 4 if physics == PHYS_NS else 1
+        self.dtype = torch.float64 if field_dtype == F64 else torch.float32
+        n_ops = 4 if physics == PHYS_NS else 3
+        c = consts or {}
+        d = ModelDesc(physics=physics, field_dtype=field_dtype, weight_dtype=weight_dtype, n=n,
+                      n_total=N, n_active=na, ensemble=ensemble,
+                      idx=_ptr(idx, torch.int32, (na, n), "idx"),
+                      w=_ptr(w, torch.float64, (n_ops, na, n), "w"),
+                      xy=_ptr(xy, torch.float64, (N, 2), "xy"), hv_coeff=float(hv_coeff),
+                      vel_u=_ptr(vel_u, torch.float64, (N,), "vel_u"),
+                      vel_v=_ptr(vel_v, torch.float64, (N,), "vel_v"), vel_period=float(vel_period),
+                      c_p=c.get("c_p", 0.0), c_v=c.get("c_v", 0.0), R_d=c.get("R_d", 0.0),
+                      g=c.get("g", 0.0), theta_bar=c.get("theta_bar", 0.0), mu=c.get("mu", 0.0))
+        if wall_nodes is not None:
+            nw, nb = wall_nodes.shape
+            d.n_walls, d.n_wall = nw, nb
+            d.wall_nodes = _ptr(wall_nodes, torch.int32, (nw, nb), "wall_nodes")
+            d.ghost_nodes = _ptr(ghost_nodes, torch.int32, (nw, nb), "ghost_nodes")
+            d.wall_dz = _ptr(wall_dz, torch.float64, (nw, nb, n), "wall_dz")
+            d.wall_dzz = _ptr(wall_dzz, torch.float64, (nw, nb, n), "wall_dzz")
+        h = _vp()
+        ctx.check(_lib.rbffd_model_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.rbffd_model_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def state_shape(self):
+        return (self.N, self.E, self.F)
+
+    def _state(self, s, name="state"):
+        return _ptr(s, self.dtype, self.state_shape(), name)
+
+    def bytes_per_node(self):
+        return int(_lib.rbffd_model_bytes_per_node(self.h))
+
+    def profile(self, enable=True):
+        self.ctx.check(_lib.rbffd_model_profile(self.h, int(enable)))
+
+    def profile_read(self):
+        """(summed fused-RHS kernel ms, launches) since the last read."""
+        ms, n = _f64(), _i64()
+        self.ctx.check(_lib.rbffd_model_profile_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
+def rbffd_model_create(ctx, *args, **kw) -> Model:
+    return Model(ctx, *args, **kw)
+
+
+def rbffd_ghost(ctx: Context, model: Model, state):
+    ctx.check(_lib.rbffd_ghost(ctx.h, model.h, model._state(state)))
+
+
+def rbffd_rhs(ctx: Context, model: Model, t, state, tendency):
+    ctx.check(_lib.rbffd_rhs(ctx.h, model.h, float(t), model._state(state),
+                             model._state(tendency, "tendency")))
+
+
+def rbffd_step(ctx: Context, model: Model, state, t, dt, n_steps, tableau=RK4):
+    """Advance in place; returns the new time. Raises on ENONFINITE."""
+    tt = _f64(float(t))
+    ctx.check(_lib.rbffd_step(ctx.h, model.h, model._state(state), ctypes.byref(tt), float(dt),
+                              int(n_steps), int(tableau)))
+    return tt.value

@@ -1,0 +1,255 @@
+"""GPU parity of the ghost closure, the fused right-hand side and the RK
+stages against the CPU oracle, through the C ABI.
+
+Tolerances: FP64 paths agree with the oracle to 1e-12 relative l2 per field
+for one evaluation (rounding-order differences only) and to 1e-9 after a
+multi-step run; the FP32-field path (FP32 first-derivative and Laplacian
+weights, FP64 hyperviscosity weights) meets 1e-6 per field on FP32
+representable inputs; BF16 weights are held to 1e-2 (bfloat16 keeps 8
+significant bits)."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.pipeline import build_ns, build_advection
+from workloads import advection_config, density_current_config, scale_config
+from workloads.fields import smooth_ns_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1509_02615_amd import rbffd
+    return rbffd
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    return R.Context(0)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+_NS_CACHE = {}
+
+
+def ns_case(layout, h):
+    key = (layout, h)
+    if key not in _NS_CACHE:
+        cfg = density_current_config(layout, h)
+        model, idx, W, Ww = build_ns(cfg)
+        _NS_CACHE[key] = (cfg, model, idx, W, Ww)
+    return _NS_CACHE[key]
+
+
+def gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=0, wdt=0, E=1, hv=None):
+    import torch
+    nd = cfg["nodes"]
+    nb = nd.wall_nodes.shape[1]
+    n = idx.shape[1]
+    Wwall = Ww.reshape(2, 2, nb, n)
+    return R.Model(ctx, R.PHYS_NS, dev(idx, torch.int32), dev(W, torch.float64), dev(nd.xy, torch.float64),
+                   nd.n_active, field_dtype=fdt, weight_dtype=wdt, ensemble=E,
+                   hv_coeff=cfg["hv_coeff"] if hv is None else hv, consts=cfg["consts"],
+                   wall_nodes=dev(nd.wall_nodes, torch.int32), ghost_nodes=dev(nd.ghost_nodes, torch.int32),
+                   wall_dz=dev(Wwall[0], torch.float64), wall_dzz=dev(Wwall[1], torch.float64))
+
+
+def rel_fields(a, b, rows):
+    return [np.linalg.norm(a[rows, f] - b[rows, f]) / np.linalg.norm(b[rows, f]) for f in range(a.shape[1])]
+
+
+@pytest.mark.parametrize("layout", ["cartesian", "hexagonal", "scattered"])
+def test_ghost_closure_parity(R, ctx, layout):
+    import torch
+    say(f"closure: {layout} 400 m, FP64, smooth seeded state")
+    cfg, om, idx, W, Ww = ns_case(layout, 400.0)
+    gm = gpu_ns(R, ctx, cfg, idx, W, Ww)
+    st = smooth_ns_state(cfg["nodes"], seed=2)
+    ref = O.ghost_closure(om, st)
+    s = dev(st, torch.float64).reshape(gm.state_shape()).contiguous()
+    R.rbffd_ghost(ctx, gm, s)
+    got = host(s).reshape(st.shape)
+    g = cfg["nodes"].ghost_nodes.ravel()
+    for f in range(4):
+        err = np.abs(got[g, f] - ref[g, f]).max() / max(np.abs(ref[g, f]).max(), 1e-300)
+        assert err <= 1e-12, (f, err)
+    wall = cfg["nodes"].wall_nodes.ravel()
+    assert np.all(got[wall, 1] == 0.0)
+
+
+@pytest.mark.parametrize("layout,h", [("cartesian", 400.0), ("hexagonal", 400.0), ("scattered", 400.0),
+                                      ("hexagonal", 200.0)])
+def test_rhs_parity_fp64(R, ctx, layout, h):
+    import torch
+    say(f"rhs: {layout} {h} m, FP64 fields and weights")
+    cfg, om, idx, W, Ww = ns_case(layout, h)
+    gm = gpu_ns(R, ctx, cfg, idx, W, Ww)
+    st = smooth_ns_state(cfg["nodes"], seed=3)
+    ref, _ = O.ns_rhs(om, st)
+    s = dev(st, torch.float64).reshape(gm.state_shape()).contiguous()
+    out = torch.full_like(s, float("nan"))
+    R.rbffd_rhs(ctx, gm, 0.0, s, out)
+    got = host(out).reshape(st.shape)
+    na = cfg["nodes"].n_active
+    errs = rel_fields(got, ref, np.arange(na))
+    say(f"   rel-l2 per field {['%.1e' % e for e in errs]}")
+    assert max(errs) <= 1e-12
+    assert np.all(got[na:] == 0.0)
+
+
+@pytest.mark.parametrize("wdt,tol", [(1, 1e-6), (2, 1e-2)])
+@pytest.mark.parametrize("h", [400.0, 200.0])
+def test_rhs_parity_reduced_precision(R, ctx, wdt, tol, h):
+    import torch
+    say(f"rhs: hexagonal {h} m, FP32 fields, weight dtype {wdt}, tol {tol}")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", h)
+    gm = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=1, wdt=wdt)
+    st = smooth_ns_state(cfg["nodes"], seed=4).astype(np.float32).astype(np.float64)
+    ref, _ = O.ns_rhs(om, st)
+    s = dev(st, torch.float32).reshape(gm.state_shape()).contiguous()
+    out = torch.empty_like(s)
+    R.rbffd_rhs(ctx, gm, 0.0, s, out)
+    got = host(out).reshape(st.shape)
+    errs = rel_fields(got, ref, np.arange(cfg["nodes"].n_active))
+    say(f"   rel-l2 per field {['%.2e' % e for e in errs]}")
+    assert max(errs) <= tol
+
+
+def test_rhs_rest_state_is_zero(R, ctx):
+    import torch
+    say("rhs: hydrostatic rest gives exactly zero tendency (FP64 and FP32)")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", 400.0)
+    for fdt, wdt, dt in ((0, 0, torch.float64), (1, 1, torch.float32)):
+        gm = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=fdt, wdt=wdt)
+        s = torch.zeros(gm.state_shape(), dtype=dt, device="cuda")
+        out = torch.full_like(s, 1.0)
+        R.rbffd_rhs(ctx, gm, 0.0, s, out)
+        assert torch.count_nonzero(out).item() == 0
+
+
+def test_ensemble_members_equal_single_runs(R, ctx):
+    import torch
+    say("rhs: ensemble E=3 (FP32) equals three single-member evaluations bit for bit")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", 400.0)
+    states = [smooth_ns_state(cfg["nodes"], seed=10 + k).astype(np.float32) for k in range(3)]
+    g1 = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=1, wdt=1)
+    singles = []
+    for st in states:
+        s = dev(st, torch.float32).reshape(g1.state_shape()).contiguous()
+        o = torch.empty_like(s)
+        R.rbffd_rhs(ctx, g1, 0.0, s, o)
+        singles.append(o.reshape(-1, 4))
+    g3 = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=1, wdt=1, E=3)
+    s3 = dev(np.stack(states, axis=1), torch.float32).contiguous()
+    o3 = torch.empty_like(s3)
+    R.rbffd_rhs(ctx, g3, 0.0, s3, o3)
+    for k in range(3):
+        assert torch.equal(o3[:, k, :], singles[k])
+
+
+def test_advection_rhs_and_bell_run(R, ctx):
+    import torch
+    say("transport: 64x64 rhs at t=0.7 and the full 2000-step RK4 bell run (FP64)")
+    cfg = advection_config(64)
+    om, idx, W, status = build_advection(cfg)
+    nd = cfg["nodes"]
+    gm = R.Model(ctx, R.PHYS_ADVECTION, dev(idx, torch.int32), dev(W, torch.float64), dev(nd.xy, torch.float64),
+                 nd.n_active, hv_coeff=cfg["hv_coeff"], vel_u=dev(cfg["U"], torch.float64),
+                 vel_v=dev(cfg["V"], torch.float64), vel_period=cfg["vel_period"])
+    psi = cfg["psi0"]
+    ref = om(0.7, psi)
+    s = dev(psi, torch.float64).reshape(gm.state_shape()).contiguous()
+    out = torch.empty_like(s)
+    R.rbffd_rhs(ctx, gm, 0.7, s, out)
+    got = host(out).ravel()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-12
+    yref, _ = O.integrate(om, psi, 0.0, cfg["dt"], 2000, "rk4")
+    t = R.rbffd_step(ctx, gm, s, 0.0, cfg["dt"], 2000, R.RK4)
+    assert abs(t - 5.0) < 1e-12
+    y = host(s).ravel()
+    d = np.linalg.norm(y - yref) / np.linalg.norm(yref)
+    e_gpu, e_ref = O.rel_l2(y, psi), O.rel_l2(yref, psi)
+    say(f"   run diff {d:.2e}; bell-return error gpu {e_gpu:.6f} oracle {e_ref:.6f}")
+    assert d <= 1e-9 and abs(e_gpu - e_ref) <= 1e-9
+
+
+@pytest.mark.parametrize("tableau", ["rk4", "wsrk3"])
+def test_ns_steps_parity(R, ctx, tableau):
+    import torch
+    say(f"step: hexagonal 400 m density current, 20 steps {tableau}, FP64 and FP32")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", 400.0)
+    f = lambda t, y: O.ns_rhs(om, y)[0]                                    # noqa: E731
+    yref, _ = O.integrate(f, cfg["state0"], 0.0, cfg["dt"], 20, tableau)
+    yref = O.ghost_closure(om, yref)
+    na = cfg["nodes"].n_active
+    tab = R.RK4 if tableau == "rk4" else R.WSRK3
+    for fdt, wdt, dt, tol in ((0, 0, torch.float64, 1e-9), (1, 1, torch.float32, 2e-5)):
+        gm = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=fdt, wdt=wdt)
+        s = dev(cfg["state0"], dt).reshape(gm.state_shape()).contiguous()
+        t = R.rbffd_step(ctx, gm, s, 0.0, cfg["dt"], 20, tab)
+        assert abs(t - 20 * cfg["dt"]) < 1e-12
+        R.rbffd_ghost(ctx, gm, s)
+        got = host(s).reshape(yref.shape)
+        errs = rel_fields(got, yref, np.arange(na))
+        say(f"   field dtype {fdt}: rel-l2 per field {['%.1e' % e for e in errs]}")
+        assert max(errs) <= tol
+
+
+def test_step_reports_nonfinite(R, ctx):
+    import torch
+    say("step: a NaN in the state is reported as ENONFINITE")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", 400.0)
+    gm = gpu_ns(R, ctx, cfg, idx, W, Ww)
+    st = cfg["state0"].copy()
+    st[500, 2] = np.nan
+    s = dev(st, torch.float64).reshape(gm.state_shape()).contiguous()
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_step(ctx, gm, s, 0.0, cfg["dt"], 3, R.RK4)
+    assert e.value.code == R.ENONFINITE
+
+
+def test_full_size_scale_rhs_sampled(R, ctx):
+    """2048 x 256 hexagonal channel (524,288 nodes): the whole GPU path
+    (search, weights, closure, fused RHS) against the oracle evaluated
+    node by node at sampled nodes away from the walls."""
+    import torch
+    from paper_1509_02615_amd import pipeline as P
+    say("full size: 2048x256 channel, GPU search+weights+rhs, 160 sampled nodes, FP64 and FP32")
+    cfg = scale_config()
+    nd = cfg["nodes"]
+    xy, idx, W, Ww, (st_a, st_w) = P.ns_weights(ctx, cfg)
+    assert int(st_a.abs().sum()) == 0 and int(st_w.abs().sum()) == 0
+    state = smooth_ns_state(nd, seed=6).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(1)
+    rows = rng.integers(6 * nd.nx, (nd.nz - 6) * nd.nx, 160)
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0), (O.HYPERLAP, 3, 7)]
+    o_idx = O.knn(nd.xy, rows, 37, nd.period_x)
+    o_W, _ = O.all_weights(nd.xy, o_idx, rows, 7, 4, ops, nd.period_x)
+    ref = O.ns_tendency(state, rows, o_idx, o_W[0], o_W[1], o_W[2], o_W[3], nd.xy[rows, 1],
+                        np.zeros(len(rows), bool), cfg["consts"], cfg["hv_coeff"])
+    assert np.array_equal(idx[torch.from_numpy(rows).cuda()].cpu().numpy(), o_idx)
+    for fdt, wdt, dt, tol in ((0, 0, torch.float64, 1e-12), (1, 1, torch.float32, 1e-6)):
+        gm = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
+        s = dev(state, dt).reshape(gm.state_shape()).contiguous()
+        out = torch.empty_like(s)
+        R.rbffd_rhs(ctx, gm, 0.0, s, out)
+        got = host(out).reshape(-1, 4)[rows]
+        errs = [np.linalg.norm(got[:, f] - ref[:, f]) / np.linalg.norm(ref[:, f]) for f in range(4)]
+        say(f"   field dtype {fdt}: rel-l2 per field over samples {['%.2e' % e for e in errs]}")
+        assert max(errs) <= tol

@@ -1,0 +1,200 @@
+"""GPU parity of the stencil search (bit-exact) and the batched weights
+(<= 1e-10 norm-wise per stencil and operator) against the CPU oracle,
+called through the C ABI."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import (advection_config, density_current_config, weights_config, unit_square_cartesian,
+                       channel, jittered_square)
+
+pytestmark = pytest.mark.gpu
+TOL_W = 1e-10
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1509_02615_amd import rbffd
+    return rbffd
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    return R.Context(0)
+
+
+def dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _knn_case(R, ctx, xy, n, period, centers=None, n_per=None, sample=None):
+    import torch
+    c_t = dev(centers, torch.int32) if centers is not None else None
+    np_t = dev(n_per, torch.int32) if n_per is not None else None
+    got = host(R.rbffd_knn(ctx, dev(xy, torch.float64), n, period, centers=c_t, n_per=np_t,
+                           n_centers=None if centers is not None else xy.shape[0]))
+    cs = np.arange(got.shape[0]) if sample is None else sample
+    for a in cs:
+        c = int(centers[a]) if centers is not None else int(a)
+        na = int(n_per[a]) if n_per is not None else n
+        ref = O.knn(xy, [c], na, period)[0]
+        assert np.array_equal(got[a, :na], ref), (a, got[a, :na], ref)
+        assert np.all(got[a, na:] == -1)
+    return got
+
+
+def test_knn_bit_exact_unit_square(R, ctx):
+    say("knn: 64x64 Cartesian, n=37, all centres")
+    nd = unit_square_cartesian(64)
+    _knn_case(R, ctx, nd.xy, 37, 0.0)
+
+
+@pytest.mark.parametrize("layout", ["cartesian", "hexagonal", "scattered"])
+def test_knn_bit_exact_channels(R, ctx, layout):
+    say(f"knn: {layout} 400 m channel, periodic x, all centres incl. walls")
+    nd = density_current_config(layout, 400.0)["nodes"]
+    _knn_case(R, ctx, nd.xy, 37, nd.period_x, centers=np.arange(nd.n_active))
+
+
+def test_knn_bit_exact_full_size_samples(R, ctx):
+    say("knn: 100 m hexagonal channel (38,400 + ghosts), 300 sampled centres; 1M scattered, 100 samples")
+    nd = density_current_config("hexagonal", 100.0)["nodes"]
+    rng = np.random.default_rng(7)
+    centers = np.arange(nd.n_active)
+    samp = np.concatenate([rng.choice(nd.n_active, 250, replace=False), np.arange(25), nd.n_active - 1 - np.arange(25)])
+    _knn_case(R, ctx, nd.xy, 37, nd.period_x, centers=centers, sample=samp)
+    cfg = weights_config(1024)
+    nd = cfg["nodes"]
+    samp = np.concatenate([rng.choice(nd.n_active, 90, replace=False), [0, 1023, nd.n_active - 1]])
+    _knn_case(R, ctx, nd.xy, cfg["n_max"], 0.0, centers=np.arange(nd.n_active), n_per=cfg["n_per"], sample=samp)
+
+
+def test_knn_edge_cases(R, ctx):
+    say("knn: edge cases (n = N, n = 1, ragged n_per, centre subset, duplicate distances)")
+    rng = np.random.default_rng(3)
+    xy = rng.uniform(0, 1, (50, 2))
+    _knn_case(R, ctx, xy, 50, 0.0)                      # whole set
+    _knn_case(R, ctx, xy, 1, 0.0)                       # the centre itself
+    nd = channel("cartesian", 16, 5, 0.0, 16.0, 4.0)    # unit lattice, periodic: heavy ties
+    n_per = rng.integers(1, 26, nd.n_active).astype(np.int32)
+    _knn_case(R, ctx, nd.xy, 25, nd.period_x, centers=np.arange(nd.n_active)[::-1].copy(), n_per=n_per)
+    with pytest.raises(R.RbffdError):
+        R.rbffd_knn(ctx, dev(xy, __import__("torch").float64), 51, 0.0)
+
+
+def _weights_parity(R, ctx, xy, ops_o, n, m, l, period, centers, sample=None, n_per=None, m_per=None,
+                    l_per=None, precision=0):
+    import torch
+    ops = [(k, kk, mo) for (k, kk, mo) in ops_o]
+    idx, W, status, rc = R.rbffd_weights(
+        ctx, dev(xy, torch.float64), ops, n, m, l, period_x=period, centers=dev(centers, torch.int32),
+        n_per=None if n_per is None else dev(n_per, torch.int32),
+        m_per=None if m_per is None else dev(m_per, torch.int32),
+        l_per=None if l_per is None else dev(l_per, torch.int32), precision=precision)
+    idx, W, status = host(idx), host(W), host(status)
+    assert rc == R.OK and np.all(status == 0)
+    cs = range(len(centers)) if sample is None else sample
+    worst = 0.0
+    for a in cs:
+        c = int(centers[a])
+        na = int(n_per[a]) if n_per is not None else n
+        ma = int(m_per[a]) if m_per is not None else m
+        la = int(l_per[a]) if l_per is not None else l
+        st = O.knn(xy, [c], na, period)[0]
+        assert np.array_equal(idx[a, :na], st)
+        Wo, so = O.stencil_weights(xy, st, c, ma, la, ops_o, period)
+        assert so == 0
+        for o in range(len(ops)):
+            err = np.linalg.norm(W[o, a, :na] - Wo[o]) / np.linalg.norm(Wo[o])
+            worst = max(worst, err)
+            assert err <= TOL_W, (a, o, err)
+            assert np.all(W[o, a, na:] == 0.0)
+    say(f"   worst norm-wise relative weight error {worst:.2e}")
+    return W
+
+
+def test_weights_parity_unit_square(R, ctx):
+    say("weights: 64x64 Cartesian, r^5 + deg 4 (Dx, Dy) and r^7 Lap^3, all 4096 stencils")
+    cfg = advection_config(64)
+    nd = cfg["nodes"]
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.HYPERLAP, 3, 7)]
+    _weights_parity(R, ctx, nd.xy, ops, 37, 5, 4, 0.0, np.arange(nd.n_active))
+
+
+@pytest.mark.parametrize("layout", ["cartesian", "hexagonal", "scattered"])
+def test_weights_parity_channels(R, ctx, layout):
+    say(f"weights: {layout} 400 m channel, r^7 + deg 4, Dx Dz Lap Lap^3 and wall Dz Dzz")
+    nd = density_current_config(layout, 400.0)["nodes"]
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0), (O.HYPERLAP, 3, 7)]
+    _weights_parity(R, ctx, nd.xy, ops, 37, 7, 4, nd.period_x, np.arange(nd.n_active))
+    _weights_parity(R, ctx, nd.xy, [(O.DZ, 0, 0), (O.DZZ, 0, 0)], 37, 7, 4, nd.period_x, nd.wall_nodes.ravel())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_weights_parity_mixed_batch(R, ctx, precision):
+    say(f"weights: mixed n/m/l batch on 40x40 jittered square, precision {precision}")
+    cfg = weights_config(40, seed=5)
+    nd = cfg["nodes"]
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.HYPERLAP, 0, 0)]
+    _weights_parity(R, ctx, nd.xy, ops, cfg["n_max"], 0, 0, 0.0, np.arange(nd.n_active),
+                    n_per=cfg["n_per"], m_per=cfg["m_per"], l_per=cfg["l_per"], precision=precision)
+
+
+def test_weights_full_size_mixed_samples(R, ctx):
+    say("weights: 1,048,576 scattered nodes, mixed l in {3,4,5}, one launch, 120 sampled stencils")
+    cfg = weights_config(1024)
+    nd = cfg["nodes"]
+    rng = np.random.default_rng(11)
+    samp = np.concatenate([rng.choice(nd.n_active, 110, replace=False), [0, 1023, 5000, nd.n_active - 1]])
+    samp = np.concatenate([samp, np.nonzero(cfg["n_per"] == cfg["n_max"])[0][:6]])
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.HYPERLAP, 0, 0)]
+    _weights_parity(R, ctx, nd.xy, ops, cfg["n_max"], 0, 0, 0.0, np.arange(nd.n_active), sample=samp,
+                    n_per=cfg["n_per"], m_per=cfg["m_per"], l_per=cfg["l_per"])
+
+
+def test_weights_reproduce_polynomials(R, ctx):
+    """Independent of the oracle: the GPU weights are exact on monomials up to
+    degree l (Section 3 constraints), in physical coordinates."""
+    import torch
+    say("weights: polynomial reproduction of GPU weights, scattered 24x24, r^7 deg 5, n = 43")
+    nd = jittered_square(24, seed=2)
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0), (O.DZZ, 0, 0), (O.HYPERLAP, 3, 0)]
+    idx, W, status, rc = R.rbffd_weights(ctx, dev(nd.xy, torch.float64), ops, 43, 7, 5,
+                                         n_centers=nd.n_active)
+    idx, W = host(idx), host(W)
+    for c in range(0, nd.n_active, 7):
+        dx = nd.xy[idx[c], 0] - nd.xy[c, 0]
+        dz = nd.xy[idx[c], 1] - nd.xy[c, 1]
+        for (a, b) in O.poly_exponents(5):
+            vals = dx ** a * dz ** b
+            for o, (kind, k, _) in enumerate(ops):
+                exact = O.poly_apply(kind, 3 if kind == O.HYPERLAP else k, a, b)
+                assert abs(W[o, c] @ vals - exact) <= 1e-10 * (np.abs(W[o, c] * vals).sum() + abs(exact))
+
+
+def test_weights_singular_and_invalid(R, ctx):
+    import torch
+    say("weights: singular one-sided Cartesian stencils (deg 5) flagged; invalid arguments rejected")
+    nd = unit_square_cartesian(21)
+    xy = dev(nd.xy, torch.float64)
+    centers = np.array([10, 10 * 21 + 10], np.int32)       # edge node, interior node
+    idx, W, status, rc = R.rbffd_weights(ctx, xy, [(O.DX, 0, 0)], 37, 7, 5, centers=dev(centers, torch.int32))
+    assert rc == R.ESINGULAR and host(status).tolist() == [1, 0]
+    for bad in (dict(m=4, l=4), dict(m=5, l=7), dict(m=5, l=4, ops=[(O.HYPERLAP, 3, 0)]),
+                dict(m=5, l=6, n=20)):
+        with pytest.raises(R.RbffdError) as e:
+            R.rbffd_weights(ctx, xy, bad.get("ops", [(O.DX, 0, 0)]), bad.get("n", 37), bad["m"], bad["l"],
+                            centers=dev(centers, torch.int32))
+        assert e.value.code == R.EINVAL
