@@ -137,6 +137,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and weight legs")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="short run for hardware-counter passes: 2 RK4 steps of the chosen precision "
+                         "and 3 plain copies of 512 MiB (counter calibration); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the multi-GPU path is not built (see the sharding notes); "
@@ -168,6 +171,19 @@ def main():
 
     fdt = {"fp32": R.F32, "fp64": R.F64, "bf16": R.F32}[args.precision]
     wdt = {"fp32": R.F32, "fp64": R.F64, "bf16": R.BF16}[args.precision]
+    if args.pmc_run:
+        model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
+        state = P.to_dev(cfg["state0"], torch.float64 if fdt == R.F64 else torch.float32)
+        state = state.reshape(model.state_shape()).contiguous()
+        R.rbffd_step(ctx, model, state, 0.0, cfg["dt"], 2, R.RK4)
+        src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            R.rbffd_stream_copy(ctx, dst, src)
+        torch.cuda.synchronize()
+        log(f"[bench] pmc run done: stage kernel {model.bytes_per_node()} B/node stencil stream, "
+            f"copy kernel 2 x {512 << 20} bytes per launch")
+        return
     main_leg = run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, args.steps, args.warmup)
     log(f"[bench] {args.precision}: {main_leg}")
 

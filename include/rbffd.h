@@ -214,6 +214,11 @@ int64_t rbffd_model_bytes_per_node(rbffd_model *model);
 int rbffd_model_profile(rbffd_model *model, int enable);
 int rbffd_model_profile_read(rbffd_model *model, double *total_ms, int64_t *launches);
 
+/* Measurement helper: copy `bytes` (a multiple of 16, 16-byte aligned
+ * pointers) from src to dst with a plain streaming kernel, so that hardware
+ * memory counters can be calibrated against a kernel of known traffic. */
+int rbffd_stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,10 +13,13 @@ oracle computes that unique solution as accurately as it can:
    rho = max_j ||x_j - x_c|| (the exact solution is invariant to this up to
    the factor rho^-q, q = derivative order; monomials are in graded order
    x^(d-b) z^b for d = 0..l, b = 0..d),
-2. LU with partial pivoting in FP64 (LAPACK getrf),
-3. iterative refinement with residuals in 64-bit-mantissa extended precision
-   until the correction stops shrinking,
-4. rescaling by rho^-q.
+2. the system is formed in 64-bit-mantissa extended precision (x87 long
+   double) from the FP64 node coordinates: for one-sided degree-5 stencils
+   rounding the entries to FP64 alone moves the weights by ~5e-10,
+3. LU with partial pivoting of the system rounded to FP64 (LAPACK getrf),
+4. iterative refinement against the extended-precision system, residuals
+   in extended precision, until the correction stops shrinking,
+5. rescaling by rho^-q (extended precision), rounded to FP64 at the end.
 
 Operator right-hand sides for phi = r^m (d = 2):
   Dx  : -m r^(m-2) x_j        (x_j, z_j: local offsets of node j)
@@ -54,9 +57,13 @@ def op_order(kind: int, k: int = 0) -> int:
 
 def phs_apply(kind: int, m: int, k: int, x: np.ndarray, z: np.ndarray) -> np.ndarray:
     """L applied to ||x - x_j||^m as a function of x, evaluated at the centre
-    (the origin of the local frame); (x, z) are the offsets of node j."""
-    x = np.asarray(x, np.float64)
-    z = np.asarray(z, np.float64)
+    (the origin of the local frame); (x, z) are the offsets of node j. The
+    result has the floating type of (x, z) (FP64 or extended)."""
+    x = np.asarray(x)
+    z = np.asarray(z)
+    if x.dtype.kind != "f":
+        x = x.astype(np.float64)
+        z = z.astype(np.float64)
     r = np.sqrt(x * x + z * z)
     out = np.zeros_like(r)
     nz = r > 0.0
@@ -98,12 +105,18 @@ def poly_apply(kind: int, k: int, a: int, b: int) -> float:
     raise ValueError(kind)
 
 
-def local_frame(xy: np.ndarray, stencil: np.ndarray, center: int, period_x: float):
-    """Offsets of the stencil nodes from the centre (minimum image in x),
-    divided by rho = the largest offset length. Returns (x, z, rho)."""
-    dx = min_image(xy[stencil, 0] - xy[center, 0], period_x)
-    dz = xy[stencil, 1] - xy[center, 1]
-    rho = float(np.sqrt(np.max(dx * dx + dz * dz)))
+def local_frame(xy: np.ndarray, stencil: np.ndarray, center: int, period_x: float,
+                dtype=np.float64):
+    """Offsets of the stencil nodes from the centre (minimum image in x, the
+    image chosen from the FP64 offset as in the stencil search), divided by
+    rho = the largest offset length, all in ``dtype``. Returns (x, z, rho)."""
+    d64 = xy[stencil, 0] - xy[center, 0]
+    shift = np.where(d64 > 0.5 * period_x, -period_x, np.where(d64 < -0.5 * period_x, period_x, 0.0)) \
+        if period_x > 0.0 else np.zeros_like(d64)
+    X = xy.astype(dtype)
+    dx = (X[stencil, 0] - X[center, 0]) + shift.astype(dtype)
+    dz = X[stencil, 1] - X[center, 1]
+    rho = np.sqrt(np.max(dx * dx + dz * dz))
     return dx / rho, dz / rho, rho
 
 
@@ -112,7 +125,7 @@ def saddle_matrix(x: np.ndarray, z: np.ndarray, m: int, l: int) -> np.ndarray:
     n = x.size
     exps = poly_exponents(l)
     M = len(exps)
-    A = np.zeros((n + M, n + M))
+    A = np.zeros((n + M, n + M), dtype=x.dtype)
     rx = x[:, None] - x[None, :]
     rz = z[:, None] - z[None, :]
     A[:n, :n] = np.sqrt(rx * rx + rz * rz) ** m
@@ -127,7 +140,7 @@ def saddle_rhs(x, z, m, l, ops):
     """Right-hand sides [L phi_j ; L p_q] for each (kind, k) in ops."""
     n = x.size
     exps = poly_exponents(l)
-    B = np.zeros((n + len(exps), len(ops)))
+    B = np.zeros((n + len(exps), len(ops)), dtype=x.dtype)
     for c, (kind, k) in enumerate(ops):
         B[:n, c] = phs_apply(kind, m, k, x, z)
         B[n:, c] = [poly_apply(kind, k, a, b) for (a, b) in exps]
@@ -135,13 +148,15 @@ def saddle_rhs(x, z, m, l, ops):
 
 
 def refined_solve(A: np.ndarray, B: np.ndarray, max_iter: int = 10):
-    """LU with partial pivoting + extended-precision iterative refinement.
-    Returns (X float64, status)."""
-    lu, piv = scipy.linalg.lu_factor(A, check_finite=True)
+    """LU with partial pivoting of A rounded to FP64 + iterative refinement
+    against A and B as given (extended precision). Returns (X extended,
+    status)."""
+    A64 = A.astype(np.float64)
+    lu, piv = scipy.linalg.lu_factor(A64, check_finite=True)
     status = 0
-    if np.min(np.abs(np.diag(lu))) < 1e-13 * np.max(np.abs(A)):
+    if np.min(np.abs(np.diag(lu))) < 1e-13 * np.max(np.abs(A64)):
         status = 1
-    X = scipy.linalg.lu_solve((lu, piv), B)
+    X = scipy.linalg.lu_solve((lu, piv), B.astype(np.float64))
     AL = A.astype(np.longdouble)
     BL = B.astype(np.longdouble)
     XL = X.astype(np.longdouble)
@@ -162,7 +177,7 @@ def refined_solve(A: np.ndarray, B: np.ndarray, max_iter: int = 10):
         prev = size
     if not converged or not np.all(np.isfinite(XL)):
         status = 1
-    return XL.astype(np.float64), status
+    return XL, status
 
 
 def stencil_weights(xy, stencil, center, m, l, ops, period_x=0.0):
@@ -172,7 +187,8 @@ def stencil_weights(xy, stencil, center, m, l, ops, period_x=0.0):
     Lap^k, k = 0 meaning the largest power the PHS order allows, (m-1)/2
     (Section 5.3: continuity needs m >= 2k+1). Operators sharing a PHS order
     share one solve. Returns (w [len(ops)][n], status)."""
-    x, z, rho = local_frame(np.asarray(xy, np.float64), np.asarray(stencil), center, period_x)
+    x, z, rho = local_frame(np.asarray(xy, np.float64), np.asarray(stencil), center, period_x,
+                            dtype=np.longdouble)
     n = x.size
     W = np.zeros((len(ops), n))
     status = 0
@@ -192,7 +208,7 @@ def stencil_weights(xy, stencil, center, m, l, ops, period_x=0.0):
         status |= st
         for c, i in enumerate(members):
             kind, k, _ = ops[i]
-            W[i] = X[:n, c] * rho ** (-op_order(kind, k))
+            W[i] = (X[:n, c] / rho ** op_order(kind, k)).astype(np.float64)
     return W, status
 
 

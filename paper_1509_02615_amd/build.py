@@ -4,9 +4,11 @@
 
 Every translation unit is compiled to an object in parallel, then linked.
 Flags: -O3, C++17, position independent, packed FP32 instructions disabled
-(-Xclang -target-feature -Xclang -packed-fp32-ops). The stencil search is
-built with -ffp-contract=off: its distance keys must round exactly like the
-plain IEEE definition.
+(-Xclang -target-feature -Xclang -packed-fp32-ops). The stencil search and
+the weights are built with -ffp-contract=off: the search's distance keys
+must round exactly like the plain IEEE definition, and the weights'
+double-double arithmetic needs every sum and product rounded as written
+(its fused multiply-adds are explicit fma calls).
 """
 
 import os
@@ -25,7 +27,7 @@ SOURCES = ["api.hip", "knn.hip", "weights.hip", "model.hip", "rhs.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
-EXTRA = {"knn.hip": ["-ffp-contract=off"]}
+EXTRA = {"knn.hip": ["-ffp-contract=off"], "weights.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src):

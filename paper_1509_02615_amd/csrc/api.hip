@@ -178,4 +178,13 @@ int rbffd_model_profile_read(rbffd_model *model, double *total_ms, int64_t *laun
   return model_profile_read(model, total_ms, launches);
 }
 
+int rbffd_stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!dst || !src || bytes < 0 || bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 ||
+      reinterpret_cast<uintptr_t>(src) % 16)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "stream copy needs 16-byte aligned pointers and size");
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return stream_copy(ctx, dst, src, bytes);
+}
+
 }  // extern "C"

@@ -167,8 +167,11 @@ bool invert_sparse_lu(int n, std::vector<double> &A, std::vector<double> &inv) {
   return true;
 }
 
-// Half-width of the cyclic window around the row maximum that leaves at most
-// 2^-56 of the row's l1 mass outside.
+// Half-width h of the cyclic window [c - h, c + h] around the row maximum c
+// that leaves at most 2^-56 of the row's l1 mass outside. The outside mass
+// is accumulated from the far end inwards (small terms first), so it is not
+// the difference of two rounded sums. Returns (n - 1) / 2 + 1 when no window
+// shorter than the row qualifies.
 int window_halfwidth(const double *row, int n, int &center) {
   double total = 0.0, best = -1.0;
   center = 0;
@@ -181,12 +184,16 @@ int window_halfwidth(const double *row, int n, int &center) {
     }
   }
   const double tol = std::ldexp(total, -56);
-  double inside = std::fabs(row[center]);
-  int h = 0;
-  while (2 * h + 1 < n && total - inside > tol) {
-    ++h;
-    inside += std::fabs(row[((center + h) % n + n) % n]);
-    if (2 * h + 1 <= n) inside += std::fabs(row[((center - h) % n + n) % n]);
+  const int hmax = (n - 1) / 2;
+  auto at = [&](int d) { return std::fabs(row[((center + d) % n + n) % n]); };
+  double tail = (n % 2 == 0) ? at(n / 2) : 0.0;  // mass at distance > hmax
+  if (tail > tol) return hmax + 1;
+  int h = hmax;
+  while (h > 0) {
+    const double next = tail + at(h) + at(-h);  // mass at distance > h - 1
+    if (next > tol) break;
+    tail = next;
+    --h;
   }
   return h;
 }

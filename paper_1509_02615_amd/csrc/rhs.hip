@@ -21,6 +21,7 @@
 // Launch geometry: 256-thread blocks, thread = (node, member); block ids are
 // remapped so that each of the 8 XCDs (which take block ids round-robin)
 // works on one contiguous node range and its L2 sees neighbouring gathers.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -228,18 +229,25 @@ struct GArgs {
   double bc_scale, theta_bar;  // dpi/dz = bc_scale * th / (theta_bar + th)
 };
 
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // B1 part 1: boundary-row residuals r = bc - (W_I u_I + W_B u_B), w_B := 0.
+// One wavefront per (boundary node, member); lanes take stencil slots.
 template <class FT>
 __global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_kernel(GArgs a) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * RHS_BLOCK + threadIdx.x;
+  const int64_t item = static_cast<int64_t>(blockIdx.x) * (RHS_BLOCK / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int E = a.E;
-  if (t >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
-  const int64_t wb = t / E;  // wall * nb + b
-  const int e = static_cast<int>(t - wb * E);
+  if (item >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
+  const int64_t wb = item / E;  // wall * nb + b
+  const int e = static_cast<int>(item - wb * E);
   FT *y = static_cast<FT *>(a.y);
   const int node = a.wall_nodes[wb];
   double ru = 0.0, rw = 0.0, rt = 0.0, rp = 0.0;
-  for (int k = 0; k < a.n; ++k) {
+  for (int k = lane; k < a.n; k += 64) {
     const int64_t s = wb * a.n + k;
     const int j = a.wall_idx[s];
     const uint8_t kj = a.kind[j];
@@ -251,40 +259,54 @@ __global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_kernel(GArgs a) {
     rp = fma(-ww.x, static_cast<double>(f.v[3]), rp);
     if (kj != 1) rw = fma(-ww.y, static_cast<double>(f.v[1]), rw);  // wall w is 0
   }
-  const double thb = static_cast<double>(y[(static_cast<int64_t>(node) * E + e) * 4 + 2]);
-  rp += a.bc_scale * thb / (a.theta_bar + thb);
-  y[(static_cast<int64_t>(node) * E + e) * 4 + 1] = FT(0);
-  double *g = a.gres + (wb * E + e) * 4;
-  g[0] = ru;
-  g[1] = rw;
-  g[2] = rt;
-  g[3] = rp;
+  ru = wave_sum(ru);
+  rw = wave_sum(rw);
+  rt = wave_sum(rt);
+  rp = wave_sum(rp);
+  if (lane == 0) {
+    const double thb = static_cast<double>(y[(static_cast<int64_t>(node) * E + e) * 4 + 2]);
+    rp += a.bc_scale * thb / (a.theta_bar + thb);
+    y[(static_cast<int64_t>(node) * E + e) * 4 + 1] = FT(0);
+    double *g = a.gres + (wb * E + e) * 4;
+    g[0] = ru;
+    g[1] = rw;
+    g[2] = rt;
+    g[3] = rp;
+  }
 }
 
 // B1 part 2: ghost values u_G = W_G^-1 r through the banded inverse.
+// One wavefront per (ghost node, member); lanes take band positions.
 template <class FT>
 __global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_kernel(GArgs a) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * RHS_BLOCK + threadIdx.x;
+  const int64_t item = static_cast<int64_t>(blockIdx.x) * (RHS_BLOCK / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int E = a.E;
-  if (t >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
-  const int64_t wg = t / E;  // wall * nb + ghost position
-  const int e = static_cast<int>(t - wg * E);
+  if (item >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
+  const int64_t wg = item / E;  // wall * nb + ghost position
+  const int e = static_cast<int>(item - wg * E);
   const int wl = static_cast<int>(wg / a.nb), gp = static_cast<int>(wg - static_cast<int64_t>(wl) * a.nb);
-  double v[4];
-  for (int f = 0; f < 4; ++f) {
-    const int op = f == 1 ? 1 : 0;
-    const int64_t row = (static_cast<int64_t>(wl) * 2 + op) * a.nb + gp;
-    const double *z = a.ginv + row * a.band;
-    int p = a.gstart[row];
-    const double *r = a.gres + (static_cast<int64_t>(wl) * a.nb * E + e) * 4 + f;
-    double s = 0.0;
-    for (int q = 0; q < a.band; ++q) {
-      s = fma(z[q], r[static_cast<int64_t>(p) * E * 4], s);
-      if (++p == a.nb) p = 0;
-    }
-    v[f] = s;
+  const int64_t row_z = (static_cast<int64_t>(wl) * 2 + 0) * a.nb + gp;   // Dz rows: u, theta', pi'
+  const int64_t row_zz = (static_cast<int64_t>(wl) * 2 + 1) * a.nb + gp;  // Dzz rows: w
+  const double *z1 = a.ginv + row_z * a.band;
+  const double *z2 = a.ginv + row_zz * a.band;
+  const int p1 = a.gstart[row_z], p2 = a.gstart[row_zz];
+  const double *r = a.gres + static_cast<int64_t>(wl) * a.nb * E * 4;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  for (int q = lane; q < a.band; q += 64) {
+    int b1 = p1 + q;
+    if (b1 >= a.nb) b1 -= a.nb;
+    int b2 = p2 + q;
+    if (b2 >= a.nb) b2 -= a.nb;
+    const double c1 = z1[q], c2 = z2[q];
+    const double *r1 = r + (static_cast<int64_t>(b1) * E + e) * 4;
+    v0 = fma(c1, r1[0], v0);
+    v2 = fma(c1, r1[2], v2);
+    v3 = fma(c1, r1[3], v3);
+    v1 = fma(c2, r[(static_cast<int64_t>(b2) * E + e) * 4 + 1], v1);
   }
-  store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.ghost_nodes[wg]) * E + e) * 4, v);
+  double v[4] = {wave_sum(v0), wave_sum(v1), wave_sum(v2), wave_sum(v3)};
+  if (lane == 0) store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.ghost_nodes[wg]) * E + e) * 4, v);
 }
 
 __global__ void misc_init_kernel(DevMisc *m, double t0) {
@@ -316,13 +338,14 @@ int launch_ghost(rbffd_ctx *ctx, rbffd_model *m, void *y) {
   g.n_walls = m->n_walls;
   g.bc_scale = m->g / (m->c_p * m->theta_bar);
   g.theta_bar = m->theta_bar;
-  const int64_t cnt = static_cast<int64_t>(m->n_walls) * m->nb * m->E;
+  const int64_t cnt = static_cast<int64_t>(m->n_walls) * m->nb * m->E;  // one wavefront each
+  const unsigned grid = grid_for(cnt, RHS_BLOCK / 64);
   if (m->fdt == RBFFD_F64) {
-    ghost_resid_kernel<double><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(g);
-    ghost_apply_kernel<double><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(g);
+    ghost_resid_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+    ghost_apply_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
   } else {
-    ghost_resid_kernel<float><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(g);
-    ghost_apply_kernel<float><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(g);
+    ghost_resid_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+    ghost_apply_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
   }
   RBFFD_HIP(ctx, hipGetLastError());
   return RBFFD_OK;
@@ -541,5 +564,22 @@ int model_profile_read(rbffd_model *m, double *total_ms, int64_t *launches) {
     (void)hipEventDestroy(p.second);
   }
   m->prof_events.clear();
+  return RBFFD_OK;
+}
+
+namespace {
+__global__ __launch_bounds__(256) void stream_copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
+                                                          int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+}  // namespace
+
+int stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes) {
+  const int64_t n = bytes / 16;
+  if (n == 0) return RBFFD_OK;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(grid_for(n, 256), 65536));
+  stream_copy_kernel<<<grid, 256, 0, ctx->stream>>>(static_cast<uint4 *>(dst), static_cast<const uint4 *>(src), n);
+  RBFFD_HIP(ctx, hipGetLastError());
   return RBFFD_OK;
 }

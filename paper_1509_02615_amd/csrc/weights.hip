@@ -17,9 +17,11 @@
 //  3. LU with partial pivoting of [A | B] (FP64, or FP32 for the
 //     mixed-precision variant);
 //  4. back substitution, then iterative refinement: residual b - A x with A
-//     and b regenerated from the offsets and accumulated in double-double,
-//     correction through the same factors, until the correction is at
-//     rounding level;
+//     and b formed in double-double arithmetic from the FP64 node
+//     coordinates (so the refinement converges to the solution of the exact
+//     system, not of its FP64 rounding, which for one-sided degree-5
+//     stencils differs by ~5e-10), correction through the same factors,
+//     until the correction is at rounding level;
 //  5. rescaling by rho^-q (q = derivative order) and the padded row write.
 //
 // FP64 matrix cores on gfx950 have the same peak as the FP64 vector ALUs,
@@ -149,28 +151,121 @@ __device__ __forceinline__ double rhs_entry(int i, int n, int m, const WOp &op, 
   return poly_rhs(op.kind, k_eff, a, b);
 }
 
-// b_i - sum_j A_ij x_j accumulated in double-double (exact products by
-// fma, error-free sums), rounded once at the end.
-__device__ double dd_residual(int i, int K, int n, int m, const double *xi, const double *ze,
-                              const double *x, double b) {
-#pragma clang fp contract(off)
-  double s = b, e = 0.0;
-  for (int j = 0; j < K; ++j) {
-    const double aij = sys_entry(i, j, n, m, xi, ze);
-    const double p = aij * x[j];
-    const double pe = fma(aij, x[j], -p);
-    const double s1 = s - p;
-    const double bb = s1 - s;
-    const double te = (s - (s1 - bb)) + (-p - bb);
-    s = s1;
-    e += te - pe;
-  }
-  return s + e;
-}
-
 __device__ __forceinline__ double wave_max(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
+}
+
+// ---- double-double arithmetic (error-free transformations: Knuth's TwoSum,
+// Dekker's product via fused multiply-add). This file is compiled without
+// FP contraction, so every sum and product below is rounded as written.
+struct dd {
+  double hi, lo;
+};
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b, bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ dd fast_two_sum(double a, double b) {
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi), t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
+__device__ __forceinline__ dd dd_mul(dd a, dd b) {
+  dd p = two_prod(a.hi, b.hi);
+  p.lo += a.hi * b.lo + a.lo * b.hi;
+  return fast_two_sum(p.hi, p.lo);
+}
+__device__ __forceinline__ dd dd_mul_d(dd a, double b) {
+  dd p = two_prod(a.hi, b);
+  p.lo += a.lo * b;
+  return fast_two_sum(p.hi, p.lo);
+}
+__device__ __forceinline__ dd dd_div(dd a, dd b) {
+  double q1 = a.hi / b.hi;
+  dd r = dd_sub(a, dd_mul_d(b, q1));
+  double q2 = r.hi / b.hi;
+  r = dd_sub(r, dd_mul_d(b, q2));
+  double q3 = r.hi / b.hi;
+  dd q = fast_two_sum(q1, q2);
+  return dd_add(q, dd{q3, 0.0});
+}
+__device__ __forceinline__ dd dd_sqrt(dd a) {
+  if (!(a.hi > 0.0)) return {0.0, 0.0};
+  double x = sqrt(a.hi);
+  dd r = dd_sub(a, two_prod(x, x));
+  return fast_two_sum(x, r.hi / (2.0 * x));
+}
+// r^p for odd p >= -1 given r2 = r*r and r
+__device__ __forceinline__ dd dd_rpow(dd r2, dd r, int p) {
+  if (p < 0) return dd_div(dd{1.0, 0.0}, r);
+  dd v = r;
+  for (int i = 0; i < (p - 1) / 2; ++i) v = dd_mul(v, r2);
+  return v;
+}
+__device__ __forceinline__ dd dd_ipow(dd x, int p) {
+  dd v{1.0, 0.0};
+  for (int i = 0; i < p; ++i) v = dd_mul(v, x);
+  return v;
+}
+
+// Entry (i, j) of [Phi P; P^T 0] in double-double from offsets (xh+xl, zh+zl).
+__device__ dd sys_entry_dd(int i, int j, int n, int m, const double *xh, const double *xl, const double *zh,
+                           const double *zl) {
+  if (i < n && j < n) {
+    dd dx = dd_sub(dd{xh[i], xl[i]}, dd{xh[j], xl[j]});
+    dd dz = dd_sub(dd{zh[i], zl[i]}, dd{zh[j], zl[j]});
+    dd r2 = dd_add(dd_mul(dx, dx), dd_mul(dz, dz));
+    if (r2.hi == 0.0) return {0.0, 0.0};
+    return dd_rpow(r2, dd_sqrt(r2), m);
+  }
+  if (i >= n && j >= n) return {0.0, 0.0};
+  const int node = i < n ? i : j;
+  int a, b;
+  mono((i < n ? j : i) - n, a, b);
+  return dd_mul(dd_ipow(dd{xh[node], xl[node]}, a), dd_ipow(dd{zh[node], zl[node]}, b));
+}
+
+// Right-hand-side entry i of operator op in double-double.
+__device__ dd rhs_entry_dd(int i, int n, int m, const WOp &op, int k, const double *xh, const double *xl,
+                           const double *zh, const double *zl) {
+  if (i >= n) {
+    int a, b;
+    mono(i - n, a, b);
+    return {poly_rhs(op.kind, k, a, b), 0.0};
+  }
+  dd x{xh[i], xl[i]}, z{zh[i], zl[i]};
+  dd r2 = dd_add(dd_mul(x, x), dd_mul(z, z));
+  if (r2.hi == 0.0) return {0.0, 0.0};
+  dd r = dd_sqrt(r2);
+  switch (op.kind) {
+    case RBFFD_DX: return dd_mul_d(dd_mul(dd_rpow(r2, r, m - 2), x), -static_cast<double>(m));
+    case RBFFD_DZ: return dd_mul_d(dd_mul(dd_rpow(r2, r, m - 2), z), -static_cast<double>(m));
+    case RBFFD_LAP: return dd_mul_d(dd_rpow(r2, r, m - 2), static_cast<double>(m * m));
+    case RBFFD_HYPERLAP: {
+      double c = 1.0;
+      for (int q = 0; q < k; ++q) c *= static_cast<double>((m - 2 * q) * (m - 2 * q));
+      return dd_mul_d(dd_rpow(r2, r, m - 2 * k), c);
+    }
+    case RBFFD_DZZ: {
+      dd t1 = dd_mul_d(dd_rpow(r2, r, m - 2), static_cast<double>(m));
+      dd t2 = dd_mul_d(dd_mul(dd_rpow(r2, r, m - 4), dd_mul(z, z)), static_cast<double>(m * (m - 2)));
+      return dd_add(t1, t2);
+    }
+  }
+  return {0.0, 0.0};
 }
 
 template <typename T>
@@ -182,13 +277,15 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
   // LDS carve-up
   double *xs = smem;                       // [8][kc] solution
   double *rs = xs + MAX_OPS * kc;          // [8][kc] residual / correction
-  double *xi = rs + MAX_OPS * kc;          // [128]
-  double *ze = xi + 128;                   // [128]
+  double *xi = rs + MAX_OPS * kc;          // [128] scaled x offsets (FP64)
+  double *ze = xi + 128;                   // [128] scaled z offsets (FP64)
+  double *xl = ze + 128;                   // [128] low parts of the double-double x offsets
+  double *zl = xl + 128;                   // [128] low parts of the double-double z offsets
   __shared__ double s_red[4];
   __shared__ int s_piv[128];
   __shared__ int s_flag, s_pivrow;
   __shared__ double s_pmin, s_amax;
-  T *A = reinterpret_cast<T *>(ze + 128);  // [kc + 8 columns][kc], column-major
+  T *A = reinterpret_cast<T *>(zl + 128);  // [kc + 8 columns][kc], column-major
 
   const int c = a.centers ? a.centers[q] : q;
   const int n = a.n_per ? a.n_per[q] : a.n_max;
@@ -222,16 +319,20 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
   const double xc = a.xy[2 * c], zc = a.xy[2 * c + 1];
   for (int t = tid; t < n; t += W_THREADS) {
     int j = a.idx[static_cast<int64_t>(q) * a.n_max + t];
-    double dx = a.xy[2 * j] - xc;
+    dd dx = two_sum(a.xy[2 * j], -xc);  // exact offset
     if (a.period > 0.0) {
       double half = 0.5 * a.period;
-      if (dx > half)
-        dx -= a.period;
-      else if (dx < -half)
-        dx += a.period;
+      double d64 = a.xy[2 * j] - xc;
+      if (d64 > half)
+        dx = dd_add(dx, dd{-a.period, 0.0});
+      else if (d64 < -half)
+        dx = dd_add(dx, dd{a.period, 0.0});
     }
-    xi[t] = dx;
-    ze[t] = a.xy[2 * j + 1] - zc;
+    dd dz = two_sum(a.xy[2 * j + 1], -zc);
+    xi[t] = dx.hi;
+    xl[t] = dx.lo;
+    ze[t] = dz.hi;
+    zl[t] = dz.lo;
   }
   __syncthreads();
   if (tid < 64) {
@@ -253,8 +354,11 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
     return;
   }
   for (int t = tid; t < n; t += W_THREADS) {
-    xi[t] = xi[t] / rho;
-    ze[t] = ze[t] / rho;
+    const dd ex = dd_div(dd{xi[t], xl[t]}, dd{rho, 0.0}), ez = dd_div(dd{ze[t], zl[t]}, dd{rho, 0.0});
+    xi[t] = ex.hi;
+    xl[t] = ex.lo;
+    ze[t] = ez.hi;
+    zl[t] = ez.lo;
   }
   __syncthreads();
 
@@ -385,10 +489,27 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
     // 5. iterative refinement with double-double residuals
     bool converged = false;
     for (int it = 0; it < a.max_iter && !converged; ++it) {
-      for (int t = tid; t < K * ng; t += W_THREADS) {
-        const int i = t % K, g = t / K;
-        rs[g * kc + i] = dd_residual(i, K, n, mg, xi, ze, xs + g * kc,
-                                     rhs_entry(i, n, mg, a.ops[gl[g]], kg[g], xi, ze));
+      {  // r = b - A x in double-double: 4 lanes per row, partial sums over j
+        const int part = tid & 3;
+        for (int i = tid >> 2; i < K; i += W_THREADS / 4) {
+          dd acc[MAX_OPS];
+          for (int g = 0; g < ng; ++g) acc[g] = dd{0.0, 0.0};
+          for (int j = part; j < K; j += 4) {
+            const dd aij = sys_entry_dd(i, j, n, mg, xi, xl, ze, zl);
+            for (int g = 0; g < ng; ++g) acc[g] = dd_add(acc[g], dd_mul_d(aij, xs[g * kc + j]));
+          }
+          for (int g = 0; g < ng; ++g) {
+            for (int off = 1; off < 4; off <<= 1) {
+              dd o{__shfl_xor(acc[g].hi, off, 64), __shfl_xor(acc[g].lo, off, 64)};
+              acc[g] = dd_add(acc[g], o);
+            }
+            if (part == 0) {
+              const dd b = rhs_entry_dd(i, n, mg, a.ops[gl[g]], kg[g], xi, xl, ze, zl);
+              const dd r = dd_sub(b, acc[g]);
+              rs[g * kc + i] = r.hi + r.lo;
+            }
+          }
+        }
       }
       __syncthreads();
       if (tid < ng) {  // row interchanges, in factorisation order
@@ -528,7 +649,7 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   a.w = w;
   a.status = st_out;
   a.k_cap = kc;
-  const size_t head = sizeof(double) * (2 * MAX_OPS * kc + 256);
+  const size_t head = sizeof(double) * (2 * MAX_OPS * kc + 512);
   if (precision == RBFFD_SOLVE_FP64) {
     a.max_iter = 3;
     size_t lds = head + sizeof(double) * static_cast<size_t>(kc) * (kc + MAX_OPS);

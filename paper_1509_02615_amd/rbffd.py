@@ -65,11 +65,12 @@ _lib.rbffd_model_bytes_per_node.argtypes = [_vp]
 _lib.rbffd_model_bytes_per_node.restype = _i64
 _lib.rbffd_model_profile.argtypes = [_vp, ctypes.c_int]
 _lib.rbffd_model_profile_read.argtypes = [_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
+_lib.rbffd_stream_copy.argtypes = [_vp, _vp, _vp, _i64]
 
 EXPORTS = ["rbffd_create", "rbffd_destroy", "rbffd_last_error", "rbffd_sync", "rbffd_knn",
            "rbffd_weights", "rbffd_model_create", "rbffd_model_destroy", "rbffd_ghost",
            "rbffd_rhs", "rbffd_step", "rbffd_model_bytes_per_node", "rbffd_model_profile",
-           "rbffd_model_profile_read"]
+           "rbffd_model_profile_read", "rbffd_stream_copy"]
 
 
 class RbffdError(RuntimeError):
@@ -237,6 +238,16 @@ def rbffd_ghost(ctx: Context, model: Model, state):
 def rbffd_rhs(ctx: Context, model: Model, t, state, tendency):
     ctx.check(_lib.rbffd_rhs(ctx.h, model.h, float(t), model._state(state),
                              model._state(tendency, "tendency")))
+
+
+def rbffd_stream_copy(ctx: Context, dst, src):
+    """Plain streaming copy of src into dst (same size, CUDA/HIP tensors)."""
+    if not (dst.is_cuda and src.is_cuda and dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("contiguous device tensors required")
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("size mismatch")
+    ctx.check(_lib.rbffd_stream_copy(ctx.h, dst.data_ptr(), src.data_ptr(), nb))
 
 
 def rbffd_step(ctx: Context, model: Model, state, t, dt, n_steps, tableau=RK4):

@@ -11,7 +11,7 @@ import pytest
 import sympy as sp
 
 import oracle as O
-from oracle.weights import saddle_matrix, saddle_rhs, local_frame, poly_exponents
+from oracle.weights import poly_exponents
 from workloads import unit_square_cartesian, jittered_square, channel
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -105,24 +105,70 @@ def test_polynomial_reproduction(m, l, n):
                 assert abs(np.dot(w, vals) - exact) <= 1e-11 * scale, (kind, a, b)
 
 
+def _mp_exact_weights(xy, st, c, m, l, ops, period):
+    """Eq. (weights) formed and solved in 40-digit arithmetic from the FP64
+    node coordinates; operator right-hand sides from sympy derivatives."""
+    mpmath.mp.dps = 40
+    mpf = mpmath.mpf
+    d64 = xy[st, 0] - xy[c, 0]
+    dx, dz = [], []
+    for i, j in enumerate(st):
+        shift = 0.0
+        if period > 0 and d64[i] > period / 2:
+            shift = -period
+        elif period > 0 and d64[i] < -period / 2:
+            shift = period
+        dx.append(mpf(float(xy[j, 0])) - mpf(float(xy[c, 0])) + mpf(shift))
+        dz.append(mpf(float(xy[j, 1])) - mpf(float(xy[c, 1])))
+    rho = mpmath.sqrt(max(a * a + b * b for a, b in zip(dx, dz)))
+    x = [a / rho for a in dx]
+    z = [b / rho for b in dz]
+    n = len(st)
+    exps = poly_exponents(l)
+    K = n + len(exps)
+    A = mpmath.zeros(K, K)
+    for i in range(n):
+        for j in range(n):
+            A[i, j] = mpmath.sqrt((x[i] - x[j]) ** 2 + (z[i] - z[j]) ** 2) ** m
+        for q, (a, b) in enumerate(exps):
+            A[i, n + q] = A[n + q, i] = x[i] ** a * z[i] ** b
+    X, Z = sp.symbols("X Z")
+    out = []
+    for kind, k in ops:
+        f = _sym_ops(m, k)[kind]
+        rhs = mpmath.zeros(K, 1)
+        for i in range(n):
+            rhs[i] = f(x[i], z[i]) if (x[i] != 0 or z[i] != 0) else mpf(0)
+        for q, (a, b) in enumerate(exps):
+            e = X ** a * Z ** b
+            h = {O.DX: sp.diff(e, X), O.DZ: sp.diff(e, Z), O.LAP: sp.diff(e, X, 2) + sp.diff(e, Z, 2),
+                 O.DZZ: sp.diff(e, Z, 2)}.get(kind)
+            if kind == O.HYPERLAP:
+                h = e
+                for _ in range(k):
+                    h = sp.diff(h, X, 2) + sp.diff(h, Z, 2)
+            rhs[n + q] = mpf(str(h.subs({X: 0, Z: 0})))
+        sol = mpmath.lu_solve(A, rhs)
+        scale = rho ** O.op_order(kind, k)
+        out.append(np.array([float(sol[i] / scale) for i in range(n)]))
+    return out
+
+
 @pytest.mark.parametrize("m,l,n", [(3, 3, 21), (7, 4, 37), (7, 5, 61)])
 def test_exact_solution_40_digits(m, l, n):
-    """The oracle reaches the exact solution of the assembled system: compare
-    with a 40-digit mpmath solve of the same FP64 matrix."""
-    mpmath.mp.dps = 40
+    """The oracle reaches the exact solution of Eq. (weights) for the given
+    FP64 node positions: compare with the system formed and solved in
+    40-digit arithmetic (independent assembly, sympy right-hand sides),
+    including one-sided degree-5 stencils whose FP64-rounded system alone
+    would move the weights by ~5e-10."""
     for xy, c, per in _stencils()[::2]:
         st = O.knn(xy, [c], n, per)[0]
-        x, z, rho = local_frame(xy, st, c, per)
         ops = [(O.DX, 0), (O.LAP, 0), (O.HYPERLAP, (m - 1) // 2)]
-        A = saddle_matrix(x, z, m, l)
-        B = saddle_rhs(x, z, m, l, ops)
-        Am = mpmath.matrix(A.tolist())
         W, _ = O.stencil_weights(xy, st, c, m, l, [(kk, k, 0) for kk, k in ops], per)
-        for j, (kind, k) in enumerate(ops):
-            xm = mpmath.lu_solve(Am, mpmath.matrix(B[:, j].tolist()))
-            ref = np.array([float(xm[i]) for i in range(x.size)]) * rho ** (-O.op_order(kind, k))
-            err = np.linalg.norm(W[j] - ref) / np.linalg.norm(ref)
-            assert err < 1e-13, (kind, err)       # extended residuals: ~kappa * 2^-64
+        ref = _mp_exact_weights(xy, st, c, m, l, ops, per)
+        for j in range(len(ops)):
+            err = np.linalg.norm(W[j] - ref[j]) / np.linalg.norm(ref[j])
+            assert err < 1e-12, (ops[j], err)
 
 
 def test_symmetry_translation_and_scale():
