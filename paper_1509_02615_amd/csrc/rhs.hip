@@ -29,7 +29,58 @@
 
 namespace {
 
-constexpr int RHS_BLOCK = 256;
+constexpr int RHS_BLOCK = 256;  // closure and transport kernels
+
+// Launch shape of the Navier-Stokes stage kernel per weight precision,
+// chosen by measurement on the 524,288-node channel: FP32 and BF16 records
+// go best with no slot unrolling and non-temporal loads of the weight stream
+// (each launch reads it exactly once, so keeping it out of the caches leaves
+// them to the neighbour gathers); FP64 with 2-slot unrolling, ordinary loads
+// and 512-thread blocks.
+template <int WDT> struct StageShape {
+  static constexpr int block = 256, unroll = 1;
+  static constexpr bool nt = true;
+};
+template <> struct StageShape<RBFFD_F64> {
+  static constexpr int block = 512, unroll = 2;
+  static constexpr bool nt = false;
+};
+
+typedef float nat_f4 __attribute__((ext_vector_type(4)));
+typedef double nat_d2 __attribute__((ext_vector_type(2)));
+template <bool NT, class T> __device__ __forceinline__ T stream_load(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <bool NT> __device__ __forceinline__ float4 stream_load4(const float4 *p) {
+  if constexpr (NT) {
+    nat_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nat_f4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+  }
+  return *p;
+}
+template <bool NT> __device__ __forceinline__ double2 stream_load2(const double2 *p) {
+  if constexpr (NT) {
+    nat_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nat_d2 *>(p));
+    return make_double2(v.x, v.y);
+  }
+  return *p;
+}
+template <bool NT> __device__ __forceinline__ uint3 stream_load3(const uint3 *p) {
+  if constexpr (NT) {
+    const unsigned *q = reinterpret_cast<const unsigned *>(p);
+    return make_uint3(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1),
+                      __builtin_nontemporal_load(q + 2));
+  }
+  return *p;
+}
+
+template <int BLOCK = RHS_BLOCK> __device__ __forceinline__ int64_t xcd_thread() {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  const int64_t full = (nb / 8) * 8;
+  const int64_t lb = b >= full ? b : (b % 8) * (nb / 8) + b / 8;
+  return lb * BLOCK + threadIdx.x;
+}
 
 __device__ __forceinline__ int64_t xcd_block() {
   const int64_t b = blockIdx.x, nb = gridDim.x;
@@ -83,8 +134,9 @@ struct NSArgs {
 };
 
 template <class FT, int WDT>
-__global__ __launch_bounds__(RHS_BLOCK) void ns_stage_kernel(NSArgs a) {
-  const int64_t t = xcd_block() * RHS_BLOCK + threadIdx.x;
+__global__ __launch_bounds__(StageShape<WDT>::block) void ns_stage_kernel(NSArgs a) {
+  using SH = StageShape<WDT>;
+  const int64_t t = xcd_thread<SH::block>();
   if (t >= a.Na * a.E) return;
   const int E = a.E;
   const int64_t i = E == 1 ? t : t / E;
@@ -95,33 +147,34 @@ __global__ __launch_bounds__(RHS_BLOCK) void ns_stage_kernel(NSArgs a) {
   double shv[4] = {0.0, 0.0, 0.0, 0.0};
   const int n = a.n;
   const int64_t Na = a.Na;
-#pragma unroll 2
+#pragma unroll SH::unroll
   for (int k = 0; k < n; ++k) {
     const int64_t s = static_cast<int64_t>(k) * Na + i;
     int j;
     FT wdx, wdz, wlp;
     double whv;
     if constexpr (WDT == RBFFD_F64) {
-      const RecF64 r = static_cast<const RecF64 *>(a.rec)[s];
-      j = a.idx_t[s];
-      wdx = r.dx;
-      wdz = r.dz;
-      wlp = r.lap;
-      whv = r.hv;
+      const double2 r0 = stream_load2<SH::nt>(reinterpret_cast<const double2 *>(a.rec) + 2 * s);
+      const double2 r1 = stream_load2<SH::nt>(reinterpret_cast<const double2 *>(a.rec) + 2 * s + 1);
+      j = stream_load<SH::nt>(a.idx_t + s);
+      wdx = r0.x;
+      wdz = r0.y;
+      wlp = r1.x;
+      whv = r1.y;
     } else if constexpr (WDT == RBFFD_F32) {
-      const RecF32 r = static_cast<const RecF32 *>(a.rec)[s];
-      j = r.idx;
-      wdx = r.dx;
-      wdz = r.dz;
-      wlp = r.lap;
-      whv = a.hv_t[s];
+      const float4 r = stream_load4<SH::nt>(reinterpret_cast<const float4 *>(a.rec) + s);
+      j = __float_as_int(r.w);
+      wdx = r.x;
+      wdz = r.y;
+      wlp = r.z;
+      whv = stream_load<SH::nt>(a.hv_t + s);
     } else {
-      const RecBF16 r = static_cast<const RecBF16 *>(a.rec)[s];
-      j = r.idx;
-      wdx = bf16f(r.dx);
-      wdz = bf16f(r.dz);
-      wlp = bf16f(r.lap);
-      whv = a.hv_t[s];
+      const uint3 r = stream_load3<SH::nt>(reinterpret_cast<const uint3 *>(a.rec) + s);
+      j = static_cast<int>(r.z);
+      wdx = __uint_as_float(r.x << 16);
+      wdz = __uint_as_float(r.x & 0xffff0000u);
+      wlp = __uint_as_float(r.y << 16);
+      whv = stream_load<SH::nt>(a.hv_t + s);
     }
     const F4<FT> f = load4(ys + (static_cast<int64_t>(j) * E + e) * 4);
 #pragma unroll
@@ -367,7 +420,6 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     RBFFD_HIP(ctx, hipEventRecord(ev0, ctx->stream));
   }
   const int64_t cnt = m->Na * m->E;
-  const unsigned grid = grid_for(cnt, RHS_BLOCK);
   DevMisc *misc = m->dev_misc.as<DevMisc>();
   if (m->physics == RBFFD_PHYS_NS) {
     NSArgs a{};
@@ -396,12 +448,16 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.acc_mode = sp.acc_mode;
     a.misc = misc;
     a.check = sp.check;
-    if (m->fdt == RBFFD_F64)
-      ns_stage_kernel<double, RBFFD_F64><<<grid, RHS_BLOCK, 0, ctx->stream>>>(a);
-    else if (m->wdt == RBFFD_F32)
-      ns_stage_kernel<float, RBFFD_F32><<<grid, RHS_BLOCK, 0, ctx->stream>>>(a);
-    else
-      ns_stage_kernel<float, RBFFD_BF16><<<grid, RHS_BLOCK, 0, ctx->stream>>>(a);
+    if (m->fdt == RBFFD_F64) {
+      constexpr int B = StageShape<RBFFD_F64>::block;
+      ns_stage_kernel<double, RBFFD_F64><<<grid_for(cnt, B), B, 0, ctx->stream>>>(a);
+    } else if (m->wdt == RBFFD_F32) {
+      constexpr int B = StageShape<RBFFD_F32>::block;
+      ns_stage_kernel<float, RBFFD_F32><<<grid_for(cnt, B), B, 0, ctx->stream>>>(a);
+    } else {
+      constexpr int B = StageShape<RBFFD_BF16>::block;
+      ns_stage_kernel<float, RBFFD_BF16><<<grid_for(cnt, B), B, 0, ctx->stream>>>(a);
+    }
   } else {
     AdvArgs a{};
     a.ys = sp.ys;
@@ -425,9 +481,9 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.misc = use_misc ? misc : nullptr;
     a.check = sp.check;
     if (m->fdt == RBFFD_F64)
-      adv_stage_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(a);
+      adv_stage_kernel<double><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(a);
     else
-      adv_stage_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(a);
+      adv_stage_kernel<float><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(a);
   }
   RBFFD_HIP(ctx, hipGetLastError());
   if (ev1) RBFFD_HIP(ctx, hipEventRecord(ev1, ctx->stream));

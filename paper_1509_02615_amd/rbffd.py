@@ -12,7 +12,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librbffd.so")
+# RBFFD_LIBRARY may point at another build of the same library
+LIB_PATH = os.environ.get("RBFFD_LIBRARY", os.path.join(_HERE, "librbffd.so"))
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1509_02615_amd.build`")
 _lib = ctypes.CDLL(LIB_PATH)
