@@ -24,6 +24,9 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3
+ROOT = os.path.dirname(os.path.abspath(__file__))
+COUNTERS = os.path.join(ROOT, "profiles", "ns_stage_kernel_hbm_counters.json")
 METRIC = "RHS node-updates/s & % HBM peak, FP32 vs FP64 at stated rel-L2; stencils/s"
 
 
@@ -38,12 +41,32 @@ def field_bytes_per_node_stage(tableau, fb, F=4, E=1):
     return v * (2 + 3 + 3) / 3.0
 
 
-def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup):
+def measured_traffic(bytes_per_launch):
+    """HBM bytes per launch of the FP32 stage kernel from the committed
+    counter passes, if the kernel sources still hash as when counted."""
+    import hashlib
+    try:
+        d = json.load(open(COUNTERS))
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in d["sources"])
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != d["source_sha256"]:
+        return None
+    if abs(d["algorithmic_bytes_per_launch"] - bytes_per_launch) > 1.0:
+        return None
+    return d["traffic_bytes_per_launch"] / 1e9          # GB per launch, like `achieved` per second
+
+
+def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup, ensemble=1):
     import torch
     nd = cfg["nodes"]
-    model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
+    model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt, ensemble=ensemble)
     dt_t = torch.float64 if fdt == R.F64 else torch.float32
-    state = P.to_dev(cfg["state0"], dt_t).reshape(model.state_shape()).contiguous()
+    s0 = np.repeat(cfg["state0"][:, None, :], ensemble, axis=1)
+    if ensemble > 1:   # members differ in the bubble amplitude, U[-17, -13] K
+        from workloads.fields import ensemble_amplitudes
+        s0 = s0 * (ensemble_amplitudes(ensemble) / -15.0)[None, :, None]
+    state = P.to_dev(s0, dt_t).reshape(model.state_shape()).contiguous()
     t = R.rbffd_step(ctx, model, state, 0.0, cfg["dt"], warmup, R.RK4)
     # timed region: K steps with events around every fused RHS launch
     model.profile(True)
@@ -66,16 +89,22 @@ def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup):
     torch.cuda.synchronize()
     graph_s = time.perf_counter() - g0
     fb = 8 if fdt == R.F64 else 4
-    per_node = model.bytes_per_node() + field_bytes_per_node_stage("rk4", fb)
+    per_node = model.bytes_per_node() + field_bytes_per_node_stage("rk4", fb, E=ensemble)
     bytes_launch = per_node * nd.n_active
     k_avg_s = k_ms / launches / 1e3
-    updates = nd.n_active * 4 * steps
+    updates = nd.n_active * ensemble * 4 * steps
     res = dict(node_updates_per_s=updates / (total_ms / 1e3), ms_per_step=total_ms / steps,
                wall_s=wall, graph_ms_per_step=graph_s * 1e3 / steps,
                kernel_avg_ms=k_ms / launches, kernel_launches=launches,
                bytes_per_node=per_node, bytes_per_launch=bytes_launch,
                kernel_gbs=bytes_launch / k_avg_s / 1e9,
                finite=bool(torch.isfinite(state).all().item()))
+    if ensemble > 1:
+        # 37 slots x (4 differences + 11 FP32 + 4 FP64 multiply-adds) + ~60 epilogue flops per
+        # member-node, counted as 2 per multiply-add
+        flops = nd.n_active * ensemble * (37 * (4 + 2 * 15) + 60)
+        res["kernel_tflops"] = flops / k_avg_s / 1e12
+        res["valu_frac_fp32_peak"] = res["kernel_tflops"] / FP32_VALU_PEAK_TFLOPS
     del model
     return res
 
@@ -194,9 +223,14 @@ def main():
                 continue
             extras[name] = run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, f2, w2, args.steps, args.warmup)
             log(f"[bench] {name}: {extras[name]}")
+        extras["ensemble64_fp32"] = run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, R.F32, R.F32,
+                                                max(args.steps // 10, 5), 2, ensemble=64)
+        log(f"[bench] ensemble 64: {extras['ensemble64_fp32']}")
         wcfg = weights_config(1024)
         extras["weights_mixed_1M_fp64"] = weights_leg(R, ctx, wcfg, R.SOLVE_FP64)
         log(f"[bench] weights fp64: {extras['weights_mixed_1M_fp64']}")
+        extras["weights_mixed_1M_fp32_ir"] = weights_leg(R, ctx, wcfg, R.SOLVE_FP32_IR)
+        log(f"[bench] weights fp32+IR: {extras['weights_mixed_1M_fp32_ir']}")
     extras["weights_scale_setup"] = dict(stencils=n_stencils, seconds=setup_s,
                                          stencils_per_s=n_stencils / setup_s,
                                          note="search + FP64 weights incl. host sync, 4+2 operators")
@@ -225,7 +259,9 @@ def main():
                                f"r^7 + degree-4 polynomials, n=37, RK4 dt=1/16 s, E=1",
                    "stages_per_step": 4, "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(k["bytes_per_launch"]) if args.precision == "fp32" else None,
+                     "traffic_unit": "GB per launch (HBM counters, calibrated)",
                      "kernel": "ns_stage_kernel", "bytes_per_launch": k["bytes_per_launch"],
                      "kernel_avg_ms": k["kernel_avg_ms"]},
         "cpu_baseline": cpu,

@@ -32,7 +32,10 @@
 
 namespace {
 
-constexpr int W_THREADS = 256;
+#ifndef RBFFD_W_THREADS
+#define RBFFD_W_THREADS 256
+#endif
+constexpr int W_THREADS = RBFFD_W_THREADS;
 constexpr int MAX_OPS = 8;
 
 struct WOp {
@@ -283,6 +286,7 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
   double *zl = xl + 128;                   // [128] low parts of the double-double z offsets
   __shared__ double s_red[4];
   __shared__ int s_piv[128];
+  __shared__ int s_gl[MAX_OPS], s_kg[MAX_OPS];  // operators of the current group, their k
   __shared__ int s_flag, s_pivrow;
   __shared__ double s_pmin, s_amax;
   T *A = reinterpret_cast<T *>(zl + 128);  // [kc + 8 columns][kc], column-major
@@ -369,25 +373,28 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
     int first = 0;
     while (done & (1u << first)) ++first;
     const int mg = a.ops[first].order ? a.ops[first].order : m;
-    int gl[MAX_OPS], ng = 0;
+    int ng = 0;
+    bool group_bad = false;
     for (int o = 0; o < a.n_ops; ++o) {
       int mo = a.ops[o].order ? a.ops[o].order : m;
       if (!(done & (1u << o)) && mo == mg) {
-        gl[ng++] = o;
+        const WOp &op = a.ops[o];
+        const int ke = (op.kind == RBFFD_HYPERLAP && op.k == 0) ? (mg - 1) / 2 : op.k;
+        if (op.kind == RBFFD_HYPERLAP && mg < 2 * ke + 1) group_bad = true;
+        if (tid == 0) {
+          s_gl[ng] = o;
+          s_kg[ng] = ke;
+        }
+        ++ng;
         done |= 1u << o;
       }
     }
-    int kg[MAX_OPS];
-    bool group_bad = false;
-    for (int g = 0; g < ng; ++g) {
-      const WOp &op = a.ops[gl[g]];
-      kg[g] = (op.kind == RBFFD_HYPERLAP && op.k == 0) ? (mg - 1) / 2 : op.k;
-      if (op.kind == RBFFD_HYPERLAP && mg < 2 * kg[g] + 1) group_bad = true;
-    }
+    __syncthreads();
     if (group_bad) {
       status = 2;
       for (int g = 0; g < ng; ++g)
-        for (int t = tid; t < a.n_max; t += W_THREADS) wrow[gl[g] * op_stride + t] = 0.0;
+        for (int t = tid; t < a.n_max; t += W_THREADS) wrow[s_gl[g] * op_stride + t] = 0.0;
+      __syncthreads();
       continue;
     }
     const int Kt = K + ng;  // columns of [A | B]
@@ -399,7 +406,7 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
     }
     for (int t = tid; t < K * ng; t += W_THREADS) {
       int i = t % K, g = t / K;
-      A[(K + g) * kc + i] = static_cast<T>(rhs_entry(i, n, mg, a.ops[gl[g]], kg[g], xi, ze));
+      A[(K + g) * kc + i] = static_cast<T>(rhs_entry(i, n, mg, a.ops[s_gl[g]], s_kg[g], xi, ze));
     }
     __syncthreads();
     if (tid < 64) {
@@ -489,24 +496,33 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
     // 5. iterative refinement with double-double residuals
     bool converged = false;
     for (int it = 0; it < a.max_iter && !converged; ++it) {
-      {  // r = b - A x in double-double: 4 lanes per row, partial sums over j
+      // r = b - A x in double-double: 4 lanes per row, partial sums over j,
+      // right-hand sides in chunks of 4 (fixed trip counts keep the
+      // accumulators in registers)
+      for (int g0 = 0; g0 < ng; g0 += 4) {
         const int part = tid & 3;
         for (int i = tid >> 2; i < K; i += W_THREADS / 4) {
-          dd acc[MAX_OPS];
-          for (int g = 0; g < ng; ++g) acc[g] = dd{0.0, 0.0};
+          dd acc[4];
+#pragma unroll
+          for (int g = 0; g < 4; ++g) acc[g] = dd{0.0, 0.0};
           for (int j = part; j < K; j += 4) {
             const dd aij = sys_entry_dd(i, j, n, mg, xi, xl, ze, zl);
-            for (int g = 0; g < ng; ++g) acc[g] = dd_add(acc[g], dd_mul_d(aij, xs[g * kc + j]));
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+              if (g0 + g < ng) acc[g] = dd_add(acc[g], dd_mul_d(aij, xs[(g0 + g) * kc + j]));
           }
-          for (int g = 0; g < ng; ++g) {
-            for (int off = 1; off < 4; off <<= 1) {
-              dd o{__shfl_xor(acc[g].hi, off, 64), __shfl_xor(acc[g].lo, off, 64)};
-              acc[g] = dd_add(acc[g], o);
-            }
-            if (part == 0) {
-              const dd b = rhs_entry_dd(i, n, mg, a.ops[gl[g]], kg[g], xi, xl, ze, zl);
-              const dd r = dd_sub(b, acc[g]);
-              rs[g * kc + i] = r.hi + r.lo;
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            if (g0 + g < ng) {
+              for (int off = 1; off < 4; off <<= 1) {
+                dd o{__shfl_xor(acc[g].hi, off, 64), __shfl_xor(acc[g].lo, off, 64)};
+                acc[g] = dd_add(acc[g], o);
+              }
+              if (part == 0) {
+                const dd b = rhs_entry_dd(i, n, mg, a.ops[s_gl[g0 + g]], s_kg[g0 + g], xi, xl, ze, zl);
+                const dd r = dd_sub(b, acc[g]);
+                rs[(g0 + g) * kc + i] = r.hi + r.lo;
+              }
             }
           }
         }
@@ -571,13 +587,13 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
     finite = isfinite(s_red[2]);
     if (!(s_pmin >= 1e-13 * s_amax) || !converged || !finite) status = status ? status : 1;
     for (int g = 0; g < ng; ++g) {
-      const WOp &op = a.ops[gl[g]];
+      const WOp &op = a.ops[s_gl[g]];
       const int qd = (op.kind == RBFFD_DX || op.kind == RBFFD_DZ) ? 1
-                     : (op.kind == RBFFD_HYPERLAP)                ? 2 * kg[g]
+                     : (op.kind == RBFFD_HYPERLAP)                ? 2 * s_kg[g]
                                                                   : 2;
       const double scale = 1.0 / ipow(rho, qd);
       for (int t = tid; t < a.n_max; t += W_THREADS)
-        wrow[gl[g] * op_stride + t] = (t < n && finite) ? xs[g * kc + t] * scale : 0.0;
+        wrow[s_gl[g] * op_stride + t] = (t < n && finite) ? xs[g * kc + t] * scale : 0.0;
     }
     __syncthreads();
   }
