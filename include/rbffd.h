@@ -160,6 +160,8 @@ typedef struct {
   double vel_period;
   /* Navier-Stokes constants (Section 6.2, 6.4) */
   double c_p, c_v, R_d, g, theta_bar, mu;
+  double u_bar;           /* uniform background wind added to u in the advective terms
+                             (translating density current, Section 6.4.2); 0 otherwise */
   /* ghost closure (Section 5.2), Navier-Stokes only */
   int32_t n_walls;        /* 0 or 2 (bottom, top)                                        */
   int32_t n_wall;         /* boundary nodes per wall = ghost nodes per wall              */

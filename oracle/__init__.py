@@ -26,4 +26,4 @@ from .weights import (
 )
 from .rhs import apply_dm, dm_matrix, advection_rhs, AdvectionModel, ghost_matrices, ghost_closure, ns_rhs, ns_tendency, NSModel
 from .timestep import rk4_step, wsrk3_step, integrate
-from .diagnostics import rel_l2, front_location, extrema
+from .diagnostics import rel_l2, front_location, extrema, translating_fronts

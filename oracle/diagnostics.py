@@ -40,3 +40,22 @@ def front_location(xy, theta, bottom_nodes, level=-0.5) -> float:
     # linear interpolation of the crossing between node i and node i+1
     f = (level - th[i]) / (th[i + 1] - th[i])
     return float(x[i] + f * (x[i + 1] - x[i]))
+
+
+def translating_fronts(xy, theta, bottom_nodes, center=18000.0, level=-0.5):
+    """Table tbl:translating: distances from x = center to the -0.5 K contour
+    on the ground on either side (the fronts face each other across the
+    centre). Left front: largest x < center with theta' <= level, right
+    front: smallest x > center with theta' <= level, each interpolated
+    linearly towards the centre."""
+    x = xy[bottom_nodes, 0]
+    th = theta[bottom_nodes]
+    order = np.argsort(x)
+    x, th = x[order], th[order]
+    cold = th <= level
+    left = np.nonzero(cold & (x < center))[0]
+    right = np.nonzero(cold & (x > center))[0]
+    i, j = left[-1], right[0]
+    xl = x[i] + (level - th[i]) / (th[i + 1] - th[i]) * (x[i + 1] - x[i])
+    xr = x[j] - (level - th[j]) / (th[j - 1] - th[j]) * (x[j] - x[j - 1])
+    return float(center - xl), float(xr - center)

@@ -16,6 +16,8 @@ closure and the PDE right-hand sides.
   ghost solves are then independent.
 * ``ns_rhs``: Eqs. uEq, wEq, thetaEq, piEq with mu * Lap on u, w, theta' and
   hv_coeff * Lap^k on all four fields; dw/dt = 0 on the walls (w_B stays 0).
+  A uniform background wind u_bar (consts["u_bar"], the translating density
+  current of Section 6.4) is added to u in the advective terms.
 """
 
 from dataclasses import dataclass
@@ -139,17 +141,18 @@ def ns_tendency(s, rows, idx, w_dx, w_dz, w_lap, w_hv, z, is_wall, consts, hv_co
     (ghost rows filled), given those rows' stencils and weights."""
     c = consts
     u, w, th, pi = (s[rows, f] for f in range(4))
+    ua = u + c.get("u_bar", 0.0)     # background wind (translating density current)
     D = lambda W: apply_dm(idx, W, s)                    # noqa: E731  [rows][4]
     dx, dz, lap, hv = D(w_dx), D(w_dz), D(w_lap), D(w_hv)
     pibar = 1.0 - c["g"] * z / (c["c_p"] * c["theta_bar"])
     dpibar = -c["g"] / (c["c_p"] * c["theta_bar"])
     out = np.zeros((len(rows), 4))
     cp_th = c["c_p"] * (c["theta_bar"] + th)
-    out[:, 0] = -u * dx[:, 0] - w * dz[:, 0] - cp_th * dx[:, 3] + c["mu"] * lap[:, 0]
-    out[:, 1] = -u * dx[:, 1] - w * dz[:, 1] - cp_th * dz[:, 3] \
+    out[:, 0] = -ua * dx[:, 0] - w * dz[:, 0] - cp_th * dx[:, 3] + c["mu"] * lap[:, 0]
+    out[:, 1] = -ua * dx[:, 1] - w * dz[:, 1] - cp_th * dz[:, 3] \
         + c["g"] * th / c["theta_bar"] + c["mu"] * lap[:, 1]
-    out[:, 2] = -u * dx[:, 2] - w * dz[:, 2] + c["mu"] * lap[:, 2]
-    out[:, 3] = -u * dx[:, 3] - w * (dpibar + dz[:, 3]) \
+    out[:, 2] = -ua * dx[:, 2] - w * dz[:, 2] + c["mu"] * lap[:, 2]
+    out[:, 3] = -ua * dx[:, 3] - w * (dpibar + dz[:, 3]) \
         - (c["R_d"] / c["c_v"]) * (pibar + pi) * (dx[:, 0] + dz[:, 1])
     out += hv_coeff * hv
     out[is_wall, 1] = 0.0

@@ -251,6 +251,7 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
   m->g = d->g;
   m->theta_bar = d->theta_bar;
   m->mu = d->mu;
+  m->u_bar = d->u_bar;
   const int64_t na = m->Na, n = m->n, cnt = na * n;
 
   // stencil indices must address existing nodes

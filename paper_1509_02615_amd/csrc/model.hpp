@@ -32,7 +32,7 @@ struct rbffd_model {
   DevBuf kind;      // uint8 [N]: 0 interior, 1 wall, 2 ghost
   DevBuf pibar;     // double [Na]
   double hv_coeff = 0.0, vel_period = 1.0;
-  double c_p = 0, c_v = 0, R_d = 0, g = 0, theta_bar = 0, mu = 0;
+  double c_p = 0, c_v = 0, R_d = 0, g = 0, theta_bar = 0, mu = 0, u_bar = 0;
   // ghost closure
   int n_walls = 0, nb = 0, band = 0;
   DevBuf wall_nodes, ghost_nodes;  // int32 [n_walls][nb]

@@ -125,7 +125,7 @@ struct NSArgs {
   const double *pibar;
   int64_t Na;
   int n, E;
-  double c_p, rcv, g, theta_bar, mu, hv, dpibar;
+  double c_p, rcv, g, theta_bar, mu, hv, dpibar, u_bar;
   double ca, cb;
   int mode;      // 0: out = f; 1: out = yn + ca f; 2: out = acc + ca f
   int acc_mode;  // 0: none; 1: acc = yn + cb f; 2: acc += cb f
@@ -186,14 +186,16 @@ __global__ __launch_bounds__(StageShape<WDT>::block) void ns_stage_kernel(NSArgs
       shv[c] = fma(whv, static_cast<double>(d), shv[c]);
     }
   }
-  // Eqs. uEq..piEq (perturbation form), evaluated in FP64
+  // Eqs. uEq..piEq (perturbation form), evaluated in FP64; a uniform
+  // background wind u_bar joins u in the advective terms
   const double u = own.v[0], w = own.v[1], th = own.v[2], pi = own.v[3];
+  const double ua = u + a.u_bar;
   const double cp_th = a.c_p * (a.theta_bar + th);
   double f[4];
-  f[0] = -u * sdx[0] - w * sdz[0] - cp_th * sdx[3] + a.mu * slp[0] + a.hv * shv[0];
-  f[1] = -u * sdx[1] - w * sdz[1] - cp_th * sdz[3] + a.g * th / a.theta_bar + a.mu * slp[1] + a.hv * shv[1];
-  f[2] = -u * sdx[2] - w * sdz[2] + a.mu * slp[2] + a.hv * shv[2];
-  f[3] = -u * sdx[3] - w * (a.dpibar + static_cast<double>(sdz[3])) -
+  f[0] = -ua * sdx[0] - w * sdz[0] - cp_th * sdx[3] + a.mu * slp[0] + a.hv * shv[0];
+  f[1] = -ua * sdx[1] - w * sdz[1] - cp_th * sdz[3] + a.g * th / a.theta_bar + a.mu * slp[1] + a.hv * shv[1];
+  f[2] = -ua * sdx[2] - w * sdz[2] + a.mu * slp[2] + a.hv * shv[2];
+  f[3] = -ua * sdx[3] - w * (a.dpibar + static_cast<double>(sdz[3])) -
          a.rcv * (a.pibar[i] + pi) * (static_cast<double>(sdx[0]) + static_cast<double>(sdz[1])) + a.hv * shv[3];
   if (a.kind[i] == 1) f[1] = 0.0;  // w stays 0 on the walls
   const int64_t o = (i * E + e) * 4;
@@ -442,6 +444,7 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.mu = m->mu;
     a.hv = m->hv_coeff;
     a.dpibar = -m->g / (m->c_p * m->theta_bar);
+    a.u_bar = m->u_bar;
     a.ca = sp.ca;
     a.cb = sp.cb;
     a.mode = sp.mode;

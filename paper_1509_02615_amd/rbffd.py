@@ -45,7 +45,7 @@ class ModelDesc(ctypes.Structure):
                 ("idx", _vp), ("w", _vp), ("xy", _vp), ("hv_coeff", _f64),
                 ("vel_u", _vp), ("vel_v", _vp), ("vel_period", _f64),
                 ("c_p", _f64), ("c_v", _f64), ("R_d", _f64), ("g", _f64), ("theta_bar", _f64),
-                ("mu", _f64), ("n_walls", _i32), ("n_wall", _i32), ("wall_nodes", _vp),
+                ("mu", _f64), ("u_bar", _f64), ("n_walls", _i32), ("n_wall", _i32), ("wall_nodes", _vp),
                 ("ghost_nodes", _vp), ("wall_dz", _vp), ("wall_dzz", _vp)]
 
 
@@ -190,7 +190,8 @@ class Model:
                       vel_u=_ptr(vel_u, torch.float64, (N,), "vel_u"),
                       vel_v=_ptr(vel_v, torch.float64, (N,), "vel_v"), vel_period=float(vel_period),
                       c_p=c.get("c_p", 0.0), c_v=c.get("c_v", 0.0), R_d=c.get("R_d", 0.0),
-                      g=c.get("g", 0.0), theta_bar=c.get("theta_bar", 0.0), mu=c.get("mu", 0.0))
+                      g=c.get("g", 0.0), theta_bar=c.get("theta_bar", 0.0), mu=c.get("mu", 0.0),
+                      u_bar=c.get("u_bar", 0.0))
         if wall_nodes is not None:
             nw, nb = wall_nodes.shape
             d.n_walls, d.n_wall = nw, nb

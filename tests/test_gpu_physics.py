@@ -56,3 +56,33 @@ def test_density_current_100m_against_table(layout, fdt):
     for g, r in zip(got[:4], ref[:4]):
         assert abs(g - r) <= 0.05 * abs(r) + 0.15, (got, ref)
     assert abs(front - ref[4]) <= 0.015 * ref[4], (front, ref[4])
+
+
+def translating_row(layout, h):
+    with open(os.path.join(GOLDEN, "translating_table.csv")) as f:
+        rows = [r for r in csv.reader(f) if r and not r[0].startswith("#")][1:]
+    return {(r[0], float(r[1])): [float(v) for v in r[2:]] for r in rows}[layout, h]
+
+
+@pytest.mark.parametrize("layout", ["hexagonal", "cartesian"])
+def test_translating_density_current_100m_against_table(layout):
+    import torch
+    from paper_1509_02615_amd import rbffd as R
+    from paper_1509_02615_amd import pipeline as P
+    from workloads import translating_config
+    print(f"translating density current: {layout} 100 m, u_bar = 20 m/s, RK4 3600 steps", flush=True)
+    ctx = R.Context(0)
+    cfg = translating_config(layout, 100.0)
+    nd = cfg["nodes"]
+    xy, idx, W, Ww, (sa, sw) = P.ns_weights(ctx, cfg)
+    model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy)
+    s = P.to_dev(cfg["state0"], torch.float64).reshape(model.state_shape()).contiguous()
+    t = 0.0
+    for _ in range(6):
+        t = R.rbffd_step(ctx, model, s, t, cfg["dt"], 600, R.RK4)
+    R.rbffd_ghost(ctx, model, s)
+    y = s.cpu().numpy().reshape(-1, 4)
+    left, right = O.translating_fronts(nd.xy, y[:, 2], nd.wall_nodes[0])
+    ref = translating_row(layout, 100.0)
+    print(f"   layout {layout}: fronts (left, right) from 18 km {left:.0f} {right:.0f} table {ref}", flush=True)
+    assert abs(left - ref[0]) <= 0.03 * ref[0] and abs(right - ref[1]) <= 0.03 * ref[1]

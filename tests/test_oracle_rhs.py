@@ -163,3 +163,32 @@ def test_density_current_400m_against_table():
     for g, r in zip(got, ref[:4]):
         assert abs(g - r) <= 0.1 * abs(r) + 0.1, (got, ref)
     assert abs(front - ref[4]) <= 0.03 * ref[4]
+
+
+def test_background_wind_term_closed_form():
+    """Translating density current (Section 6.4): with theta' = A sin(k x)
+    only, the theta' tendency away from the walls is -u_bar A k cos(k x) -
+    mu A k^2 sin(k x) (hyperviscosity off), to the stencil accuracy."""
+    from workloads import translating_config
+    cfg = translating_config("hexagonal", 400.0)
+    cfg["hv_coeff"] = 0.0
+    nd = cfg["nodes"]
+    model, *_ = build_ns(cfg)
+    k = 2 * np.pi / nd.period_x * 3
+    A = 2.0
+    st = np.zeros((nd.n_total, 4))
+    st[:, 2] = A * np.sin(k * nd.xy[:, 0])
+    out, _ = O.ns_rhs(model, st)
+    x = nd.xy[:nd.n_active, 0]
+    exact = -20.0 * A * k * np.cos(k * x) - cfg["consts"]["mu"] * A * k * k * np.sin(k * x)
+    rows = np.arange(nd.n_active) // nd.nx
+    inner = (rows >= 4) & (rows <= nd.nz - 5)
+    err = np.abs(out[:nd.n_active, 2][inner] - exact[inner]).max() / np.abs(exact).max()
+    assert err < 1e-4, err          # truncation at k h ~ 0.2; a wrong wind term is O(1)
+
+
+def test_translating_fronts_interpolate():
+    xy = np.array([[x, 0.0] for x in (16000.0, 17000.0, 18000.0, 19000.0, 20000.0)])
+    th = np.array([-2.0, 0.0, 0.0, 0.0, -1.0])
+    left, right = O.translating_fronts(xy, th, np.arange(5))
+    assert left == pytest.approx(18000.0 - 16750.0) and right == pytest.approx(19500.0 - 18000.0)

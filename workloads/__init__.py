@@ -12,5 +12,5 @@ from .fields import (
     ensemble_amplitudes,
 )
 from .configs import (
-    advection_config, density_current_config, weights_config, scale_config,
+    advection_config, density_current_config, weights_config, scale_config, translating_config,
 )

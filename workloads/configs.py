@@ -53,6 +53,21 @@ def density_current_config(layout: str = "hexagonal", h: float = 100.0, seed: in
     return _ns_config(nodes, f"density-current-{layout}-{int(h)}m", dt, tableau)
 
 
+def translating_config(layout: str = "hexagonal", h: float = 100.0, seed: int = 0, tableau: str = "rk4"):
+    """Translating density current (Section 6.4): as the density current but
+    on [0, 36] x [0, 6.4] km with a background wind u_bar = 20 m/s and the
+    bubble centred at x = 18 km, so that at 900 s the two fronts face each
+    other across x = 18 km."""
+    length, height = 36000.0, 6400.0
+    nx = int(round(length / h))
+    nz = int(round(height / h)) + 1 if layout == "cartesian" else int(round(height / (h * np.sqrt(3.0) / 2.0))) + 1
+    nodes = channel(layout, nx, nz, 0.0, length, height, seed=seed)
+    cfg = _ns_config(nodes, f"translating-density-current-{layout}-{int(h)}m", DT_TABLE[float(h)], tableau)
+    cfg["consts"]["u_bar"] = 20.0
+    cfg["state0"] = straka_state(nodes, c=cfg["consts"], center=(18000.0, 3000.0))
+    return cfg
+
+
 def scale_config(nx: int = 2048, nz: int = 256, tableau: str = "rk4"):
     """Density current on a 2048 x 256 hexagonal-row channel at 25 m column
     spacing (rows at 6400/255 m), 524,288 active nodes plus 2 x 2048 ghosts."""

@@ -45,11 +45,12 @@ def straka_theta(xy: np.ndarray, amplitude: float = -15.0, center=(0.0, 3000.0),
     return T / pi_bar(z, c)
 
 
-def straka_state(nodes, amplitude: float = -15.0, c=NS_CONSTANTS, dtype=np.float64) -> np.ndarray:
+def straka_state(nodes, amplitude: float = -15.0, c=NS_CONSTANTS, dtype=np.float64,
+                 center=(0.0, 3000.0)) -> np.ndarray:
     """Initial density-current state [n_total][4] = (u, w, theta', pi'); all
     zero except theta'. Ghost rows are filled by the closure before use."""
     s = np.zeros((nodes.n_total, 4), dtype=np.float64)
-    s[:, 2] = straka_theta(nodes.xy, amplitude=amplitude, c=c)
+    s[:, 2] = straka_theta(nodes.xy, amplitude=amplitude, c=c, center=center)
     s[nodes.n_active:] = 0.0
     return s.astype(dtype)
 
