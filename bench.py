@@ -67,6 +67,7 @@ def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup, ensembl
         from workloads.fields import ensemble_amplitudes
         s0 = s0 * (ensemble_amplitudes(ensemble) / -15.0)[None, :, None]
     state = P.to_dev(s0, dt_t).reshape(model.state_shape()).contiguous()
+    shape, tune_us = R.rbffd_model_tune(ctx, model, state)
     t = R.rbffd_step(ctx, model, state, 0.0, cfg["dt"], warmup, R.RK4)
     # timed region: K steps with events around every fused RHS launch
     model.profile(True)
@@ -98,7 +99,7 @@ def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup, ensembl
                kernel_avg_ms=k_ms / launches, kernel_launches=launches,
                bytes_per_node=per_node, bytes_per_launch=bytes_launch,
                kernel_gbs=bytes_launch / k_avg_s / 1e9,
-               finite=bool(torch.isfinite(state).all().item()))
+               finite=bool(torch.isfinite(state).all().item()), tuned_shape=shape, tune_us=tune_us)
     if ensemble > 1:
         # 37 slots x (4 differences + 11 FP32 + 4 FP64 multiply-adds) + ~60 epilogue flops per
         # member-node, counted as 2 per multiply-add

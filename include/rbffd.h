@@ -216,6 +216,14 @@ int64_t rbffd_model_bytes_per_node(rbffd_model *model);
 int rbffd_model_profile(rbffd_model *model, int enable);
 int rbffd_model_profile_read(rbffd_model *model, double *total_ms, int64_t *launches);
 
+/* Autotuning of the fused right-hand-side kernel: run the closure on `state`
+ * (its ghost entries are overwritten), time every compiled launch shape of
+ * the kernel (block size, slot unrolling, cached or non-temporal weight
+ * loads) on a few evaluations of this model's data, and keep the fastest
+ * for all later calls. Returns the shape index and its time per launch (us).
+ * Synchronises. Transport models keep their single shape (chosen = -1). */
+int rbffd_model_tune(rbffd_ctx *ctx, rbffd_model *model, void *state, int *chosen, double *best_us);
+
 /* Measurement helper: copy `bytes` (a multiple of 16, 16-byte aligned
  * pointers) from src to dst with a plain streaming kernel, so that hardware
  * memory counters can be calibrated against a kernel of known traffic. */

@@ -178,6 +178,13 @@ int rbffd_model_profile_read(rbffd_model *model, double *total_ms, int64_t *laun
   return model_profile_read(model, total_ms, launches);
 }
 
+int rbffd_model_tune(rbffd_ctx *ctx, rbffd_model *model, void *state, int *chosen, double *best_us) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!model || !state || !chosen || !best_us) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return model_tune(ctx, model, state, chosen, best_us);
+}
+
 int rbffd_stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes) {
   if (!ctx) return RBFFD_EINVAL;
   if (!dst || !src || bytes < 0 || bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 ||

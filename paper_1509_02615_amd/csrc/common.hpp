@@ -69,6 +69,7 @@ int64_t model_bytes_per_node(rbffd_model *m);
 int model_profile(rbffd_model *m, int enable);
 int model_profile_read(rbffd_model *m, double *total_ms, int64_t *launches);
 int stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes);
+int model_tune(rbffd_ctx *ctx, rbffd_model *m, void *state, int *chosen, double *best_us);
 
 // Launch geometry helper: grid of blocks covering n items.
 inline unsigned grid_for(int64_t n, int block) {

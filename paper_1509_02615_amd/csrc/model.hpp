@@ -50,6 +50,7 @@ struct rbffd_model {
   double graph_dt = 0.0;
   int graph_tableau = -1;
   int64_t bytes_per_node = 0;
+  int shape = -1;  // stage-kernel launch shape (-1: the precision's default)
   // kernel timing (measurement only)
   int profile = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;

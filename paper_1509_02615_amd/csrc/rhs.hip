@@ -31,19 +31,23 @@ namespace {
 
 constexpr int RHS_BLOCK = 256;  // closure and transport kernels
 
-// Launch shape of the Navier-Stokes stage kernel per weight precision,
-// chosen by measurement on the 524,288-node channel: FP32 and BF16 records
-// go best with no slot unrolling and non-temporal loads of the weight stream
-// (each launch reads it exactly once, so keeping it out of the caches leaves
-// them to the neighbour gathers); FP64 with 2-slot unrolling, ordinary loads
-// and 512-thread blocks.
-template <int WDT> struct StageShape {
-  static constexpr int block = 256, unroll = 1;
-  static constexpr bool nt = true;
+// Launch shapes of the Navier-Stokes stage kernel: block size, slot
+// unrolling and whether the weight stream is loaded non-temporally (each
+// launch reads it exactly once; keeping it out of the caches leaves them to
+// the neighbour gathers). rbffd_model_tune times them on the model's data.
+// Defaults, measured on the 524,288-node channel: shape 0 for FP32 and BF16
+// records, shape 2 for FP64.
+struct Shape {
+  int block, unroll;
+  bool nt;
 };
-template <> struct StageShape<RBFFD_F64> {
-  static constexpr int block = 512, unroll = 2;
-  static constexpr bool nt = false;
+constexpr Shape kShapes[] = {{256, 1, true}, {256, 2, false}, {512, 2, false},
+                             {128, 1, true}, {512, 1, true},  {256, 4, true}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+inline int default_shape(int wdt) { return wdt == RBFFD_F64 ? 2 : 0; }
+template <int S> struct StageShape {
+  static constexpr int block = kShapes[S].block, unroll = kShapes[S].unroll;
+  static constexpr bool nt = kShapes[S].nt;
 };
 
 typedef float nat_f4 __attribute__((ext_vector_type(4)));
@@ -133,13 +137,20 @@ struct NSArgs {
   int check;     // record the step of the first non-finite output
 };
 
-template <class FT, int WDT>
-__global__ __launch_bounds__(StageShape<WDT>::block) void ns_stage_kernel(NSArgs a) {
-  using SH = StageShape<WDT>;
+// MW ("member wavefront"): the ensemble size is a multiple of 64, so a
+// wavefront holds 64 members of one node; the node index is then
+// wave-uniform and the weight records are fetched once per wavefront through
+// the scalar cache and broadcast (the gathers stay vector loads, 64
+// consecutive members = one contiguous 1 KiB span in FP32).
+template <class FT, int WDT, int S, bool MW = false>
+__global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a) {
+  using SH = StageShape<S>;
+  constexpr bool NT = SH::nt && !MW;
   const int64_t t = xcd_thread<SH::block>();
   if (t >= a.Na * a.E) return;
   const int E = a.E;
-  const int64_t i = E == 1 ? t : t / E;
+  int64_t i = E == 1 ? t : t / E;
+  if constexpr (MW) i = __builtin_amdgcn_readfirstlane(static_cast<int>(i));
   const int e = static_cast<int>(t - i * E);
   const FT *ys = static_cast<const FT *>(a.ys);
   const F4<FT> own = load4(ys + (i * E + e) * 4);
@@ -154,27 +165,27 @@ __global__ __launch_bounds__(StageShape<WDT>::block) void ns_stage_kernel(NSArgs
     FT wdx, wdz, wlp;
     double whv;
     if constexpr (WDT == RBFFD_F64) {
-      const double2 r0 = stream_load2<SH::nt>(reinterpret_cast<const double2 *>(a.rec) + 2 * s);
-      const double2 r1 = stream_load2<SH::nt>(reinterpret_cast<const double2 *>(a.rec) + 2 * s + 1);
-      j = stream_load<SH::nt>(a.idx_t + s);
+      const double2 r0 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s);
+      const double2 r1 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s + 1);
+      j = stream_load<NT>(a.idx_t + s);
       wdx = r0.x;
       wdz = r0.y;
       wlp = r1.x;
       whv = r1.y;
     } else if constexpr (WDT == RBFFD_F32) {
-      const float4 r = stream_load4<SH::nt>(reinterpret_cast<const float4 *>(a.rec) + s);
+      const float4 r = stream_load4<NT>(reinterpret_cast<const float4 *>(a.rec) + s);
       j = __float_as_int(r.w);
       wdx = r.x;
       wdz = r.y;
       wlp = r.z;
-      whv = stream_load<SH::nt>(a.hv_t + s);
+      whv = stream_load<NT>(a.hv_t + s);
     } else {
-      const uint3 r = stream_load3<SH::nt>(reinterpret_cast<const uint3 *>(a.rec) + s);
+      const uint3 r = stream_load3<NT>(reinterpret_cast<const uint3 *>(a.rec) + s);
       j = static_cast<int>(r.z);
       wdx = __uint_as_float(r.x << 16);
       wdz = __uint_as_float(r.x & 0xffff0000u);
       wlp = __uint_as_float(r.y << 16);
-      whv = stream_load<SH::nt>(a.hv_t + s);
+      whv = stream_load<NT>(a.hv_t + s);
     }
     const F4<FT> f = load4(ys + (static_cast<int64_t>(j) * E + e) * 4);
 #pragma unroll
@@ -406,6 +417,27 @@ int launch_ghost(rbffd_ctx *ctx, rbffd_model *m, void *y) {
   return RBFFD_OK;
 }
 
+template <class FT, int WDT, int S>
+void launch_ns_one(int64_t cnt, hipStream_t st, const NSArgs &a) {
+  constexpr int B = StageShape<S>::block;
+  if (a.E % 64 == 0)
+    ns_stage_kernel<FT, WDT, S, true><<<grid_for(cnt, B), B, 0, st>>>(a);
+  else
+    ns_stage_kernel<FT, WDT, S, false><<<grid_for(cnt, B), B, 0, st>>>(a);
+}
+
+template <class FT, int WDT>
+void launch_ns_shape(int shape, int64_t cnt, hipStream_t st, const NSArgs &a) {
+  switch (shape) {
+    case 0: launch_ns_one<FT, WDT, 0>(cnt, st, a); break;
+    case 1: launch_ns_one<FT, WDT, 1>(cnt, st, a); break;
+    case 2: launch_ns_one<FT, WDT, 2>(cnt, st, a); break;
+    case 3: launch_ns_one<FT, WDT, 3>(cnt, st, a); break;
+    case 4: launch_ns_one<FT, WDT, 4>(cnt, st, a); break;
+    default: launch_ns_one<FT, WDT, 5>(cnt, st, a); break;
+  }
+}
+
 struct StageSpec {
   const void *ys, *yn;
   void *out;
@@ -451,16 +483,13 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.acc_mode = sp.acc_mode;
     a.misc = misc;
     a.check = sp.check;
-    if (m->fdt == RBFFD_F64) {
-      constexpr int B = StageShape<RBFFD_F64>::block;
-      ns_stage_kernel<double, RBFFD_F64><<<grid_for(cnt, B), B, 0, ctx->stream>>>(a);
-    } else if (m->wdt == RBFFD_F32) {
-      constexpr int B = StageShape<RBFFD_F32>::block;
-      ns_stage_kernel<float, RBFFD_F32><<<grid_for(cnt, B), B, 0, ctx->stream>>>(a);
-    } else {
-      constexpr int B = StageShape<RBFFD_BF16>::block;
-      ns_stage_kernel<float, RBFFD_BF16><<<grid_for(cnt, B), B, 0, ctx->stream>>>(a);
-    }
+    const int shape = m->shape >= 0 ? m->shape : default_shape(m->wdt);
+    if (m->fdt == RBFFD_F64)
+      launch_ns_shape<double, RBFFD_F64>(shape, cnt, ctx->stream, a);
+    else if (m->wdt == RBFFD_F32)
+      launch_ns_shape<float, RBFFD_F32>(shape, cnt, ctx->stream, a);
+    else
+      launch_ns_shape<float, RBFFD_BF16>(shape, cnt, ctx->stream, a);
   } else {
     AdvArgs a{};
     a.ys = sp.ys;
@@ -641,4 +670,54 @@ int stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes) {
   stream_copy_kernel<<<grid, 256, 0, ctx->stream>>>(static_cast<uint4 *>(dst), static_cast<const uint4 *>(src), n);
   RBFFD_HIP(ctx, hipGetLastError());
   return RBFFD_OK;
+}
+
+// Time every launch shape of the stage kernel on this model's data (a few
+// tendency evaluations of `state` into the model's stage buffer, HIP events
+// on the context stream) and keep the fastest.
+int model_tune(rbffd_ctx *ctx, rbffd_model *m, void *state, int *chosen, double *best_us) {
+  if (m->physics != RBFFD_PHYS_NS) {
+    *chosen = -1;
+    *best_us = 0.0;
+    return RBFFD_OK;
+  }
+  const int saved_profile = m->profile;
+  m->profile = 0;
+  hipEvent_t e0, e1;
+  RBFFD_HIP(ctx, hipEventCreate(&e0));
+  RBFFD_HIP(ctx, hipEventCreate(&e1));
+  int rc = launch_ghost(ctx, m, state);
+  double best = 1e300;
+  int best_s = default_shape(m->wdt);
+  StageSpec sp{state, state, m->ya.p, 0.0, 0.0, 0.0, 0, 0, 0};
+  for (int sh = 0; sh < kNumShapes && rc == RBFFD_OK; ++sh) {
+    m->shape = sh;
+    rc = launch_stage(ctx, m, sp, 0.0, false, 0.0);  // warm-up
+    if (rc) break;
+    RBFFD_HIP(ctx, hipEventRecord(e0, ctx->stream));
+    constexpr int reps = 5;
+    for (int r = 0; r < reps && rc == RBFFD_OK; ++r) rc = launch_stage(ctx, m, sp, 0.0, false, 0.0);
+    RBFFD_HIP(ctx, hipEventRecord(e1, ctx->stream));
+    RBFFD_HIP(ctx, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    RBFFD_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+    const double us = 1e3 * ms / reps;
+    if (us < best) {
+      best = us;
+      best_s = sh;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  m->shape = best_s;
+  m->profile = saved_profile;
+  if (m->exec) {  // a captured graph holds the old shape
+    (void)hipGraphExecDestroy(m->exec);
+    m->exec = nullptr;
+    (void)hipGraphDestroy(m->graph);
+    m->graph = nullptr;
+  }
+  *chosen = best_s;
+  *best_us = best;
+  return rc;
 }

@@ -67,11 +67,12 @@ _lib.rbffd_model_bytes_per_node.restype = _i64
 _lib.rbffd_model_profile.argtypes = [_vp, ctypes.c_int]
 _lib.rbffd_model_profile_read.argtypes = [_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
 _lib.rbffd_stream_copy.argtypes = [_vp, _vp, _vp, _i64]
+_lib.rbffd_model_tune.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_f64)]
 
 EXPORTS = ["rbffd_create", "rbffd_destroy", "rbffd_last_error", "rbffd_sync", "rbffd_knn",
            "rbffd_weights", "rbffd_model_create", "rbffd_model_destroy", "rbffd_ghost",
            "rbffd_rhs", "rbffd_step", "rbffd_model_bytes_per_node", "rbffd_model_profile",
-           "rbffd_model_profile_read", "rbffd_stream_copy"]
+           "rbffd_model_profile_read", "rbffd_stream_copy", "rbffd_model_tune"]
 
 
 class RbffdError(RuntimeError):
@@ -240,6 +241,14 @@ def rbffd_ghost(ctx: Context, model: Model, state):
 def rbffd_rhs(ctx: Context, model: Model, t, state, tendency):
     ctx.check(_lib.rbffd_rhs(ctx.h, model.h, float(t), model._state(state),
                              model._state(tendency, "tendency")))
+
+
+def rbffd_model_tune(ctx: Context, model: Model, state):
+    """Pick the fastest stage-kernel launch shape on this model's data;
+    returns (shape index, microseconds per launch)."""
+    ch, us = ctypes.c_int(), _f64()
+    ctx.check(_lib.rbffd_model_tune(ctx.h, model.h, model._state(state), ctypes.byref(ch), ctypes.byref(us)))
+    return ch.value, us.value
 
 
 def rbffd_stream_copy(ctx: Context, dst, src):

@@ -270,3 +270,27 @@ def test_full_size_scale_rhs_sampled(R, ctx):
         errs = [np.linalg.norm(got[:, f] - ref[:, f]) / np.linalg.norm(ref[:, f]) for f in range(4)]
         say(f"   field dtype {fdt}: rel-l2 per field over samples {['%.2e' % e for e in errs]}")
         assert max(errs) <= tol
+
+
+@pytest.mark.parametrize("fdt,wdt", [(0, 0), (1, 1), (1, 2)])
+def test_tuned_shape_gives_identical_results(R, ctx, fdt, wdt):
+    """rbffd_model_tune only changes the launch shape (block size, slot
+    unrolling, load caching), never a thread's arithmetic: results are
+    bit-identical before and after tuning."""
+    import torch
+    say(f"tune: hexagonal 400 m, field dtype {fdt}, weight dtype {wdt}")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", 400.0)
+    gm = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=fdt, wdt=wdt)
+    dt = torch.float64 if fdt == 0 else torch.float32
+    s = dev(smooth_ns_state(cfg["nodes"], seed=5), dt).reshape(gm.state_shape()).contiguous()
+    o1 = torch.empty_like(s)
+    R.rbffd_rhs(ctx, gm, 0.0, s, o1)
+    shape, us = R.rbffd_model_tune(ctx, gm, s)
+    say(f"   chosen shape {shape}, {us:.1f} us per launch")
+    assert 0 <= shape < 6 and us > 0
+    o2 = torch.empty_like(s)
+    R.rbffd_rhs(ctx, gm, 0.0, s, o2)
+    assert torch.equal(o1, o2)
+    s1 = s.clone()
+    R.rbffd_step(ctx, gm, s1, 0.0, cfg["dt"], 3, R.RK4)     # graph recaptured with the new shape
+    assert torch.isfinite(s1).all()
