@@ -205,13 +205,14 @@ def main():
         model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
         state = P.to_dev(cfg["state0"], torch.float64 if fdt == R.F64 else torch.float32)
         state = state.reshape(model.state_shape()).contiguous()
+        shape, _ = R.rbffd_model_tune(ctx, model, state)     # same launch shape as the timed region
         R.rbffd_step(ctx, model, state, 0.0, cfg["dt"], 2, R.RK4)
         src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             R.rbffd_stream_copy(ctx, dst, src)
         torch.cuda.synchronize()
-        log(f"[bench] pmc run done: stage kernel {model.bytes_per_node()} B/node stencil stream, "
+        log(f"[bench] pmc run done: stage kernel shape {shape}, {model.bytes_per_node()} B/node stencil stream, "
             f"copy kernel 2 x {512 << 20} bytes per launch")
         return
     main_leg = run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, args.steps, args.warmup)
