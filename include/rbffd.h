@@ -224,6 +224,59 @@ int rbffd_model_profile_read(rbffd_model *model, double *total_ms, int64_t *laun
  * Synchronises. Transport models keep their single shape (chosen = -1). */
 int rbffd_model_tune(rbffd_ctx *ctx, rbffd_model *model, void *state, int *chosen, double *best_us);
 
+/* ---- learned coarse closure (a per-node network on stencil-gathered fields) */
+
+/* A small network corrects the right-hand side of a coarse Navier-Stokes
+ * model: for node i and member e its input is the stencil-gathered state --
+ * slot 0 the node's own four fields, slots k >= 1 the differences
+ * f(j_k) - f(i), each field divided by in_scale[field] (37 x 4 = 148 values) --
+ * plus one per-node value (node_feature[i], e.g. height / domain height),
+ * zero-padded to 160. Layers: h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2),
+ * y = W3 h2 + b3, with 128 hidden units, BF16 weights and activations and
+ * FP32 accumulation on the matrix cores; the correction in physical units
+ * is y[c] * out_scale[c]. Training minimises the mean of (y - target)^2 over
+ * samples and fields with Adam on FP32 master weights.
+ * Parameter layout (FP32, contiguous): W1 [128][160], b1 [128], W2 [128][128],
+ * b2 [128], W3 [16][128] (rows 4..15 unused, kept 0), b3 [16] (4..15 unused). */
+#define RBFFD_CLOSURE_NPARAMS (128 * 160 + 128 + 128 * 128 + 128 + 16 * 128 + 16)
+
+typedef struct rbffd_closure rbffd_closure;  /* opaque, library-owned */
+
+typedef struct {
+  int64_t max_samples;          /* largest n_active * E used with this closure        */
+  const float *init_params;     /* [RBFFD_CLOSURE_NPARAMS] device, copied at creation  */
+  const double *node_feature;   /* [n_active] device, copied at creation               */
+  float in_scale[4];            /* input scale per field                               */
+  float out_scale[4];           /* output scale per field                              */
+} rbffd_closure_desc;
+
+/* Bind a closure to a Navier-Stokes model (its stencils, node count and E). */
+int rbffd_closure_create(rbffd_ctx *ctx, rbffd_model *model, const rbffd_closure_desc *desc,
+                         rbffd_closure **out);
+int rbffd_closure_destroy(rbffd_closure *cl);
+/* Device pointer to the FP32 master parameters (library-owned, layout above). */
+float *rbffd_closure_params(rbffd_closure *cl);
+/* Correction y * out_scale for every active node and member of `state`
+ * ([N][E][4] FP32, ghost rows filled): out [n_active][E][4] FP32. */
+int rbffd_closure_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, float *out);
+/* Loss and its gradient with respect to the parameters for targets
+ * [n_active][E][4] FP32 (already divided by out_scale); grad
+ * [RBFFD_CLOSURE_NPARAMS] FP32 device (overwritten); *loss on the host.
+ * Synchronises. */
+int rbffd_closure_gradient(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target,
+                           float *grad, double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the same loss; the
+ * step counter is kept inside. Synchronises to return *loss. */
+int rbffd_closure_train_step(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target,
+                             double lr, double *loss);
+/* Coarse time stepping with the correction: each of n_steps steps is one
+ * rbffd_step of the model followed by state += dt * correction(state before
+ * the step) on the active nodes. A member whose correction is not finite
+ * keeps the plain step (the fallback); *n_fallback counts such
+ * (member, step) pairs (host, may be NULL). */
+int rbffd_closure_step(rbffd_ctx *ctx, rbffd_closure *cl, void *state, double *t, double dt, int64_t n_steps,
+                       int tableau, int64_t *n_fallback);
+
 /* Measurement helper: copy `bytes` (a multiple of 16, 16-byte aligned
  * pointers) from src to dst with a plain streaming kernel, so that hardware
  * memory counters can be calibrated against a kernel of known traffic. */

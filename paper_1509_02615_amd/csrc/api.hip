@@ -185,6 +185,52 @@ int rbffd_model_tune(rbffd_ctx *ctx, rbffd_model *model, void *state, int *chose
   return model_tune(ctx, model, state, chosen, best_us);
 }
 
+int rbffd_closure_create(rbffd_ctx *ctx, rbffd_model *model, const rbffd_closure_desc *desc, rbffd_closure **out) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!model || !desc || !out) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  *out = nullptr;
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return closure_create(ctx, model, desc, out);
+}
+
+int rbffd_closure_destroy(rbffd_closure *cl) { return closure_destroy(cl); }
+
+float *rbffd_closure_params(rbffd_closure *cl) { return cl ? closure_params(cl) : nullptr; }
+
+int rbffd_closure_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, float *out) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!cl || !state || !out) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return closure_forward(ctx, cl, state, out);
+}
+
+int rbffd_closure_gradient(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target, float *grad,
+                           double *loss) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!cl || !state || !target || !grad || !loss) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return closure_gradient(ctx, cl, state, target, grad, loss);
+}
+
+int rbffd_closure_train_step(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target, double lr,
+                             double *loss) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!cl || !state || !target || !loss) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  if (!(lr > 0.0)) return rbffd_fail(ctx, RBFFD_EINVAL, "learning rate must be positive");
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return closure_train_step(ctx, cl, state, target, lr, loss);
+}
+
+int rbffd_closure_step(rbffd_ctx *ctx, rbffd_closure *cl, void *state, double *t, double dt, int64_t n_steps,
+                       int tableau, int64_t *n_fallback) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!cl || !state || !t) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  if (n_steps < 0 || !(dt > 0.0) || (tableau != RBFFD_RK4 && tableau != RBFFD_WSRK3))
+    return rbffd_fail(ctx, RBFFD_EINVAL, "bad step arguments");
+  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  return closure_step(ctx, cl, state, t, dt, n_steps, tableau, n_fallback);
+}
+
 int rbffd_stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes) {
   if (!ctx) return RBFFD_EINVAL;
   if (!dst || !src || bytes < 0 || bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 ||

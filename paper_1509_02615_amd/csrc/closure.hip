@@ -1,0 +1,485 @@
+// Learned coarse closure: a per-node network on stencil-gathered fields that
+// corrects a coarse Navier-Stokes right-hand side (trained on fine runs of
+// the same method restricted to the coarse nodes).
+//
+// Network: x (148 gathered values + 1 node value, padded to 160) ->
+// h1 = tanh(W1 x + b1) (128) -> h2 = tanh(W2 h1 + b2) (128) -> y = W3 h2 + b3
+// (4, padded to 16). BF16 weights and activations, FP32 accumulation on the
+// matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// Every product is one kernel, C = A . B^T with both operands contiguous
+// along the contraction index (samples x features, or features x samples
+// for the weight gradients), and an epilogue per use:
+//   bias + tanh -> BF16        (hidden layers)
+//   bias -> FP32               (output layer)
+//   x (1 - h^2) -> BF16        (back-propagation through tanh)
+//   atomic FP32 accumulation   (weight gradients, split over sample chunks)
+// Lane layout of the 16x16x32 instruction: lane l holds A[l%16][8(l/16)..+7],
+// B[8(l/16)..+7][l%16] (so row l%16 of B^T) and D[4(l/16)..+3][l%16].
+#include <cmath>
+#include <new>
+
+#include "model.hpp"
+
+namespace {
+
+constexpr int HID = 128, KIN = 160, NOUT = 16, NSLOT_MAX = 37;
+constexpr int OW1 = 0, OB1 = OW1 + HID * KIN, OW2 = OB1 + HID, OB2 = OW2 + HID * HID, OW3 = OB2 + HID,
+              OB3 = OW3 + NOUT * HID, NPARAM = OB3 + NOUT;
+static_assert(NPARAM == RBFFD_CLOSURE_NPARAMS, "parameter layout");
+
+typedef __attribute__((ext_vector_type(4))) float f4v;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf8v;
+
+enum { EPI_TANH = 0, EPI_BIAS = 1, EPI_DTANH = 2, EPI_ATOMIC = 3 };
+
+// C[m][n] (epilogue) = sum_k A[m][k] B[n][k]; A: M x K (lda), B: 16*NT x K
+// (ldb); K a multiple of 32 within [kbeg, kend) = blockIdx.y's chunk. Four
+// wavefronts, each 16 rows x 16*NT columns.
+template <int EPI, int NT>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const __bf16 *__restrict__ A, int lda,
+                                                      const __bf16 *__restrict__ B, int ldb, int M, int K,
+                                                      int k_chunk, const float *__restrict__ bias,
+                                                      const __bf16 *__restrict__ H, int ldh, void *C, int ldc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = blockIdx.x * 64 + wave * 16;
+  const int kbeg = blockIdx.y * k_chunk, kend = min(K, kbeg + k_chunk);
+  f4v acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+  const int row = m0 + (lane & 15), koff = 8 * (lane >> 4);
+  const bool rowok = row < M;
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+    bf8v a;
+    if (rowok) {
+      a = *reinterpret_cast<const bf8v *>(A + static_cast<int64_t>(row) * lda + k0 + koff);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = static_cast<__bf16>(0.0f);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const bf8v b = *reinterpret_cast<const bf8v *>(B + static_cast<int64_t>(16 * t + (lane & 15)) * ldb + k0 + koff);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int c = 16 * t + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = m0 + 4 * (lane >> 4) + i;
+      if (r >= M) continue;
+      const float v = acc[t][i];
+      const int64_t o = static_cast<int64_t>(r) * ldc + c;
+      if constexpr (EPI == EPI_TANH) {
+        static_cast<__bf16 *>(C)[o] = static_cast<__bf16>(tanhf(v + bias[c]));
+      } else if constexpr (EPI == EPI_BIAS) {
+        static_cast<float *>(C)[o] = v + bias[c];
+      } else if constexpr (EPI == EPI_DTANH) {
+        const float h = static_cast<float>(H[static_cast<int64_t>(r) * ldh + c]);
+        static_cast<__bf16 *>(C)[o] = static_cast<__bf16>(v * (1.0f - h * h));
+      } else {
+        atomicAdd(static_cast<float *>(C) + o, v);
+      }
+    }
+  }
+}
+
+// Input features, one thread per (sample, 4-value group): slot 0 = own
+// fields, slots 1..36 = differences, group 37 = node value + zeros, 38..39 = 0.
+__global__ void features_kernel(const float *__restrict__ y, const int *__restrict__ idx_t, int64_t Na, int n, int E,
+                                const float *__restrict__ nodef, float4 inv_scale, __bf16 *__restrict__ X) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t S = Na * E;
+  if (t >= S * 40) return;
+  const int64_t s = t / 40;
+  const int k = static_cast<int>(t - s * 40);
+  const int64_t i = s / E;
+  const int e = static_cast<int>(s - i * E);
+  float v[4] = {0.f, 0.f, 0.f, 0.f};
+  const float4 own = *reinterpret_cast<const float4 *>(y + (i * E + e) * 4);
+  if (k == 0) {
+    v[0] = own.x * inv_scale.x;
+    v[1] = own.y * inv_scale.y;
+    v[2] = own.z * inv_scale.z;
+    v[3] = own.w * inv_scale.w;
+  } else if (k < n) {
+    const int j = idx_t[static_cast<int64_t>(k) * Na + i];
+    const float4 f = *reinterpret_cast<const float4 *>(y + (static_cast<int64_t>(j) * E + e) * 4);
+    v[0] = (f.x - own.x) * inv_scale.x;
+    v[1] = (f.y - own.y) * inv_scale.y;
+    v[2] = (f.z - own.z) * inv_scale.z;
+    v[3] = (f.w - own.w) * inv_scale.w;
+  } else if (k == NSLOT_MAX) {
+    v[0] = nodef[i];
+  }
+  __bf16 *o = X + s * KIN + 4 * k;
+  for (int c = 0; c < 4; ++c) o[c] = static_cast<__bf16>(v[c]);
+}
+
+// out[c][s] = in[s][c] for s < S, 0 for S <= s < Sp; 32x32 tiles through LDS.
+template <class T>
+__global__ void transpose_kernel(const T *__restrict__ in, int ldi, int64_t S, int Cn, __bf16 *__restrict__ out,
+                                 int64_t Sp) {
+  __shared__ float tile[32][33];
+  const int64_t s0 = static_cast<int64_t>(blockIdx.x) * 32;
+  const int c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t s = s0 + r;
+    const int c = c0 + tx;
+    tile[r][tx] = (s < S && c < Cn) ? static_cast<float>(in[s * ldi + c]) : 0.0f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r;
+    const int64_t s = s0 + tx;
+    if (c < Cn && s < Sp) out[static_cast<int64_t>(c) * Sp + s] = static_cast<__bf16>(tile[tx][r]);
+  }
+}
+
+// dY = 2 (Y - T) / (4 S) for the 4 outputs (BF16, padded to 32 columns for
+// the next product; FP32 copy [S][4] for the output bias gradient) and the
+// loss sum of (Y - T)^2 / (4 S).
+__global__ void loss_kernel(const float *__restrict__ Y, const float *__restrict__ T, int64_t S,
+                            __bf16 *__restrict__ dY, float *__restrict__ dY32, double *__restrict__ loss) {
+  __shared__ double red[256];
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  double l = 0.0;
+  if (s < S) {
+    const float inv = 1.0f / static_cast<float>(4 * S);
+    for (int c = 0; c < 32; ++c) {
+      float g = 0.0f;
+      if (c < 4) {
+        const float d = Y[s * NOUT + c] - T[s * 4 + c];
+        l += static_cast<double>(d) * d;
+        g = 2.0f * d * inv;
+        dY32[s * 4 + c] = g;
+      }
+      dY[s * 32 + c] = static_cast<__bf16>(g);
+    }
+  }
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, red[0] / (4.0 * static_cast<double>(S)));
+}
+
+// grad[c] += sum_s D[s][c] over a chunk of samples (bias gradients).
+template <class T>
+__global__ void colsum_kernel(const T *__restrict__ D, int ldd, int64_t S, int Cn, int64_t chunk,
+                              float *__restrict__ grad) {
+  const int c = threadIdx.x;
+  if (c >= Cn) return;
+  const int64_t b = static_cast<int64_t>(blockIdx.x) * chunk, e = min(S, b + chunk);
+  float acc = 0.0f;
+  for (int64_t s = b; s < e; ++s) acc += static_cast<float>(D[s * ldd + c]);
+  atomicAdd(grad + c, acc);
+}
+
+// BF16 copies of the weights (and the transposed W2, W3 the backward pass uses).
+__global__ void pack_kernel(const float *__restrict__ p, __bf16 *__restrict__ w1, __bf16 *__restrict__ w2,
+                            __bf16 *__restrict__ w3, __bf16 *__restrict__ w2t, __bf16 *__restrict__ w3t) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < HID * KIN) w1[t] = static_cast<__bf16>(p[OW1 + t]);
+  if (t < HID * HID) {
+    const int r = t / HID, c = t % HID;
+    w2[t] = static_cast<__bf16>(p[OW2 + t]);
+    w2t[c * HID + r] = static_cast<__bf16>(p[OW2 + t]);
+  }
+  if (t < NOUT * HID) {
+    const int r = t / HID, c = t % HID;
+    w3[t] = static_cast<__bf16>(p[OW3 + t]);
+    w3t[c * 32 + r] = static_cast<__bf16>(p[OW3 + t]);   // columns 16..31 stay 0
+  }
+}
+
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m1,
+                            float *__restrict__ m2, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float gt = g[t];
+  const float a = b1 * m1[t] + (1.0f - b1) * gt;
+  const float v = b2 * m2[t] + (1.0f - b2) * gt * gt;
+  m1[t] = a;
+  m2[t] = v;
+  p[t] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// Per member: 1 if any correction value of that member is not finite.
+__global__ void check_kernel(const float *__restrict__ Y, int64_t Na, int E, int *__restrict__ bad) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= Na * E) return;
+  const int e = static_cast<int>(s % E);
+  for (int c = 0; c < 4; ++c)
+    if (!isfinite(Y[s * NOUT + c])) {
+      atomicOr(bad + e, 1);
+      return;
+    }
+}
+
+// y_active += dt * Y * out_scale, except for members flagged non-finite.
+__global__ void apply_kernel(float *__restrict__ y, const float *__restrict__ Y, int64_t Na, int E,
+                             const int *__restrict__ bad, float4 out_scale, float dt) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= Na * E) return;
+  const int e = static_cast<int>(s % E);
+  if (bad[e]) return;
+  float *o = y + s * 4;
+  const float *q = Y + s * NOUT;
+  o[0] += dt * q[0] * out_scale.x;
+  o[1] += dt * q[1] * out_scale.y;
+  o[2] += dt * q[2] * out_scale.z;
+  o[3] += dt * q[3] * out_scale.w;
+}
+
+__global__ void scale_out_kernel(const float *__restrict__ Y, int64_t S, float4 sc, float *__restrict__ out) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  out[s * 4 + 0] = Y[s * NOUT + 0] * sc.x;
+  out[s * 4 + 1] = Y[s * NOUT + 1] * sc.y;
+  out[s * 4 + 2] = Y[s * NOUT + 2] * sc.z;
+  out[s * 4 + 3] = Y[s * NOUT + 3] * sc.w;
+}
+
+// Stencil indices out of the model's slot-major records.
+__global__ void idx_from_rec_kernel(const RecF32 *__restrict__ r32, const RecBF16 *__restrict__ rbf, int64_t cnt,
+                                    int *__restrict__ out) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  out[t] = r32 ? r32[t].idx : rbf[t].idx;
+}
+
+__global__ void f64_to_f32_kernel(const double *__restrict__ a, int64_t n, float *__restrict__ b) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) b[t] = static_cast<float>(a[t]);
+}
+
+}  // namespace
+
+struct rbffd_closure {
+  rbffd_model *model = nullptr;
+  int64_t max_s = 0, sp_max = 0;
+  float4 inv_in{}, out_sc{};
+  DevBuf params, grad, m1, m2, nodef, idx;
+  DevBuf w1, w2, w3, w2t, w3t;                       // BF16 weights
+  DevBuf X, H1, H2, Y, dY, dY32, dH1, dH2;           // activations [S][.]
+  DevBuf XT, H1T, H2T, dH1T, dH2T, dYT;              // transposed [.][Sp]
+  DevBuf loss, bad;
+  int64_t step = 0;
+};
+
+namespace {
+
+template <int EPI, int NT>
+void gemm(hipStream_t s, const __bf16 *A, int lda, const __bf16 *B, int ldb, int M, int K, int k_chunk,
+          const float *bias, const __bf16 *H, int ldh, void *C, int ldc) {
+  dim3 grid((M + 63) / 64, (K + k_chunk - 1) / k_chunk);
+  gemm_nt_kernel<EPI, NT><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, K, k_chunk, bias, H, ldh, C, ldc);
+}
+
+template <class T> const T *cp(const DevBuf &b) { return b.as<T>(); }
+
+// Forward pass for S = Na * E samples of `state` into Y (normalised output).
+int forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int64_t S) {
+  hipStream_t s = ctx->stream;
+  rbffd_model *m = cl->model;
+  features_kernel<<<grid_for(S * 40, 256), 256, 0, s>>>(static_cast<const float *>(state), cl->idx.as<int>(), m->Na,
+                                                         m->n, m->E, cl->nodef.as<float>(), cl->inv_in,
+                                                         cl->X.as<__bf16>());
+  const float *p = cl->params.as<float>();
+  const int Si = static_cast<int>(S);
+  gemm<EPI_TANH, 8>(s, cp<__bf16>(cl->X), KIN, cp<__bf16>(cl->w1), KIN, Si, KIN, KIN, p + OB1, nullptr, 0,
+                    cl->H1.p, HID);
+  gemm<EPI_TANH, 8>(s, cp<__bf16>(cl->H1), HID, cp<__bf16>(cl->w2), HID, Si, HID, HID, p + OB2, nullptr, 0,
+                    cl->H2.p, HID);
+  gemm<EPI_BIAS, 1>(s, cp<__bf16>(cl->H2), HID, cp<__bf16>(cl->w3), HID, Si, HID, HID, p + OB3, nullptr, 0,
+                    cl->Y.p, NOUT);
+  RBFFD_HIP(ctx, hipGetLastError());
+  return RBFFD_OK;
+}
+
+// Loss and parameter gradient (into cl->grad) for targets T [S][4].
+int backward(rbffd_ctx *ctx, rbffd_closure *cl, const float *T, int64_t S) {
+  hipStream_t s = ctx->stream;
+  const int Si = static_cast<int>(S);
+  const int64_t Sp = (S + 31) / 32 * 32;
+  float *g = cl->grad.as<float>();
+  RBFFD_HIP(ctx, hipMemsetAsync(cl->grad.p, 0, sizeof(float) * NPARAM, s));
+  RBFFD_HIP(ctx, hipMemsetAsync(cl->loss.p, 0, sizeof(double), s));
+  loss_kernel<<<grid_for(S, 256), 256, 0, s>>>(cl->Y.as<float>(), T, S, cl->dY.as<__bf16>(), cl->dY32.as<float>(),
+                                               cl->loss.as<double>());
+  // back through the layers: dH2 = (dY W3) (1 - h2^2), dH1 = (dH2 W2) (1 - h1^2)
+  gemm<EPI_DTANH, 8>(s, cp<__bf16>(cl->dY), 32, cp<__bf16>(cl->w3t), 32, Si, 32, 32, nullptr, cp<__bf16>(cl->H2),
+                     HID, cl->dH2.p, HID);
+  gemm<EPI_DTANH, 8>(s, cp<__bf16>(cl->dH2), HID, cp<__bf16>(cl->w2t), HID, Si, HID, HID, nullptr,
+                     cp<__bf16>(cl->H1), HID, cl->dH1.p, HID);
+  // transposes for the weight gradients (contraction over samples)
+  auto tr = [&](const __bf16 *in, int ldi, int Cn, DevBuf &out) {
+    dim3 grid(static_cast<unsigned>(Sp / 32), (Cn + 31) / 32);
+    transpose_kernel<__bf16><<<grid, 256, 0, s>>>(in, ldi, S, Cn, out.as<__bf16>(), Sp);
+  };
+  tr(cp<__bf16>(cl->X), KIN, KIN, cl->XT);
+  tr(cp<__bf16>(cl->H1), HID, HID, cl->H1T);
+  tr(cp<__bf16>(cl->H2), HID, HID, cl->H2T);
+  tr(cp<__bf16>(cl->dH1), HID, HID, cl->dH1T);
+  tr(cp<__bf16>(cl->dH2), HID, HID, cl->dH2T);
+  tr(cp<__bf16>(cl->dY), 32, NOUT, cl->dYT);
+  const int Ki = static_cast<int>(Sp);
+  const int chunk = 4096;
+  gemm<EPI_ATOMIC, 10>(s, cp<__bf16>(cl->dH1T), Ki, cp<__bf16>(cl->XT), Ki, HID, Ki, chunk, nullptr, nullptr, 0,
+                       g + OW1, KIN);
+  gemm<EPI_ATOMIC, 8>(s, cp<__bf16>(cl->dH2T), Ki, cp<__bf16>(cl->H1T), Ki, HID, Ki, chunk, nullptr, nullptr, 0,
+                      g + OW2, HID);
+  gemm<EPI_ATOMIC, 8>(s, cp<__bf16>(cl->dYT), Ki, cp<__bf16>(cl->H2T), Ki, NOUT, Ki, chunk, nullptr, nullptr, 0,
+                      g + OW3, HID);
+  const int64_t cch = 2048;
+  const unsigned nb = static_cast<unsigned>((S + cch - 1) / cch);
+  colsum_kernel<__bf16><<<nb, HID, 0, s>>>(cp<__bf16>(cl->dH1), HID, S, HID, cch, g + OB1);
+  colsum_kernel<__bf16><<<nb, HID, 0, s>>>(cp<__bf16>(cl->dH2), HID, S, HID, cch, g + OB2);
+  colsum_kernel<float><<<nb, HID, 0, s>>>(cp<float>(cl->dY32), 4, S, 4, cch, g + OB3);
+  RBFFD_HIP(ctx, hipGetLastError());
+  return RBFFD_OK;
+}
+
+void repack(rbffd_closure *cl, hipStream_t s) {
+  pack_kernel<<<grid_for(HID * KIN, 256), 256, 0, s>>>(cl->params.as<float>(), cl->w1.as<__bf16>(), cl->w2.as<__bf16>(),
+                                                        cl->w3.as<__bf16>(), cl->w2t.as<__bf16>(), cl->w3t.as<__bf16>());
+}
+
+}  // namespace
+
+int closure_create(rbffd_ctx *ctx, rbffd_model *m, const rbffd_closure_desc *d, rbffd_closure **out) {
+  if (m->physics != RBFFD_PHYS_NS || m->fdt != RBFFD_F32)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "the closure needs a Navier-Stokes model with FP32 fields");
+  if (m->n > NSLOT_MAX) return rbffd_fail(ctx, RBFFD_EINVAL, "the closure takes stencils of at most 37 nodes");
+  if (!d->init_params || !d->node_feature) return rbffd_fail(ctx, RBFFD_EINVAL, "null closure input");
+  const int64_t S = m->Na * m->E;
+  if (d->max_samples < S || d->max_samples > (int64_t(1) << 28))
+    return rbffd_fail(ctx, RBFFD_EINVAL, "max_samples must cover n_active * E (%lld)", (long long)S);
+  for (int c = 0; c < 4; ++c)
+    if (!(d->in_scale[c] > 0.0f) || !(d->out_scale[c] > 0.0f))
+      return rbffd_fail(ctx, RBFFD_EINVAL, "scales must be positive");
+  auto *cl = new (std::nothrow) rbffd_closure();
+  if (!cl) return rbffd_fail(ctx, RBFFD_ENOMEM, "host allocation");
+  cl->model = m;
+  cl->max_s = d->max_samples;
+  cl->sp_max = (d->max_samples + 31) / 32 * 32;
+  cl->inv_in = make_float4(1.0f / d->in_scale[0], 1.0f / d->in_scale[1], 1.0f / d->in_scale[2], 1.0f / d->in_scale[3]);
+  cl->out_sc = make_float4(d->out_scale[0], d->out_scale[1], d->out_scale[2], d->out_scale[3]);
+  const size_t Sx = static_cast<size_t>(cl->max_s), Sp = static_cast<size_t>(cl->sp_max), b2 = 2;
+  bool ok = cl->params.alloc(4 * NPARAM) == hipSuccess && cl->grad.alloc(4 * NPARAM) == hipSuccess &&
+            cl->m1.alloc(4 * NPARAM) == hipSuccess && cl->m2.alloc(4 * NPARAM) == hipSuccess &&
+            cl->nodef.alloc(4 * m->Na) == hipSuccess && cl->idx.alloc(4 * m->Na * m->n) == hipSuccess &&
+            cl->w1.alloc(b2 * HID * KIN) == hipSuccess && cl->w2.alloc(b2 * HID * HID) == hipSuccess &&
+            cl->w3.alloc(b2 * NOUT * HID) == hipSuccess && cl->w2t.alloc(b2 * HID * HID) == hipSuccess &&
+            cl->w3t.alloc(b2 * HID * 32) == hipSuccess && cl->X.alloc(b2 * Sx * KIN) == hipSuccess &&
+            cl->H1.alloc(b2 * Sx * HID) == hipSuccess && cl->H2.alloc(b2 * Sx * HID) == hipSuccess &&
+            cl->Y.alloc(4 * Sx * NOUT) == hipSuccess && cl->dY.alloc(b2 * Sx * 32) == hipSuccess &&
+            cl->dY32.alloc(4 * Sx * 4) == hipSuccess && cl->dH1.alloc(b2 * Sx * HID) == hipSuccess &&
+            cl->dH2.alloc(b2 * Sx * HID) == hipSuccess && cl->XT.alloc(b2 * KIN * Sp) == hipSuccess &&
+            cl->H1T.alloc(b2 * HID * Sp) == hipSuccess && cl->H2T.alloc(b2 * HID * Sp) == hipSuccess &&
+            cl->dH1T.alloc(b2 * HID * Sp) == hipSuccess && cl->dH2T.alloc(b2 * HID * Sp) == hipSuccess &&
+            cl->dYT.alloc(b2 * NOUT * Sp) == hipSuccess && cl->loss.alloc(8) == hipSuccess &&
+            cl->bad.alloc(4 * m->E) == hipSuccess;
+  if (!ok) {
+    delete cl;
+    return rbffd_fail(ctx, RBFFD_ENOMEM, "device allocation (closure)");
+  }
+  hipStream_t s = ctx->stream;
+  bool cp_ok = hipMemcpyAsync(cl->params.p, d->init_params, 4 * NPARAM, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+               hipMemsetAsync(cl->m1.p, 0, 4 * NPARAM, s) == hipSuccess &&
+               hipMemsetAsync(cl->m2.p, 0, 4 * NPARAM, s) == hipSuccess &&
+               hipMemsetAsync(cl->w3t.p, 0, b2 * HID * 32, s) == hipSuccess &&
+               hipMemsetAsync(cl->w3.p, 0, b2 * NOUT * HID, s) == hipSuccess;
+  if (!cp_ok) {
+    delete cl;
+    return rbffd_fail(ctx, RBFFD_EDEVICE, "closure set-up copies");
+  }
+  f64_to_f32_kernel<<<grid_for(m->Na, 256), 256, 0, s>>>(d->node_feature, m->Na, cl->nodef.as<float>());
+  const int64_t cnt = m->Na * m->n;
+  idx_from_rec_kernel<<<grid_for(cnt, 256), 256, 0, s>>>(m->wdt == RBFFD_F32 ? m->rec.as<RecF32>() : nullptr,
+                                                         m->wdt == RBFFD_BF16 ? m->rec.as<RecBF16>() : nullptr, cnt,
+                                                         cl->idx.as<int>());
+  repack(cl, s);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    delete cl;
+    return rbffd_fail(ctx, RBFFD_EDEVICE, "closure set-up");
+  }
+  *out = cl;
+  return RBFFD_OK;
+}
+
+int closure_destroy(rbffd_closure *cl) {
+  delete cl;
+  return RBFFD_OK;
+}
+
+float *closure_params(rbffd_closure *cl) { return cl->params.as<float>(); }
+
+int closure_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, float *out) {
+  const int64_t S = cl->model->Na * cl->model->E;
+  int rc = forward(ctx, cl, state, S);
+  if (rc) return rc;
+  scale_out_kernel<<<grid_for(S, 256), 256, 0, ctx->stream>>>(cl->Y.as<float>(), S, cl->out_sc, out);
+  RBFFD_HIP(ctx, hipGetLastError());
+  return RBFFD_OK;
+}
+
+int closure_gradient(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target, float *grad,
+                     double *loss) {
+  const int64_t S = cl->model->Na * cl->model->E;
+  int rc = forward(ctx, cl, state, S);
+  if (!rc) rc = backward(ctx, cl, target, S);
+  if (rc) return rc;
+  if (grad) RBFFD_HIP(ctx, hipMemcpyAsync(grad, cl->grad.p, 4 * NPARAM, hipMemcpyDeviceToDevice, ctx->stream));
+  RBFFD_HIP(ctx, hipMemcpyAsync(loss, cl->loss.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  RBFFD_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return RBFFD_OK;
+}
+
+int closure_train_step(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target, double lr,
+                       double *loss) {
+  int rc = closure_gradient(ctx, cl, state, target, nullptr, loss);
+  if (rc) return rc;
+  cl->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - powf(b1, static_cast<float>(cl->step)), c2 = 1.0f - powf(b2, static_cast<float>(cl->step));
+  adam_kernel<<<grid_for(NPARAM, 256), 256, 0, ctx->stream>>>(cl->params.as<float>(), cl->grad.as<float>(),
+                                                              cl->m1.as<float>(), cl->m2.as<float>(), NPARAM,
+                                                              static_cast<float>(lr), b1, b2, 1e-8f, c1, c2);
+  repack(cl, ctx->stream);
+  RBFFD_HIP(ctx, hipGetLastError());
+  return RBFFD_OK;
+}
+
+int closure_step(rbffd_ctx *ctx, rbffd_closure *cl, void *state, double *t, double dt, int64_t n_steps, int tableau,
+                 int64_t *n_fallback) {
+  rbffd_model *m = cl->model;
+  const int64_t S = m->Na * m->E;
+  hipStream_t s = ctx->stream;
+  int64_t fb = 0;
+  std::vector<int> hb(m->E);
+  for (int64_t k = 0; k < n_steps; ++k) {
+    int rc = model_ghost(ctx, m, state);
+    if (!rc) rc = forward(ctx, cl, state, S);  // correction of the state before the step
+    if (!rc) rc = model_step(ctx, m, state, t, dt, 1, tableau);
+    if (rc) return rc;
+    RBFFD_HIP(ctx, hipMemsetAsync(cl->bad.p, 0, sizeof(int) * m->E, s));
+    check_kernel<<<grid_for(S, 256), 256, 0, s>>>(cl->Y.as<float>(), m->Na, m->E, cl->bad.as<int>());
+    apply_kernel<<<grid_for(S, 256), 256, 0, s>>>(static_cast<float *>(state), cl->Y.as<float>(), m->Na, m->E,
+                                                  cl->bad.as<int>(), cl->out_sc, static_cast<float>(dt));
+    RBFFD_HIP(ctx, hipGetLastError());
+    if (n_fallback) {
+      RBFFD_HIP(ctx, hipMemcpyAsync(hb.data(), cl->bad.p, sizeof(int) * m->E, hipMemcpyDeviceToHost, s));
+      RBFFD_HIP(ctx, hipStreamSynchronize(s));
+      for (int v : hb) fb += v;
+    }
+  }
+  if (n_fallback) *n_fallback = fb;
+  return RBFFD_OK;
+}

@@ -70,6 +70,16 @@ int model_profile(rbffd_model *m, int enable);
 int model_profile_read(rbffd_model *m, double *total_ms, int64_t *launches);
 int stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes);
 int model_tune(rbffd_ctx *ctx, rbffd_model *m, void *state, int *chosen, double *best_us);
+int closure_create(rbffd_ctx *ctx, rbffd_model *m, const rbffd_closure_desc *d, rbffd_closure **out);
+int closure_destroy(rbffd_closure *cl);
+float *closure_params(rbffd_closure *cl);
+int closure_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, float *out);
+int closure_gradient(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target, float *grad,
+                     double *loss);
+int closure_train_step(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target, double lr,
+                       double *loss);
+int closure_step(rbffd_ctx *ctx, rbffd_closure *cl, void *state, double *t, double dt, int64_t n_steps, int tableau,
+                 int64_t *n_fallback);
 
 // Launch geometry helper: grid of blocks covering n items.
 inline unsigned grid_for(int64_t n, int block) {

@@ -69,10 +69,29 @@ _lib.rbffd_model_profile_read.argtypes = [_vp, ctypes.POINTER(_f64), ctypes.POIN
 _lib.rbffd_stream_copy.argtypes = [_vp, _vp, _vp, _i64]
 _lib.rbffd_model_tune.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_f64)]
 
+
+class ClosureDesc(ctypes.Structure):
+    _fields_ = [("max_samples", _i64), ("init_params", _vp), ("node_feature", _vp),
+                ("in_scale", ctypes.c_float * 4), ("out_scale", ctypes.c_float * 4)]
+
+
+CLOSURE_NPARAMS = 128 * 160 + 128 + 128 * 128 + 128 + 16 * 128 + 16
+_lib.rbffd_closure_create.argtypes = [_vp, _vp, ctypes.POINTER(ClosureDesc), ctypes.POINTER(_vp)]
+_lib.rbffd_closure_destroy.argtypes = [_vp]
+_lib.rbffd_closure_params.argtypes = [_vp]
+_lib.rbffd_closure_params.restype = _vp
+_lib.rbffd_closure_forward.argtypes = [_vp, _vp, _vp, _vp]
+_lib.rbffd_closure_gradient.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_f64)]
+_lib.rbffd_closure_train_step.argtypes = [_vp, _vp, _vp, _vp, _f64, ctypes.POINTER(_f64)]
+_lib.rbffd_closure_step.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_f64), _f64, _i64, ctypes.c_int,
+                                    ctypes.POINTER(_i64)]
+
 EXPORTS = ["rbffd_create", "rbffd_destroy", "rbffd_last_error", "rbffd_sync", "rbffd_knn",
            "rbffd_weights", "rbffd_model_create", "rbffd_model_destroy", "rbffd_ghost",
            "rbffd_rhs", "rbffd_step", "rbffd_model_bytes_per_node", "rbffd_model_profile",
-           "rbffd_model_profile_read", "rbffd_stream_copy", "rbffd_model_tune"]
+           "rbffd_model_profile_read", "rbffd_stream_copy", "rbffd_model_tune", "rbffd_closure_create",
+           "rbffd_closure_destroy", "rbffd_closure_params", "rbffd_closure_forward", "rbffd_closure_gradient",
+           "rbffd_closure_train_step", "rbffd_closure_step"]
 
 
 class RbffdError(RuntimeError):
@@ -109,9 +128,11 @@ class Context:
             raise RbffdError(rc, "rbffd_create failed")
         self.h = h
 
-    def close(self):
+    def close(self, _destroy=_lib.rbffd_destroy):
+        # the destroy function is bound at class creation so that objects
+        # collected at interpreter exit still release their handle
         if getattr(self, "h", None):
-            _lib.rbffd_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     __del__ = close
@@ -204,9 +225,11 @@ class Model:
         ctx.check(_lib.rbffd_model_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
         self.h = h
 
-    def close(self):
+    def close(self, _destroy=_lib.rbffd_model_destroy):
+        # the destroy function is bound at class creation so that objects
+        # collected at interpreter exit still release their handle
         if getattr(self, "h", None):
-            _lib.rbffd_model_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     __del__ = close
@@ -267,3 +290,79 @@ def rbffd_step(ctx: Context, model: Model, state, t, dt, n_steps, tableau=RK4):
     ctx.check(_lib.rbffd_step(ctx.h, model.h, model._state(state), ctypes.byref(tt), float(dt),
                               int(n_steps), int(tableau)))
     return tt.value
+
+
+class Closure:
+    """rbffd_closure_*: the learned coarse correction bound to an FP32
+    Navier-Stokes model."""
+
+    def __init__(self, ctx: Context, model: Model, init_params, node_feature, in_scale, out_scale,
+                 max_samples=None):
+        self.ctx, self.model = ctx, model
+        d = ClosureDesc(max_samples=int(max_samples or model.Na * model.E),
+                        init_params=_ptr(init_params, torch.float32, (CLOSURE_NPARAMS,), "init_params"),
+                        node_feature=_ptr(node_feature, torch.float64, (model.Na,), "node_feature"))
+        d.in_scale[:] = [float(v) for v in in_scale]
+        d.out_scale[:] = [float(v) for v in out_scale]
+        h = _vp()
+        ctx.check(_lib.rbffd_closure_create(ctx.h, model.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+
+    def close(self, _destroy=_lib.rbffd_closure_destroy):
+        # the destroy function is bound at class creation so that objects
+        # collected at interpreter exit still release their handle
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def params(self):
+        """A copy of the FP32 master parameters (torch tensor on the device)."""
+        p = _lib.rbffd_closure_params(self.h)
+        out = torch.empty(CLOSURE_NPARAMS, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        _copy_device(out.data_ptr(), p, 4 * CLOSURE_NPARAMS)
+        return out
+
+    def _t(self, t, name):
+        m = self.model
+        return _ptr(t, torch.float32, (m.Na, m.E, 4), name)
+
+    def forward(self, state):
+        out = torch.empty((self.model.Na, self.model.E, 4), dtype=torch.float32, device="cuda")
+        self.ctx.check(_lib.rbffd_closure_forward(self.ctx.h, self.h, self.model._state(state), out.data_ptr()))
+        return out
+
+    def gradient(self, state, target):
+        g = torch.empty(CLOSURE_NPARAMS, dtype=torch.float32, device="cuda")
+        loss = _f64()
+        self.ctx.check(_lib.rbffd_closure_gradient(self.ctx.h, self.h, self.model._state(state),
+                                                   self._t(target, "target"), g.data_ptr(), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, state, target, lr):
+        loss = _f64()
+        self.ctx.check(_lib.rbffd_closure_train_step(self.ctx.h, self.h, self.model._state(state),
+                                                     self._t(target, "target"), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def step(self, state, t, dt, n_steps, tableau=RK4):
+        tt, fb = _f64(float(t)), _i64()
+        self.ctx.check(_lib.rbffd_closure_step(self.ctx.h, self.h, self.model._state(state), ctypes.byref(tt),
+                                               float(dt), int(n_steps), int(tableau), ctypes.byref(fb)))
+        return tt.value, fb.value
+
+
+_hip = None
+
+
+def _copy_device(dst, src, nbytes):
+    """Device-to-device copy through the HIP runtime the library links."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int]
+    rc = _hip.hipMemcpy(_vp(dst), _vp(src), nbytes, 3)      # hipMemcpyDeviceToDevice
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")

@@ -12,7 +12,7 @@ LIB = os.path.join(ROOT, "paper_1509_02615_amd", "librbffd.so")
 
 def declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char \*)\s*(rbffd_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char \*|float \*)\s*(rbffd_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_hot_path():

@@ -13,4 +13,5 @@ from .fields import (
 )
 from .configs import (
     advection_config, density_current_config, weights_config, scale_config, translating_config,
+    closure_config,
 )

@@ -105,3 +105,25 @@ def weights_config(n_side: int = 1024, seed: int = 0):
 
 def smooth_state_for(nodes, seed: int = 2, dtype=np.float64):
     return smooth_ns_state(nodes, seed=seed, dtype=dtype)
+
+
+def closure_config(n_members: int = 64, n_train: int = 48, seed: int = 1, coarse_h: float = 400.0,
+                   fine_h: float = 50.0):
+    """Learned-closure workload: the density current on nested Cartesian node
+    sets -- coarse 400 m (128 x 17 nodes, dt = 1 s) and fine 50 m
+    (1024 x 129, dt = 1/8 s), every coarse node also a fine node -- with an
+    ensemble whose bubble amplitudes are drawn from U[-17, -13] K. The first
+    n_train members train the network, the rest judge it."""
+    from .fields import ensemble_amplitudes
+    coarse = density_current_config("cartesian", coarse_h)
+    fine = density_current_config("cartesian", fine_h)
+    cn, fn = coarse["nodes"], fine["nodes"]
+    r = int(round(coarse_h / fine_h))
+    ci = np.arange(cn.n_active)
+    col, row = ci % cn.nx, ci // cn.nx
+    fmap = (row * r) * fn.nx + col * r
+    assert np.allclose(fn.xy[fmap], cn.xy[:cn.n_active])
+    amps = ensemble_amplitudes(n_members, seed=seed)
+    return dict(name=f"closure-density-current-cartesian-{int(coarse_h)}m-from-{int(fine_h)}m",
+                coarse=coarse, fine=fine, fine_of_coarse=fmap, amplitudes=amps, n_train=n_train,
+                node_feature=cn.xy[:cn.n_active, 1] / cn.height, ratio=r)
