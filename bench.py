@@ -25,6 +25,10 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+# closure network per node-sample: 149 inputs -> 128 -> 128 -> 4 outputs,
+# 2 flops per multiply-add (the kernels pad to 160 inputs and 16 outputs)
+CLOSURE_FLOP_PER_SAMPLE = 2 * (149 * 128 + 128 * 128 + 128 * 4)
 ROOT = os.path.dirname(os.path.abspath(__file__))
 COUNTERS = os.path.join(ROOT, "profiles", "ns_stage_kernel_hbm_counters.json")
 METRIC = "RHS node-updates/s & % HBM peak, FP32 vs FP64 at stated rel-L2; stencils/s"
@@ -133,6 +137,61 @@ def weights_leg(R, ctx, cfg, precision):
     return dict(stencils=nd.n_active, ms=ms, stencils_per_s=nd.n_active / (ms / 1e3), singular=bad)
 
 
+def closure_leg(R, ctx, calls=20, members=256):
+    """Learned closure on its coarse grid (400 m Cartesian channel, 128 x 17
+    nodes) for 256 members: 557,056 node-samples per fused forward call
+    (relu network, seeded random weights, a state developed by 60 plain
+    steps), timed over `calls` calls; plus the corrected coarse step against
+    the plain one."""
+    import torch
+    from paper_1509_02615_amd import closure as CL
+    from workloads import closure_config
+    from workloads.fields import ensemble_amplitudes
+    cc = closure_config()
+    cm, _ = CL.coarse_model(ctx, cc, members)
+    dt = cc["coarse"]["dt"]
+    state = CL.to_full(cm, CL.ensemble_state(cc["coarse"], ensemble_amplitudes(members))[:cm.Na])
+    R.rbffd_step(ctx, cm, state, 0.0, dt, 60, R.RK4)
+    rng = np.random.default_rng(7)
+    blocks = [rng.uniform(-1, 1, (128, 160)) / np.sqrt(149.0), rng.normal(0, 0.1, 128),
+              rng.uniform(-1, 1, (128, 128)) / np.sqrt(128.0), rng.normal(0, 0.1, 128),
+              np.vstack([rng.uniform(-1, 1, (4, 128)) / np.sqrt(128.0), np.zeros((12, 128))]),
+              np.concatenate([rng.normal(0, 0.1, 4), np.zeros(12)])]
+    params = torch.from_numpy(np.concatenate([b.ravel() for b in blocks]).astype(np.float32)).cuda()
+    nodef = torch.from_numpy(cc["node_feature"]).cuda()
+    cl = R.Closure(ctx, cm, params, nodef, [2.0, 2.0, 1.8, 3e-4], [1e-3, 1e-3, 7e-4, 3e-6],
+                   activation=R.ACT_RELU)
+    S = cm.Na * members
+    for _ in range(3):
+        cl.forward(state)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(calls):
+        cl.forward(state)
+    ev1.record()
+    torch.cuda.synchronize()
+    fwd_s = ev0.elapsed_time(ev1) / calls / 1e3
+    tflops = S * CLOSURE_FLOP_PER_SAMPLE / fwd_s / 1e12
+    n = 10
+    ev0.record()
+    R.rbffd_step(ctx, cm, state, 0.0, dt, n, R.RK4)
+    ev1.record()
+    torch.cuda.synchronize()
+    plain_ms = ev0.elapsed_time(ev1) / n
+    ev0.record()
+    cl.step(state, 0.0, dt, n, R.RK4)
+    ev1.record()
+    torch.cuda.synchronize()
+    corr_ms = ev0.elapsed_time(ev1) / n
+    return dict(samples=S, forward_us=fwd_s * 1e6, samples_per_s=S / fwd_s,
+                roofline={"bound": "mfma", "achieved": tflops, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": tflops / BF16_MFMA_PEAK_TFLOPS, "flop_per_sample": CLOSURE_FLOP_PER_SAMPLE},
+                plain_step_ms=plain_ms, corrected_step_ms=corr_ms,
+                note="forward call = fused gather + 3-layer network kernel + output scaling; "
+                     "steps: 4-stage RK4 of 256 members, corrected = plain + forward + correction")
+
+
 def cpu_baseline(cfg, min_seconds=10.0):
     """The oracle's RHS on a bounded sample: one 2048-node row of the same
     channel (row 128), stencils and weights from the oracle (untimed), then
@@ -167,6 +226,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and weight legs")
+    ap.add_argument("--closure-only", action="store_true",
+                    help="run only the learned-closure leg and print its result (for profiling)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware-counter passes: 2 RK4 steps of the chosen precision "
                          "and 3 plain copies of 512 MiB (counter calibration); prints no JSON line")
@@ -183,6 +244,9 @@ def main():
 
     torch.cuda.set_device(0)
     ctx = R.Context(0)
+    if args.closure_only:
+        print(json.dumps(closure_leg(R, ctx, calls=args.steps)), flush=True)
+        return
     cfg = scale_config()
     nd = cfg["nodes"]
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
@@ -233,6 +297,8 @@ def main():
         log(f"[bench] weights fp64: {extras['weights_mixed_1M_fp64']}")
         extras["weights_mixed_1M_fp32_ir"] = weights_leg(R, ctx, wcfg, R.SOLVE_FP32_IR)
         log(f"[bench] weights fp32+IR: {extras['weights_mixed_1M_fp32_ir']}")
+        extras["closure_forward_256x2176"] = closure_leg(R, ctx)
+        log(f"[bench] closure: {extras['closure_forward_256x2176']}")
     extras["weights_scale_setup"] = dict(stencils=n_stencils, seconds=setup_s,
                                          stencils_per_s=n_stencils / setup_s,
                                          note="search + FP64 weights incl. host sync, 4+2 operators")

@@ -231,9 +231,11 @@ int rbffd_model_tune(rbffd_ctx *ctx, rbffd_model *model, void *state, int *chose
  * slot 0 the node's own four fields, slots k >= 1 the differences
  * f(j_k) - f(i), each field divided by in_scale[field] (37 x 4 = 148 values) --
  * plus one per-node value (node_feature[i], e.g. height / domain height),
- * zero-padded to 160. Layers: h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2),
- * y = W3 h2 + b3, with 128 hidden units, BF16 weights and activations and
- * FP32 accumulation on the matrix cores; the correction in physical units
+ * zero-padded to 160. Layers: h1 = a(W1 x + b1), h2 = a(W2 h1 + b2),
+ * y = W3 h2 + b3, with 128 hidden units, activation a = tanh or relu
+ * (max(v, 0), one vector operation per value where tanh costs about
+ * twenty), BF16 weights and activations and FP32 accumulation on the
+ * matrix cores; the correction in physical units
  * is y[c] * out_scale[c]. Training minimises the mean of (y - target)^2 over
  * samples and fields with Adam on FP32 master weights.
  * Parameter layout (FP32, contiguous): W1 [128][160], b1 [128], W2 [128][128],
@@ -242,12 +244,15 @@ int rbffd_model_tune(rbffd_ctx *ctx, rbffd_model *model, void *state, int *chose
 
 typedef struct rbffd_closure rbffd_closure;  /* opaque, library-owned */
 
+enum { RBFFD_ACT_TANH = 0, RBFFD_ACT_RELU = 1 };
+
 typedef struct {
   int64_t max_samples;          /* largest n_active * E used with this closure        */
   const float *init_params;     /* [RBFFD_CLOSURE_NPARAMS] device, copied at creation  */
   const double *node_feature;   /* [n_active] device, copied at creation               */
   float in_scale[4];            /* input scale per field                               */
   float out_scale[4];           /* output scale per field                              */
+  int32_t activation;           /* RBFFD_ACT_TANH or RBFFD_ACT_RELU                    */
 } rbffd_closure_desc;
 
 /* Bind a closure to a Navier-Stokes model (its stencils, node count and E). */

@@ -1,12 +1,13 @@
 """CPU oracle of the learned coarse closure's network. TEST INFRASTRUCTURE ONLY.
 
-The network is not in the paper: it is this build's correction to the coarse
+The network is not in the paper: it is a learned correction to the coarse
 right-hand side, defined by the closure interface of the C ABI. For node i
 and member e the input is the stencil-gathered state -- slot 0 the node's own
 fields, slots k >= 1 the differences f(j_k) - f(i), each field divided by its
 input scale -- plus one per-node value, zero-padded to 160; then
-h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), y = W3 h2 + b3 (128 hidden,
-4 outputs); loss = mean over samples and outputs of (y - target)^2.
+h1 = a(W1 x + b1), h2 = a(W2 h1 + b2), y = W3 h2 + b3 (128 hidden, 4 outputs)
+with the activation a = tanh or a = relu (max(v, 0)); loss = mean over
+samples and outputs of (y - target)^2.
 
 Everything here is FP64. With ``emulate=True`` the values the GPU stores in
 bfloat16 (inputs, weights, hidden activations and back-propagated
@@ -18,6 +19,16 @@ plain FP64 network, whose analytic gradient is pinned by finite differences.
 import numpy as np
 
 HID, KIN, NOUT, NSLOT = 128, 160, 16, 37
+TANH, RELU = 0, 1
+
+
+def _act(v, act):
+    return np.tanh(v) if act == TANH else np.maximum(v, 0.0)
+
+
+def _dact(h, act):
+    """Derivative of the activation expressed through its output h."""
+    return 1.0 - h * h if act == TANH else (h > 0.0).astype(np.float64)
 OW1 = 0
 OB1 = OW1 + HID * KIN
 OW2 = OB1 + HID
@@ -57,21 +68,21 @@ def features(state, idx, node_feature, in_scale):
     return X.reshape(na * E, KIN)
 
 
-def forward(p, X, emulate=False):
+def forward(p, X, emulate=False, act=TANH):
     W1, b1, W2, b2, W3, b3 = unpack(p)
     r = bf16 if emulate else (lambda v: np.asarray(v, dtype=np.float64))
     Xr, W1r, W2r, W3r = r(X), r(W1), r(W2), r(W3)
-    H1 = r(np.tanh(Xr @ W1r.T + b1))
-    H2 = r(np.tanh(H1 @ W2r.T + b2))
+    H1 = r(_act(Xr @ W1r.T + b1, act))
+    H2 = r(_act(H1 @ W2r.T + b2, act))
     Y = H2 @ W3r.T + b3
     return Y, H1, H2, Xr
 
 
-def loss_and_grad(p, X, T, emulate=False):
+def loss_and_grad(p, X, T, emulate=False, act=TANH):
     """Loss and its gradient for targets T [S][4] (only outputs 0..3 enter)."""
     W1, b1, W2, b2, W3, b3 = unpack(p)
     r = bf16 if emulate else (lambda v: np.asarray(v, dtype=np.float64))
-    Y, H1, H2, Xr = forward(p, X, emulate)
+    Y, H1, H2, Xr = forward(p, X, emulate, act)
     S = X.shape[0]
     D = Y[:, :4] - T
     loss = float(np.sum(D * D) / (4 * S))
@@ -80,8 +91,8 @@ def loss_and_grad(p, X, T, emulate=False):
     if emulate:
         dY32 = np.asarray(dY32, dtype=np.float32).astype(np.float64)
     dY = r(dY32)
-    dH2 = r((dY @ r(W3)) * (1.0 - H2 * H2))
-    dH1 = r((dH2 @ r(W2)) * (1.0 - H1 * H1))
+    dH2 = r((dY @ r(W3)) * _dact(H2, act))
+    dH1 = r((dH2 @ r(W2)) * _dact(H1, act))
     g = np.zeros(NPARAM)
     g[OW1:OB1] = (dH1.T @ Xr).ravel()
     g[OB1:OW2] = dH1.sum(axis=0)

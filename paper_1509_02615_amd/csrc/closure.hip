@@ -10,14 +10,16 @@
 // Every product is one kernel, C = A . B^T with both operands contiguous
 // along the contraction index (samples x features, or features x samples
 // for the weight gradients), and an epilogue per use:
-//   bias + tanh -> BF16        (hidden layers)
+//   bias + activation -> BF16  (hidden layers)
 //   bias -> FP32               (output layer)
-//   x (1 - h^2) -> BF16        (back-propagation through tanh)
+//   x a'(h) -> BF16            (back-propagation through the activation)
 //   atomic FP32 accumulation   (weight gradients, split over sample chunks)
 // Lane layout of the 16x16x32 instruction: lane l holds A[l%16][8(l/16)..+7],
 // B[8(l/16)..+7][l%16] (so row l%16 of B^T) and D[4(l/16)..+3][l%16].
+#include <algorithm>
 #include <cmath>
 #include <new>
+#include <vector>
 
 #include "model.hpp"
 
@@ -31,7 +33,7 @@ static_assert(NPARAM == RBFFD_CLOSURE_NPARAMS, "parameter layout");
 typedef __attribute__((ext_vector_type(4))) float f4v;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf8v;
 
-enum { EPI_TANH = 0, EPI_BIAS = 1, EPI_DTANH = 2, EPI_ATOMIC = 3 };
+enum { EPI_ACT = 0, EPI_BIAS = 1, EPI_DACT = 2, EPI_ATOMIC = 3 };
 
 // C[m][n] (epilogue) = sum_k A[m][k] B[n][k]; A: M x K (lda), B: 16*NT x K
 // (ldb); K a multiple of 32 within [kbeg, kend) = blockIdx.y's chunk. Four
@@ -40,7 +42,8 @@ template <int EPI, int NT>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const __bf16 *__restrict__ A, int lda,
                                                       const __bf16 *__restrict__ B, int ldb, int M, int K,
                                                       int k_chunk, const float *__restrict__ bias,
-                                                      const __bf16 *__restrict__ H, int ldh, void *C, int ldc) {
+                                                      const __bf16 *__restrict__ H, int ldh, void *C, int ldc,
+                                                      int act) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m0 = blockIdx.x * 64 + wave * 16;
   const int kbeg = blockIdx.y * k_chunk, kend = min(K, kbeg + k_chunk);
@@ -72,15 +75,201 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const __bf16 *__restrict__
       if (r >= M) continue;
       const float v = acc[t][i];
       const int64_t o = static_cast<int64_t>(r) * ldc + c;
-      if constexpr (EPI == EPI_TANH) {
-        static_cast<__bf16 *>(C)[o] = static_cast<__bf16>(tanhf(v + bias[c]));
+      if constexpr (EPI == EPI_ACT) {
+        const float z = v + bias[c];
+        static_cast<__bf16 *>(C)[o] =
+            static_cast<__bf16>(act == RBFFD_ACT_RELU ? __builtin_elementwise_maximum(z, 0.0f) : tanhf(z));
       } else if constexpr (EPI == EPI_BIAS) {
         static_cast<float *>(C)[o] = v + bias[c];
-      } else if constexpr (EPI == EPI_DTANH) {
+      } else if constexpr (EPI == EPI_DACT) {
         const float h = static_cast<float>(H[static_cast<int64_t>(r) * ldh + c]);
-        static_cast<__bf16 *>(C)[o] = static_cast<__bf16>(v * (1.0f - h * h));
+        static_cast<__bf16 *>(C)[o] = static_cast<__bf16>(act == RBFFD_ACT_RELU ? (h > 0.0f ? v : 0.0f)
+                                                                                : v * (1.0f - h * h));
       } else {
         atomicAdd(static_cast<float *>(C) + o, v);
+      }
+    }
+  }
+}
+
+// ---- fused forward pass -------------------------------------------------
+// One kernel from the state to the normalised correction. The products are
+// computed transposed, H^T = W X^T: the weights are the A operand (packed in
+// LDS as per-lane fragments, shared by every sample tile of the block) and
+// the samples the B operand, so lane l always holds sample l%16 of its tile:
+// the input fragment is gathered straight from the state, and a layer's
+// accumulators (outputs 16t + 4(l/16) + i) become the next layer's B
+// fragment without moving data between lanes, once the contraction index of
+// the next weight matrix is permuted to that order (mlp_perm). The biases
+// enter as the accumulator input of each output tile's first product.
+constexpr int FR1 = 8 * 5, FR2 = 8 * 4, FR3 = 4, NFRAG = FR1 + FR2 + FR3;  // 16 B x 64 lanes each
+constexpr int NBIAS = HID + HID + NOUT;
+constexpr size_t MLP_LDS = static_cast<size_t>(NFRAG) * 64 * 16 + NBIAS * sizeof(float);
+
+// Position p of a 32-wide contraction block j of layers 2 and 3 -> hidden unit.
+__host__ __device__ constexpr int mlp_perm(int j, int p) {
+  return 32 * j + ((p & 7) < 4 ? 4 * (p >> 3) + (p & 7) : 16 + 4 * (p >> 3) + (p & 7) - 4);
+}
+
+// frag[f][lane][q], f < FR1: W1 tile (t = f / 5, k-block j = f % 5); then W2
+// tiles (t = f' / 4, j = f' % 4) and W3 (j) with permuted contraction index.
+__global__ void frag_pack_kernel(const float *__restrict__ p, __bf16 *__restrict__ frag) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NFRAG * 512) return;
+  const int f = t >> 9, l = (t >> 3) & 63, q = t & 7;
+  const int row = l & 15, pos = 8 * (l >> 4) + q;
+  float v;
+  if (f < FR1) {
+    v = p[OW1 + (16 * (f / 5) + row) * KIN + 32 * (f % 5) + pos];
+  } else if (f < FR1 + FR2) {
+    const int g = f - FR1;
+    v = p[OW2 + (16 * (g / 4) + row) * HID + mlp_perm(g % 4, pos)];
+  } else {
+    v = p[OW3 + row * HID + mlp_perm(f - FR1 - FR2, pos)];
+  }
+  frag[t] = static_cast<__bf16>(v);
+}
+
+// The activation; relu propagates NaN (IEEE maximum, one instruction).
+template <int ACT> __device__ __forceinline__ float act_fn(float v) {
+  if constexpr (ACT == RBFFD_ACT_RELU) {
+    return __builtin_elementwise_maximum(v, 0.0f);
+  } else {
+    return tanhf(v);
+  }
+}
+
+// Input fragment of contraction block j for one sample: slots 8j + 2g and
+// 8j + 2g + 1 (four fields each). Branch-free: a slot past the stencil
+// re-reads the node itself (difference 0); slot 37 carries the node value.
+__device__ __forceinline__ bf8v gather_block(const float *__restrict__ y, const int *__restrict__ idx_t, int64_t Na,
+                                             int n, int E, float nodev, float4 inv, int64_t i, int e, float4 own,
+                                             int slot0) {
+  bf8v x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int slot = slot0 + h;
+    const int64_t j = (slot >= 1 && slot < n) ? idx_t[static_cast<int64_t>(slot) * Na + i] : i;
+    const float4 f = *reinterpret_cast<const float4 *>(y + (j * E + e) * 4);
+    const float4 b = slot == 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : own;
+    float v0 = (f.x - b.x) * inv.x, v1 = (f.y - b.y) * inv.y, v2 = (f.z - b.z) * inv.z, v3 = (f.w - b.w) * inv.w;
+    if (slot == NSLOT_MAX) v0 = nodev;
+    x[4 * h + 0] = static_cast<__bf16>(v0);
+    x[4 * h + 1] = static_cast<__bf16>(v1);
+    x[4 * h + 2] = static_cast<__bf16>(v2);
+    x[4 * h + 3] = static_cast<__bf16>(v3);
+  }
+  return x;
+}
+
+// Y[s][0..3] for S samples, T tiles of 16 samples per wavefront, two
+// wavefronts per SIMD; blocks of 4 wavefronts loop over contiguous unit
+// ranges (XCD-aware block order).
+#ifndef RBFFD_MLP_T
+#define RBFFD_MLP_T 2
+#endif
+template <int T, int ACT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void mlp_forward_kernel(
+    const float *__restrict__ y, const int *__restrict__ idx_t, int64_t Na, int n, int E,
+    const float *__restrict__ nodef, float4 inv, const __bf16 *__restrict__ frag_g, const float *__restrict__ params,
+    float *__restrict__ Y, int64_t S) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char mlp_lds[];
+  const bf8v *s_frag = reinterpret_cast<const bf8v *>(mlp_lds);
+  float *s_bias = reinterpret_cast<float *>(mlp_lds + static_cast<size_t>(NFRAG) * 64 * 16);
+  {
+    const f4v *src = reinterpret_cast<const f4v *>(frag_g);
+    f4v *dst = reinterpret_cast<f4v *>(mlp_lds);
+    for (int k = threadIdx.x; k < NFRAG * 64; k += 256) dst[k] = src[k];
+    for (int k = threadIdx.x; k < NBIAS; k += 256)
+      s_bias[k] = k < HID ? params[OB1 + k] : (k < 2 * HID ? params[OB2 + k - HID] : params[OB3 + k - 2 * HID]);
+  }
+  __syncthreads();
+  const f4v *s_b4 = reinterpret_cast<const f4v *>(s_bias);   // 4 consecutive biases per lane group
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const int64_t units = (S + 16 * T - 1) / (16 * T);
+  const int64_t nb = gridDim.x, b = blockIdx.x, full = (nb / 8) * 8;
+  const int64_t lb = b >= full ? b : (b % 8) * (nb / 8) + b / 8;
+  const int64_t per = (units + nb - 1) / nb;
+  const int64_t u_end = min(units, (lb + 1) * per);
+  for (int64_t u = lb * per + wave; u < u_end; u += 4) {
+    const int64_t base = u * 16 * T;
+    // keeps the weight fragments' LDS reads inside the loop: hoisted out of
+    // it as loop-invariant they would need 304 registers
+    asm volatile("" ::: "memory");
+    int64_t si[T];
+    int se[T];
+    float4 own[T];
+    float nodev[T];
+#pragma unroll
+    for (int tl = 0; tl < T; ++tl) {
+      const int64_t s = min(base + 16 * tl + r, S - 1);     // rows past S compute a copy, never stored
+      si[tl] = s / E;
+      se[tl] = static_cast<int>(s - si[tl] * E);
+      own[tl] = *reinterpret_cast<const float4 *>(y + s * 4);
+      nodev[tl] = nodef[si[tl]];
+    }
+    // layer 1: 8 output tiles, 5 contraction blocks gathered one at a time
+    f4v acc[8][T];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      bf8v x[T];
+#pragma unroll
+      for (int tl = 0; tl < T; ++tl)
+        x[tl] = gather_block(y, idx_t, Na, n, E, nodev[tl], inv, si[tl], se[tl], own[tl], 8 * j + 2 * g);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const bf8v a = s_frag[(t * 5 + j) * 64 + lane];
+        const f4v c0 = s_b4[4 * t + g];
+#pragma unroll
+        for (int tl = 0; tl < T; ++tl)
+          acc[t][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x[tl], j == 0 ? c0 : acc[t][tl], 0, 0, 0);
+      }
+    }
+    bf8v hb[4][T];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int tl = 0; tl < T; ++tl)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          hb[j][tl][i] = static_cast<__bf16>(act_fn<ACT>(acc[2 * j][tl][i]));
+          hb[j][tl][4 + i] = static_cast<__bf16>(act_fn<ACT>(acc[2 * j + 1][tl][i]));
+        }
+    // layer 2
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const bf8v a = s_frag[FR1 * 64 + (t * 4 + j) * 64 + lane];
+        const f4v c0 = s_b4[32 + 4 * t + g];
+#pragma unroll
+        for (int tl = 0; tl < T; ++tl)
+          acc[t][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[j][tl], j == 0 ? c0 : acc[t][tl], 0, 0, 0);
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int tl = 0; tl < T; ++tl)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          hb[j][tl][i] = static_cast<__bf16>(act_fn<ACT>(acc[2 * j][tl][i]));
+          hb[j][tl][4 + i] = static_cast<__bf16>(act_fn<ACT>(acc[2 * j + 1][tl][i]));
+        }
+    // layer 3: one output tile, outputs 0..3 in the lanes of group 0
+    f4v out[T];
+    const f4v c3 = s_b4[64 + g];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf8v a = s_frag[(FR1 + FR2 + j) * 64 + lane];
+#pragma unroll
+      for (int tl = 0; tl < T; ++tl)
+        out[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[j][tl], j == 0 ? c3 : out[tl], 0, 0, 0);
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int tl = 0; tl < T; ++tl) {
+        const int64_t s = base + 16 * tl + r;
+        if (s < S) *reinterpret_cast<float4 *>(Y + s * 4) = make_float4(out[tl][0], out[tl][1], out[tl][2], out[tl][3]);
       }
     }
   }
@@ -211,39 +400,39 @@ __global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, 
 }
 
 // Per member: 1 if any correction value of that member is not finite.
-__global__ void check_kernel(const float *__restrict__ Y, int64_t Na, int E, int *__restrict__ bad) {
+__global__ void check_kernel(const float *__restrict__ Y, int ys, int64_t Na, int E, int *__restrict__ bad) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= Na * E) return;
   const int e = static_cast<int>(s % E);
   for (int c = 0; c < 4; ++c)
-    if (!isfinite(Y[s * NOUT + c])) {
+    if (!isfinite(Y[s * ys + c])) {
       atomicOr(bad + e, 1);
       return;
     }
 }
 
 // y_active += dt * Y * out_scale, except for members flagged non-finite.
-__global__ void apply_kernel(float *__restrict__ y, const float *__restrict__ Y, int64_t Na, int E,
+__global__ void apply_kernel(float *__restrict__ y, const float *__restrict__ Y, int ys, int64_t Na, int E,
                              const int *__restrict__ bad, float4 out_scale, float dt) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= Na * E) return;
   const int e = static_cast<int>(s % E);
   if (bad[e]) return;
   float *o = y + s * 4;
-  const float *q = Y + s * NOUT;
+  const float *q = Y + s * ys;
   o[0] += dt * q[0] * out_scale.x;
   o[1] += dt * q[1] * out_scale.y;
   o[2] += dt * q[2] * out_scale.z;
   o[3] += dt * q[3] * out_scale.w;
 }
 
-__global__ void scale_out_kernel(const float *__restrict__ Y, int64_t S, float4 sc, float *__restrict__ out) {
+__global__ void scale_out_kernel(const float *__restrict__ Y, int ys, int64_t S, float4 sc, float *__restrict__ out) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= S) return;
-  out[s * 4 + 0] = Y[s * NOUT + 0] * sc.x;
-  out[s * 4 + 1] = Y[s * NOUT + 1] * sc.y;
-  out[s * 4 + 2] = Y[s * NOUT + 2] * sc.z;
-  out[s * 4 + 3] = Y[s * NOUT + 3] * sc.w;
+  out[s * 4 + 0] = Y[s * ys + 0] * sc.x;
+  out[s * 4 + 1] = Y[s * ys + 1] * sc.y;
+  out[s * 4 + 2] = Y[s * ys + 2] * sc.z;
+  out[s * 4 + 3] = Y[s * ys + 3] * sc.w;
 }
 
 // Stencil indices out of the model's slot-major records.
@@ -269,17 +458,19 @@ struct rbffd_closure {
   DevBuf w1, w2, w3, w2t, w3t;                       // BF16 weights
   DevBuf X, H1, H2, Y, dY, dY32, dH1, dH2;           // activations [S][.]
   DevBuf XT, H1T, H2T, dH1T, dH2T, dYT;              // transposed [.][Sp]
+  DevBuf frag, Yc;                                   // fused forward: packed weights, Y [S][4]
   DevBuf loss, bad;
   int64_t step = 0;
+  int act = RBFFD_ACT_TANH;
 };
 
 namespace {
 
 template <int EPI, int NT>
 void gemm(hipStream_t s, const __bf16 *A, int lda, const __bf16 *B, int ldb, int M, int K, int k_chunk,
-          const float *bias, const __bf16 *H, int ldh, void *C, int ldc) {
+          const float *bias, const __bf16 *H, int ldh, void *C, int ldc, int act = RBFFD_ACT_TANH) {
   dim3 grid((M + 63) / 64, (K + k_chunk - 1) / k_chunk);
-  gemm_nt_kernel<EPI, NT><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, K, k_chunk, bias, H, ldh, C, ldc);
+  gemm_nt_kernel<EPI, NT><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, K, k_chunk, bias, H, ldh, C, ldc, act);
 }
 
 template <class T> const T *cp(const DevBuf &b) { return b.as<T>(); }
@@ -293,10 +484,10 @@ int forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int64_t S) {
                                                          cl->X.as<__bf16>());
   const float *p = cl->params.as<float>();
   const int Si = static_cast<int>(S);
-  gemm<EPI_TANH, 8>(s, cp<__bf16>(cl->X), KIN, cp<__bf16>(cl->w1), KIN, Si, KIN, KIN, p + OB1, nullptr, 0,
-                    cl->H1.p, HID);
-  gemm<EPI_TANH, 8>(s, cp<__bf16>(cl->H1), HID, cp<__bf16>(cl->w2), HID, Si, HID, HID, p + OB2, nullptr, 0,
-                    cl->H2.p, HID);
+  gemm<EPI_ACT, 8>(s, cp<__bf16>(cl->X), KIN, cp<__bf16>(cl->w1), KIN, Si, KIN, KIN, p + OB1, nullptr, 0,
+                   cl->H1.p, HID, cl->act);
+  gemm<EPI_ACT, 8>(s, cp<__bf16>(cl->H1), HID, cp<__bf16>(cl->w2), HID, Si, HID, HID, p + OB2, nullptr, 0,
+                   cl->H2.p, HID, cl->act);
   gemm<EPI_BIAS, 1>(s, cp<__bf16>(cl->H2), HID, cp<__bf16>(cl->w3), HID, Si, HID, HID, p + OB3, nullptr, 0,
                     cl->Y.p, NOUT);
   RBFFD_HIP(ctx, hipGetLastError());
@@ -313,11 +504,11 @@ int backward(rbffd_ctx *ctx, rbffd_closure *cl, const float *T, int64_t S) {
   RBFFD_HIP(ctx, hipMemsetAsync(cl->loss.p, 0, sizeof(double), s));
   loss_kernel<<<grid_for(S, 256), 256, 0, s>>>(cl->Y.as<float>(), T, S, cl->dY.as<__bf16>(), cl->dY32.as<float>(),
                                                cl->loss.as<double>());
-  // back through the layers: dH2 = (dY W3) (1 - h2^2), dH1 = (dH2 W2) (1 - h1^2)
-  gemm<EPI_DTANH, 8>(s, cp<__bf16>(cl->dY), 32, cp<__bf16>(cl->w3t), 32, Si, 32, 32, nullptr, cp<__bf16>(cl->H2),
-                     HID, cl->dH2.p, HID);
-  gemm<EPI_DTANH, 8>(s, cp<__bf16>(cl->dH2), HID, cp<__bf16>(cl->w2t), HID, Si, HID, HID, nullptr,
-                     cp<__bf16>(cl->H1), HID, cl->dH1.p, HID);
+  // back through the layers: dH2 = (dY W3) a'(h2), dH1 = (dH2 W2) a'(h1)
+  gemm<EPI_DACT, 8>(s, cp<__bf16>(cl->dY), 32, cp<__bf16>(cl->w3t), 32, Si, 32, 32, nullptr, cp<__bf16>(cl->H2),
+                    HID, cl->dH2.p, HID, cl->act);
+  gemm<EPI_DACT, 8>(s, cp<__bf16>(cl->dH2), HID, cp<__bf16>(cl->w2t), HID, Si, HID, HID, nullptr,
+                    cp<__bf16>(cl->H1), HID, cl->dH1.p, HID, cl->act);
   // transposes for the weight gradients (contraction over samples)
   auto tr = [&](const __bf16 *in, int ldi, int Cn, DevBuf &out) {
     dim3 grid(static_cast<unsigned>(Sp / 32), (Cn + 31) / 32);
@@ -349,6 +540,34 @@ int backward(rbffd_ctx *ctx, rbffd_closure *cl, const float *T, int64_t S) {
 void repack(rbffd_closure *cl, hipStream_t s) {
   pack_kernel<<<grid_for(HID * KIN, 256), 256, 0, s>>>(cl->params.as<float>(), cl->w1.as<__bf16>(), cl->w2.as<__bf16>(),
                                                         cl->w3.as<__bf16>(), cl->w2t.as<__bf16>(), cl->w3t.as<__bf16>());
+  frag_pack_kernel<<<grid_for(NFRAG * 512, 256), 256, 0, s>>>(cl->params.as<float>(), cl->frag.as<__bf16>());
+}
+
+constexpr int MLP_T = RBFFD_MLP_T;
+
+template <int ACT> void set_mlp_lds(bool &ok) {
+  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_forward_kernel<MLP_T, ACT>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(MLP_LDS)) == hipSuccess;
+}
+
+// Fused forward pass into cl->Yc [S][4]: at most two blocks of 4 wavefronts
+// per compute unit (the packed weights take 77 KB of LDS per block).
+int forward_fused(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int64_t S) {
+  rbffd_model *m = cl->model;
+  const int64_t units = (S + 16 * MLP_T - 1) / (16 * MLP_T);
+  const unsigned nb = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(512, (units + 3) / 4)));
+  auto launch = [&](auto kern) {
+    kern<<<nb, 256, MLP_LDS, ctx->stream>>>(static_cast<const float *>(state), cl->idx.as<int>(), m->Na, m->n, m->E,
+                                            cl->nodef.as<float>(), cl->inv_in, cl->frag.as<__bf16>(),
+                                            cl->params.as<float>(), cl->Yc.as<float>(), S);
+  };
+  if (cl->act == RBFFD_ACT_RELU) {
+    launch(mlp_forward_kernel<MLP_T, RBFFD_ACT_RELU>);
+  } else {
+    launch(mlp_forward_kernel<MLP_T, RBFFD_ACT_TANH>);
+  }
+  RBFFD_HIP(ctx, hipGetLastError());
+  return RBFFD_OK;
 }
 
 }  // namespace
@@ -358,6 +577,8 @@ int closure_create(rbffd_ctx *ctx, rbffd_model *m, const rbffd_closure_desc *d, 
     return rbffd_fail(ctx, RBFFD_EINVAL, "the closure needs a Navier-Stokes model with FP32 fields");
   if (m->n > NSLOT_MAX) return rbffd_fail(ctx, RBFFD_EINVAL, "the closure takes stencils of at most 37 nodes");
   if (!d->init_params || !d->node_feature) return rbffd_fail(ctx, RBFFD_EINVAL, "null closure input");
+  if (d->activation != RBFFD_ACT_TANH && d->activation != RBFFD_ACT_RELU)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "activation must be RBFFD_ACT_TANH or RBFFD_ACT_RELU");
   const int64_t S = m->Na * m->E;
   if (d->max_samples < S || d->max_samples > (int64_t(1) << 28))
     return rbffd_fail(ctx, RBFFD_EINVAL, "max_samples must cover n_active * E (%lld)", (long long)S);
@@ -367,6 +588,7 @@ int closure_create(rbffd_ctx *ctx, rbffd_model *m, const rbffd_closure_desc *d, 
   auto *cl = new (std::nothrow) rbffd_closure();
   if (!cl) return rbffd_fail(ctx, RBFFD_ENOMEM, "host allocation");
   cl->model = m;
+  cl->act = d->activation;
   cl->max_s = d->max_samples;
   cl->sp_max = (d->max_samples + 31) / 32 * 32;
   cl->inv_in = make_float4(1.0f / d->in_scale[0], 1.0f / d->in_scale[1], 1.0f / d->in_scale[2], 1.0f / d->in_scale[3]);
@@ -385,10 +607,18 @@ int closure_create(rbffd_ctx *ctx, rbffd_model *m, const rbffd_closure_desc *d, 
             cl->H1T.alloc(b2 * HID * Sp) == hipSuccess && cl->H2T.alloc(b2 * HID * Sp) == hipSuccess &&
             cl->dH1T.alloc(b2 * HID * Sp) == hipSuccess && cl->dH2T.alloc(b2 * HID * Sp) == hipSuccess &&
             cl->dYT.alloc(b2 * NOUT * Sp) == hipSuccess && cl->loss.alloc(8) == hipSuccess &&
-            cl->bad.alloc(4 * m->E) == hipSuccess;
+            cl->bad.alloc(4 * m->E) == hipSuccess && cl->frag.alloc(b2 * NFRAG * 512) == hipSuccess &&
+            cl->Yc.alloc(4 * Sx * 4) == hipSuccess;
   if (!ok) {
     delete cl;
     return rbffd_fail(ctx, RBFFD_ENOMEM, "device allocation (closure)");
+  }
+  bool lds_ok = true;
+  set_mlp_lds<RBFFD_ACT_TANH>(lds_ok);
+  set_mlp_lds<RBFFD_ACT_RELU>(lds_ok);
+  if (!lds_ok) {
+    delete cl;
+    return rbffd_fail(ctx, RBFFD_EDEVICE, "closure: LDS size of the fused forward kernel");
   }
   hipStream_t s = ctx->stream;
   bool cp_ok = hipMemcpyAsync(cl->params.p, d->init_params, 4 * NPARAM, hipMemcpyDeviceToDevice, s) == hipSuccess &&
@@ -423,9 +653,9 @@ float *closure_params(rbffd_closure *cl) { return cl->params.as<float>(); }
 
 int closure_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, float *out) {
   const int64_t S = cl->model->Na * cl->model->E;
-  int rc = forward(ctx, cl, state, S);
+  int rc = forward_fused(ctx, cl, state, S);
   if (rc) return rc;
-  scale_out_kernel<<<grid_for(S, 256), 256, 0, ctx->stream>>>(cl->Y.as<float>(), S, cl->out_sc, out);
+  scale_out_kernel<<<grid_for(S, 256), 256, 0, ctx->stream>>>(cl->Yc.as<float>(), 4, S, cl->out_sc, out);
   RBFFD_HIP(ctx, hipGetLastError());
   return RBFFD_OK;
 }
@@ -466,12 +696,12 @@ int closure_step(rbffd_ctx *ctx, rbffd_closure *cl, void *state, double *t, doub
   std::vector<int> hb(m->E);
   for (int64_t k = 0; k < n_steps; ++k) {
     int rc = model_ghost(ctx, m, state);
-    if (!rc) rc = forward(ctx, cl, state, S);  // correction of the state before the step
+    if (!rc) rc = forward_fused(ctx, cl, state, S);  // correction of the state before the step
     if (!rc) rc = model_step(ctx, m, state, t, dt, 1, tableau);
     if (rc) return rc;
     RBFFD_HIP(ctx, hipMemsetAsync(cl->bad.p, 0, sizeof(int) * m->E, s));
-    check_kernel<<<grid_for(S, 256), 256, 0, s>>>(cl->Y.as<float>(), m->Na, m->E, cl->bad.as<int>());
-    apply_kernel<<<grid_for(S, 256), 256, 0, s>>>(static_cast<float *>(state), cl->Y.as<float>(), m->Na, m->E,
+    check_kernel<<<grid_for(S, 256), 256, 0, s>>>(cl->Yc.as<float>(), 4, m->Na, m->E, cl->bad.as<int>());
+    apply_kernel<<<grid_for(S, 256), 256, 0, s>>>(static_cast<float *>(state), cl->Yc.as<float>(), 4, m->Na, m->E,
                                                   cl->bad.as<int>(), cl->out_sc, static_cast<float>(dt));
     RBFFD_HIP(ctx, hipGetLastError());
     if (n_fallback) {

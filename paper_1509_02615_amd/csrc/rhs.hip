@@ -375,6 +375,78 @@ __global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_kernel(GArgs a) {
   if (lane == 0) store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.ghost_nodes[wg]) * E + e) * 4, v);
 }
 
+// Ensembles (E >= GHOST_MEMBER_LANES): the same two steps with one thread
+// per (boundary or ghost node, member), members in consecutive lanes, so
+// every stencil slot and band position is one coalesced load across the
+// wavefront. Sums run in slot / band order, so such members agree with
+// single-member runs to rounding rather than bit for bit.
+constexpr int GHOST_MEMBER_LANES = 16;
+
+template <class FT>
+__global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_members_kernel(GArgs a) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * RHS_BLOCK + threadIdx.x;
+  const int E = a.E;
+  if (t >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
+  const int64_t wb = t / E;
+  const int e = static_cast<int>(t - wb * E);
+  FT *y = static_cast<FT *>(a.y);
+  double ru = 0.0, rw = 0.0, rt = 0.0, rp = 0.0;
+  // branch-free body so that several slots' loads are in flight: a ghost
+  // entry (kind 2) contributes an exact zero, as does w at a wall node
+#pragma unroll 4
+  for (int k = 0; k < a.n; ++k) {
+    const int64_t s = wb * a.n + k;
+    const int j = a.wall_idx[s];
+    const uint8_t kj = a.kind[j];
+    const double2 ww = a.wall_w[s];
+    const F4<FT> f = load4(y + (static_cast<int64_t>(j) * E + e) * 4);
+    const bool g = kj == 2, wz = kj != 0;
+    ru = fma(-ww.x, g ? 0.0 : static_cast<double>(f.v[0]), ru);
+    rt = fma(-ww.x, g ? 0.0 : static_cast<double>(f.v[2]), rt);
+    rp = fma(-ww.x, g ? 0.0 : static_cast<double>(f.v[3]), rp);
+    rw = fma(-ww.y, wz ? 0.0 : static_cast<double>(f.v[1]), rw);
+  }
+  const int node = a.wall_nodes[wb];
+  const double thb = static_cast<double>(y[(static_cast<int64_t>(node) * E + e) * 4 + 2]);
+  rp += a.bc_scale * thb / (a.theta_bar + thb);
+  y[(static_cast<int64_t>(node) * E + e) * 4 + 1] = FT(0);
+  double *g = a.gres + (wb * E + e) * 4;
+  g[0] = ru;
+  g[1] = rw;
+  g[2] = rt;
+  g[3] = rp;
+}
+
+template <class FT>
+__global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_members_kernel(GArgs a) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * RHS_BLOCK + threadIdx.x;
+  const int E = a.E;
+  if (t >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
+  const int64_t wg = t / E;
+  const int e = static_cast<int>(t - wg * E);
+  const int wl = static_cast<int>(wg / a.nb), gp = static_cast<int>(wg - static_cast<int64_t>(wl) * a.nb);
+  const int64_t row_z = (static_cast<int64_t>(wl) * 2 + 0) * a.nb + gp;
+  const int64_t row_zz = (static_cast<int64_t>(wl) * 2 + 1) * a.nb + gp;
+  const double *z1 = a.ginv + row_z * a.band;
+  const double *z2 = a.ginv + row_zz * a.band;
+  const int p1 = a.gstart[row_z], p2 = a.gstart[row_zz];
+  const double *r = a.gres + static_cast<int64_t>(wl) * a.nb * E * 4;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  int b1 = p1, b2 = p2;
+#pragma unroll 4
+  for (int q = 0; q < a.band; ++q) {
+    const double c1 = z1[q], c2 = z2[q];
+    const double4 r1 = *reinterpret_cast<const double4 *>(r + (static_cast<int64_t>(b1) * E + e) * 4);
+    v[0] = fma(c1, r1.x, v[0]);
+    v[2] = fma(c1, r1.z, v[2]);
+    v[3] = fma(c1, r1.w, v[3]);
+    v[1] = fma(c2, r[(static_cast<int64_t>(b2) * E + e) * 4 + 1], v[1]);
+    if (++b1 == a.nb) b1 = 0;
+    if (++b2 == a.nb) b2 = 0;
+  }
+  store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.ghost_nodes[wg]) * E + e) * 4, v);
+}
+
 __global__ void misc_init_kernel(DevMisc *m, double t0) {
   m->nonfinite_step = INT_MAX;
   m->step_ctr = 0;
@@ -404,8 +476,20 @@ int launch_ghost(rbffd_ctx *ctx, rbffd_model *m, void *y) {
   g.n_walls = m->n_walls;
   g.bc_scale = m->g / (m->c_p * m->theta_bar);
   g.theta_bar = m->theta_bar;
-  const int64_t cnt = static_cast<int64_t>(m->n_walls) * m->nb * m->E;  // one wavefront each
-  const unsigned grid = grid_for(cnt, RHS_BLOCK / 64);
+  const int64_t cnt = static_cast<int64_t>(m->n_walls) * m->nb * m->E;
+  if (m->E >= GHOST_MEMBER_LANES) {                                       // one thread each
+    const unsigned grid = grid_for(cnt, RHS_BLOCK);
+    if (m->fdt == RBFFD_F64) {
+      ghost_resid_members_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+      ghost_apply_members_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+    } else {
+      ghost_resid_members_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+      ghost_apply_members_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+    }
+    RBFFD_HIP(ctx, hipGetLastError());
+    return RBFFD_OK;
+  }
+  const unsigned grid = grid_for(cnt, RHS_BLOCK / 64);                   // one wavefront each
   if (m->fdt == RBFFD_F64) {
     ghost_resid_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
     ghost_apply_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);

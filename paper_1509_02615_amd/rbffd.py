@@ -72,9 +72,11 @@ _lib.rbffd_model_tune.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int), c
 
 class ClosureDesc(ctypes.Structure):
     _fields_ = [("max_samples", _i64), ("init_params", _vp), ("node_feature", _vp),
-                ("in_scale", ctypes.c_float * 4), ("out_scale", ctypes.c_float * 4)]
+                ("in_scale", ctypes.c_float * 4), ("out_scale", ctypes.c_float * 4),
+                ("activation", ctypes.c_int32)]
 
 
+ACT_TANH, ACT_RELU = 0, 1
 CLOSURE_NPARAMS = 128 * 160 + 128 + 128 * 128 + 128 + 16 * 128 + 16
 _lib.rbffd_closure_create.argtypes = [_vp, _vp, ctypes.POINTER(ClosureDesc), ctypes.POINTER(_vp)]
 _lib.rbffd_closure_destroy.argtypes = [_vp]
@@ -297,11 +299,12 @@ class Closure:
     Navier-Stokes model."""
 
     def __init__(self, ctx: Context, model: Model, init_params, node_feature, in_scale, out_scale,
-                 max_samples=None):
+                 max_samples=None, activation=ACT_TANH):
         self.ctx, self.model = ctx, model
         d = ClosureDesc(max_samples=int(max_samples or model.Na * model.E),
                         init_params=_ptr(init_params, torch.float32, (CLOSURE_NPARAMS,), "init_params"),
-                        node_feature=_ptr(node_feature, torch.float64, (model.Na,), "node_feature"))
+                        node_feature=_ptr(node_feature, torch.float64, (model.Na,), "node_feature"),
+                        activation=int(activation))
         d.in_scale[:] = [float(v) for v in in_scale]
         d.out_scale[:] = [float(v) for v in out_scale]
         h = _vp()

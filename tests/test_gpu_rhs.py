@@ -180,6 +180,33 @@ def test_ensemble_members_equal_single_runs(R, ctx):
         assert torch.equal(o3[:, k, :], singles[k])
 
 
+@pytest.mark.parametrize("E", [16, 64])
+def test_large_ensemble_members_match_single_runs(R, ctx, E):
+    """From 16 members on, the ghost closure runs one member per lane with
+    its sums in slot order (and from 64 the stage kernel one member per
+    wavefront): each member agrees with its single-member run to FP32
+    rounding."""
+    import torch
+    say(f"rhs: ensemble E={E} (FP32) vs single-member evaluations, rel-l2 <= 1e-6 per member")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", 400.0)
+    states = [smooth_ns_state(cfg["nodes"], seed=30 + k).astype(np.float32) for k in range(E)]
+    g1 = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=1, wdt=1)
+    gE = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=1, wdt=1, E=E)
+    sE = dev(np.stack(states, axis=1), torch.float32).contiguous()
+    oE = torch.empty_like(sE)
+    R.rbffd_rhs(ctx, gE, 0.0, sE, oE)
+    worst = 0.0
+    for k in range(0, E, 5):
+        s = dev(states[k], torch.float32).reshape(g1.state_shape()).contiguous()
+        o = torch.empty_like(s)
+        R.rbffd_rhs(ctx, g1, 0.0, s, o)
+        a, b = oE[:, k, :].double(), o.reshape(-1, 4).double()
+        for c in range(4):
+            worst = max(worst, float(torch.linalg.norm(a[:, c] - b[:, c]) / torch.linalg.norm(b[:, c])))
+    say(f"   worst per-field rel-l2 {worst:.2e}")
+    assert worst <= 1e-6
+
+
 def test_advection_rhs_and_bell_run(R, ctx):
     import torch
     say("transport: 64x64 rhs at t=0.7 and the full 2000-step RK4 bell run (FP64)")

@@ -3,19 +3,21 @@ bfloat16 rounding it emulates, and the feature definition on fields whose
 stencil differences are known."""
 
 import numpy as np
+import pytest
 import torch
 
 from oracle import closure as C
 
 
-def test_gradient_matches_finite_differences():
+@pytest.mark.parametrize("act", [C.TANH, C.RELU])
+def test_gradient_matches_finite_differences(act):
     rng = np.random.default_rng(0)
     p = C.init_params(seed=3).astype(np.float64)
     p[C.OB1:C.OW2] = rng.normal(0, 0.1, C.HID)
     p[C.OB3:C.OB3 + 4] = rng.normal(0, 0.1, 4)
     X = rng.normal(0, 1, (40, C.KIN))
     T = rng.normal(0, 1, (40, 4))
-    loss, g = C.loss_and_grad(p, X, T)
+    loss, g = C.loss_and_grad(p, X, T, act=act)
     picks = np.concatenate([rng.choice(np.arange(C.OW1, C.OB1), 12), rng.choice(np.arange(C.OB1, C.OW2), 4),
                             rng.choice(np.arange(C.OW2, C.OB2), 12), rng.choice(np.arange(C.OB2, C.OW3), 4),
                             rng.choice(np.arange(C.OW3, C.OW3 + 4 * C.HID), 8), np.arange(C.OB3, C.OB3 + 4)])
@@ -24,8 +26,11 @@ def test_gradient_matches_finite_differences():
         pp, pm = p.copy(), p.copy()
         pp[q] += h
         pm[q] -= h
-        fd = (C.loss_and_grad(pp, X, T)[0] - C.loss_and_grad(pm, X, T)[0]) / (2 * h)
+        fd = (C.loss_and_grad(pp, X, T, act=act)[0] - C.loss_and_grad(pm, X, T, act=act)[0]) / (2 * h)
         assert abs(fd - g[q]) <= 1e-6 * max(1e-3, abs(g[q])) + 1e-10, (q, fd, g[q])
+    if act == C.RELU:   # both layers have units on each side of the kink
+        _, H1, H2, _ = C.forward(p, X, act=act)
+        assert 0.2 < (H1 > 0).mean() < 0.8 and 0.2 < (H2 > 0).mean() < 0.8
     # unused padded outputs get no gradient
     assert np.all(g[C.OW3 + 4 * C.HID:C.OB3] == 0.0) and np.all(g[C.OB3 + 4:] == 0.0)
 
