@@ -162,14 +162,26 @@ __device__ __forceinline__ bf8v gather_block(const float *__restrict__ y, const 
   return x;
 }
 
-// Y[s][0..3] for S samples, T tiles of 16 samples per wavefront, two
-// wavefronts per SIMD; blocks of 4 wavefronts loop over contiguous unit
-// ranges (XCD-aware block order).
+// Y[s][0..3] for S samples, T tiles of 16 samples per wavefront; blocks of
+// MLP_WAVES wavefronts share one LDS copy of the weights and loop over
+// contiguous unit ranges (XCD-aware block order); MLP_OCC wavefronts per SIMD
+// bound the registers. Measured on 557,056 samples: one 16-wavefront block
+// per compute unit at four wavefronts per SIMD and T = 1 is fastest (more
+// wavefronts hide the gather latency better than larger tiles save LDS
+// reads of the weight fragments).
 #ifndef RBFFD_MLP_T
-#define RBFFD_MLP_T 2
+#define RBFFD_MLP_T 1
 #endif
+#ifndef RBFFD_MLP_WAVES
+#define RBFFD_MLP_WAVES 16
+#endif
+#ifndef RBFFD_MLP_OCC
+#define RBFFD_MLP_OCC 4
+#endif
+constexpr int MLP_WAVES = RBFFD_MLP_WAVES, MLP_OCC = RBFFD_MLP_OCC;
 template <int T, int ACT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void mlp_forward_kernel(
+__global__ __launch_bounds__(64 * MLP_WAVES) __attribute__((amdgpu_waves_per_eu(MLP_OCC, MLP_OCC))) void
+mlp_forward_kernel(
     const float *__restrict__ y, const int *__restrict__ idx_t, int64_t Na, int n, int E,
     const float *__restrict__ nodef, float4 inv, const __bf16 *__restrict__ frag_g, const float *__restrict__ params,
     float *__restrict__ Y, int64_t S) {
@@ -179,8 +191,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   {
     const f4v *src = reinterpret_cast<const f4v *>(frag_g);
     f4v *dst = reinterpret_cast<f4v *>(mlp_lds);
-    for (int k = threadIdx.x; k < NFRAG * 64; k += 256) dst[k] = src[k];
-    for (int k = threadIdx.x; k < NBIAS; k += 256)
+    for (int k = threadIdx.x; k < NFRAG * 64; k += 64 * MLP_WAVES) dst[k] = src[k];
+    for (int k = threadIdx.x; k < NBIAS; k += 64 * MLP_WAVES)
       s_bias[k] = k < HID ? params[OB1 + k] : (k < 2 * HID ? params[OB2 + k - HID] : params[OB3 + k - 2 * HID]);
   }
   __syncthreads();
@@ -191,7 +203,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int64_t lb = b >= full ? b : (b % 8) * (nb / 8) + b / 8;
   const int64_t per = (units + nb - 1) / nb;
   const int64_t u_end = min(units, (lb + 1) * per);
-  for (int64_t u = lb * per + wave; u < u_end; u += 4) {
+  for (int64_t u = lb * per + wave; u < u_end; u += MLP_WAVES) {
     const int64_t base = u * 16 * T;
     // keeps the weight fragments' LDS reads inside the loop: hoisted out of
     // it as loop-invariant they would need 304 registers
@@ -208,53 +220,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       own[tl] = *reinterpret_cast<const float4 *>(y + s * 4);
       nodev[tl] = nodef[si[tl]];
     }
-    // layer 1: 8 output tiles, 5 contraction blocks gathered one at a time
-    f4v acc[8][T];
+    // output tile outermost: only one tile's accumulators are live, so the
+    // whole input (5 blocks) and both hidden fragments fit in 128 registers
+    // and four wavefronts run per SIMD
+    bf8v x[5][T];
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      bf8v x[T];
+    for (int j = 0; j < 5; ++j)
 #pragma unroll
       for (int tl = 0; tl < T; ++tl)
-        x[tl] = gather_block(y, idx_t, Na, n, E, nodev[tl], inv, si[tl], se[tl], own[tl], 8 * j + 2 * g);
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const bf8v a = s_frag[(t * 5 + j) * 64 + lane];
-        const f4v c0 = s_b4[4 * t + g];
-#pragma unroll
-        for (int tl = 0; tl < T; ++tl)
-          acc[t][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x[tl], j == 0 ? c0 : acc[t][tl], 0, 0, 0);
-      }
-    }
+        x[j][tl] = gather_block(y, idx_t, Na, n, E, nodev[tl], inv, si[tl], se[tl], own[tl], 8 * j + 2 * g);
     bf8v hb[4][T];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int t = 0; t < 8; ++t) {
+      f4v acc[T];
+      const f4v c0 = s_b4[4 * t + g];
 #pragma unroll
-      for (int tl = 0; tl < T; ++tl)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          hb[j][tl][i] = static_cast<__bf16>(act_fn<ACT>(acc[2 * j][tl][i]));
-          hb[j][tl][4 + i] = static_cast<__bf16>(act_fn<ACT>(acc[2 * j + 1][tl][i]));
-        }
-    // layer 2
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const bf8v a = s_frag[FR1 * 64 + (t * 4 + j) * 64 + lane];
-        const f4v c0 = s_b4[32 + 4 * t + g];
+      for (int j = 0; j < 5; ++j) {
+        const bf8v a = s_frag[(t * 5 + j) * 64 + lane];
 #pragma unroll
         for (int tl = 0; tl < T; ++tl)
-          acc[t][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[j][tl], j == 0 ? c0 : acc[t][tl], 0, 0, 0);
+          acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x[j][tl], j == 0 ? c0 : acc[tl], 0, 0, 0);
       }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int tl = 0; tl < T; ++tl)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          hb[j][tl][i] = static_cast<__bf16>(act_fn<ACT>(acc[2 * j][tl][i]));
-          hb[j][tl][4 + i] = static_cast<__bf16>(act_fn<ACT>(acc[2 * j + 1][tl][i]));
-        }
+        for (int i = 0; i < 4; ++i) hb[t >> 1][tl][4 * (t & 1) + i] = static_cast<__bf16>(act_fn<ACT>(acc[tl][i]));
+    }
+    bf8v hb2[4][T];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      f4v acc[T];
+      const f4v c0 = s_b4[32 + 4 * t + g];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bf8v a = s_frag[FR1 * 64 + (t * 4 + j) * 64 + lane];
+#pragma unroll
+        for (int tl = 0; tl < T; ++tl)
+          acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, hb[j][tl], j == 0 ? c0 : acc[tl], 0, 0, 0);
+      }
+#pragma unroll
+      for (int tl = 0; tl < T; ++tl)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) hb2[t >> 1][tl][4 * (t & 1) + i] = static_cast<__bf16>(act_fn<ACT>(acc[tl][i]));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int tl = 0; tl < T; ++tl) hb[j][tl] = hb2[j][tl];
     // layer 3: one output tile, outputs 0..3 in the lanes of group 0
     f4v out[T];
     const f4v c3 = s_b4[64 + g];
@@ -550,14 +562,18 @@ template <int ACT> void set_mlp_lds(bool &ok) {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(MLP_LDS)) == hipSuccess;
 }
 
-// Fused forward pass into cl->Yc [S][4]: at most two blocks of 4 wavefronts
-// per compute unit (the packed weights take 77 KB of LDS per block).
+// Fused forward pass into cl->Yc [S][4]. Resident blocks per compute unit:
+// as many as LDS (160 KB, 77 KB of packed weights each) and the SIMDs'
+// wavefront slots allow; the grid is one wave of them.
 int forward_fused(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int64_t S) {
   rbffd_model *m = cl->model;
+  constexpr int per_cu = std::min<int>(static_cast<int>((160 * 1024) / MLP_LDS), 4 * MLP_OCC / MLP_WAVES);
+  static_assert(per_cu >= 1, "fused forward launch shape");
   const int64_t units = (S + 16 * MLP_T - 1) / (16 * MLP_T);
-  const unsigned nb = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(512, (units + 3) / 4)));
+  const unsigned nb = static_cast<unsigned>(
+      std::max<int64_t>(1, std::min<int64_t>(256 * per_cu, (units + MLP_WAVES - 1) / MLP_WAVES)));
   auto launch = [&](auto kern) {
-    kern<<<nb, 256, MLP_LDS, ctx->stream>>>(static_cast<const float *>(state), cl->idx.as<int>(), m->Na, m->n, m->E,
+    kern<<<nb, 64 * MLP_WAVES, MLP_LDS, ctx->stream>>>(static_cast<const float *>(state), cl->idx.as<int>(), m->Na, m->n, m->E,
                                             cl->nodef.as<float>(), cl->inv_in, cl->frag.as<__bf16>(),
                                             cl->params.as<float>(), cl->Yc.as<float>(), S);
   };
