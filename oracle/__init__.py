@@ -21,9 +21,9 @@ It shares no code with the HIP path; both read their inputs from the
 
 from .stencils import knn, min_image
 from .weights import (
-    DX, DZ, LAP, HYPERLAP, DZZ, poly_exponents, phs_apply, poly_apply,
+    DX, DZ, LAP, HYPERLAP, DZZ, DXX, poly_exponents, phs_apply, poly_apply,
     stencil_weights, all_weights, op_order,
 )
 from .rhs import apply_dm, dm_matrix, advection_rhs, AdvectionModel, ghost_matrices, ghost_closure, ns_rhs, ns_tendency, NSModel
 from .timestep import rk4_step, wsrk3_step, integrate
-from .diagnostics import rel_l2, front_location, extrema, translating_fronts
+from .diagnostics import rel_l2, front_location, extrema, translating_fronts, bubble_height

@@ -59,3 +59,27 @@ def translating_fronts(xy, theta, bottom_nodes, center=18000.0, level=-0.5):
     xl = x[i] + (level - th[i]) / (th[i + 1] - th[i]) * (x[i + 1] - x[i])
     xr = x[j] - (level - th[j]) / (th[j - 1] - th[j]) * (x[j] - x[j - 1])
     return float(center - xl), float(xr - center)
+
+
+def bubble_height(xy, theta, rows, x0=5000.0, level=0.1):
+    """Table tbl:bubble: the height where the ``level`` contour of theta'
+    crosses the line x = x0, taken at the top of the bubble. Per node row,
+    theta' and z are interpolated linearly in x to x0; the topmost row with
+    theta' >= level and the row above it are then interpolated linearly in
+    z."""
+    zs, ts = [], []
+    for r in rows:
+        x = xy[r, 0]
+        o = np.argsort(x)
+        x, z, t = x[o], xy[r, 1][o], theta[r][o]
+        k = int(np.searchsorted(x, x0))
+        if k == 0 or k == x.size:
+            continue
+        a = (x0 - x[k - 1]) / (x[k] - x[k - 1])
+        zs.append(z[k - 1] + a * (z[k] - z[k - 1]))
+        ts.append(t[k - 1] + a * (t[k] - t[k - 1]))
+    zs, ts = np.array(zs), np.array(ts)
+    top = np.nonzero(ts >= level)[0][-1]
+    if top == zs.size - 1:
+        return float(zs[top])
+    return float(zs[top] + (level - ts[top]) / (ts[top + 1] - ts[top]) * (zs[top + 1] - zs[top]))

@@ -7,23 +7,29 @@ closure and the PDE right-hand sides.
 * ``advection_rhs``: flux-form transport psi_t = -(u psi)_x - (v psi)_y
   (Section 6.1) plus hyperviscosity hv_coeff * Lap^k psi (Section 5.3), with
   velocity (U, V)(x) * cos(pi t / vel_period).
-* ``ghost_closure``: Section 5.2. For each wall and boundary condition the
-  boundary-node rows of a differentiation matrix split as
-  W_I u_I + W_B u_B + W_G u_G = bc, so u_G = W_G^-1 (bc - W_I u_I - W_B u_B),
-  solved here with a dense LU of W_G. Section 6.4 boundary conditions:
-  du/dz = dtheta'/dz = 0, dpi'/dz = g theta' / (c_p theta_bar (theta_bar +
-  theta')), w = 0 and d2w/dz2 = 0. Order: w_B is set to 0 first; the four
-  ghost solves are then independent.
+* ``ghost_closure``: Section 5.2. Each boundary row (a boundary node, its
+  ghost, and the normal of its wall) carries one equation per field; the
+  rows of a differentiation matrix split as W_I u_I + W_B u_B + W_G u_G = bc,
+  so u_G = W_G^-1 (bc - W_I u_I - W_B u_B), solved here with a sparse LU of
+  W_G (all rows together: near a corner of a box the rows of two walls share
+  ghosts). Boundary conditions, with n the wall normal:
+  walls normal to z (Section 6.4, Eq. BCbubble): du/dz = dtheta'/dz = 0,
+  dpi'/dz = g theta' / (c_p theta_bar (theta_bar + theta')), w = 0 and
+  d2w/dz2 = 0; walls normal to x (Section 6.5): u = 0, d2u/dx2 = 0,
+  dw/dx = dtheta'/dx = dpi'/dx = 0. Order: w_B (resp. u_B) is set to 0
+  first; the four ghost solves are then independent.
 * ``ns_rhs``: Eqs. uEq, wEq, thetaEq, piEq with mu * Lap on u, w, theta' and
-  hv_coeff * Lap^k on all four fields; dw/dt = 0 on the walls (w_B stays 0).
-  A uniform background wind u_bar (consts["u_bar"], the translating density
-  current of Section 6.4) is added to u in the advective terms.
+  hv_coeff * Lap^k on all four fields; dw/dt = 0 on walls normal to z and
+  du/dt = 0 on walls normal to x (those values stay 0). A uniform
+  background wind u_bar (consts["u_bar"], the translating density current of
+  Section 6.4) is added to u in the advective terms.
 """
 
 from dataclasses import dataclass
 import numpy as np
 import scipy.linalg
 import scipy.sparse
+import scipy.sparse.linalg
 
 
 def apply_dm(idx: np.ndarray, w: np.ndarray, f: np.ndarray) -> np.ndarray:
@@ -64,23 +70,22 @@ class AdvectionModel:
             + self.hv_coeff * (self.Dhv @ psi)
 
 
-def ghost_matrices(idx, w_wall, wall_nodes, ghost_nodes):
-    """Split the wall rows of a differentiation matrix (weights ``w_wall``
-    [n_walls][n_wall][n] at the nodes ``wall_nodes``) into the ghost block
-    W_G [n_walls][n_wall][n_wall] and the rest. Returns W_G."""
-    n_walls, nb = wall_nodes.shape
-    WG = np.zeros((n_walls, nb, nb))
-    for wl in range(n_walls):
-        pos = {int(g): p for p, g in enumerate(ghost_nodes[wl])}
-        others = set(int(g) for o in range(n_walls) if o != wl for g in ghost_nodes[o])
-        for b, node in enumerate(wall_nodes[wl]):
-            for k, j in enumerate(idx[node]):
-                j = int(j)
-                if j in pos:
-                    WG[wl, b, pos[j]] += w_wall[wl, b, k]
-                elif j in others:
-                    raise ValueError("a wall stencil reaches the other wall's ghosts")
-    return WG
+def ghost_matrices(idx, rows_w, bnd_nodes, bnd_ghosts):
+    """The ghost block W_G [R][R] (sparse) of one operator per boundary row:
+    row r holds the weights ``rows_w[r]`` of the stencil of node
+    ``bnd_nodes[r]`` at the ghost columns, column c being ghost
+    ``bnd_ghosts[c]``."""
+    col = {int(g): c for c, g in enumerate(bnd_ghosts)}
+    R = len(bnd_nodes)
+    r_i, c_i, v = [], [], []
+    for r, node in enumerate(bnd_nodes):
+        for k, j in enumerate(idx[node]):
+            c = col.get(int(j))
+            if c is not None:
+                r_i.append(r)
+                c_i.append(c)
+                v.append(rows_w[r][k])
+    return scipy.sparse.csc_matrix((v, (r_i, c_i)), shape=(R, R))
 
 
 @dataclass
@@ -93,52 +98,58 @@ class NSModel:
     w_hv: np.ndarray
     z: np.ndarray              # [n_total] node heights
     n_active: int
-    wall_nodes: np.ndarray     # [n_walls][n_wall]
-    ghost_nodes: np.ndarray    # [n_walls][n_wall]
-    wall_dz: np.ndarray        # [n_walls][n_wall][n] Dz weights at wall nodes
-    wall_dzz: np.ndarray       # [n_walls][n_wall][n] Dzz weights at wall nodes
-    consts: dict               # c_p, c_v, R_d, g, theta_bar, mu
+    bnd_nodes: np.ndarray      # [R] boundary node of each boundary row
+    bnd_ghosts: np.ndarray     # [R] its ghost
+    bnd_normal: np.ndarray     # [R] 0: wall normal to z, 1: wall normal to x
+    bnd_d1: np.ndarray         # [R][n] first normal-derivative weights (Dz or Dx)
+    bnd_d2: np.ndarray         # [R][n] second normal-derivative weights (Dzz or Dxx)
+    consts: dict               # c_p, c_v, R_d, g, theta_bar, mu (u_bar)
     hv_coeff: float
 
     def __post_init__(self):
-        self.WG_dz = ghost_matrices(self.idx, self.wall_dz, self.wall_nodes, self.ghost_nodes)
-        self.WG_dzz = ghost_matrices(self.idx, self.wall_dzz, self.wall_nodes, self.ghost_nodes)
-        self.lu_dz = [scipy.linalg.lu_factor(m) for m in self.WG_dz]
-        self.lu_dzz = [scipy.linalg.lu_factor(m) for m in self.WG_dzz]
+        zn = (self.bnd_normal == 0)[:, None]
+        self.w_u = np.where(zn, self.bnd_d1, self.bnd_d2)      # du/dz, or d2u/dx2
+        self.w_w = np.where(zn, self.bnd_d2, self.bnd_d1)      # d2w/dz2, or dw/dx
+        mats = [ghost_matrices(self.idx, W, self.bnd_nodes, self.bnd_ghosts)
+                for W in (self.w_u, self.w_w, self.bnd_d1)]
+        self.lu = [scipy.sparse.linalg.splu(m) for m in mats] if len(self.bnd_nodes) else []
         ghost = np.zeros(self.z.shape[0], bool)
-        ghost[self.ghost_nodes.ravel()] = True
+        ghost[self.bnd_ghosts] = True
         self.is_ghost = ghost
+        self.zwall = np.zeros(self.n_active, bool)
+        self.zwall[self.bnd_nodes[self.bnd_normal == 0]] = True
+        self.xwall = np.zeros(self.n_active, bool)
+        self.xwall[self.bnd_nodes[self.bnd_normal == 1]] = True
 
 
 def ghost_closure(model: NSModel, state: np.ndarray) -> np.ndarray:
     """Return a copy of ``state`` [n_total][4] (u, w, theta', pi') with w = 0
-    on the walls and the ghost rows set from the Section 5.2 solve."""
+    on walls normal to z, u = 0 on walls normal to x, and the ghost rows set
+    from the Section 5.2 solve."""
     s = np.array(state, dtype=np.float64, copy=True)
+    if not len(model.bnd_nodes):
+        return s
     c = model.consts
-    s[model.wall_nodes.ravel(), 1] = 0.0
-    for wl in range(model.wall_nodes.shape[0]):
-        nodes = model.wall_nodes[wl]
-        rows = model.idx[nodes]                              # [n_wall][n]
-        keep = ~model.is_ghost[rows]                         # non-ghost entries
-        wz = np.where(keep, model.wall_dz[wl], 0.0)
-        wzz = np.where(keep, model.wall_dzz[wl], 0.0)
-        th_b = s[nodes, 2]
-        bc = {0: 0.0, 1: 0.0, 2: 0.0,
-              3: c["g"] * th_b / (c["c_p"] * c["theta_bar"] * (c["theta_bar"] + th_b))}
-        for f in range(4):
-            if f == 1:
-                r = -apply_dm(rows, wzz, s[:, 1])
-                g = scipy.linalg.lu_solve(model.lu_dzz[wl], r)
-            else:
-                r = bc[f] - apply_dm(rows, wz, s[:, f])
-                g = scipy.linalg.lu_solve(model.lu_dz[wl], r)
-            s[model.ghost_nodes[wl], f] = g
+    s[np.nonzero(model.zwall)[0], 1] = 0.0
+    s[np.nonzero(model.xwall)[0], 0] = 0.0
+    nodes = model.bnd_nodes
+    rows = model.idx[nodes]                                  # [R][n]
+    keep = ~model.is_ghost[rows]                             # non-ghost entries
+    th_b = s[nodes, 2]
+    bc_pi = np.where(model.bnd_normal == 0,
+                     c["g"] * th_b / (c["c_p"] * c["theta_bar"] * (c["theta_bar"] + th_b)), 0.0)
+    for f, W, lu, bc in ((0, model.w_u, model.lu[0], 0.0), (1, model.w_w, model.lu[1], 0.0),
+                         (2, model.bnd_d1, model.lu[2], 0.0), (3, model.bnd_d1, model.lu[2], bc_pi)):
+        r = bc - apply_dm(rows, np.where(keep, W, 0.0), s[:, f])
+        s[model.bnd_ghosts, f] = lu.solve(r)
     return s
 
 
-def ns_tendency(s, rows, idx, w_dx, w_dz, w_lap, w_hv, z, is_wall, consts, hv_coeff):
+def ns_tendency(s, rows, idx, w_dx, w_dz, w_lap, w_hv, z, is_wall, consts, hv_coeff, is_xwall=None):
     """Eqs. uEq..piEq at the nodes ``rows`` of a closed state ``s`` [n_total][4]
-    (ghost rows filled), given those rows' stencils and weights."""
+    (ghost rows filled), given those rows' stencils and weights. ``is_wall``
+    marks rows on walls normal to z (dw/dt = 0), ``is_xwall`` rows on walls
+    normal to x (du/dt = 0)."""
     c = consts
     u, w, th, pi = (s[rows, f] for f in range(4))
     ua = u + c.get("u_bar", 0.0)     # background wind (translating density current)
@@ -156,6 +167,8 @@ def ns_tendency(s, rows, idx, w_dx, w_dz, w_lap, w_hv, z, is_wall, consts, hv_co
         - (c["R_d"] / c["c_v"]) * (pibar + pi) * (dx[:, 0] + dz[:, 1])
     out += hv_coeff * hv
     out[is_wall, 1] = 0.0
+    if is_xwall is not None:
+        out[is_xwall, 0] = 0.0
     return out
 
 
@@ -164,9 +177,8 @@ def ns_rhs(model: NSModel, state: np.ndarray):
     closed state (ghost rows filled) it was evaluated on."""
     s = ghost_closure(model, state)
     na = model.n_active
-    is_wall = np.zeros(na, bool)
-    is_wall[model.wall_nodes.ravel()] = True
     out = np.zeros_like(s)
     out[:na] = ns_tendency(s, np.arange(na), model.idx, model.w_dx, model.w_dz, model.w_lap,
-                           model.w_hv, model.z[:na], is_wall, model.consts, model.hv_coeff)
+                           model.w_hv, model.z[:na], model.zwall, model.consts, model.hv_coeff,
+                           model.xwall)
     return out, s

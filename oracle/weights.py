@@ -28,6 +28,7 @@ Operator right-hand sides for phi = r^m (d = 2):
   Lap^k: prod_{i<k} (m-2i)^2 r^(m-2k)   (Eq. eqn:laplacian applied k times;
                               continuous only for m >= 2k+1, Section 5.3)
   Dzz : m r^(m-2) + m(m-2) r^(m-4) z_j^2
+  Dxx : m r^(m-2) + m(m-2) r^(m-4) x_j^2
 and 0 at the centre node (r = 0) for every operator.
 Polynomial rows hold L p_q at the centre: Lap^k(x^a z^b) at 0 is
 C(k, a/2) a! b! when a + b = 2k with a, b even, else 0.
@@ -42,7 +43,7 @@ import scipy.linalg
 
 from .stencils import min_image
 
-DX, DZ, LAP, HYPERLAP, DZZ = 1, 2, 3, 4, 5
+DX, DZ, LAP, HYPERLAP, DZZ, DXX = 1, 2, 3, 4, 5, 6
 
 
 def poly_exponents(l: int):
@@ -52,7 +53,7 @@ def poly_exponents(l: int):
 
 def op_order(kind: int, k: int = 0) -> int:
     """Derivative order q of the operator (weights scale as rho^-q)."""
-    return {DX: 1, DZ: 1, LAP: 2, DZZ: 2, HYPERLAP: 2 * k}[kind]
+    return {DX: 1, DZ: 1, LAP: 2, DZZ: 2, DXX: 2, HYPERLAP: 2 * k}[kind]
 
 
 def phs_apply(kind: int, m: int, k: int, x: np.ndarray, z: np.ndarray) -> np.ndarray:
@@ -83,6 +84,8 @@ def phs_apply(kind: int, m: int, k: int, x: np.ndarray, z: np.ndarray) -> np.nda
         out[nz] = c * rn ** (m - 2 * k)
     elif kind == DZZ:
         out[nz] = m * rn ** (m - 2) + m * (m - 2) * rn ** (m - 4) * z[nz] ** 2
+    elif kind == DXX:
+        out[nz] = m * rn ** (m - 2) + m * (m - 2) * rn ** (m - 4) * x[nz] ** 2
     else:
         raise ValueError(kind)
     return out
@@ -98,6 +101,8 @@ def poly_apply(kind: int, k: int, a: int, b: int) -> float:
         return 2.0 if (a, b) in ((2, 0), (0, 2)) else 0.0
     if kind == DZZ:
         return 2.0 if (a, b) == (0, 2) else 0.0
+    if kind == DXX:
+        return 2.0 if (a, b) == (2, 0) else 0.0
     if kind == HYPERLAP:
         if a + b != 2 * k or a % 2 or b % 2:
             return 0.0

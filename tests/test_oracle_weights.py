@@ -15,7 +15,7 @@ from oracle.weights import poly_exponents
 from workloads import unit_square_cartesian, jittered_square, channel
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-OPS = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0), (O.DZZ, 0, 0)]
+OPS = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0), (O.DZZ, 0, 0), (O.DXX, 0, 0)]
 
 
 def test_unisolvent_case_is_central_differences():
@@ -41,7 +41,7 @@ def _sym_ops(m, k):
     for _ in range(k):
         hk = lap(hk)
     exprs = {O.DX: sp.diff(phi, x), O.DZ: sp.diff(phi, z), O.LAP: lap(phi),
-             O.DZZ: sp.diff(phi, z, 2), O.HYPERLAP: hk}
+             O.DZZ: sp.diff(phi, z, 2), O.DXX: sp.diff(phi, x, 2), O.HYPERLAP: hk}
     return {kk: sp.lambdify((a, b), e.subs({x: 0, z: 0}), "mpmath") for kk, e in exprs.items()}
 
 
@@ -52,12 +52,12 @@ def test_operator_rhs_matches_symbolic_derivatives(m, k):
     f = _sym_ops(m, k)
     rng = np.random.default_rng(5)
     pts = rng.uniform(-1, 1, (12, 2))
-    for kind in (O.DX, O.DZ, O.LAP, O.DZZ, O.HYPERLAP):
+    for kind in (O.DX, O.DZ, O.LAP, O.DZZ, O.DXX, O.HYPERLAP):
         got = O.phs_apply(kind, m, k, pts[:, 0], pts[:, 1])
         ref = np.array([float(f[kind](p[0], p[1])) for p in pts])
         np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14)
     # the centre (r = 0) entry is zero for every operator
-    for kind in (O.DX, O.DZ, O.LAP, O.DZZ, O.HYPERLAP):
+    for kind in (O.DX, O.DZ, O.LAP, O.DZZ, O.DXX, O.HYPERLAP):
         assert O.phs_apply(kind, m, k, np.zeros(1), np.zeros(1))[0] == 0.0
 
 
@@ -71,6 +71,7 @@ def test_poly_rows_match_symbolic():
                 h = sp.diff(h, x, 2) + sp.diff(h, z, 2)
             assert O.poly_apply(O.HYPERLAP, k, a, b) == float(h.subs({x: 0, z: 0}))
             assert O.poly_apply(O.DZZ, 0, a, b) == float(sp.diff(e, z, 2).subs({x: 0, z: 0}))
+            assert O.poly_apply(O.DXX, 0, a, b) == float(sp.diff(e, x, 2).subs({x: 0, z: 0}))
 
 
 def _stencils():
@@ -142,7 +143,7 @@ def _mp_exact_weights(xy, st, c, m, l, ops, period):
         for q, (a, b) in enumerate(exps):
             e = X ** a * Z ** b
             h = {O.DX: sp.diff(e, X), O.DZ: sp.diff(e, Z), O.LAP: sp.diff(e, X, 2) + sp.diff(e, Z, 2),
-                 O.DZZ: sp.diff(e, Z, 2)}.get(kind)
+                 O.DZZ: sp.diff(e, Z, 2), O.DXX: sp.diff(e, X, 2)}.get(kind)
             if kind == O.HYPERLAP:
                 h = e
                 for _ in range(k):
@@ -163,7 +164,7 @@ def test_exact_solution_40_digits(m, l, n):
     would move the weights by ~5e-10."""
     for xy, c, per in _stencils()[::2]:
         st = O.knn(xy, [c], n, per)[0]
-        ops = [(O.DX, 0), (O.LAP, 0), (O.HYPERLAP, (m - 1) // 2)]
+        ops = [(O.DX, 0), (O.LAP, 0), (O.DXX, 0), (O.HYPERLAP, (m - 1) // 2)]
         W, _ = O.stencil_weights(xy, st, c, m, l, [(kk, k, 0) for kk, k in ops], per)
         ref = _mp_exact_weights(xy, st, c, m, l, ops, per)
         for j in range(len(ops)):

@@ -68,6 +68,22 @@ def translating_config(layout: str = "hexagonal", h: float = 100.0, seed: int = 
     return cfg
 
 
+def bubble_config(layout: str = "cartesian", h: float = 200.0, seed: int = 0, mu: float = 10.0,
+                  tableau: str = "rk4"):
+    """Rising thermal bubble (Section 6.5): the closed box [0, 10] x [0, 10]
+    km with walls on all four sides, mu = 10 m^2/s, a warm 2 K cone of radius
+    1.5 km at (5, 3) km, run to t = 1100 s with the time step of Section
+    6.3's table."""
+    from .nodes import box
+    from .fields import bubble_state
+    nodes = box(layout, h, 10000.0, 10000.0, seed=seed)
+    cfg = _ns_config(nodes, f"rising-bubble-{layout}-{int(h)}m", DT_TABLE[float(h)], tableau)
+    cfg["consts"]["mu"] = mu
+    cfg["t_end"] = 1100.0
+    cfg["state0"] = bubble_state(nodes)
+    return cfg
+
+
 def scale_config(nx: int = 2048, nz: int = 256, tableau: str = "rk4"):
     """Density current on a 2048 x 256 hexagonal-row channel at 25 m column
     spacing (rows at 6400/255 m), 524,288 active nodes plus 2 x 2048 ghosts."""

@@ -55,6 +55,18 @@ def straka_state(nodes, amplitude: float = -15.0, c=NS_CONSTANTS, dtype=np.float
     return s.astype(dtype)
 
 
+def bubble_state(nodes, amplitude: float = 2.0, radius: float = 1500.0, center=(5000.0, 3000.0),
+                 dtype=np.float64) -> np.ndarray:
+    """Rising thermal bubble (Section 6.5): theta' = amplitude * max(0, 1 -
+    r / radius), a C0 cone around ``center``; u = w = pi' = 0. Ghost rows are
+    filled by the closure before use."""
+    s = np.zeros((nodes.n_total, 4), dtype=np.float64)
+    r = np.hypot(nodes.xy[:, 0] - center[0], nodes.xy[:, 1] - center[1])
+    s[:, 2] = amplitude * np.maximum(0.0, 1.0 - r / radius)
+    s[nodes.n_active:] = 0.0
+    return s.astype(dtype)
+
+
 def smooth_ns_state(nodes, seed: int = 2, modes: int = 4, dtype=np.float64) -> np.ndarray:
     """Seeded smooth developed-looking state [n_total][4] on an x-periodic
     channel: u, w ~ 15 m/s, theta' ~ 10 K, pi' ~ 1e-3, built from a few

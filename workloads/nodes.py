@@ -1,18 +1,23 @@
 """Node sets (Section 5.1: Cartesian, hexagonal, quasi-uniform scattered) and
-the ghost-node rows of Section 5.2, for the paper's test domains.
+the ghost nodes of Section 5.2, for the paper's test domains.
 
 Ordering convention used everywhere: active nodes (those that carry a stencil
 and prognostic values) come first, row by row from the bottom wall upwards,
-then the ghost rows (bottom ghost row, then top ghost row). Ghost node ``g`` of
-a wall sits in the ghost row next to boundary node ``g`` of the same wall.
+then the ghost nodes. Every boundary row pairs one boundary node with one
+ghost straight outside it and records the wall's normal direction
+(``bnd_nodes``, ``bnd_ghosts``, ``bnd_normal``: 0 for a wall normal to z,
+1 for a wall normal to x). A corner node of a closed box sits on two walls
+and so appears in two boundary rows, with one ghost for each.
 """
 
 from dataclasses import dataclass, field
 import numpy as np
 
 KIND_INTERIOR = 0
-KIND_WALL = 1
+KIND_WALL = 1          # on a wall normal to z (w = 0 there)
 KIND_GHOST = 2
+KIND_XWALL = 4         # on a wall normal to x (u = 0 there); corners carry 1 | 4
+NORMAL_Z, NORMAL_X = 0, 1
 
 
 @dataclass
@@ -27,6 +32,11 @@ class NodeSet:
     wall_nodes: np.ndarray = field(default_factory=lambda: np.zeros((0, 0), np.int32))
     ghost_nodes: np.ndarray = field(default_factory=lambda: np.zeros((0, 0), np.int32))
     height: float = 0.0
+    width: float = 0.0
+    bnd_nodes: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    bnd_ghosts: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    bnd_normal: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    rows: list = field(default_factory=list)    # active node indices of each row, bottom up
 
     @property
     def n_total(self) -> int:
@@ -35,8 +45,8 @@ class NodeSet:
     def kinds(self) -> np.ndarray:
         k = np.zeros(self.n_total, np.int8)
         k[self.n_active:] = KIND_GHOST
-        if self.wall_nodes.size:
-            k[self.wall_nodes.ravel()] = KIND_WALL
+        k[self.bnd_nodes[self.bnd_normal == NORMAL_Z]] |= KIND_WALL
+        k[self.bnd_nodes[self.bnd_normal == NORMAL_X]] |= KIND_XWALL
         return k
 
 
@@ -94,7 +104,70 @@ def channel(layout: str, nx: int, nz: int, x_left: float, length: float, height:
     wall = np.stack([np.arange(nx), (nz - 1) * nx + np.arange(nx)]).astype(np.int32)
     ghost = np.stack([n_active + np.arange(nx), n_active + nx + np.arange(nx)]).astype(np.int32)
     return NodeSet(xy=xy, n_active=n_active, period_x=length, h=hx, layout=layout,
-                   nx=nx, nz=nz, wall_nodes=wall, ghost_nodes=ghost, height=height)
+                   nx=nx, nz=nz, wall_nodes=wall, ghost_nodes=ghost, height=height, width=length,
+                   bnd_nodes=wall.ravel().copy(), bnd_ghosts=ghost.ravel().copy(),
+                   bnd_normal=np.zeros(2 * nx, np.int32),
+                   rows=[np.arange(r * nx, (r + 1) * nx) for r in range(nz)])
+
+
+def box(layout: str, h: float, width: float, height: float, seed: int = 0, jitter: float = 0.2) -> NodeSet:
+    """Closed box [0, width] x [0, height] with walls on all four sides and one
+    ghost straight outside every boundary node of every wall.
+
+    * ``cartesian``: columns x = i h (i = 0 .. width/h), rows h apart.
+    * ``hexagonal``: rows about h sqrt(3)/2 apart (count rounded so that the
+      top wall is a row); even rows x = i h, odd rows shifted by h/2 and
+      closed by a node on each lateral wall (x = 0 and x = width).
+    * ``scattered``: hexagonal positions jittered by U[-jitter h, jitter h]
+      in x and z, wall nodes along their wall only, corners fixed (PCG64
+      stream seeded with ``seed``).
+
+    Ghosts of the bottom and top walls sit one row spacing below/above their
+    boundary node; ghosts of the lateral walls one spacing h to the left/right.
+    """
+    if layout not in ("cartesian", "hexagonal", "scattered"):
+        raise ValueError(layout)
+    ncol = int(round(width / h)) + 1
+    if layout == "cartesian":
+        nz = int(round(height / h)) + 1
+    else:
+        nz = int(round(height / (h * np.sqrt(3.0) / 2.0))) + 1
+    dz = height / (nz - 1)
+    shifted = layout in ("hexagonal", "scattered")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts, rows, start = [], [], 0
+    for r in range(nz):
+        if shifted and r % 2:
+            x = np.concatenate([[0.0], (np.arange(ncol - 1) + 0.5) * h, [width]])
+        else:
+            x = np.arange(ncol, dtype=np.float64) * h
+            x[-1] = width
+        z = np.full(x.size, height if r == nz - 1 else r * dz)
+        if layout == "scattered":
+            side = (x == 0.0) | (x == width)
+            if 0 < r < nz - 1:
+                x = np.where(side, x, x + rng.uniform(-jitter * h, jitter * h, x.size))
+                z = z + rng.uniform(-jitter * h, jitter * h, x.size)
+            else:
+                x = np.where(side, x, x + rng.uniform(-jitter * h, jitter * h, x.size))
+        pts.append(np.stack([x, z], axis=1))
+        rows.append(np.arange(start, start + x.size))
+        start += x.size
+    n_active = start
+    bottom, top = rows[0], rows[-1]
+    left = np.array([rw[0] for rw in rows])
+    right = np.array([rw[-1] for rw in rows])
+    act = np.concatenate(pts, axis=0)
+    ghosts = [np.stack([act[bottom, 0], np.full(bottom.size, -dz)], axis=1),
+              np.stack([act[top, 0], np.full(top.size, height + dz)], axis=1),
+              np.stack([np.full(nz, -h), act[left, 1]], axis=1),
+              np.stack([np.full(nz, width + h), act[right, 1]], axis=1)]
+    xy = np.concatenate([act] + ghosts, axis=0)
+    bnd = np.concatenate([bottom, top, left, right]).astype(np.int32)
+    normal = np.concatenate([np.zeros(bottom.size + top.size), np.ones(2 * nz)]).astype(np.int32)
+    return NodeSet(xy=xy, n_active=n_active, period_x=0.0, h=h, layout=layout, nx=ncol, nz=nz,
+                   height=height, width=width, bnd_nodes=bnd,
+                   bnd_ghosts=(n_active + np.arange(bnd.size)).astype(np.int32), bnd_normal=normal, rows=rows)
 
 
 def straka_nodes(layout: str, h: float, seed: int = 0) -> NodeSet:
