@@ -259,7 +259,7 @@ def main():
     xy, idx, W, Ww, (st_a, st_w) = P.ns_weights(ctx, cfg, xy=xy)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - s0
-    n_stencils = nd.n_active + nd.wall_nodes.size
+    n_stencils = nd.n_active + nd.bnd_nodes.size
     assert int(st_a.abs().sum()) == 0 and int(st_w.abs().sum()) == 0
     log(f"[bench] search + weights for {n_stencils} stencils: {setup_s:.3f} s")
 

@@ -55,7 +55,8 @@ typedef enum {
   RBFFD_DZ = 2,        /* d/dz (the second coordinate; d/dy in the unit square)  */
   RBFFD_LAP = 3,       /* Laplacian                                              */
   RBFFD_HYPERLAP = 4,  /* Laplacian^k, k = rbffd_op.k (Section 5.3)              */
-  RBFFD_DZZ = 5        /* d2/dz2 (wall closure of w, Section 6.4)                */
+  RBFFD_DZZ = 5,       /* d2/dz2 (wall closure of w, Section 6.4)                */
+  RBFFD_DXX = 6        /* d2/dx2 (lateral-wall closure of u, Section 6.5)        */
 } rbffd_op_kind;
 
 typedef struct {
@@ -162,22 +163,33 @@ typedef struct {
   double c_p, c_v, R_d, g, theta_bar, mu;
   double u_bar;           /* uniform background wind added to u in the advective terms
                              (translating density current, Section 6.4.2); 0 otherwise */
-  /* ghost closure (Section 5.2), Navier-Stokes only */
-  int32_t n_walls;        /* 0 or 2 (bottom, top)                                        */
-  int32_t n_wall;         /* boundary nodes per wall = ghost nodes per wall              */
-  const int32_t *wall_nodes;   /* [n_walls][n_wall] active indices of boundary nodes     */
-  const int32_t *ghost_nodes;  /* [n_walls][n_wall] ghost indices; ghost g pairs with
-                                  boundary node g (W_G rows/columns in this order)       */
-  const double *wall_dz;  /* [n_walls][n_wall][n] Dz weights of the boundary rows        */
-  const double *wall_dzz; /* [n_walls][n_wall][n] Dzz weights of the boundary rows       */
+  /* ghost closure (Section 5.2), Navier-Stokes only. One boundary row per
+   * (boundary node, wall): a corner node of a closed box has two rows, one
+   * per wall, each with its own ghost. Row r's stencil is idx[bnd_nodes[r]].
+   * Walls normal to z (bottom, top; Section 6.4): du/dz = dtheta'/dz = 0,
+   * dpi'/dz = g theta' / (c_p theta_bar (theta_bar + theta')), w = 0 and
+   * d2w/dz2 = 0. Walls normal to x (lateral; Section 6.5): u = 0,
+   * d2u/dx2 = 0, dw/dx = dtheta'/dx = dpi'/dx = 0. */
+  int32_t n_bnd;          /* number of boundary rows (0: no walls)                       */
+  int32_t reserved1;
+  const int32_t *bnd_nodes;   /* [n_bnd] active index of each row's boundary node        */
+  const int32_t *bnd_ghosts;  /* [n_bnd] its ghost node (each ghost in exactly one row;
+                                 every node >= n_active is a ghost)                      */
+  const int32_t *bnd_normal;  /* [n_bnd] 0: wall normal to z, 1: wall normal to x         */
+  const double *bnd_d1;   /* [n_bnd][n] weights of the first derivative along the normal
+                             (Dz or Dx) at the boundary node                             */
+  const double *bnd_d2;   /* [n_bnd][n] weights of the second derivative along the normal
+                             (Dzz or Dxx)                                                */
 } rbffd_model_desc;
 
 /* Build a model: repack stencils and weights into the library's slot-major
- * layout, mark wall nodes, and factor and invert each wall's ghost block W_G
- * (Section 5.2) once on the host, keeping the inverse to rounding accuracy
- * in a cyclic band. Synchronises. The caller's arrays may be freed after.
- * EINVAL: inconsistent sizes, a wall stencil that reaches the other wall's
- * ghosts; ESINGULAR: a singular W_G. */
+ * layout, mark wall nodes, and factor and invert the ghost blocks W_G
+ * (Section 5.2; one per field's operator set, split into the independent
+ * groups of rows that share no ghost) once on the host, keeping each inverse
+ * row to rounding accuracy as its entries above a certified cut-off.
+ * Synchronises. The caller's arrays may be freed after. EINVAL:
+ * inconsistent sizes or indices, a ghost listed twice or missing;
+ * ESINGULAR: a singular W_G. */
 int rbffd_model_create(rbffd_ctx *ctx, const rbffd_model_desc *desc, rbffd_model **out);
 int rbffd_model_destroy(rbffd_model *model);
 

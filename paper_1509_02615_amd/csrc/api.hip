@@ -92,7 +92,7 @@ int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops,
     return rbffd_fail(ctx, RBFFD_EINVAL, "degree l=%d outside 0..6", st->l_uniform);
   for (int i = 0; i < n_ops; ++i) {
     const rbffd_op &o = ops[i];
-    if (o.kind < RBFFD_DX || o.kind > RBFFD_DZZ || o.reserved != 0 || o.k < 0 || o.k > 7 ||
+    if (o.kind < RBFFD_DX || o.kind > RBFFD_DXX || o.reserved != 0 || o.k < 0 || o.k > 7 ||
         o.phs_order < 0 || o.phs_order > 15 || (o.phs_order && o.phs_order % 2 == 0))
       return rbffd_fail(ctx, RBFFD_EINVAL, "bad operator %d (kind %d k %d order %d)", i, o.kind,
                         o.k, o.phs_order);

@@ -1,16 +1,18 @@
 // Model set-up: repack the differentiation matrices into slot-major device
 // layouts, mark wall and ghost nodes, and prepare the ghost-node closure.
 //
-// Ghost closure (Section 5.2, Eq. bcEqn): at the boundary nodes of a wall,
+// Ghost closure (Section 5.2, Eq. bcEqn): at the boundary rows,
 // W_I u_I + W_B u_B + W_G u_G = bc, so u_G = W_G^-1 (bc - W_I u_I - W_B u_B).
-// W_G (boundary rows x ghost columns, one ghost per boundary node) is a
-// cyclic band matrix. It is factored once here on the host (LU with partial
-// pivoting that skips structural zeros) and inverted column by column. Its
-// inverse decays geometrically away from the band, so each row is stored as
-// the cyclic window, centred on the row's largest entry, outside of which the
-// l1 mass is below 2^-56 of the row's l1 mass: applying the window is the
-// exact solve up to rounding. Each Runge-Kutta stage then applies the
-// windows on the GPU.
+// W_G has one row per boundary row and one column per ghost; there are three
+// of them (the operators applied to u, to w, and to theta' and pi'). The rows
+// split into groups that share no ghost (the two walls of a channel; the
+// whole perimeter of a closed box, whose corner rows couple two walls); each
+// group's block is factored once here on the host (LU with partial pivoting
+// that skips structural zeros) and inverted column by column. The inverse
+// decays geometrically away from a row's own ghost, so each inverse row keeps
+// only its entries above a cut-off chosen so that the dropped l1 mass is
+// below 2^-56 of the row's l1 mass: applying the kept entries is the exact
+// solve up to rounding. Each Runge-Kutta stage applies them on the GPU.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -89,12 +91,9 @@ __global__ void pibar_kernel(const double *__restrict__ xy, int64_t na, double g
   if (i < na) pb[i] = 1.0 - gk * xy[2 * i + 1];
 }
 
-__global__ void kind_kernel(uint8_t *__restrict__ kind, int64_t n_total, int64_t na, const int *__restrict__ walls,
-                            int count) {
+__global__ void kind_kernel(uint8_t *__restrict__ kind, int64_t n_total, int64_t na) {
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n_total) kind[i] = i < na ? 0 : 2;
-  // wall marks are written by a second launch of the same kernel (count > 0)
-  if (count > 0 && i < count) kind[walls[i]] = 1;
+  if (i < n_total) kind[i] = i < na ? 0 : KIND_GHOST;
 }
 
 // ---- host-side ghost block factorisation ---------------------------------
@@ -167,35 +166,28 @@ bool invert_sparse_lu(int n, std::vector<double> &A, std::vector<double> &inv) {
   return true;
 }
 
-// Half-width h of the cyclic window [c - h, c + h] around the row maximum c
-// that leaves at most 2^-56 of the row's l1 mass outside. The outside mass
-// is accumulated from the far end inwards (small terms first), so it is not
-// the difference of two rounded sums. Returns (n - 1) / 2 + 1 when no window
-// shorter than the row qualifies.
-int window_halfwidth(const double *row, int n, int &center) {
-  double total = 0.0, best = -1.0;
-  center = 0;
-  for (int j = 0; j < n; ++j) {
-    double v = std::fabs(row[j]);
-    total += v;
-    if (v > best) {
-      best = v;
-      center = j;
-    }
-  }
+// Indices of the entries of `row` (length n) to keep: all but the smallest
+// ones whose l1 mass stays below 2^-56 of the row's l1 mass. The dropped
+// mass is accumulated smallest first, so it is not the difference of two
+// rounded sums. Returned in increasing index order.
+std::vector<int> certified_support(const double *row, int n) {
+  std::vector<int> order(n);
+  for (int j = 0; j < n; ++j) order[j] = j;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return std::fabs(row[a]) < std::fabs(row[b]); });
+  double total = 0.0;
+  for (int j : order) total += std::fabs(row[j]);
   const double tol = std::ldexp(total, -56);
-  const int hmax = (n - 1) / 2;
-  auto at = [&](int d) { return std::fabs(row[((center + d) % n + n) % n]); };
-  double tail = (n % 2 == 0) ? at(n / 2) : 0.0;  // mass at distance > hmax
-  if (tail > tol) return hmax + 1;
-  int h = hmax;
-  while (h > 0) {
-    const double next = tail + at(h) + at(-h);  // mass at distance > h - 1
-    if (next > tol) break;
-    tail = next;
-    --h;
-  }
-  return h;
+  double dropped = 0.0;
+  int first = 0;
+  while (first < n && dropped + std::fabs(row[order[first]]) <= tol) dropped += std::fabs(row[order[first++]]);
+  std::vector<int> keep(order.begin() + first, order.end());
+  std::sort(keep.begin(), keep.end());
+  return keep;
+}
+
+int find_root(std::vector<int> &parent, int x) {
+  while (parent[x] != x) x = parent[x] = parent[parent[x]];
+  return x;
 }
 
 }  // namespace
@@ -225,9 +217,11 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
   if (d->physics == RBFFD_PHYS_ADVECTION && (!d->vel_u || !d->vel_v || !(d->vel_period != 0.0)))
     return rbffd_fail(ctx, RBFFD_EINVAL, "transport needs vel_u, vel_v and vel_period");
   if (d->physics == RBFFD_PHYS_NS) {
-    if (d->n_walls != 0 && d->n_walls != 2) return rbffd_fail(ctx, RBFFD_EINVAL, "n_walls must be 0 or 2");
-    if (d->n_walls && (d->n_wall < 1 || !d->wall_nodes || !d->ghost_nodes || !d->wall_dz || !d->wall_dzz))
-      return rbffd_fail(ctx, RBFFD_EINVAL, "incomplete wall description");
+    if (d->n_bnd < 0) return rbffd_fail(ctx, RBFFD_EINVAL, "n_bnd must be >= 0");
+    if (d->n_bnd && (!d->bnd_nodes || !d->bnd_ghosts || !d->bnd_normal || !d->bnd_d1 || !d->bnd_d2))
+      return rbffd_fail(ctx, RBFFD_EINVAL, "incomplete boundary-row description");
+    if (static_cast<int64_t>(d->n_bnd) != d->n_total - d->n_active)
+      return rbffd_fail(ctx, RBFFD_EINVAL, "every node past n_active must be the ghost of one boundary row");
     if (!(d->c_p > 0 && d->c_v > 0 && d->theta_bar > 0))
       return rbffd_fail(ctx, RBFFD_EINVAL, "bad physical constants");
   }
@@ -297,102 +291,140 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
     pibar_kernel<<<grid_for(na, 256), 256, 0, s>>>(d->xy, na, d->g / (d->c_p * d->theta_bar), m->pibar.as<double>());
   }
   if (m->kind.alloc(m->N) != hipSuccess) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation");
-  kind_kernel<<<grid_for(m->N, 256), 256, 0, s>>>(m->kind.as<uint8_t>(), m->N, na, nullptr, 0);
+  kind_kernel<<<grid_for(m->N, 256), 256, 0, s>>>(m->kind.as<uint8_t>(), m->N, na);
   if (hipGetLastError() != hipSuccess) return fail_model(ctx, m, RBFFD_EDEVICE, "repack launch");
 
   // ghost closure
-  if (m->physics == RBFFD_PHYS_NS && d->n_walls == 2) {
-    const int nw = 2, nb = d->n_wall;
-    m->n_walls = nw;
-    m->nb = nb;
-    std::vector<int> h_wall(nw * nb), h_ghost(nw * nb), h_widx(static_cast<size_t>(nw) * nb * n);
-    std::vector<double> h_dz(static_cast<size_t>(nw) * nb * n), h_dzz(static_cast<size_t>(nw) * nb * n);
-    if (hipMemcpyAsync(h_wall.data(), d->wall_nodes, sizeof(int) * nw * nb, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(h_ghost.data(), d->ghost_nodes, sizeof(int) * nw * nb, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(h_dz.data(), d->wall_dz, sizeof(double) * h_dz.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(h_dzz.data(), d->wall_dzz, sizeof(double) * h_dzz.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (m->physics == RBFFD_PHYS_NS && d->n_bnd > 0) {
+    const int R = d->n_bnd;
+    m->n_bnd = R;
+    std::vector<int> h_node(R), h_ghost(R), h_norm(R), h_widx(static_cast<size_t>(R) * n);
+    std::vector<double> h_d1(static_cast<size_t>(R) * n), h_d2(static_cast<size_t>(R) * n);
+    if (hipMemcpyAsync(h_node.data(), d->bnd_nodes, sizeof(int) * R, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(h_ghost.data(), d->bnd_ghosts, sizeof(int) * R, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(h_norm.data(), d->bnd_normal, sizeof(int) * R, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(h_d1.data(), d->bnd_d1, sizeof(double) * h_d1.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(h_d2.data(), d->bnd_d2, sizeof(double) * h_d2.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
-      return fail_model(ctx, m, RBFFD_EDEVICE, "wall copy");
-    for (int i = 0; i < nw * nb; ++i) {
-      if (h_wall[i] < 0 || h_wall[i] >= na) return fail_model(ctx, m, RBFFD_EINVAL, "wall node not active");
-      if (h_ghost[i] < na || h_ghost[i] >= m->N) return fail_model(ctx, m, RBFFD_EINVAL, "ghost node index not a ghost");
-      if (hipMemcpyAsync(&h_widx[static_cast<size_t>(i) * n], d->idx + static_cast<int64_t>(h_wall[i]) * n,
+      return fail_model(ctx, m, RBFFD_EDEVICE, "boundary-row copy");
+    std::vector<int> gcol(R, -1);  // ghost (index - na) -> its row
+    for (int r = 0; r < R; ++r) {
+      if (h_node[r] < 0 || h_node[r] >= na) return fail_model(ctx, m, RBFFD_EINVAL, "boundary node not active");
+      if (h_ghost[r] < na || h_ghost[r] >= m->N) return fail_model(ctx, m, RBFFD_EINVAL, "ghost index not a ghost");
+      if (h_norm[r] != 0 && h_norm[r] != 1) return fail_model(ctx, m, RBFFD_EINVAL, "wall normal must be 0 or 1");
+      int &c = gcol[h_ghost[r] - static_cast<int>(na)];
+      if (c >= 0) return fail_model(ctx, m, RBFFD_EINVAL, "ghost node listed twice");
+      c = r;
+      if (hipMemcpyAsync(&h_widx[static_cast<size_t>(r) * n], d->idx + static_cast<int64_t>(h_node[r]) * n,
                          sizeof(int) * n, hipMemcpyDeviceToHost, s) != hipSuccess)
-        return fail_model(ctx, m, RBFFD_EDEVICE, "wall stencil copy");
+        return fail_model(ctx, m, RBFFD_EDEVICE, "boundary stencil copy");
     }
-    if (hipStreamSynchronize(s) != hipSuccess) return fail_model(ctx, m, RBFFD_EDEVICE, "wall stencil copy");
-    // ghost position per wall; W_G rows = boundary positions, columns = ghost positions
-    std::vector<int> gpos(m->N - na, -1), gwall(m->N - na, -1);
-    for (int wl = 0; wl < nw; ++wl)
-      for (int p = 0; p < nb; ++p) {
-        int gi = h_ghost[wl * nb + p] - static_cast<int>(na);
-        if (gwall[gi] >= 0) return fail_model(ctx, m, RBFFD_EINVAL, "ghost node listed twice");
-        gpos[gi] = p;
-        gwall[gi] = wl;
+    if (hipStreamSynchronize(s) != hipSuccess) return fail_model(ctx, m, RBFFD_EDEVICE, "boundary stencil copy");
+    // per field's operator: u takes d1 on z-normal rows and d2 on x-normal
+    // rows, w the reverse, theta' and pi' d1 everywhere
+    auto weight = [&](int mat, int r, int k) {
+      const size_t e = static_cast<size_t>(r) * n + k;
+      const bool zn = h_norm[r] == 0;
+      return mat == 2 ? h_d1[e] : ((mat == 0) == zn ? h_d1[e] : h_d2[e]);
+    };
+    // groups of rows that share ghosts (union-find over row - ghost-column links)
+    std::vector<int> parent(R);
+    for (int r = 0; r < R; ++r) parent[r] = r;
+    for (int r = 0; r < R; ++r)
+      for (int k = 0; k < n; ++k) {
+        const int j = h_widx[static_cast<size_t>(r) * n + k];
+        if (j >= na) {
+          const int a = find_root(parent, r), b = find_root(parent, gcol[j - static_cast<int>(na)]);
+          if (a != b) parent[a] = b;
+        }
       }
-    std::vector<double> h_ww(static_cast<size_t>(nw) * nb * n * 2);
-    std::vector<std::vector<double>> inv(nw * 2);
-    int half = 0;
-    std::vector<int> centers(nw * 2 * nb);
-    for (int wl = 0; wl < nw; ++wl) {
-      for (int op = 0; op < 2; ++op) {
-        const std::vector<double> &W = op == 0 ? h_dz : h_dzz;
-        std::vector<double> G(static_cast<size_t>(nb) * nb, 0.0);
-        for (int b = 0; b < nb; ++b)
-          for (int k = 0; k < n; ++k) {
-            size_t e = (static_cast<size_t>(wl) * nb + b) * n + k;
-            int j = h_widx[e];
-            if (j >= na) {
-              int gi = j - static_cast<int>(na);
-              if (gwall[gi] != wl) return fail_model(ctx, m, RBFFD_EINVAL, "wall stencil reaches another wall's ghosts");
-              G[static_cast<size_t>(b) * nb + gpos[gi]] += W[e];
+    std::vector<std::vector<int>> groups;
+    {
+      std::vector<int> gid(R, -1);
+      for (int r = 0; r < R; ++r) {
+        const int root = find_root(parent, r);
+        if (gid[root] < 0) {
+          gid[root] = static_cast<int>(groups.size());
+          groups.emplace_back();
+        }
+        groups[gid[root]].push_back(r);
+      }
+    }
+    // inverse rows of the three blocks, CSR over the ghost rows
+    std::vector<std::vector<std::pair<int, double>>> inv_rows(3 * static_cast<size_t>(R));
+    std::vector<int> local(R, -1);
+    for (const auto &grp : groups) {
+      const int gm = static_cast<int>(grp.size());
+      for (int i = 0; i < gm; ++i) local[grp[i]] = i;
+      bool has_x = false;
+      for (int r : grp) has_x = has_x || h_norm[r] == 1;
+      std::vector<double> inv_tp;
+      for (int mat : {2, 1, 0}) {
+        std::vector<double> inv;
+        if (mat == 0 && !has_x) {
+          inv = inv_tp;  // u and theta' take the same operator on z-normal rows
+        } else {
+          std::vector<double> G(static_cast<size_t>(gm) * gm, 0.0);
+          for (int i = 0; i < gm; ++i)
+            for (int k = 0; k < n; ++k) {
+              const int j = h_widx[static_cast<size_t>(grp[i]) * n + k];
+              if (j >= na) G[static_cast<size_t>(i) * gm + local[gcol[j - static_cast<int>(na)]]] += weight(mat, grp[i], k);
             }
-          }
-        if (!invert_sparse_lu(nb, G, inv[wl * 2 + op]))
-          return fail_model(ctx, m, RBFFD_ESINGULAR, "singular ghost block W_G");
-        for (int r = 0; r < nb; ++r) {
-          int c;
-          int h = window_halfwidth(&inv[wl * 2 + op][static_cast<size_t>(r) * nb], nb, c);
-          centers[(wl * 2 + op) * nb + r] = c;
-          half = std::max(half, h);
+          if (!invert_sparse_lu(gm, G, inv)) return fail_model(ctx, m, RBFFD_ESINGULAR, "singular ghost block W_G");
         }
+        for (int i = 0; i < gm; ++i) {
+          const double *row = &inv[static_cast<size_t>(i) * gm];
+          auto &out = inv_rows[static_cast<size_t>(mat) * R + grp[i]];
+          for (int q : certified_support(row, gm)) out.push_back({grp[q], row[q]});
+          std::sort(out.begin(), out.end());
+        }
+        if (mat == 2) inv_tp = std::move(inv);
       }
-      for (int b = 0; b < nb; ++b)
-        for (int k = 0; k < n; ++k) {
-          size_t e = (static_cast<size_t>(wl) * nb + b) * n + k;
-          bool ghost = h_widx[e] >= na;
-          h_ww[2 * e] = ghost ? 0.0 : h_dz[e];
-          h_ww[2 * e + 1] = ghost ? 0.0 : h_dzz[e];
-        }
     }
-    int band = std::min(2 * half + 1, nb);
-    m->band = band;
-    std::vector<double> h_band(static_cast<size_t>(nw) * 2 * nb * band);
-    std::vector<int> h_start(nw * 2 * nb);
-    for (int mat = 0; mat < nw * 2; ++mat)
-      for (int r = 0; r < nb; ++r) {
-        int st = band == nb ? 0 : centers[mat * nb + r] - half;
-        st = ((st % nb) + nb) % nb;
-        h_start[mat * nb + r] = st;
-        for (int t = 0; t < band; ++t)
-          h_band[(static_cast<size_t>(mat) * nb + r) * band + t] = inv[mat][static_cast<size_t>(r) * nb + (st + t) % nb];
+    std::vector<int> h_ptr(3 * (static_cast<size_t>(R) + 1)), h_col;
+    std::vector<double> h_val;
+    for (int mat = 0; mat < 3; ++mat) {
+      h_ptr[static_cast<size_t>(mat) * (R + 1)] = static_cast<int>(h_col.size());
+      for (int r = 0; r < R; ++r) {
+        for (auto &e : inv_rows[static_cast<size_t>(mat) * R + r]) {
+          h_col.push_back(e.first);
+          h_val.push_back(e.second);
+        }
+        h_ptr[static_cast<size_t>(mat) * (R + 1) + r + 1] = static_cast<int>(h_col.size());
+        m->inv_max_row = std::max<int>(m->inv_max_row, static_cast<int>(inv_rows[static_cast<size_t>(mat) * R + r].size()));
       }
-    ok = m->wall_nodes.alloc(sizeof(int) * nw * nb) == hipSuccess &&
-         m->ghost_nodes.alloc(sizeof(int) * nw * nb) == hipSuccess &&
-         m->wall_idx.alloc(sizeof(int) * h_widx.size()) == hipSuccess &&
+    }
+    // boundary weights with ghost entries zeroed; node kinds
+    std::vector<double> h_ww(static_cast<size_t>(R) * n * 2);
+    for (int r = 0; r < R; ++r)
+      for (int k = 0; k < n; ++k) {
+        const size_t e = static_cast<size_t>(r) * n + k;
+        const bool ghost = h_widx[e] >= na;
+        h_ww[2 * e] = ghost ? 0.0 : h_d1[e];
+        h_ww[2 * e + 1] = ghost ? 0.0 : h_d2[e];
+      }
+    std::vector<uint8_t> h_kind(static_cast<size_t>(m->N), 0);
+    for (int64_t i = na; i < m->N; ++i) h_kind[i] = KIND_GHOST;
+    for (int r = 0; r < R; ++r) h_kind[h_node[r]] |= h_norm[r] == 0 ? KIND_ZWALL : KIND_XWALL;
+    ok = m->bnd_nodes.alloc(sizeof(int) * R) == hipSuccess && m->bnd_ghosts.alloc(sizeof(int) * R) == hipSuccess &&
+         m->bnd_normal.alloc(sizeof(int) * R) == hipSuccess && m->wall_idx.alloc(sizeof(int) * h_widx.size()) == hipSuccess &&
          m->wall_w.alloc(sizeof(double) * h_ww.size()) == hipSuccess &&
-         m->ginv.alloc(sizeof(double) * h_band.size()) == hipSuccess &&
-         m->gstart.alloc(sizeof(int) * h_start.size()) == hipSuccess &&
-         m->gres.alloc(sizeof(double) * nw * nb * m->E * 4) == hipSuccess;
+         m->inv_ptr.alloc(sizeof(int) * h_ptr.size()) == hipSuccess &&
+         m->inv_col.alloc(sizeof(int) * std::max<size_t>(1, h_col.size())) == hipSuccess &&
+         m->inv_val.alloc(sizeof(double) * std::max<size_t>(1, h_val.size())) == hipSuccess &&
+         m->gres.alloc(sizeof(double) * R * m->E * 4) == hipSuccess;
     if (!ok) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation (closure)");
-    ok = hipMemcpy(m->wall_nodes.p, h_wall.data(), sizeof(int) * nw * nb, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(m->ghost_nodes.p, h_ghost.data(), sizeof(int) * nw * nb, hipMemcpyHostToDevice) == hipSuccess &&
+    ok = hipMemcpy(m->bnd_nodes.p, h_node.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->bnd_ghosts.p, h_ghost.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->bnd_normal.p, h_norm.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(m->wall_idx.p, h_widx.data(), sizeof(int) * h_widx.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(m->wall_w.p, h_ww.data(), sizeof(double) * h_ww.size(), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(m->ginv.p, h_band.data(), sizeof(double) * h_band.size(), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(m->gstart.p, h_start.data(), sizeof(int) * h_start.size(), hipMemcpyHostToDevice) == hipSuccess;
+         hipMemcpy(m->inv_ptr.p, h_ptr.data(), sizeof(int) * h_ptr.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         (h_col.empty() ||
+          (hipMemcpy(m->inv_col.p, h_col.data(), sizeof(int) * h_col.size(), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(m->inv_val.p, h_val.data(), sizeof(double) * h_val.size(), hipMemcpyHostToDevice) == hipSuccess)) &&
+         hipMemcpy(m->kind.p, h_kind.data(), static_cast<size_t>(m->N), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) return fail_model(ctx, m, RBFFD_EDEVICE, "closure upload");
-    kind_kernel<<<grid_for(nw * nb, 256), 256, 0, s>>>(m->kind.as<uint8_t>(), 0, na, m->wall_nodes.as<int>(), nw * nb);
   }
   // RK buffers
   const size_t sb = m->state_bytes();

@@ -20,6 +20,10 @@ struct RecAdv {      // transport: folded flux weights and Lap^k
   double adv, hv;
 };
 
+// Node kinds (bits): on a wall normal to z (w = 0), ghost, on a wall normal
+// to x (u = 0); a corner of a closed box carries both wall bits.
+constexpr uint8_t KIND_ZWALL = 1, KIND_GHOST = 2, KIND_XWALL = 4;
+
 struct rbffd_model {
   rbffd_ctx *ctx = nullptr;
   int physics = 0, fdt = RBFFD_F64, wdt = RBFFD_F64;
@@ -29,18 +33,20 @@ struct rbffd_model {
   DevBuf idx_t;     // int32 [n][Na] (F64 and transport layouts)
   DevBuf rec;       // RecF64 / RecF32 / RecBF16 / RecAdv [n][Na]
   DevBuf hv_t;      // double [n][Na] (F32 / BF16 layouts)
-  DevBuf kind;      // uint8 [N]: 0 interior, 1 wall, 2 ghost
+  DevBuf kind;      // uint8 [N]: KIND_* bits (0: interior)
   DevBuf pibar;     // double [Na]
   double hv_coeff = 0.0, vel_period = 1.0;
   double c_p = 0, c_v = 0, R_d = 0, g = 0, theta_bar = 0, mu = 0, u_bar = 0;
-  // ghost closure
-  int n_walls = 0, nb = 0, band = 0;
-  DevBuf wall_nodes, ghost_nodes;  // int32 [n_walls][nb]
-  DevBuf wall_idx;                 // int32 [n_walls][nb][n]
-  DevBuf wall_w;                   // double2 {dz, dzz} [n_walls][nb][n], ghost entries zeroed
-  DevBuf ginv;                     // double [n_walls][2][nb][band]  (0: Dz, 1: Dzz)
-  DevBuf gstart;                   // int32 [n_walls][2][nb]
-  DevBuf gres;                     // double [n_walls][nb][E][4]
+  // ghost closure over R boundary rows
+  int n_bnd = 0, inv_max_row = 0;
+  DevBuf bnd_nodes, bnd_ghosts;    // int32 [R]
+  DevBuf bnd_normal;               // int32 [R]: 0 wall normal to z, 1 normal to x
+  DevBuf wall_idx;                 // int32 [R][n] the rows' stencils
+  DevBuf wall_w;                   // double2 {d1, d2} [R][n], ghost entries zeroed
+  DevBuf inv_ptr;                  // int32 [3][R+1] CSR starts of W_G^-1 rows (u, w, theta'/pi')
+  DevBuf inv_col;                  // int32 [nnz] boundary row of each kept entry
+  DevBuf inv_val;                  // double [nnz]
+  DevBuf gres;                     // double [R][E][4] residuals
   // time stepping
   DevBuf ya, yb, acc;              // [N][E][F] stage buffers
   DevBuf dev_misc;                 // {int nonfinite_step, int step_ctr, double t0}

@@ -208,7 +208,9 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
   f[2] = -ua * sdx[2] - w * sdz[2] + a.mu * slp[2] + a.hv * shv[2];
   f[3] = -ua * sdx[3] - w * (a.dpibar + static_cast<double>(sdz[3])) -
          a.rcv * (a.pibar[i] + pi) * (static_cast<double>(sdx[0]) + static_cast<double>(sdz[1])) + a.hv * shv[3];
-  if (a.kind[i] == 1) f[1] = 0.0;  // w stays 0 on the walls
+  const uint8_t kd = a.kind[i];
+  if (kd & KIND_ZWALL) f[1] = 0.0;  // w stays 0 on walls normal to z
+  if (kd & KIND_XWALL) f[0] = 0.0;  // u stays 0 on walls normal to x
   const int64_t o = (i * E + e) * 4;
   double r[4];
   if (a.mode == 0) {
@@ -286,13 +288,14 @@ __global__ __launch_bounds__(RHS_BLOCK) void adv_stage_kernel(AdvArgs a) {
 
 struct GArgs {
   void *y;  // [N][E][4]
-  const int *wall_nodes, *ghost_nodes, *wall_idx, *gstart;
-  const double2 *wall_w;
-  const double *ginv;
-  double *gres;
+  const int *bnd_nodes, *bnd_ghosts, *bnd_normal, *wall_idx;
+  const double2 *wall_w;   // {d1, d2} per (row, slot), ghost entries zeroed
+  const int *inv_ptr, *inv_col;
+  const double *inv_val;
+  double *gres;            // [R][E][4]
   const uint8_t *kind;
-  int nb, n, E, band, n_walls;
-  double bc_scale, theta_bar;  // dpi/dz = bc_scale * th / (theta_bar + th)
+  int R, n, E;
+  double bc_scale, theta_bar;  // dpi/dz = bc_scale * th / (theta_bar + th) on walls normal to z
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -300,151 +303,147 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// B1 part 1: boundary-row residuals r = bc - (W_I u_I + W_B u_B), w_B := 0.
-// One wavefront per (boundary node, member); lanes take stencil slots.
+// One stencil slot's contribution to the residuals of a boundary row with
+// normal `nrm`: u takes d1 on walls normal to z and d2 on walls normal to x,
+// w the reverse, theta' and pi' d1. Values at ghosts count as 0 (their
+// weights are zeroed as well), w at nodes on walls normal to z and u at
+// nodes on walls normal to x are 0 (they are being set to 0).
 template <class FT>
-__global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_kernel(GArgs a) {
-  const int64_t item = static_cast<int64_t>(blockIdx.x) * (RHS_BLOCK / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int E = a.E;
-  if (item >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
-  const int64_t wb = item / E;  // wall * nb + b
-  const int e = static_cast<int>(item - wb * E);
+__device__ __forceinline__ void resid_slot(const GArgs &a, int64_t row, int k, int e, int nrm, double &ru, double &rw,
+                                           double &rt, double &rp) {
+  const int64_t sl = row * a.n + k;
+  const int j = a.wall_idx[sl];
+  const uint8_t kj = a.kind[j];
+  const double2 ww = a.wall_w[sl];
+  const F4<FT> f = load4(static_cast<const FT *>(a.y) + (static_cast<int64_t>(j) * a.E + e) * 4);
+  const bool g = kj & KIND_GHOST;
+  const double wu = nrm ? ww.y : ww.x, wv = nrm ? ww.x : ww.y;
+  ru = fma(-wu, (g || (kj & KIND_XWALL)) ? 0.0 : static_cast<double>(f.v[0]), ru);
+  rw = fma(-wv, (g || (kj & KIND_ZWALL)) ? 0.0 : static_cast<double>(f.v[1]), rw);
+  rt = fma(-ww.x, g ? 0.0 : static_cast<double>(f.v[2]), rt);
+  rp = fma(-ww.x, g ? 0.0 : static_cast<double>(f.v[3]), rp);
+}
+
+// Finish a row: boundary-condition data, the wall value set to 0, residuals out.
+template <class FT>
+__device__ __forceinline__ void resid_store(const GArgs &a, int64_t row, int e, int nrm, double ru, double rw,
+                                            double rt, double rp) {
   FT *y = static_cast<FT *>(a.y);
-  const int node = a.wall_nodes[wb];
-  double ru = 0.0, rw = 0.0, rt = 0.0, rp = 0.0;
-  for (int k = lane; k < a.n; k += 64) {
-    const int64_t s = wb * a.n + k;
-    const int j = a.wall_idx[s];
-    const uint8_t kj = a.kind[j];
-    if (kj == 2) continue;  // ghost entries form W_G
-    const double2 ww = a.wall_w[s];
-    const F4<FT> f = load4(y + (static_cast<int64_t>(j) * E + e) * 4);
-    ru = fma(-ww.x, static_cast<double>(f.v[0]), ru);
-    rt = fma(-ww.x, static_cast<double>(f.v[2]), rt);
-    rp = fma(-ww.x, static_cast<double>(f.v[3]), rp);
-    if (kj != 1) rw = fma(-ww.y, static_cast<double>(f.v[1]), rw);  // wall w is 0
-  }
-  ru = wave_sum(ru);
-  rw = wave_sum(rw);
-  rt = wave_sum(rt);
-  rp = wave_sum(rp);
-  if (lane == 0) {
-    const double thb = static_cast<double>(y[(static_cast<int64_t>(node) * E + e) * 4 + 2]);
+  const int64_t o = (static_cast<int64_t>(a.bnd_nodes[row]) * a.E + e) * 4;
+  if (nrm == 0) {
+    const double thb = static_cast<double>(y[o + 2]);
     rp += a.bc_scale * thb / (a.theta_bar + thb);
-    y[(static_cast<int64_t>(node) * E + e) * 4 + 1] = FT(0);
-    double *g = a.gres + (wb * E + e) * 4;
-    g[0] = ru;
-    g[1] = rw;
-    g[2] = rt;
-    g[3] = rp;
+    y[o + 1] = FT(0);
+  } else {
+    y[o + 0] = FT(0);
   }
-}
-
-// B1 part 2: ghost values u_G = W_G^-1 r through the banded inverse.
-// One wavefront per (ghost node, member); lanes take band positions.
-template <class FT>
-__global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_kernel(GArgs a) {
-  const int64_t item = static_cast<int64_t>(blockIdx.x) * (RHS_BLOCK / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int E = a.E;
-  if (item >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
-  const int64_t wg = item / E;  // wall * nb + ghost position
-  const int e = static_cast<int>(item - wg * E);
-  const int wl = static_cast<int>(wg / a.nb), gp = static_cast<int>(wg - static_cast<int64_t>(wl) * a.nb);
-  const int64_t row_z = (static_cast<int64_t>(wl) * 2 + 0) * a.nb + gp;   // Dz rows: u, theta', pi'
-  const int64_t row_zz = (static_cast<int64_t>(wl) * 2 + 1) * a.nb + gp;  // Dzz rows: w
-  const double *z1 = a.ginv + row_z * a.band;
-  const double *z2 = a.ginv + row_zz * a.band;
-  const int p1 = a.gstart[row_z], p2 = a.gstart[row_zz];
-  const double *r = a.gres + static_cast<int64_t>(wl) * a.nb * E * 4;
-  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-  for (int q = lane; q < a.band; q += 64) {
-    int b1 = p1 + q;
-    if (b1 >= a.nb) b1 -= a.nb;
-    int b2 = p2 + q;
-    if (b2 >= a.nb) b2 -= a.nb;
-    const double c1 = z1[q], c2 = z2[q];
-    const double *r1 = r + (static_cast<int64_t>(b1) * E + e) * 4;
-    v0 = fma(c1, r1[0], v0);
-    v2 = fma(c1, r1[2], v2);
-    v3 = fma(c1, r1[3], v3);
-    v1 = fma(c2, r[(static_cast<int64_t>(b2) * E + e) * 4 + 1], v1);
-  }
-  double v[4] = {wave_sum(v0), wave_sum(v1), wave_sum(v2), wave_sum(v3)};
-  if (lane == 0) store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.ghost_nodes[wg]) * E + e) * 4, v);
-}
-
-// Ensembles (E >= GHOST_MEMBER_LANES): the same two steps with one thread
-// per (boundary or ghost node, member), members in consecutive lanes, so
-// every stencil slot and band position is one coalesced load across the
-// wavefront. Sums run in slot / band order, so such members agree with
-// single-member runs to rounding rather than bit for bit.
-constexpr int GHOST_MEMBER_LANES = 16;
-
-template <class FT>
-__global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_members_kernel(GArgs a) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * RHS_BLOCK + threadIdx.x;
-  const int E = a.E;
-  if (t >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
-  const int64_t wb = t / E;
-  const int e = static_cast<int>(t - wb * E);
-  FT *y = static_cast<FT *>(a.y);
-  double ru = 0.0, rw = 0.0, rt = 0.0, rp = 0.0;
-  // branch-free body so that several slots' loads are in flight: a ghost
-  // entry (kind 2) contributes an exact zero, as does w at a wall node
-#pragma unroll 4
-  for (int k = 0; k < a.n; ++k) {
-    const int64_t s = wb * a.n + k;
-    const int j = a.wall_idx[s];
-    const uint8_t kj = a.kind[j];
-    const double2 ww = a.wall_w[s];
-    const F4<FT> f = load4(y + (static_cast<int64_t>(j) * E + e) * 4);
-    const bool g = kj == 2, wz = kj != 0;
-    ru = fma(-ww.x, g ? 0.0 : static_cast<double>(f.v[0]), ru);
-    rt = fma(-ww.x, g ? 0.0 : static_cast<double>(f.v[2]), rt);
-    rp = fma(-ww.x, g ? 0.0 : static_cast<double>(f.v[3]), rp);
-    rw = fma(-ww.y, wz ? 0.0 : static_cast<double>(f.v[1]), rw);
-  }
-  const int node = a.wall_nodes[wb];
-  const double thb = static_cast<double>(y[(static_cast<int64_t>(node) * E + e) * 4 + 2]);
-  rp += a.bc_scale * thb / (a.theta_bar + thb);
-  y[(static_cast<int64_t>(node) * E + e) * 4 + 1] = FT(0);
-  double *g = a.gres + (wb * E + e) * 4;
+  double *g = a.gres + (row * a.E + e) * 4;
   g[0] = ru;
   g[1] = rw;
   g[2] = rt;
   g[3] = rp;
 }
 
+// B1 part 1: boundary-row residuals r = bc - (W_I u_I + W_B u_B).
+// One wavefront per (boundary row, member); lanes take stencil slots.
+template <class FT>
+__global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_kernel(GArgs a) {
+  const int64_t item = static_cast<int64_t>(blockIdx.x) * (RHS_BLOCK / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (item >= static_cast<int64_t>(a.R) * a.E) return;
+  const int64_t row = item / a.E;
+  const int e = static_cast<int>(item - row * a.E);
+  const int nrm = a.bnd_normal[row];
+  double ru = 0.0, rw = 0.0, rt = 0.0, rp = 0.0;
+  for (int k = lane; k < a.n; k += 64) resid_slot<FT>(a, row, k, e, nrm, ru, rw, rt, rp);
+  ru = wave_sum(ru);
+  rw = wave_sum(rw);
+  rt = wave_sum(rt);
+  rp = wave_sum(rp);
+  if (lane == 0) resid_store<FT>(a, row, e, nrm, ru, rw, rt, rp);
+}
+
+// B1 part 2: ghost values u_G = W_G^-1 r through the kept inverse entries.
+// One wavefront per (ghost row, member); lanes take entries.
+template <class FT>
+__global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_kernel(GArgs a) {
+  const int64_t item = static_cast<int64_t>(blockIdx.x) * (RHS_BLOCK / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (item >= static_cast<int64_t>(a.R) * a.E) return;
+  const int64_t row = item / a.E;
+  const int e = static_cast<int>(item - row * a.E);
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int mat = 0; mat < 3; ++mat) {
+    const int *ptr = a.inv_ptr + static_cast<int64_t>(mat) * (a.R + 1);
+    for (int q = ptr[row] + lane; q < ptr[row + 1]; q += 64) {
+      const double c = a.inv_val[q];
+      const double *r = a.gres + (static_cast<int64_t>(a.inv_col[q]) * a.E + e) * 4;
+      if (mat == 0) {
+        v[0] = fma(c, r[0], v[0]);
+      } else if (mat == 1) {
+        v[1] = fma(c, r[1], v[1]);
+      } else {
+        v[2] = fma(c, r[2], v[2]);
+        v[3] = fma(c, r[3], v[3]);
+      }
+    }
+  }
+  for (int f = 0; f < 4; ++f) v[f] = wave_sum(v[f]);
+  if (lane == 0) store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.bnd_ghosts[row]) * a.E + e) * 4, v);
+}
+
+// Ensembles (E >= GHOST_MEMBER_LANES): the same two steps with one thread
+// per (boundary row, member), members in consecutive lanes, so every
+// stencil slot and inverse entry is one coalesced load across the
+// wavefront. Sums run in slot / entry order, so such members agree with
+// single-member runs to rounding rather than bit for bit.
+constexpr int GHOST_MEMBER_LANES = 16;
+
+template <class FT>
+__global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_members_kernel(GArgs a) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * RHS_BLOCK + threadIdx.x;
+  if (t >= static_cast<int64_t>(a.R) * a.E) return;
+  const int64_t row = t / a.E;
+  const int e = static_cast<int>(t - row * a.E);
+  const int nrm = a.bnd_normal[row];
+  double ru = 0.0, rw = 0.0, rt = 0.0, rp = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < a.n; ++k) resid_slot<FT>(a, row, k, e, nrm, ru, rw, rt, rp);
+  resid_store<FT>(a, row, e, nrm, ru, rw, rt, rp);
+}
+
 template <class FT>
 __global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_members_kernel(GArgs a) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * RHS_BLOCK + threadIdx.x;
-  const int E = a.E;
-  if (t >= static_cast<int64_t>(a.n_walls) * a.nb * E) return;
-  const int64_t wg = t / E;
-  const int e = static_cast<int>(t - wg * E);
-  const int wl = static_cast<int>(wg / a.nb), gp = static_cast<int>(wg - static_cast<int64_t>(wl) * a.nb);
-  const int64_t row_z = (static_cast<int64_t>(wl) * 2 + 0) * a.nb + gp;
-  const int64_t row_zz = (static_cast<int64_t>(wl) * 2 + 1) * a.nb + gp;
-  const double *z1 = a.ginv + row_z * a.band;
-  const double *z2 = a.ginv + row_zz * a.band;
-  const int p1 = a.gstart[row_z], p2 = a.gstart[row_zz];
-  const double *r = a.gres + static_cast<int64_t>(wl) * a.nb * E * 4;
+  if (t >= static_cast<int64_t>(a.R) * a.E) return;
+  const int64_t row = t / a.E;
+  const int e = static_cast<int>(t - row * a.E);
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  int b1 = p1, b2 = p2;
+  {
+    const int q0 = a.inv_ptr[row], q1 = a.inv_ptr[row + 1];
 #pragma unroll 4
-  for (int q = 0; q < a.band; ++q) {
-    const double c1 = z1[q], c2 = z2[q];
-    const double4 r1 = *reinterpret_cast<const double4 *>(r + (static_cast<int64_t>(b1) * E + e) * 4);
-    v[0] = fma(c1, r1.x, v[0]);
-    v[2] = fma(c1, r1.z, v[2]);
-    v[3] = fma(c1, r1.w, v[3]);
-    v[1] = fma(c2, r[(static_cast<int64_t>(b2) * E + e) * 4 + 1], v[1]);
-    if (++b1 == a.nb) b1 = 0;
-    if (++b2 == a.nb) b2 = 0;
+    for (int q = q0; q < q1; ++q) v[0] = fma(a.inv_val[q], a.gres[(static_cast<int64_t>(a.inv_col[q]) * a.E + e) * 4], v[0]);
   }
-  store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.ghost_nodes[wg]) * E + e) * 4, v);
+  {
+    const int *ptr = a.inv_ptr + (a.R + 1);
+    const int q0 = ptr[row], q1 = ptr[row + 1];
+#pragma unroll 4
+    for (int q = q0; q < q1; ++q)
+      v[1] = fma(a.inv_val[q], a.gres[(static_cast<int64_t>(a.inv_col[q]) * a.E + e) * 4 + 1], v[1]);
+  }
+  {
+    const int *ptr = a.inv_ptr + 2 * static_cast<int64_t>(a.R + 1);
+    const int q0 = ptr[row], q1 = ptr[row + 1];
+#pragma unroll 4
+    for (int q = q0; q < q1; ++q) {
+      const double c = a.inv_val[q];
+      const double2 r = *reinterpret_cast<const double2 *>(a.gres + (static_cast<int64_t>(a.inv_col[q]) * a.E + e) * 4 + 2);
+      v[2] = fma(c, r.x, v[2]);
+      v[3] = fma(c, r.y, v[3]);
+    }
+  }
+  store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.bnd_ghosts[row]) * a.E + e) * 4, v);
 }
 
 __global__ void misc_init_kernel(DevMisc *m, double t0) {
@@ -458,25 +457,25 @@ __global__ void tick_kernel(DevMisc *m) { m->step_ctr += 1; }
 // ---- host-side launchers ----------------------------------------------------
 
 int launch_ghost(rbffd_ctx *ctx, rbffd_model *m, void *y) {
-  if (m->physics != RBFFD_PHYS_NS || m->n_walls == 0) return RBFFD_OK;
+  if (m->physics != RBFFD_PHYS_NS || m->n_bnd == 0) return RBFFD_OK;
   GArgs g{};
   g.y = y;
-  g.wall_nodes = m->wall_nodes.as<int>();
-  g.ghost_nodes = m->ghost_nodes.as<int>();
+  g.bnd_nodes = m->bnd_nodes.as<int>();
+  g.bnd_ghosts = m->bnd_ghosts.as<int>();
+  g.bnd_normal = m->bnd_normal.as<int>();
   g.wall_idx = m->wall_idx.as<int>();
-  g.gstart = m->gstart.as<int>();
   g.wall_w = m->wall_w.as<double2>();
-  g.ginv = m->ginv.as<double>();
+  g.inv_ptr = m->inv_ptr.as<int>();
+  g.inv_col = m->inv_col.as<int>();
+  g.inv_val = m->inv_val.as<double>();
   g.gres = m->gres.as<double>();
   g.kind = m->kind.as<uint8_t>();
-  g.nb = m->nb;
+  g.R = m->n_bnd;
   g.n = m->n;
   g.E = m->E;
-  g.band = m->band;
-  g.n_walls = m->n_walls;
   g.bc_scale = m->g / (m->c_p * m->theta_bar);
   g.theta_bar = m->theta_bar;
-  const int64_t cnt = static_cast<int64_t>(m->n_walls) * m->nb * m->E;
+  const int64_t cnt = static_cast<int64_t>(m->n_bnd) * m->E;
   if (m->E >= GHOST_MEMBER_LANES) {                                       // one thread each
     const unsigned grid = grid_for(cnt, RHS_BLOCK);
     if (m->fdt == RBFFD_F64) {
@@ -486,16 +485,15 @@ int launch_ghost(rbffd_ctx *ctx, rbffd_model *m, void *y) {
       ghost_resid_members_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
       ghost_apply_members_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
     }
-    RBFFD_HIP(ctx, hipGetLastError());
-    return RBFFD_OK;
-  }
-  const unsigned grid = grid_for(cnt, RHS_BLOCK / 64);                   // one wavefront each
-  if (m->fdt == RBFFD_F64) {
-    ghost_resid_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
-    ghost_apply_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
   } else {
-    ghost_resid_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
-    ghost_apply_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+    const unsigned grid = grid_for(cnt, RHS_BLOCK / 64);                 // one wavefront each
+    if (m->fdt == RBFFD_F64) {
+      ghost_resid_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+      ghost_apply_kernel<double><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+    } else {
+      ghost_resid_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+      ghost_apply_kernel<float><<<grid, RHS_BLOCK, 0, ctx->stream>>>(g);
+    }
   }
   RBFFD_HIP(ctx, hipGetLastError());
   return RBFFD_OK;

@@ -100,9 +100,11 @@ __device__ double phs_rhs(int kind, int m, int k, double x, double z) {
       for (int i = 0; i < k; ++i) c *= static_cast<double>((m - 2 * i) * (m - 2 * i));
       return c * ipow(r, m - 2 * k);
     }
-    case RBFFD_DZZ: {
+    case RBFFD_DZZ:
+    case RBFFD_DXX: {
+      const double t = kind == RBFFD_DZZ ? z : x;   // the differentiated coordinate
       double a = m * ipow(r, m - 2);
-      double b = (m >= 4) ? m * (m - 2) * ipow(r, m - 4) * z * z : m * (m - 2) * z * z / r;
+      double b = (m >= 4) ? m * (m - 2) * ipow(r, m - 4) * t * t : m * (m - 2) * t * t / r;
       return a + b;
     }
   }
@@ -116,6 +118,7 @@ __device__ double poly_rhs(int kind, int k, int a, int b) {
     case RBFFD_DZ: return (a == 0 && b == 1) ? 1.0 : 0.0;
     case RBFFD_LAP: return ((a == 2 && b == 0) || (a == 0 && b == 2)) ? 2.0 : 0.0;
     case RBFFD_DZZ: return (a == 0 && b == 2) ? 2.0 : 0.0;
+    case RBFFD_DXX: return (a == 2 && b == 0) ? 2.0 : 0.0;
     case RBFFD_HYPERLAP: {
       if (a + b != 2 * k || (a & 1) || (b & 1)) return 0.0;
       double c = fact(k) / (fact(a / 2) * fact(k - a / 2));
@@ -262,9 +265,11 @@ __device__ dd rhs_entry_dd(int i, int n, int m, const WOp &op, int k, const doub
       for (int q = 0; q < k; ++q) c *= static_cast<double>((m - 2 * q) * (m - 2 * q));
       return dd_mul_d(dd_rpow(r2, r, m - 2 * k), c);
     }
-    case RBFFD_DZZ: {
+    case RBFFD_DZZ:
+    case RBFFD_DXX: {
+      const dd t = op.kind == RBFFD_DZZ ? z : x;
       dd t1 = dd_mul_d(dd_rpow(r2, r, m - 2), static_cast<double>(m));
-      dd t2 = dd_mul_d(dd_mul(dd_rpow(r2, r, m - 4), dd_mul(z, z)), static_cast<double>(m * (m - 2)));
+      dd t2 = dd_mul_d(dd_mul(dd_rpow(r2, r, m - 4), dd_mul(t, t)), static_cast<double>(m * (m - 2)));
       return dd_add(t1, t2);
     }
   }

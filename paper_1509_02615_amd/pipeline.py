@@ -25,16 +25,28 @@ def advection_ops(cfg):
 
 
 def ns_weights(ctx, cfg, xy=None):
-    """Stencils and weights of a channel workload: (xy, idx, W, Wwall, status)."""
+    """Stencils and weights of a channel or box workload:
+    (xy, idx, W, Wwall, status), Wwall [2][R][n] the boundary rows' first and
+    second normal-derivative weights (Dz, Dzz on walls normal to z; Dx, Dxx
+    on walls normal to x)."""
     nd = cfg["nodes"]
     if xy is None:
         xy = to_dev(nd.xy, torch.float64)
     idx, W, status, _ = R.rbffd_weights(ctx, xy, ns_ops(cfg), cfg["n"], cfg["m"], cfg["l"],
                                         period_x=nd.period_x, n_centers=nd.n_active)
-    # the wall rows repeat the (deterministic) search for the wall centres
-    wall = to_dev(nd.wall_nodes.ravel(), torch.int32)
-    _, Ww, wstatus, _ = R.rbffd_weights(ctx, xy, [(R.DZ, 0, 0), (R.DZZ, 0, 0)], cfg["n"], cfg["m"], cfg["l"],
-                                        period_x=nd.period_x, centers=wall)
+    # the boundary rows repeat the (deterministic) search for their centres
+    R_ = len(nd.bnd_nodes)
+    Ww = torch.zeros((2, R_, cfg["n"]), dtype=torch.float64, device="cuda")
+    wstatus = torch.zeros(R_, dtype=torch.int32, device="cuda")
+    for normal, ops in ((0, [(R.DZ, 0, 0), (R.DZZ, 0, 0)]), (1, [(R.DX, 0, 0), (R.DXX, 0, 0)])):
+        sel = np.nonzero(nd.bnd_normal == normal)[0]
+        if sel.size:
+            centers = to_dev(nd.bnd_nodes[sel], torch.int32)
+            _, Wn, st, _ = R.rbffd_weights(ctx, xy, ops, cfg["n"], cfg["m"], cfg["l"], period_x=nd.period_x,
+                                           centers=centers)
+            rows = to_dev(sel, torch.int64)
+            Ww[:, rows] = Wn
+            wstatus[rows] = st
     return xy, idx, W, Ww, (status, wstatus)
 
 
@@ -43,13 +55,14 @@ def ns_model(ctx, cfg, idx, W, Ww, xy=None, field_dtype=R.F64, weight_dtype=R.F6
     nd = cfg["nodes"]
     if xy is None:
         xy = to_dev(nd.xy, torch.float64)
-    nb = nd.wall_nodes.shape[1]
     n = idx.shape[1]
+    Ww = Ww.reshape(2, -1, n)
     return R.Model(ctx, R.PHYS_NS, idx, W, xy, nd.n_active, field_dtype=field_dtype,
                    weight_dtype=weight_dtype, ensemble=ensemble,
                    hv_coeff=cfg["hv_coeff"] if hv_coeff is None else hv_coeff, consts=cfg["consts"],
-                   wall_nodes=to_dev(nd.wall_nodes, torch.int32), ghost_nodes=to_dev(nd.ghost_nodes, torch.int32),
-                   wall_dz=Ww[0].reshape(2, nb, n).contiguous(), wall_dzz=Ww[1].reshape(2, nb, n).contiguous())
+                   bnd_nodes=to_dev(nd.bnd_nodes, torch.int32), bnd_ghosts=to_dev(nd.bnd_ghosts, torch.int32),
+                   bnd_normal=to_dev(nd.bnd_normal, torch.int32),
+                   bnd_d1=Ww[0].contiguous(), bnd_d2=Ww[1].contiguous())
 
 
 def advection_model(ctx, cfg, idx, W, xy=None, field_dtype=R.F64, ensemble=1):

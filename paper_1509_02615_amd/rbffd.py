@@ -19,7 +19,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EDEVICE, ESINGULAR, ENONFINITE = 0, -1, -2, -3, -4, -5
-DX, DZ, LAP, HYPERLAP, DZZ = 1, 2, 3, 4, 5
+DX, DZ, LAP, HYPERLAP, DZZ, DXX = 1, 2, 3, 4, 5, 6
 SOLVE_FP64, SOLVE_FP32_IR = 0, 1
 F64, F32, BF16 = 0, 1, 2
 PHYS_ADVECTION, PHYS_NS = 1, 2
@@ -45,8 +45,8 @@ class ModelDesc(ctypes.Structure):
                 ("idx", _vp), ("w", _vp), ("xy", _vp), ("hv_coeff", _f64),
                 ("vel_u", _vp), ("vel_v", _vp), ("vel_period", _f64),
                 ("c_p", _f64), ("c_v", _f64), ("R_d", _f64), ("g", _f64), ("theta_bar", _f64),
-                ("mu", _f64), ("u_bar", _f64), ("n_walls", _i32), ("n_wall", _i32), ("wall_nodes", _vp),
-                ("ghost_nodes", _vp), ("wall_dz", _vp), ("wall_dzz", _vp)]
+                ("mu", _f64), ("u_bar", _f64), ("n_bnd", _i32), ("reserved1", _i32), ("bnd_nodes", _vp),
+                ("bnd_ghosts", _vp), ("bnd_normal", _vp), ("bnd_d1", _vp), ("bnd_d2", _vp)]
 
 
 _lib.rbffd_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _vp]
@@ -197,7 +197,7 @@ class Model:
 
     def __init__(self, ctx: Context, physics, idx, w, xy, n_active, field_dtype=F64, weight_dtype=F64,
                  ensemble=1, hv_coeff=0.0, vel_u=None, vel_v=None, vel_period=1.0, consts=None,
-                 wall_nodes=None, ghost_nodes=None, wall_dz=None, wall_dzz=None):
+                 bnd_nodes=None, bnd_ghosts=None, bnd_normal=None, bnd_d1=None, bnd_d2=None):
         self.ctx = ctx
         N = xy.shape[0]
         na, n = idx.shape
@@ -216,13 +216,14 @@ class Model:
                       c_p=c.get("c_p", 0.0), c_v=c.get("c_v", 0.0), R_d=c.get("R_d", 0.0),
                       g=c.get("g", 0.0), theta_bar=c.get("theta_bar", 0.0), mu=c.get("mu", 0.0),
                       u_bar=c.get("u_bar", 0.0))
-        if wall_nodes is not None:
-            nw, nb = wall_nodes.shape
-            d.n_walls, d.n_wall = nw, nb
-            d.wall_nodes = _ptr(wall_nodes, torch.int32, (nw, nb), "wall_nodes")
-            d.ghost_nodes = _ptr(ghost_nodes, torch.int32, (nw, nb), "ghost_nodes")
-            d.wall_dz = _ptr(wall_dz, torch.float64, (nw, nb, n), "wall_dz")
-            d.wall_dzz = _ptr(wall_dzz, torch.float64, (nw, nb, n), "wall_dzz")
+        if bnd_nodes is not None:
+            nr = bnd_nodes.shape[0]
+            d.n_bnd = nr
+            d.bnd_nodes = _ptr(bnd_nodes, torch.int32, (nr,), "bnd_nodes")
+            d.bnd_ghosts = _ptr(bnd_ghosts, torch.int32, (nr,), "bnd_ghosts")
+            d.bnd_normal = _ptr(bnd_normal, torch.int32, (nr,), "bnd_normal")
+            d.bnd_d1 = _ptr(bnd_d1, torch.float64, (nr, n), "bnd_d1")
+            d.bnd_d2 = _ptr(bnd_d2, torch.float64, (nr, n), "bnd_d2")
         h = _vp()
         ctx.check(_lib.rbffd_model_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
         self.h = h

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from workloads import density_current_config
+from workloads import density_current_config, bubble_config
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -86,3 +86,73 @@ def test_translating_density_current_100m_against_table(layout):
     ref = translating_row(layout, 100.0)
     print(f"   layout {layout}: fronts (left, right) from 18 km {left:.0f} {right:.0f} table {ref}", flush=True)
     assert abs(left - ref[0]) <= 0.03 * ref[0] and abs(right - ref[1]) <= 0.03 * ref[1]
+
+
+def bubble_row(layout, h):
+    with open(os.path.join(GOLDEN, "bubble_table.csv")) as f:
+        rows = [r for r in csv.reader(f) if r and not r[0].startswith("#")][1:]
+    return {(r[0], float(r[1])): [float(v) for v in r[2:]] for r in rows}[layout, h]
+
+
+def run_bubble(layout, h, fdt=0):
+    import torch
+    from paper_1509_02615_amd import rbffd as R
+    from paper_1509_02615_amd import pipeline as P
+    ctx = R.Context(0)
+    cfg = bubble_config(layout, h)
+    nd = cfg["nodes"]
+    xy, idx, W, Ww, (sa, sw) = P.ns_weights(ctx, cfg)
+    assert int(sa.abs().sum()) == 0 and int(sw.abs().sum()) == 0
+    model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=fdt)
+    s = P.to_dev(cfg["state0"], torch.float64 if fdt == 0 else torch.float32).reshape(model.state_shape()).contiguous()
+    n = int(round(cfg["t_end"] / cfg["dt"]))
+    t = R.rbffd_step(ctx, model, s, 0.0, cfg["dt"], n, R.RK4)
+    assert abs(t - 1100.0) < 1e-9
+    R.rbffd_ghost(ctx, model, s)
+    y = s.double().cpu().numpy().reshape(-1, 4)
+    na = nd.n_active
+    got = [y[:na, 2].min(), y[:na, 2].max(), y[:na, 1].min(), y[:na, 1].max(),
+           O.bubble_height(nd.xy, y[:, 2], nd.rows)]
+    return cfg, y, got
+
+
+@pytest.mark.parametrize("layout,h,fdt", [("cartesian", 200.0, 0), ("hexagonal", 200.0, 0), ("scattered", 200.0, 0),
+                                          ("cartesian", 100.0, 0), ("hexagonal", 100.0, 0),
+                                          ("scattered", 100.0, 0), ("cartesian", 100.0, 1)])
+def test_rising_bubble_against_table(layout, h, fdt):
+    """Section 6.5 (mu = 10 m^2/s, t = 1100 s) through the whole GPU path,
+    four-wall ghost closure included, against Table tbl:bubble: max theta'
+    and the w' extrema within 12%, min theta' (~ -0.1 K) within 0.05 K, the
+    bubble height within 2.5%."""
+    print(f"rising bubble: {layout} {h} m, field dtype {fdt}", flush=True)
+    cfg, y, got = run_bubble(layout, h, fdt)
+    ref = bubble_row(layout, h)
+    print(f"   got {np.round(got, 3).tolist()} table {ref}", flush=True)
+    assert abs(got[0] - ref[0]) <= 0.05
+    for k in (1, 2, 3):
+        assert abs(got[k] - ref[k]) <= 0.12 * abs(ref[k]), (k, got, ref)
+    assert abs(got[4] - ref[4]) <= 0.025 * ref[4], (got, ref)
+
+
+def test_rising_bubble_converges():
+    """Section 6.5: Cartesian nodes at 400, 200, 100 and 50 m against a 25 m
+    run of the same method, theta' compared on the nodes all grids share
+    (every 400 m node is a node of each finer grid). The error falls with
+    every halving of h, the last step at better than second order."""
+    errs = []
+    ref_cfg, ref_y, _ = run_bubble("cartesian", 25.0)
+    rxy = ref_cfg["nodes"].xy[:ref_cfg["nodes"].n_active]
+    key = {(round(x, 3), round(z, 3)): i for i, (x, z) in enumerate(rxy)}
+    for h in (400.0, 200.0, 100.0, 50.0):
+        cfg, y, _ = run_bubble("cartesian", h)
+        nd = cfg["nodes"]
+        common = [(i, key[(round(x, 3), round(z, 3))]) for i, (x, z) in enumerate(nd.xy[:nd.n_active])
+                  if (round(x, 3), round(z, 3)) in key and abs(x % 400.0) < 1e-6 and abs(z % 400.0) < 1e-6]
+        a = np.array([y[i, 2] for i, _ in common])
+        b = np.array([ref_y[j, 2] for _, j in common])
+        errs.append(np.linalg.norm(a - b) / np.linalg.norm(b))
+    orders = [np.log2(errs[k] / errs[k + 1]) for k in range(3)]
+    print(f"   theta' rel-l2 vs 25 m at 400/200/100/50 m: {['%.2e' % e for e in errs]}, "
+          f"orders {['%.2f' % o for o in orders]}", flush=True)
+    assert all(errs[k + 1] < errs[k] for k in range(3))
+    assert orders[-1] > 2.0

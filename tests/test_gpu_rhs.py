@@ -61,14 +61,14 @@ def ns_case(layout, h, translating=False):
 def gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=0, wdt=0, E=1, hv=None):
     import torch
     nd = cfg["nodes"]
-    nb = nd.wall_nodes.shape[1]
     n = idx.shape[1]
-    Wwall = Ww.reshape(2, 2, nb, n)
+    Wwall = Ww.reshape(2, -1, n)
     return R.Model(ctx, R.PHYS_NS, dev(idx, torch.int32), dev(W, torch.float64), dev(nd.xy, torch.float64),
                    nd.n_active, field_dtype=fdt, weight_dtype=wdt, ensemble=E,
                    hv_coeff=cfg["hv_coeff"] if hv is None else hv, consts=cfg["consts"],
-                   wall_nodes=dev(nd.wall_nodes, torch.int32), ghost_nodes=dev(nd.ghost_nodes, torch.int32),
-                   wall_dz=dev(Wwall[0], torch.float64), wall_dzz=dev(Wwall[1], torch.float64))
+                   bnd_nodes=dev(nd.bnd_nodes, torch.int32), bnd_ghosts=dev(nd.bnd_ghosts, torch.int32),
+                   bnd_normal=dev(nd.bnd_normal, torch.int32),
+                   bnd_d1=dev(Wwall[0], torch.float64), bnd_d2=dev(Wwall[1], torch.float64))
 
 
 def rel_fields(a, b, rows):
@@ -108,6 +108,96 @@ def test_ghost_closure_parity(R, ctx, layout):
         assert err <= 1e-12, (f, err)
     wall = cfg["nodes"].wall_nodes.ravel()
     assert np.all(got[wall, 1] == 0.0)
+
+
+_BOX_CACHE = {}
+
+
+def box_case(layout):
+    """The rising-bubble box (four walls) at 400 m."""
+    if layout not in _BOX_CACHE:
+        from workloads import bubble_config
+        cfg = bubble_config(layout, 400.0)
+        model, idx, W, Ww = build_ns(cfg)
+        _BOX_CACHE[layout] = (cfg, model, idx, W, Ww)
+    return _BOX_CACHE[layout]
+
+
+def box_state(nd, seed):
+    """Seeded smooth state on the box: u, w ~ 15 m/s, theta' ~ 10 K, pi' ~ 1e-3."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x, z = nd.xy[:, 0] / nd.width, nd.xy[:, 1] / nd.height
+    s = np.zeros((nd.n_total, 4))
+    for f, amp in enumerate([15.0, 15.0, 10.0, 1e-3]):
+        for _ in range(3):
+            kx, kz = rng.integers(1, 4, 2)
+            px, pz = rng.uniform(0, 2 * np.pi, 2)
+            s[:, f] += rng.uniform(-1, 1) * amp / 3 * np.cos(np.pi * kx * x + px) * np.cos(np.pi * kz * z + pz)
+    s[nd.n_active:] = 0.0
+    return s
+
+
+@pytest.mark.parametrize("layout", ["cartesian", "hexagonal", "scattered"])
+def test_box_ghost_closure_parity(R, ctx, layout):
+    """Four walls (Section 6.5): lateral rows close u with d2/dx2 and w,
+    theta', pi' with d/dx; corner rows of two walls share one coupled solve."""
+    import torch
+    say(f"closure: rising-bubble box {layout} 400 m, FP64")
+    cfg, om, idx, W, Ww = box_case(layout)
+    nd = cfg["nodes"]
+    gm = gpu_ns(R, ctx, cfg, idx, W, Ww)
+    st = box_state(nd, seed=4)
+    ref = O.ghost_closure(om, st)
+    s = dev(st, torch.float64).reshape(gm.state_shape()).contiguous()
+    R.rbffd_ghost(ctx, gm, s)
+    got = host(s).reshape(st.shape)
+    g = nd.bnd_ghosts
+    for f in range(4):
+        err = np.abs(got[g, f] - ref[g, f]).max() / max(np.abs(ref[g, f]).max(), 1e-300)
+        say(f"   field {f}: max ghost error / max ghost {err:.1e}")
+        assert err <= 1e-12, (f, err)
+    zn = nd.bnd_normal == 0
+    assert np.all(got[nd.bnd_nodes[zn], 1] == 0.0) and np.all(got[nd.bnd_nodes[~zn], 0] == 0.0)
+
+
+@pytest.mark.parametrize("layout,fdt,tol", [("cartesian", 0, 1e-12), ("hexagonal", 0, 1e-12),
+                                            ("scattered", 0, 1e-12), ("cartesian", 1, 1e-6)])
+def test_box_rhs_parity(R, ctx, layout, fdt, tol):
+    import torch
+    say(f"rhs: rising-bubble box {layout} 400 m, field/weight dtype {fdt}")
+    cfg, om, idx, W, Ww = box_case(layout)
+    nd = cfg["nodes"]
+    gm = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=fdt, wdt=fdt)
+    st = box_state(nd, seed=5)
+    if fdt == 1:
+        st = st.astype(np.float32).astype(np.float64)
+    ref, _ = O.ns_rhs(om, st)
+    s = dev(st, torch.float64 if fdt == 0 else torch.float32).reshape(gm.state_shape()).contiguous()
+    out = torch.full_like(s, float("nan"))
+    R.rbffd_rhs(ctx, gm, 0.0, s, out)
+    got = host(out).reshape(st.shape)
+    errs = rel_fields(got, ref, np.arange(nd.n_active))
+    say(f"   rel-l2 per field {['%.1e' % e for e in errs]}")
+    assert max(errs) <= tol
+    k = nd.kinds()[:nd.n_active]
+    assert np.all(got[:nd.n_active][(k & 1) > 0, 1] == 0.0) and np.all(got[:nd.n_active][(k & 4) > 0, 0] == 0.0)
+
+
+def test_box_steps_parity(R, ctx):
+    """30 RK4 steps of the rising bubble (FP64), Cartesian 400 m, against the
+    oracle's integration."""
+    import torch
+    say("steps: rising bubble, cartesian 400 m, 30 RK4 steps, FP64")
+    cfg, om, idx, W, Ww = box_case("cartesian")
+    gm = gpu_ns(R, ctx, cfg, idx, W, Ww)
+    yref, _ = O.integrate(lambda t, y: O.ns_rhs(om, y)[0], cfg["state0"], 0.0, cfg["dt"], 30, "rk4")
+    s = dev(cfg["state0"], torch.float64).reshape(gm.state_shape()).contiguous()
+    R.rbffd_step(ctx, gm, s, 0.0, cfg["dt"], 30, R.RK4)
+    got = host(s).reshape(yref.shape)
+    na = cfg["nodes"].n_active
+    errs = [np.linalg.norm(got[:na, f] - yref[:na, f]) / np.linalg.norm(yref[:na, f]) for f in range(4)]
+    say(f"   rel-l2 per field {['%.1e' % e for e in errs]}")
+    assert max(errs) <= 1e-10
 
 
 @pytest.mark.parametrize("layout,h", [("cartesian", 400.0), ("hexagonal", 400.0), ("scattered", 400.0),

@@ -142,6 +142,19 @@ def test_weights_parity_channels(R, ctx, layout):
     _weights_parity(R, ctx, nd.xy, [(O.DZ, 0, 0), (O.DZZ, 0, 0)], 37, 7, 4, nd.period_x, nd.wall_nodes.ravel())
 
 
+@pytest.mark.parametrize("layout", ["cartesian", "hexagonal", "scattered"])
+def test_weights_parity_box(R, ctx, layout):
+    """The closed box of the rising bubble (Section 6.5): interior operators,
+    and Dx, Dxx at the lateral boundary rows (corners included)."""
+    from workloads import bubble_config
+    say(f"weights: {layout} 400 m box, r^7 + deg 4, Dx Dz Lap Lap^3 and lateral-wall Dx Dxx")
+    nd = bubble_config(layout, 400.0)["nodes"]
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0), (O.HYPERLAP, 3, 7)]
+    _weights_parity(R, ctx, nd.xy, ops, 37, 7, 4, 0.0, np.arange(nd.n_active))
+    lateral = nd.bnd_nodes[nd.bnd_normal == 1]
+    _weights_parity(R, ctx, nd.xy, [(O.DX, 0, 0), (O.DXX, 0, 0)], 37, 7, 4, 0.0, lateral)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_weights_parity_mixed_batch(R, ctx, precision):
     say(f"weights: mixed n/m/l batch on 40x40 jittered square, precision {precision}")
@@ -170,7 +183,7 @@ def test_weights_reproduce_polynomials(R, ctx):
     import torch
     say("weights: polynomial reproduction of GPU weights, scattered 24x24, r^7 deg 5, n = 43")
     nd = jittered_square(24, seed=2)
-    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0), (O.DZZ, 0, 0), (O.HYPERLAP, 3, 0)]
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0), (O.DZZ, 0, 0), (O.DXX, 0, 0), (O.HYPERLAP, 3, 0)]
     idx, W, status, rc = R.rbffd_weights(ctx, dev(nd.xy, torch.float64), ops, 43, 7, 5,
                                          n_centers=nd.n_active)
     idx, W = host(idx), host(W)
