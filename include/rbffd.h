@@ -180,6 +180,10 @@ typedef struct {
                              (Dz or Dx) at the boundary node                             */
   const double *bnd_d2;   /* [n_bnd][n] weights of the second derivative along the normal
                              (Dzz or Dxx)                                                */
+  /* transport mirror boundary (Section 6.1): nodes past n_active are mirror
+   * ghosts whose values are copied from active node mirror_src[k] before
+   * every right-hand side; required for transport when n_total > n_active */
+  const int32_t *mirror_src;  /* [n_total - n_active] or NULL                           */
 } rbffd_model_desc;
 
 /* Build a model: repack stencils and weights into the library's slot-major

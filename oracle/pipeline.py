@@ -41,7 +41,8 @@ def build_advection(cfg):
     centers = np.arange(nd.n_active)
     idx = knn(nd.xy, centers, cfg["n"], nd.period_x)
     W, status = all_weights(nd.xy, idx, centers, cfg["m"], cfg["l"], advection_ops(cfg), nd.period_x)
-    model = AdvectionModel(idx, W[0], W[1], W[2], cfg["U"], cfg["V"], cfg["hv_coeff"], cfg["vel_period"])
+    model = AdvectionModel(idx, W[0], W[1], W[2], cfg["U"], cfg["V"], cfg["hv_coeff"], cfg["vel_period"],
+                           cfg.get("mirror_src"))
     return model, idx, W, status
 
 

@@ -57,17 +57,33 @@ def advection_rhs(t, psi, idx, w_dx, w_dy, w_hv, U, V, hv_coeff, vel_period):
 
 class AdvectionModel:
     """``advection_rhs`` with the three differentiation matrices prebuilt in
-    CSR form, for long runs."""
+    CSR form, for long runs. With ``mirror_src`` (Section 6.1 mirror
+    boundary) the state also holds ghost nodes n_active.. whose values are
+    copies of the active nodes ``mirror_src``; they are refreshed before every
+    evaluation and their tendency is 0."""
 
-    def __init__(self, idx, w_dx, w_dy, w_hv, U, V, hv_coeff, vel_period):
-        n = idx.shape[0]
+    def __init__(self, idx, w_dx, w_dy, w_hv, U, V, hv_coeff, vel_period, mirror_src=None):
+        self.na = idx.shape[0]
+        n = U.shape[0]
         self.Dx, self.Dy, self.Dhv = (dm_matrix(idx, w, n) for w in (w_dx, w_dy, w_hv))
         self.U, self.V, self.hv_coeff, self.vel_period = U, V, hv_coeff, vel_period
+        self.mirror_src = mirror_src
+
+    def mirror(self, psi):
+        """psi with the ghost values set from their mirror sources."""
+        if self.mirror_src is None:
+            return psi
+        psi = np.array(psi, dtype=np.float64, copy=True)
+        psi[self.na:] = psi[self.mirror_src]
+        return psi
 
     def __call__(self, t, psi):
+        psi = self.mirror(psi)
         a = np.cos(np.pi * t / self.vel_period)
-        return -(self.Dx @ (self.U * a * psi) + self.Dy @ (self.V * a * psi)) \
+        out = np.zeros_like(psi)
+        out[:self.na] = -(self.Dx @ (self.U * a * psi) + self.Dy @ (self.V * a * psi)) \
             + self.hv_coeff * (self.Dhv @ psi)
+        return out
 
 
 def ghost_matrices(idx, rows_w, bnd_nodes, bnd_ghosts):

@@ -12,7 +12,10 @@
 // decays geometrically away from a row's own ghost, so each inverse row keeps
 // only its entries above a cut-off chosen so that the dropped l1 mass is
 // below 2^-56 of the row's l1 mass: applying the kept entries is the exact
-// solve up to rounding. Each Runge-Kutta stage applies them on the GPU.
+// solve up to rounding. They are stored as the shortest cyclic window of the
+// group's rows that holds them all (for a channel wall, a band around the
+// row's own position), so the GPU finds each entry's row by arithmetic.
+// Each Runge-Kutta stage applies the windows.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -185,6 +188,21 @@ std::vector<int> certified_support(const double *row, int n) {
   return keep;
 }
 
+// Shortest cyclic window [start, start + len) of 0..n-1 that holds every
+// index in `keep` (sorted, non-empty): the complement of the largest gap.
+void cyclic_window(const std::vector<int> &keep, int n, int &start, int &len) {
+  int best_gap = -1, after = keep[0];
+  for (size_t i = 0; i < keep.size(); ++i) {
+    const int a = keep[i], b = i + 1 < keep.size() ? keep[i + 1] : keep[0] + n;
+    if (b - a - 1 > best_gap) {
+      best_gap = b - a - 1;
+      after = b % n;
+    }
+  }
+  start = after;
+  len = n - best_gap;
+}
+
 int find_root(std::vector<int> &parent, int x) {
   while (parent[x] != x) x = parent[x] = parent[parent[x]];
   return x;
@@ -216,6 +234,8 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
   if (!d->idx || !d->w || !d->xy) return rbffd_fail(ctx, RBFFD_EINVAL, "null idx, w or xy");
   if (d->physics == RBFFD_PHYS_ADVECTION && (!d->vel_u || !d->vel_v || !(d->vel_period != 0.0)))
     return rbffd_fail(ctx, RBFFD_EINVAL, "transport needs vel_u, vel_v and vel_period");
+  if (d->physics == RBFFD_PHYS_ADVECTION && d->n_total > d->n_active && !d->mirror_src)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "transport nodes past n_active need mirror_src");
   if (d->physics == RBFFD_PHYS_NS) {
     if (d->n_bnd < 0) return rbffd_fail(ctx, RBFFD_EINVAL, "n_bnd must be >= 0");
     if (d->n_bnd && (!d->bnd_nodes || !d->bnd_ghosts || !d->bnd_normal || !d->bnd_d1 || !d->bnd_d2))
@@ -294,6 +314,21 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
   kind_kernel<<<grid_for(m->N, 256), 256, 0, s>>>(m->kind.as<uint8_t>(), m->N, na);
   if (hipGetLastError() != hipSuccess) return fail_model(ctx, m, RBFFD_EDEVICE, "repack launch");
 
+  // transport mirror ghosts: sources must be active nodes
+  if (m->physics == RBFFD_PHYS_ADVECTION && m->N > na) {
+    const int64_t ng = m->N - na;
+    std::vector<int> h_src(ng);
+    if (hipMemcpyAsync(h_src.data(), d->mirror_src, sizeof(int) * ng, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail_model(ctx, m, RBFFD_EDEVICE, "mirror source copy");
+    for (int v : h_src)
+      if (v < 0 || v >= na) return fail_model(ctx, m, RBFFD_EINVAL, "mirror source not an active node");
+    if (m->mirror_src.alloc(sizeof(int) * ng) != hipSuccess) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation");
+    if (hipMemcpy(m->mirror_src.p, h_src.data(), sizeof(int) * ng, hipMemcpyHostToDevice) != hipSuccess)
+      return fail_model(ctx, m, RBFFD_EDEVICE, "mirror source upload");
+    m->n_mirror = ng;
+  }
+
   // ghost closure
   if (m->physics == RBFFD_PHYS_NS && d->n_bnd > 0) {
     const int R = d->n_bnd;
@@ -350,8 +385,22 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
         groups[gid[root]].push_back(r);
       }
     }
-    // inverse rows of the three blocks, CSR over the ghost rows
-    std::vector<std::vector<std::pair<int, double>>> inv_rows(3 * static_cast<size_t>(R));
+    // rows renumbered so each group is contiguous: group rows first, in
+    // the caller's order within the group
+    std::vector<int> perm;                 // new position -> caller's row
+    std::vector<int> h_g0(R), h_gm(R);     // per new row: its group's first position and size
+    for (const auto &grp : groups) {
+      const int g0 = static_cast<int>(perm.size());
+      for (int r : grp) {
+        h_g0[perm.size()] = g0;
+        h_gm[perm.size()] = static_cast<int>(grp.size());
+        perm.push_back(r);
+      }
+    }
+    // inverse rows of the three blocks as cyclic windows over the group
+    std::vector<int> h_win(3 * static_cast<size_t>(R) * 2);     // {start, len} per (matrix, new row)
+    std::vector<int64_t> h_off(3 * static_cast<size_t>(R));      // value offset per (matrix, new row)
+    std::vector<double> h_val;
     std::vector<int> local(R, -1);
     for (const auto &grp : groups) {
       const int gm = static_cast<int>(grp.size());
@@ -372,57 +421,60 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
             }
           if (!invert_sparse_lu(gm, G, inv)) return fail_model(ctx, m, RBFFD_ESINGULAR, "singular ghost block W_G");
         }
+        const int g0 = h_g0[static_cast<size_t>(std::find(perm.begin(), perm.end(), grp[0]) - perm.begin())];
         for (int i = 0; i < gm; ++i) {
           const double *row = &inv[static_cast<size_t>(i) * gm];
-          auto &out = inv_rows[static_cast<size_t>(mat) * R + grp[i]];
-          for (int q : certified_support(row, gm)) out.push_back({grp[q], row[q]});
-          std::sort(out.begin(), out.end());
+          int st = 0, len = 0;
+          cyclic_window(certified_support(row, gm), gm, st, len);
+          const size_t slot = static_cast<size_t>(mat) * R + g0 + i;
+          h_win[2 * slot] = st;
+          h_win[2 * slot + 1] = len;
+          h_off[slot] = static_cast<int64_t>(h_val.size());
+          for (int q = 0; q < len; ++q) h_val.push_back(row[(st + q) % gm]);
+          m->inv_max_row = std::max(m->inv_max_row, len);
         }
         if (mat == 2) inv_tp = std::move(inv);
       }
     }
-    std::vector<int> h_ptr(3 * (static_cast<size_t>(R) + 1)), h_col;
-    std::vector<double> h_val;
-    for (int mat = 0; mat < 3; ++mat) {
-      h_ptr[static_cast<size_t>(mat) * (R + 1)] = static_cast<int>(h_col.size());
-      for (int r = 0; r < R; ++r) {
-        for (auto &e : inv_rows[static_cast<size_t>(mat) * R + r]) {
-          h_col.push_back(e.first);
-          h_val.push_back(e.second);
-        }
-        h_ptr[static_cast<size_t>(mat) * (R + 1) + r + 1] = static_cast<int>(h_col.size());
-        m->inv_max_row = std::max<int>(m->inv_max_row, static_cast<int>(inv_rows[static_cast<size_t>(mat) * R + r].size()));
+    m->u_shares_tp = std::all_of(h_norm.begin(), h_norm.end(), [](int v) { return v == 0; }) ? 1 : 0;
+    // per-row arrays in the new order; boundary weights with ghost entries zeroed
+    std::vector<int> p_node(R), p_ghost(R), p_norm(R), p_widx(static_cast<size_t>(R) * n);
+    std::vector<double> h_ww(static_cast<size_t>(R) * n * 2);
+    for (int r = 0; r < R; ++r) {
+      const int o = perm[r];
+      p_node[r] = h_node[o];
+      p_ghost[r] = h_ghost[o];
+      p_norm[r] = h_norm[o];
+      for (int k = 0; k < n; ++k) {
+        const size_t e = static_cast<size_t>(r) * n + k, eo = static_cast<size_t>(o) * n + k;
+        p_widx[e] = h_widx[eo];
+        const bool ghost = h_widx[eo] >= na;
+        h_ww[2 * e] = ghost ? 0.0 : h_d1[eo];
+        h_ww[2 * e + 1] = ghost ? 0.0 : h_d2[eo];
       }
     }
-    // boundary weights with ghost entries zeroed; node kinds
-    std::vector<double> h_ww(static_cast<size_t>(R) * n * 2);
-    for (int r = 0; r < R; ++r)
-      for (int k = 0; k < n; ++k) {
-        const size_t e = static_cast<size_t>(r) * n + k;
-        const bool ghost = h_widx[e] >= na;
-        h_ww[2 * e] = ghost ? 0.0 : h_d1[e];
-        h_ww[2 * e + 1] = ghost ? 0.0 : h_d2[e];
-      }
     std::vector<uint8_t> h_kind(static_cast<size_t>(m->N), 0);
     for (int64_t i = na; i < m->N; ++i) h_kind[i] = KIND_GHOST;
     for (int r = 0; r < R; ++r) h_kind[h_node[r]] |= h_norm[r] == 0 ? KIND_ZWALL : KIND_XWALL;
+    std::vector<int2> h_grp(R);
+    for (int r = 0; r < R; ++r) h_grp[r] = make_int2(h_g0[r], h_gm[r]);
     ok = m->bnd_nodes.alloc(sizeof(int) * R) == hipSuccess && m->bnd_ghosts.alloc(sizeof(int) * R) == hipSuccess &&
-         m->bnd_normal.alloc(sizeof(int) * R) == hipSuccess && m->wall_idx.alloc(sizeof(int) * h_widx.size()) == hipSuccess &&
+         m->bnd_normal.alloc(sizeof(int) * R) == hipSuccess && m->wall_idx.alloc(sizeof(int) * p_widx.size()) == hipSuccess &&
          m->wall_w.alloc(sizeof(double) * h_ww.size()) == hipSuccess &&
-         m->inv_ptr.alloc(sizeof(int) * h_ptr.size()) == hipSuccess &&
-         m->inv_col.alloc(sizeof(int) * std::max<size_t>(1, h_col.size())) == hipSuccess &&
-         m->inv_val.alloc(sizeof(double) * std::max<size_t>(1, h_val.size())) == hipSuccess &&
+         m->inv_grp.alloc(sizeof(int2) * R) == hipSuccess && m->inv_win.alloc(sizeof(int) * h_win.size()) == hipSuccess &&
+         m->inv_off.alloc(sizeof(int64_t) * h_off.size()) == hipSuccess &&
+         m->inv_val.alloc(sizeof(double) * h_val.size()) == hipSuccess &&
          m->gres.alloc(sizeof(double) * R * m->E * 4) == hipSuccess;
     if (!ok) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation (closure)");
-    ok = hipMemcpy(m->bnd_nodes.p, h_node.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(m->bnd_ghosts.p, h_ghost.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(m->bnd_normal.p, h_norm.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(m->wall_idx.p, h_widx.data(), sizeof(int) * h_widx.size(), hipMemcpyHostToDevice) == hipSuccess &&
+    ok = hipMemcpy(m->bnd_nodes.p, p_node.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->bnd_ghosts.p, p_ghost.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->bnd_normal.p, p_norm.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->wall_idx.p, p_widx.data(), sizeof(int) * p_widx.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(m->wall_w.p, h_ww.data(), sizeof(double) * h_ww.size(), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(m->inv_ptr.p, h_ptr.data(), sizeof(int) * h_ptr.size(), hipMemcpyHostToDevice) == hipSuccess &&
-         (h_col.empty() ||
-          (hipMemcpy(m->inv_col.p, h_col.data(), sizeof(int) * h_col.size(), hipMemcpyHostToDevice) == hipSuccess &&
-           hipMemcpy(m->inv_val.p, h_val.data(), sizeof(double) * h_val.size(), hipMemcpyHostToDevice) == hipSuccess)) &&
+         hipMemcpy(m->inv_grp.p, h_grp.data(), sizeof(int2) * R, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->inv_win.p, h_win.data(), sizeof(int) * h_win.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->inv_off.p, h_off.data(), sizeof(int64_t) * h_off.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(m->inv_val.p, h_val.data(), sizeof(double) * h_val.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(m->kind.p, h_kind.data(), static_cast<size_t>(m->N), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) return fail_model(ctx, m, RBFFD_EDEVICE, "closure upload");
   }

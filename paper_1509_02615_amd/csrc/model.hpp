@@ -39,14 +39,21 @@ struct rbffd_model {
   double c_p = 0, c_v = 0, R_d = 0, g = 0, theta_bar = 0, mu = 0, u_bar = 0;
   // ghost closure over R boundary rows
   int n_bnd = 0, inv_max_row = 0;
+  int u_shares_tp = 0;             // no wall normal to x: u's W_G equals theta prime's
+  // (rows reordered so that each group of rows sharing ghosts is contiguous)
   DevBuf bnd_nodes, bnd_ghosts;    // int32 [R]
   DevBuf bnd_normal;               // int32 [R]: 0 wall normal to z, 1 normal to x
   DevBuf wall_idx;                 // int32 [R][n] the rows' stencils
   DevBuf wall_w;                   // double2 {d1, d2} [R][n], ghost entries zeroed
-  DevBuf inv_ptr;                  // int32 [3][R+1] CSR starts of W_G^-1 rows (u, w, theta'/pi')
-  DevBuf inv_col;                  // int32 [nnz] boundary row of each kept entry
-  DevBuf inv_val;                  // double [nnz]
+  DevBuf inv_grp;                  // int2 [R] {first row, size} of the row's group
+  DevBuf inv_win;                  // int [3][R][2] {start, length} of each W_G^-1 row's cyclic
+                                   // window within the group (u, w, theta'/pi')
+  DevBuf inv_off;                  // int64 [3][R] offset of the window's values
+  DevBuf inv_val;                  // double: window values
   DevBuf gres;                     // double [R][E][4] residuals
+  // transport mirror ghosts
+  int64_t n_mirror = 0;
+  DevBuf mirror_src;               // int32 [N - Na]
   // time stepping
   DevBuf ya, yb, acc;              // [N][E][F] stage buffers
   DevBuf dev_misc;                 // {int nonfinite_step, int step_ctr, double t0}

@@ -290,11 +290,14 @@ struct GArgs {
   void *y;  // [N][E][4]
   const int *bnd_nodes, *bnd_ghosts, *bnd_normal, *wall_idx;
   const double2 *wall_w;   // {d1, d2} per (row, slot), ghost entries zeroed
-  const int *inv_ptr, *inv_col;
+  const int2 *inv_grp;     // {first row, size} of each row's group
+  const int *inv_win;      // {start, length} per (matrix, row)
+  const int64_t *inv_off;  // window value offset per (matrix, row)
   const double *inv_val;
   double *gres;            // [R][E][4]
   const uint8_t *kind;
   int R, n, E;
+  int u_shared;                // 1: u's block equals theta prime's (no wall normal to x)
   double bc_scale, theta_bar;  // dpi/dz = bc_scale * th / (theta_bar + th) on walls normal to z
 };
 
@@ -363,8 +366,26 @@ __global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_kernel(GArgs a) {
   if (lane == 0) resid_store<FT>(a, row, e, nrm, ru, rw, rt, rp);
 }
 
-// B1 part 2: ghost values u_G = W_G^-1 r through the kept inverse entries.
-// One wavefront per (ghost row, member); lanes take entries.
+// One W_G^-1 row (matrix `mat`, boundary row `row`): the cyclic window of
+// its group's rows that holds its kept entries.
+struct InvRow {
+  const double *val;
+  int g0, gm, start, len;
+};
+__device__ __forceinline__ InvRow inv_row(const GArgs &a, int mat, int64_t row) {
+  const int2 g = a.inv_grp[row];
+  const int64_t slot = static_cast<int64_t>(mat) * a.R + row;
+  return InvRow{a.inv_val + a.inv_off[slot], g.x, g.y, a.inv_win[2 * slot], a.inv_win[2 * slot + 1]};
+}
+// boundary row of window position q (< len <= gm)
+__device__ __forceinline__ int64_t win_row(const InvRow &w, int q) {
+  int p = w.start + q;
+  if (p >= w.gm) p -= w.gm;
+  return w.g0 + p;
+}
+
+// B1 part 2: ghost values u_G = W_G^-1 r through the inverse windows.
+// One wavefront per (ghost row, member); lanes take window positions.
 template <class FT>
 __global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_kernel(GArgs a) {
   const int64_t item = static_cast<int64_t>(blockIdx.x) * (RHS_BLOCK / 64) + (threadIdx.x >> 6);
@@ -373,21 +394,21 @@ __global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_kernel(GArgs a) {
   const int64_t row = item / a.E;
   const int e = static_cast<int>(item - row * a.E);
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int mat = 0; mat < 3; ++mat) {
-    const int *ptr = a.inv_ptr + static_cast<int64_t>(mat) * (a.R + 1);
-    for (int q = ptr[row] + lane; q < ptr[row + 1]; q += 64) {
-      const double c = a.inv_val[q];
-      const double *r = a.gres + (static_cast<int64_t>(a.inv_col[q]) * a.E + e) * 4;
-      if (mat == 0) {
-        v[0] = fma(c, r[0], v[0]);
-      } else if (mat == 1) {
-        v[1] = fma(c, r[1], v[1]);
-      } else {
-        v[2] = fma(c, r[2], v[2]);
-        v[3] = fma(c, r[3], v[3]);
-      }
+  // the rows' window descriptors first (independent loads), then one pass
+  // over the longest window
+  const InvRow wt = inv_row(a, 2, row), ww = inv_row(a, 1, row);
+  const InvRow wu = a.u_shared ? InvRow{nullptr, 0, 1, 0, 0} : inv_row(a, 0, row);
+  const int L = max(max(wt.len, ww.len), wu.len);
+  for (int q = lane; q < L; q += 64) {
+    if (q < wt.len) {
+      const double c = wt.val[q];
+      const double *r = a.gres + (win_row(wt, q) * a.E + e) * 4;
+      if (a.u_shared) v[0] = fma(c, r[0], v[0]);
+      v[2] = fma(c, r[2], v[2]);
+      v[3] = fma(c, r[3], v[3]);
     }
+    if (q < ww.len) v[1] = fma(ww.val[q], a.gres[(win_row(ww, q) * a.E + e) * 4 + 1], v[1]);
+    if (q < wu.len) v[0] = fma(wu.val[q], a.gres[(win_row(wu, q) * a.E + e) * 4], v[0]);
   }
   for (int f = 0; f < 4; ++f) v[f] = wave_sum(v[f]);
   if (lane == 0) store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.bnd_ghosts[row]) * a.E + e) * 4, v);
@@ -420,27 +441,35 @@ __global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_members_kernel(GArgs a)
   const int64_t row = t / a.E;
   const int e = static_cast<int>(t - row * a.E);
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  {
-    const int q0 = a.inv_ptr[row], q1 = a.inv_ptr[row + 1];
+  if (!a.u_shared) {
+    const InvRow w = inv_row(a, 0, row);
 #pragma unroll 4
-    for (int q = q0; q < q1; ++q) v[0] = fma(a.inv_val[q], a.gres[(static_cast<int64_t>(a.inv_col[q]) * a.E + e) * 4], v[0]);
+    for (int q = 0; q < w.len; ++q) v[0] = fma(w.val[q], a.gres[(win_row(w, q) * a.E + e) * 4], v[0]);
   }
   {
-    const int *ptr = a.inv_ptr + (a.R + 1);
-    const int q0 = ptr[row], q1 = ptr[row + 1];
+    const InvRow w = inv_row(a, 1, row);
 #pragma unroll 4
-    for (int q = q0; q < q1; ++q)
-      v[1] = fma(a.inv_val[q], a.gres[(static_cast<int64_t>(a.inv_col[q]) * a.E + e) * 4 + 1], v[1]);
+    for (int q = 0; q < w.len; ++q) v[1] = fma(w.val[q], a.gres[(win_row(w, q) * a.E + e) * 4 + 1], v[1]);
   }
   {
-    const int *ptr = a.inv_ptr + 2 * static_cast<int64_t>(a.R + 1);
-    const int q0 = ptr[row], q1 = ptr[row + 1];
+    const InvRow w = inv_row(a, 2, row);
+    if (a.u_shared) {
 #pragma unroll 4
-    for (int q = q0; q < q1; ++q) {
-      const double c = a.inv_val[q];
-      const double2 r = *reinterpret_cast<const double2 *>(a.gres + (static_cast<int64_t>(a.inv_col[q]) * a.E + e) * 4 + 2);
-      v[2] = fma(c, r.x, v[2]);
-      v[3] = fma(c, r.y, v[3]);
+      for (int q = 0; q < w.len; ++q) {
+        const double c = w.val[q];
+        const double4 r = *reinterpret_cast<const double4 *>(a.gres + (win_row(w, q) * a.E + e) * 4);
+        v[0] = fma(c, r.x, v[0]);
+        v[2] = fma(c, r.z, v[2]);
+        v[3] = fma(c, r.w, v[3]);
+      }
+    } else {
+#pragma unroll 4
+      for (int q = 0; q < w.len; ++q) {
+        const double c = w.val[q];
+        const double2 r = *reinterpret_cast<const double2 *>(a.gres + (win_row(w, q) * a.E + e) * 4 + 2);
+        v[2] = fma(c, r.x, v[2]);
+        v[3] = fma(c, r.y, v[3]);
+      }
     }
   }
   store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.bnd_ghosts[row]) * a.E + e) * 4, v);
@@ -456,7 +485,29 @@ __global__ void tick_kernel(DevMisc *m) { m->step_ctr += 1; }
 
 // ---- host-side launchers ----------------------------------------------------
 
+// Transport mirror boundary (Section 6.1): ghost k takes the value of active
+// node src[k], for every member.
+template <class FT>
+__global__ void mirror_kernel(FT *__restrict__ y, const int *__restrict__ src, int64_t na, int64_t ng, int E) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= ng * E) return;
+  const int64_t k = t / E;
+  const int e = static_cast<int>(t - k * E);
+  y[(na + k) * E + e] = y[static_cast<int64_t>(src[k]) * E + e];
+}
+
 int launch_ghost(rbffd_ctx *ctx, rbffd_model *m, void *y) {
+  if (m->physics == RBFFD_PHYS_ADVECTION && m->n_mirror > 0) {
+    const int64_t cnt = m->n_mirror * m->E;
+    if (m->fdt == RBFFD_F64)
+      mirror_kernel<double><<<grid_for(cnt, 256), 256, 0, ctx->stream>>>(static_cast<double *>(y), m->mirror_src.as<int>(),
+                                                                        m->Na, m->n_mirror, m->E);
+    else
+      mirror_kernel<float><<<grid_for(cnt, 256), 256, 0, ctx->stream>>>(static_cast<float *>(y), m->mirror_src.as<int>(),
+                                                                       m->Na, m->n_mirror, m->E);
+    RBFFD_HIP(ctx, hipGetLastError());
+    return RBFFD_OK;
+  }
   if (m->physics != RBFFD_PHYS_NS || m->n_bnd == 0) return RBFFD_OK;
   GArgs g{};
   g.y = y;
@@ -465,12 +516,14 @@ int launch_ghost(rbffd_ctx *ctx, rbffd_model *m, void *y) {
   g.bnd_normal = m->bnd_normal.as<int>();
   g.wall_idx = m->wall_idx.as<int>();
   g.wall_w = m->wall_w.as<double2>();
-  g.inv_ptr = m->inv_ptr.as<int>();
-  g.inv_col = m->inv_col.as<int>();
+  g.inv_grp = m->inv_grp.as<int2>();
+  g.inv_win = m->inv_win.as<int>();
+  g.inv_off = m->inv_off.as<int64_t>();
   g.inv_val = m->inv_val.as<double>();
   g.gres = m->gres.as<double>();
   g.kind = m->kind.as<uint8_t>();
   g.R = m->n_bnd;
+  g.u_shared = m->u_shares_tp;
   g.n = m->n;
   g.E = m->E;
   g.bc_scale = m->g / (m->c_p * m->theta_bar);

@@ -69,9 +69,11 @@ def advection_model(ctx, cfg, idx, W, xy=None, field_dtype=R.F64, ensemble=1):
     nd = cfg["nodes"]
     if xy is None:
         xy = to_dev(nd.xy, torch.float64)
+    src = cfg.get("mirror_src")
     return R.Model(ctx, R.PHYS_ADVECTION, idx, W, xy, nd.n_active, field_dtype=field_dtype,
                    ensemble=ensemble, hv_coeff=cfg["hv_coeff"], vel_u=to_dev(cfg["U"], torch.float64),
-                   vel_v=to_dev(cfg["V"], torch.float64), vel_period=cfg["vel_period"])
+                   vel_v=to_dev(cfg["V"], torch.float64), vel_period=cfg["vel_period"],
+                   mirror_src=None if src is None else to_dev(src, torch.int32))
 
 
 def advection_weights(ctx, cfg, xy=None):

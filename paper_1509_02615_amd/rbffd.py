@@ -46,7 +46,8 @@ class ModelDesc(ctypes.Structure):
                 ("vel_u", _vp), ("vel_v", _vp), ("vel_period", _f64),
                 ("c_p", _f64), ("c_v", _f64), ("R_d", _f64), ("g", _f64), ("theta_bar", _f64),
                 ("mu", _f64), ("u_bar", _f64), ("n_bnd", _i32), ("reserved1", _i32), ("bnd_nodes", _vp),
-                ("bnd_ghosts", _vp), ("bnd_normal", _vp), ("bnd_d1", _vp), ("bnd_d2", _vp)]
+                ("bnd_ghosts", _vp), ("bnd_normal", _vp), ("bnd_d1", _vp), ("bnd_d2", _vp),
+                ("mirror_src", _vp)]
 
 
 _lib.rbffd_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _vp]
@@ -197,7 +198,7 @@ class Model:
 
     def __init__(self, ctx: Context, physics, idx, w, xy, n_active, field_dtype=F64, weight_dtype=F64,
                  ensemble=1, hv_coeff=0.0, vel_u=None, vel_v=None, vel_period=1.0, consts=None,
-                 bnd_nodes=None, bnd_ghosts=None, bnd_normal=None, bnd_d1=None, bnd_d2=None):
+                 bnd_nodes=None, bnd_ghosts=None, bnd_normal=None, bnd_d1=None, bnd_d2=None, mirror_src=None):
         self.ctx = ctx
         N = xy.shape[0]
         na, n = idx.shape
@@ -224,6 +225,8 @@ class Model:
             d.bnd_normal = _ptr(bnd_normal, torch.int32, (nr,), "bnd_normal")
             d.bnd_d1 = _ptr(bnd_d1, torch.float64, (nr, n), "bnd_d1")
             d.bnd_d2 = _ptr(bnd_d2, torch.float64, (nr, n), "bnd_d2")
+        if mirror_src is not None:
+            d.mirror_src = _ptr(mirror_src, torch.int32, (N - na,), "mirror_src")
         h = _vp()
         ctx.check(_lib.rbffd_model_create(ctx.h, ctypes.byref(d), ctypes.byref(h)))
         self.h = h

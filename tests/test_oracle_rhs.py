@@ -174,6 +174,51 @@ def test_bell_return_improves_with_resolution():
     assert errs[1] < 0.85 * errs[0] and errs[1] < 0.9, errs
 
 
+def test_mirror_boundary_stencils_are_symmetric():
+    """Section 6.1 mirror boundary: the 37-node stencil of every edge node is
+    closed under reflection across its edge, ghost values copy their sources,
+    and Dx at a node on x = 0 (Dy at y = 0) is antisymmetric, so it gives 0
+    on mirror-extended data."""
+    cfg = advection_config(20, mirror=True)
+    model, idx, W, status = build_advection(cfg)
+    assert status.sum() == 0
+    nd = cfg["nodes"]
+    xy = nd.xy
+    key = {(round(x, 12), round(y, 12)): j for j, (x, y) in enumerate(xy)}
+    rng = np.random.default_rng(1)
+    psi = model.mirror(rng.standard_normal(nd.n_total))
+    assert np.array_equal(psi[nd.n_active:], psi[nd.mirror_src])
+    for i in range(nd.n_active):
+        x, y = xy[i]
+        for axis, on in ((0, x == 0.0), (1, y == 0.0)):
+            if not on:
+                continue
+            st = set(int(j) for j in idx[i])
+            for j in idx[i]:
+                p = list(xy[j])
+                p[axis] = -p[axis]
+                m = key[(round(p[0], 12), round(p[1], 12))]
+                assert m in st
+                k_j, k_m = list(idx[i]).index(j), list(idx[i]).index(m)
+                assert abs(W[axis][i][k_j] + W[axis][i][k_m]) <= 1e-9 * np.abs(W[axis][i]).max()
+            d = W[axis][i] @ psi[idx[i]]
+            assert abs(d) <= 1e-9 * np.abs(W[axis][i] * psi[idx[i]]).sum()
+
+
+def test_mirror_bell_return_improves_with_resolution():
+    """The transport run with mirror ghosts instead of one-sided stencils
+    also brings the bell back at T, better under refinement."""
+    errs = []
+    for n in (24, 40):
+        cfg = advection_config(n, mirror=True)
+        model, idx, W, status = build_advection(cfg)
+        assert status.sum() == 0
+        y, _ = O.integrate(model, model.mirror(cfg["psi0"]), 0.0, cfg["dt"], 2000, "rk4")
+        na = cfg["nodes"].n_active
+        errs.append(O.rel_l2(y[:na], cfg["psi0"][:na]))
+    assert errs[1] < 0.85 * errs[0] and errs[1] < 0.9, errs
+
+
 @pytest.mark.slow
 def test_density_current_400m_against_table():
     """Table tbl:straka, hexagonal 400 m: the oracle's run to 900 s lands

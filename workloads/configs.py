@@ -26,19 +26,23 @@ NS_HV_C = 0.25
 DT_TABLE = {800.0: 2.0, 400.0: 1.0, 200.0: 0.5, 100.0: 0.25, 50.0: 0.125, 25.0: 0.0625}
 
 
-def advection_config(n_side: int = 64):
+def advection_config(n_side: int = 64, mirror: bool = False):
     """Scalar transport: Cartesian n_side^2 on [0,1]^2, r^5 + degree-4
     polynomials (15 terms), 37-node stencils, Dx, Dy and Laplacian-cubed
-    hyperviscosity (HV PHS order 7), RK4 with dt = 2.5e-3 to T = 5."""
-    nodes = unit_square_cartesian(n_side)
+    hyperviscosity (HV PHS order 7), RK4 with dt = 2.5e-3 to T = 5. With
+    ``mirror`` the edges get mirror ghosts (Section 6.1) instead of one-sided
+    stencils; the velocity is the same analytic field at every node."""
+    from .nodes import mirrored_square
+    nodes = mirrored_square(n_side) if mirror else unit_square_cartesian(n_side)
     U, V = swirl_velocity(nodes.xy)
     h = nodes.h
     return dict(
-        name=f"advection-cartesian-{n_side}x{n_side}",
+        name=f"advection-cartesian-{n_side}x{n_side}" + ("-mirror" if mirror else ""),
         nodes=nodes, m=5, l=4, n=37, hv_k=3, hv_m=7,
         hv_coeff=2.0 ** -6 * h ** 6,
         U=U, V=V, vel_period=5.0,
         psi0=cosine_bell(nodes.xy),
+        mirror_src=getattr(nodes, "mirror_src", None),
         dt=2.5e-3, t_end=5.0, tableau="rk4",
     )
 

@@ -61,6 +61,33 @@ def unit_square_cartesian(n_side: int = 64) -> NodeSet:
                    layout="cartesian", nx=n_side, nz=n_side)
 
 
+def mirrored_square(n_side: int = 64, depth: int = 3) -> NodeSet:
+    """The n_side x n_side Cartesian lattice on [0,1]^2 of
+    ``unit_square_cartesian`` plus mirror ghosts (Section 6.1): every node
+    within ``depth`` spacings of an edge, off that edge, is reflected across
+    it (across both edges near a corner, which gives the corner's diagonal
+    ghosts too). Ghost k takes the value of active node ``mirror_src[k]``, so
+    boundary stencils are mirror-symmetric and need no boundary condition.
+    depth = 3 completes the 37-node stencils (shells up to r^2 = 10 h^2)."""
+    base = unit_square_cartesian(n_side)
+    h = base.h
+    lim = depth * h * (1.0 + 1e-9)
+    pts, src = [], []
+    for i, (x, y) in enumerate(base.xy):
+        xs = [x] + ([-x] if 0.0 < x <= lim else []) + ([2.0 - x] if 0.0 < 1.0 - x <= lim else [])
+        ys = [y] + ([-y] if 0.0 < y <= lim else []) + ([2.0 - y] if 0.0 < 1.0 - y <= lim else [])
+        for a, xv in enumerate(xs):
+            for b, yv in enumerate(ys):
+                if a or b:
+                    pts.append((xv, yv))
+                    src.append(i)
+    xy = np.concatenate([base.xy, np.array(pts)], axis=0)
+    nd = NodeSet(xy=xy, n_active=base.n_active, period_x=0.0, h=h, layout="cartesian", nx=n_side, nz=n_side,
+                 height=1.0, width=1.0)
+    nd.mirror_src = np.array(src, np.int32)
+    return nd
+
+
 def channel(layout: str, nx: int, nz: int, x_left: float, length: float, height: float,
             seed: int = 0, jitter: float = 0.2) -> NodeSet:
     """x-periodic channel [x_left, x_left+length) x [0, height] with walls at
