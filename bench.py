@@ -26,6 +26,7 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+FP64_PEAK_TFLOPS = 78.6
 # closure network per node-sample: 149 inputs -> 128 -> 128 -> 4 outputs,
 # 2 flops per multiply-add (the kernels pad to 160 inputs and 16 outputs)
 CLOSURE_FLOP_PER_SAMPLE = 2 * (149 * 128 + 128 * 128 + 128 * 4)
@@ -134,7 +135,15 @@ def weights_leg(R, ctx, cfg, precision):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
     bad = int((status != 0).sum().item())
-    return dict(stencils=nd.n_active, ms=ms, stencils_per_s=nd.n_active / (ms / 1e3), singular=bad)
+    # algorithmic flops of the solves: LU of K x K (2/3 K^3) and the forward and
+    # back substitution of the 3 right-hand sides (2 K^2 each); K = n + M
+    K = cfg["n_per"].astype(np.float64) + (cfg["l_per"] + 1) * (cfg["l_per"] + 2) / 2
+    flops = float(np.sum(2.0 / 3.0 * K ** 3 + 2.0 * K ** 2 * 3))
+    return dict(stencils=nd.n_active, ms=ms, stencils_per_s=nd.n_active / (ms / 1e3), singular=bad,
+                solve_tflops=flops / (ms / 1e3) / 1e12,
+                fp64_peak_frac=flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+                note="solve flops only (2/3 K^3 + 2 K^2 per right-hand side); assembly and "
+                     "double-double refinement are extra work, not counted")
 
 
 def closure_leg(R, ctx, calls=20, members=256):

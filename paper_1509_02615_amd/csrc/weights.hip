@@ -26,6 +26,7 @@
 //
 // FP64 matrix cores on gfx950 have the same peak as the FP64 vector ALUs,
 // so the factorisation is written on the vector ALUs.
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -61,6 +62,7 @@ struct WArgs {
   int *status;
   int k_cap;
   int max_iter;
+  const int *list;  // stencils of this launch (NULL: blockIdx.x itself)
 };
 
 __device__ __forceinline__ int n_terms(int l) { return (l + 1) * (l + 2) / 2; }
@@ -161,6 +163,7 @@ __device__ __forceinline__ double wave_max(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
 }
+
 
 // ---- double-double arithmetic (error-free transformations: Knuth's TwoSum,
 // Dekker's product via fused multiply-add). This file is compiled without
@@ -277,24 +280,24 @@ __device__ dd rhs_entry_dd(int i, int n, int m, const WOp &op, int k, const doub
 }
 
 template <typename T>
-__global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
+__global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void weights_kernel(WArgs a) {
   extern __shared__ double smem[];
-  const int q = blockIdx.x;
+  const int q = a.list ? a.list[blockIdx.x] : blockIdx.x;
   const int tid = threadIdx.x;
   const int kc = a.k_cap;
-  // LDS carve-up
-  double *xs = smem;                       // [8][kc] solution
-  double *rs = xs + MAX_OPS * kc;          // [8][kc] residual / correction
-  double *xi = rs + MAX_OPS * kc;          // [128] scaled x offsets (FP64)
-  double *ze = xi + 128;                   // [128] scaled z offsets (FP64)
-  double *xl = ze + 128;                   // [128] low parts of the double-double x offsets
-  double *zl = xl + 128;                   // [128] low parts of the double-double z offsets
+  // LDS carve-up, sized by the launch's largest system kc and operator count
+  double *xs = smem;                       // [n_ops][kc] solution
+  double *rs = xs + a.n_ops * kc;          // [n_ops][kc] residual / correction
+  double *xi = rs + a.n_ops * kc;          // [kc] scaled x offsets (FP64)
+  double *ze = xi + kc;                    // [kc] scaled z offsets (FP64)
+  double *xl = ze + kc;                    // [kc] low parts of the double-double x offsets
+  double *zl = xl + kc;                    // [kc] low parts of the double-double z offsets
   __shared__ double s_red[4];
   __shared__ int s_piv[128];
   __shared__ int s_gl[MAX_OPS], s_kg[MAX_OPS];  // operators of the current group, their k
   __shared__ int s_flag, s_pivrow;
   __shared__ double s_pmin, s_amax;
-  T *A = reinterpret_cast<T *>(zl + 128);  // [kc + 8 columns][kc], column-major
+  T *A = reinterpret_cast<T *>(zl + kc);   // [kc + n_ops columns][kc], column-major
 
   const int c = a.centers ? a.centers[q] : q;
   const int n = a.n_per ? a.n_per[q] : a.n_max;
@@ -404,19 +407,20 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
     }
     const int Kt = K + ng;  // columns of [A | B]
 
-    // 2. assembly, column-major: element (i, j) at j*kc + i
-    for (int t = tid; t < K * K; t += W_THREADS) {
-      int i = t % K, j = t / K;
-      A[j * kc + i] = static_cast<T>(sys_entry(i, j, n, mg, xi, ze));
-    }
-    for (int t = tid; t < K * ng; t += W_THREADS) {
-      int i = t % K, g = t / K;
-      A[(K + g) * kc + i] = static_cast<T>(rhs_entry(i, n, mg, a.ops[s_gl[g]], s_kg[g], xi, ze));
-    }
+    // 2. assembly, column-major: element (i, j) at j*kc + i; wavefronts take
+    // columns, lanes rows
+    constexpr int NW = W_THREADS / 64;
+    const int wv = tid >> 6, ln = tid & 63;
+    for (int j = wv; j < K; j += NW)
+      for (int i = ln; i < K; i += 64) A[j * kc + i] = static_cast<T>(sys_entry(i, j, n, mg, xi, ze));
+    for (int g = wv; g < ng; g += NW)
+      for (int i = ln; i < K; i += 64)
+        A[(K + g) * kc + i] = static_cast<T>(rhs_entry(i, n, mg, a.ops[s_gl[g]], s_kg[g], xi, ze));
     __syncthreads();
     if (tid < 64) {
       double v = 0.0;
-      for (int t = tid; t < K * K; t += 64) v = fmax(v, fabs(static_cast<double>(A[(t / K) * kc + t % K])));
+      for (int j = 0; j < K; ++j)
+        for (int i = tid; i < K; i += 64) v = fmax(v, fabs(static_cast<double>(A[j * kc + i])));
       v = wave_max(v);
       if (tid == 0) {
         s_amax = v;
@@ -486,15 +490,16 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
     }
 
     // 4. back substitution U x = y (y = transformed right-hand sides)
-    for (int t = tid; t < K * ng; t += W_THREADS) xs[(t / K) * kc + t % K] = A[(K + t / K) * kc + t % K];
+    for (int g = wv; g < ng; g += NW)
+      for (int i = ln; i < K; i += 64) xs[g * kc + i] = A[(K + g) * kc + i];
     __syncthreads();
+    // wavefronts take right-hand sides, lanes rows (no integer division)
     for (int k = K - 1; k >= 0; --k) {
       if (tid < ng) xs[tid * kc + k] = xs[tid * kc + k] / static_cast<double>(A[k * kc + k]);
       __syncthreads();
-      for (int t = tid; t < k * ng; t += W_THREADS) {
-        int i = t % k, g = t / k;
-        xs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), xs[g * kc + k], xs[g * kc + i]);
-      }
+      for (int g = wv; g < ng; g += NW)
+        for (int i = ln; i < k; i += 64)
+          xs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), xs[g * kc + k], xs[g * kc + i]);
       __syncthreads();
     }
 
@@ -545,26 +550,25 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
       }
       __syncthreads();
       for (int k = 0; k < K - 1; ++k) {  // unit lower triangle
-        for (int t = tid; t < (K - k - 1) * ng; t += W_THREADS) {
-          int i = k + 1 + t % (K - k - 1), g = t / (K - k - 1);
-          rs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), rs[g * kc + k], rs[g * kc + i]);
-        }
+        for (int g = wv; g < ng; g += NW)
+          for (int i = k + 1 + ln; i < K; i += 64)
+            rs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), rs[g * kc + k], rs[g * kc + i]);
         __syncthreads();
       }
       for (int k = K - 1; k >= 0; --k) {  // upper triangle
         if (tid < ng) rs[tid * kc + k] = rs[tid * kc + k] / static_cast<double>(A[k * kc + k]);
         __syncthreads();
-        for (int t = tid; t < k * ng; t += W_THREADS) {
-          int i = t % k, g = t / k;
-          rs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), rs[g * kc + k], rs[g * kc + i]);
-        }
+        for (int g = wv; g < ng; g += NW)
+          for (int i = ln; i < k; i += 64)
+            rs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), rs[g * kc + k], rs[g * kc + i]);
         __syncthreads();
       }
       // x += d; converged when |d| <= 2^-48 |x| (max norms over the group)
       if (tid < 64) {
         double dmax = 0.0, xmax = 0.0;
-        for (int t = tid; t < K * ng; t += 64) {
-          int i = t % K, g = t / K;
+        for (int t = 0; t < ng * 2; ++t) {
+          const int g = t >> 1, i = tid + 64 * (t & 1);
+          if (i >= K) continue;
           double d = rs[g * kc + i];
           double xn = xs[g * kc + i] + d;
           xs[g * kc + i] = xn;
@@ -584,7 +588,8 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
     bool finite = true;
     if (tid < 64) {
       double v = 0.0;
-      for (int t = tid; t < K * ng; t += 64) v = fmax(v, fabs(xs[(t / K) * kc + t % K]));
+      for (int g = 0; g < ng; ++g)
+        for (int i = tid; i < K; i += 64) v = fmax(v, fabs(xs[g * kc + i]));
       v = wave_max(v);
       if (tid == 0) s_red[2] = v;
     }
@@ -603,6 +608,48 @@ __global__ __launch_bounds__(W_THREADS) void weights_kernel(WArgs a) {
     __syncthreads();
   }
   if (tid == 0 && a.status) a.status[q] = status;
+}
+
+// Launch buckets by system size: each bucket's launch reserves LDS for its
+// own largest K, so small systems do not pay for the largest one.
+constexpr int NBUCKET = 6;
+__host__ __device__ constexpr int bucket_cap(int b) {
+  return b == 0 ? 32 : b == 1 ? 48 : b == 2 ? 64 : b == 3 ? 80 : b == 4 ? 96 : 128;
+}
+__device__ __forceinline__ int bucket_of(int K) {
+  int b = 0;
+  while (b < NBUCKET - 1 && K > bucket_cap(b)) ++b;
+  return b;
+}
+
+// count[b] and the largest K in bucket b (kmax[b])
+__global__ void bucket_count_kernel(const int *n_per, int n_max, const int *l_per, int l_uni, int nc, int *count,
+                                    int *kmax) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  const int K = (n_per ? n_per[q] : n_max) + n_terms(l_per ? l_per[q] : l_uni);
+  const int b = bucket_of(K);
+  atomicAdd(&count[b], 1);
+  atomicMax(&kmax[b], K);
+}
+
+// cursor[b] starts at bucket b's offset in `list`. Each wavefront reserves
+// one run per bucket and fills it in ascending stencil order, so stencils
+// that are neighbours in memory stay neighbours in a launch.
+__global__ void bucket_fill_kernel(const int *n_per, int n_max, const int *l_per, int l_uni, int nc, int *cursor,
+                                   int *list) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool ok = q < nc;
+  const int b = ok ? bucket_of((n_per ? n_per[q] : n_max) + n_terms(l_per ? l_per[q] : l_uni)) : -1;
+  for (int bb = 0; bb < NBUCKET; ++bb) {
+    const uint64_t mask = __ballot(b == bb);
+    if (mask == 0) continue;
+    int base = 0;
+    if (lane == __ffsll(static_cast<unsigned long long>(mask)) - 1) base = atomicAdd(&cursor[bb], __popcll(mask));
+    base = __shfl(base, __ffsll(static_cast<unsigned long long>(mask)) - 1, 64);
+    if (b == bb) list[base + __popcll(mask & ((uint64_t(1) << lane) - 1))] = q;
+  }
 }
 
 // Per-stencil system size K = n + M and a count of invalid parameter sets.
@@ -669,21 +716,47 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   a.n_ops = n_ops;
   a.w = w;
   a.status = st_out;
-  a.k_cap = kc;
-  const size_t head = sizeof(double) * (2 * MAX_OPS * kc + 512);
-  if (precision == RBFFD_SOLVE_FP64) {
-    a.max_iter = 3;
-    size_t lds = head + sizeof(double) * static_cast<size_t>(kc) * (kc + MAX_OPS);
-    if (lds > 156 * 1024) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d too large for LDS", kc);
-    RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<double>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    weights_kernel<double><<<nc, W_THREADS, lds, s>>>(a);
-  } else {
-    a.max_iter = 30;
-    size_t lds = head + sizeof(float) * static_cast<size_t>(kc) * (kc + MAX_OPS);
-    RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<float>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-    weights_kernel<float><<<nc, W_THREADS, lds, s>>>(a);
+  a.max_iter = precision == RBFFD_SOLVE_FP64 ? 3 : 30;
+  // stencils bucketed by K, one launch per non-empty bucket
+  DevBuf d_cnt, d_list;
+  RBFFD_HIP(ctx, d_cnt.alloc(3 * NBUCKET * sizeof(int)));
+  RBFFD_HIP(ctx, d_list.alloc(sizeof(int) * std::max(nc, 1)));
+  RBFFD_HIP(ctx, hipMemsetAsync(d_cnt.p, 0, 3 * NBUCKET * sizeof(int), s));
+  bucket_count_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
+                                                        d_cnt.as<int>(), d_cnt.as<int>() + 2 * NBUCKET);
+  RBFFD_HIP(ctx, hipGetLastError());
+  int cnt[3 * NBUCKET];   // counts, starts, largest K
+  RBFFD_HIP(ctx, hipMemcpyAsync(cnt, d_cnt.p, 3 * NBUCKET * sizeof(int), hipMemcpyDeviceToHost, s));
+  RBFFD_HIP(ctx, hipStreamSynchronize(s));
+  for (int b = 0, off = 0; b < NBUCKET; ++b) {
+    cnt[NBUCKET + b] = off;  // start of bucket b
+    off += cnt[b];
+  }
+  RBFFD_HIP(ctx, hipMemcpyAsync(d_cnt.as<int>() + NBUCKET, cnt + NBUCKET, NBUCKET * sizeof(int),
+                                hipMemcpyHostToDevice, s));
+  bucket_fill_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
+                                                       d_cnt.as<int>() + NBUCKET, d_list.as<int>());
+  RBFFD_HIP(ctx, hipGetLastError());
+  int used = 0;
+  for (int b = 0; b < NBUCKET; ++b) used += cnt[b] > 0;
+  for (int b = 0; b < NBUCKET; ++b) {
+    if (cnt[b] == 0) continue;
+    const int cap = cnt[2 * NBUCKET + b];  // the bucket's largest K
+    a.k_cap = cap;
+    a.list = used > 1 ? d_list.as<int>() + cnt[NBUCKET + b] : nullptr;
+    const size_t head = sizeof(double) * (2 * static_cast<size_t>(n_ops) * cap + 4 * static_cast<size_t>(cap));
+    if (precision == RBFFD_SOLVE_FP64) {
+      const size_t lds = head + sizeof(double) * static_cast<size_t>(cap) * (cap + n_ops);
+      if (lds > 156 * 1024) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d too large for LDS", cap);
+      RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<double>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+      weights_kernel<double><<<cnt[b], W_THREADS, lds, s>>>(a);
+    } else {
+      const size_t lds = head + sizeof(float) * static_cast<size_t>(cap) * (cap + n_ops);
+      RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<float>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+      weights_kernel<float><<<cnt[b], W_THREADS, lds, s>>>(a);
+    }
   }
   RBFFD_HIP(ctx, hipGetLastError());
   RBFFD_HIP(ctx, hipMemsetAsync(d_k.p, 0, 4 * sizeof(int), s));
