@@ -146,6 +146,50 @@ def weights_leg(R, ctx, cfg, precision):
                      "double-double refinement are extra work, not counted")
 
 
+def fullrun_leg(R, P, ctx, cfg, idx, W, Ww, xy, t_end=900.0, chunk=1800):
+    """The density current on the 2048 x 256 channel run to t_end with FP64,
+    FP32 and BF16-weight fields/weights from the same initial state (RK4,
+    dt = 1/16 s, 14,400 steps): theta' rel-l2 over the active nodes of the
+    reduced-precision runs against the FP64 run, and each run's theta'/w'
+    extrema and front (the -0.5 K contour on the ground)."""
+    import torch
+    nd = cfg["nodes"]
+    n = int(round(t_end / cfg["dt"]))
+    out, fields = {}, {}
+    for name, (fdt, wdt) in {"fp64": (R.F64, R.F64), "fp32": (R.F32, R.F32), "bf16": (R.F32, R.BF16)}.items():
+        model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
+        s = P.to_dev(cfg["state0"], torch.float64 if fdt == R.F64 else torch.float32)
+        s = s.reshape(model.state_shape()).contiguous()
+        t, done = 0.0, 0
+        w0 = time.perf_counter()
+        while done < n:
+            k = min(chunk, n - done)
+            t = R.rbffd_step(ctx, model, s, t, cfg["dt"], k, R.RK4)
+            done += k
+        R.rbffd_ghost(ctx, model, s)
+        torch.cuda.synchronize()
+        y = s.double().cpu().numpy().reshape(-1, 4)
+        na = nd.n_active
+        th = y[:na, 2]
+        bottom = nd.wall_nodes[0]
+        x, tb = nd.xy[bottom, 0], y[bottom, 2]
+        cold = np.nonzero((tb <= -0.5) & (x >= 0.0))[0]
+        front = None
+        if cold.size:
+            i = cold[np.argmax(x[cold])]
+            j = i + 1 if i + 1 < bottom.size else i
+            front = float(x[i] + (-0.5 - tb[i]) / (tb[j] - tb[i]) * (x[j] - x[i])) if j != i and tb[j] != tb[i] else float(x[i])
+        fields[name] = th
+        out[name] = dict(seconds=time.perf_counter() - w0, steps=n, t=t, theta_min=float(th.min()),
+                         theta_max=float(th.max()), w_min=float(y[:na, 1].min()), w_max=float(y[:na, 1].max()),
+                         front_m=front)
+        del model
+    ref = fields["fp64"]
+    for name in ("fp32", "bf16"):
+        out[name]["theta_rel_l2_vs_fp64"] = float(np.linalg.norm(fields[name] - ref) / np.linalg.norm(ref))
+    return out
+
+
 def closure_leg(R, ctx, calls=20, members=256):
     """Learned closure on its coarse grid (400 m Cartesian channel, 128 x 17
     nodes) for 256 members: 557,056 node-samples per fused forward call
@@ -237,6 +281,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and weight legs")
     ap.add_argument("--closure-only", action="store_true",
                     help="run only the learned-closure leg and print its result (for profiling)")
+    ap.add_argument("--fullrun-only", action="store_true",
+                    help="run only the FP64/FP32/BF16 runs to t = 900 s and print their comparison")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware-counter passes: 2 RK4 steps of the chosen precision "
                          "and 3 plain copies of 512 MiB (counter calibration); prints no JSON line")
@@ -271,6 +317,9 @@ def main():
     n_stencils = nd.n_active + nd.bnd_nodes.size
     assert int(st_a.abs().sum()) == 0 and int(st_w.abs().sum()) == 0
     log(f"[bench] search + weights for {n_stencils} stencils: {setup_s:.3f} s")
+    if args.fullrun_only:
+        print(json.dumps(fullrun_leg(R, P, ctx, cfg, idx, W, Ww, xy)), flush=True)
+        return
 
     fdt = {"fp32": R.F32, "fp64": R.F64, "bf16": R.F32}[args.precision]
     wdt = {"fp32": R.F32, "fp64": R.F64, "bf16": R.BF16}[args.precision]
@@ -308,6 +357,8 @@ def main():
         log(f"[bench] weights fp32+IR: {extras['weights_mixed_1M_fp32_ir']}")
         extras["closure_forward_256x2176"] = closure_leg(R, ctx)
         log(f"[bench] closure: {extras['closure_forward_256x2176']}")
+        extras["precision_fullrun_900s"] = fullrun_leg(R, P, ctx, cfg, idx, W, Ww, xy)
+        log(f"[bench] full runs to 900 s: {extras['precision_fullrun_900s']}")
     extras["weights_scale_setup"] = dict(stencils=n_stencils, seconds=setup_s,
                                          stencils_per_s=n_stencils / setup_s,
                                          note="search + FP64 weights incl. host sync, 4+2 operators")
@@ -342,6 +393,10 @@ def main():
                      "kernel": "ns_stage_kernel", "bytes_per_launch": k["bytes_per_launch"],
                      "kernel_avg_ms": k["kernel_avg_ms"]},
         "cpu_baseline": cpu,
+        "accuracy": None if "precision_fullrun_900s" not in extras else {
+            "theta_rel_l2_at_900s_vs_fp64": {k: extras["precision_fullrun_900s"][k]["theta_rel_l2_vs_fp64"]
+                                             for k in ("fp32", "bf16")},
+            "note": "same workload run 14,400 RK4 steps to t = 900 s in FP64, FP32 and with BF16 weights"},
         "extras": extras,
     }
     print(json.dumps(line), flush=True)

@@ -156,3 +156,46 @@ def test_rising_bubble_converges():
           f"orders {['%.2f' % o for o in orders]}", flush=True)
     assert all(errs[k + 1] < errs[k] for k in range(3))
     assert orders[-1] > 2.0
+
+
+def test_density_current_25m_fp64_fp32_bf16_to_900s():
+    """The 2048 x 256 channel (25 m columns, 524,288 nodes) run to t = 900 s
+    (14,400 RK4 steps) in FP64, FP32 and with BF16 weights. FP64 against the
+    25 m reference row of Table tbl:straka (extrema within 0.5% / 0.05 K,
+    front within 0.2%); FP32 within 1e-4 theta' rel-l2 of FP64 (measured
+    7e-6); BF16 weights within 0.1 (measured 0.033)."""
+    import torch
+    from paper_1509_02615_amd import rbffd as R
+    from paper_1509_02615_amd import pipeline as P
+    from workloads import scale_config
+    print("density current 2048x256 to 900 s: FP64, FP32, BF16 weights", flush=True)
+    ctx = R.Context(0)
+    cfg = scale_config()
+    nd = cfg["nodes"]
+    xy, idx, W, Ww, (sa, sw) = P.ns_weights(ctx, cfg)
+    assert int(sa.abs().sum()) == 0 and int(sw.abs().sum()) == 0
+    th = {}
+    for name, (fdt, wdt) in {"fp64": (0, 0), "fp32": (1, 1), "bf16": (1, 2)}.items():
+        model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
+        s = P.to_dev(cfg["state0"], torch.float64 if fdt == 0 else torch.float32).reshape(model.state_shape()).contiguous()
+        t = 0.0
+        for _ in range(8):
+            t = R.rbffd_step(ctx, model, s, t, cfg["dt"], 1800, R.RK4)
+        assert abs(t - 900.0) < 1e-9
+        R.rbffd_ghost(ctx, model, s)
+        y = s.double().cpu().numpy().reshape(-1, 4)
+        th[name] = y[:nd.n_active, 2]
+        if name == "fp64":
+            e = O.extrema(y, nd.n_active)
+            front = O.front_location(nd.xy, y[:, 2], nd.wall_nodes[0])
+            got = [e["theta_min"], e["theta_max"], e["w_min"], e["w_max"], front]
+            ref = table_row("reference", 25.0)
+            print(f"   fp64: got {np.round(got, 3).tolist()} table (25 m reference) {ref}", flush=True)
+            for g, r in zip(got[:4], ref[:4]):
+                assert abs(g - r) <= 0.005 * abs(r) + 0.05, (got, ref)
+            assert abs(front - ref[4]) <= 0.002 * ref[4]
+        del model
+    r32 = np.linalg.norm(th["fp32"] - th["fp64"]) / np.linalg.norm(th["fp64"])
+    rbf = np.linalg.norm(th["bf16"] - th["fp64"]) / np.linalg.norm(th["fp64"])
+    print(f"   theta' rel-l2 vs FP64 at 900 s: FP32 {r32:.2e}, BF16 weights {rbf:.2e}", flush=True)
+    assert r32 <= 1e-4 and rbf <= 0.1
