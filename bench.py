@@ -281,6 +281,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and weight legs")
     ap.add_argument("--closure-only", action="store_true",
                     help="run only the learned-closure leg and print its result (for profiling)")
+    ap.add_argument("--weights-only", action="store_true",
+                    help="run only the mixed 1M-stencil weights batch (FP64) once and print its result "
+                         "(for profiling)")
     ap.add_argument("--fullrun-only", action="store_true",
                     help="run only the FP64/FP32/BF16 runs to t = 900 s and print their comparison")
     ap.add_argument("--pmc-run", action="store_true",
@@ -301,6 +304,10 @@ def main():
     ctx = R.Context(0)
     if args.closure_only:
         print(json.dumps(closure_leg(R, ctx, calls=args.steps)), flush=True)
+        return
+    if args.weights_only:
+        from workloads import weights_config
+        print(json.dumps(weights_leg(R, ctx, weights_config(1024), R.SOLVE_FP64)), flush=True)
         return
     cfg = scale_config()
     nd = cfg["nodes"]

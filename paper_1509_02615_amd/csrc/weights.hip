@@ -296,7 +296,7 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
   __shared__ int s_piv[128];
   __shared__ int s_gl[MAX_OPS], s_kg[MAX_OPS];  // operators of the current group, their k
   __shared__ int s_flag, s_pivrow;
-  __shared__ double s_pmin, s_amax;
+  __shared__ double s_pmin, s_amax, s_akk, s_pval;
   T *A = reinterpret_cast<T *>(zl + kc);   // [kc + n_ops columns][kc], column-major
 
   const int c = a.centers ? a.centers[q] : q;
@@ -453,22 +453,29 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
           s_pivrow = bi;
           s_piv[k] = bi;
           s_pmin = fmin(s_pmin, best);
+          s_akk = static_cast<double>(A[k * kc + k]);
+          s_pval = static_cast<double>(A[k * kc + bi]);
         }
       }
       __syncthreads();
+      // row interchange k <-> p in the other columns, and the multipliers of
+      // column k (whose old row k now sits at row p) in the same phase
       const int p = s_pivrow;
+      const T piv = static_cast<T>(s_pval), akk = static_cast<T>(s_akk);
       if (p != k) {
         for (int j = tid; j < Kt; j += W_THREADS) {
+          if (j == k) continue;
           T tmp = A[j * kc + k];
           A[j * kc + k] = A[j * kc + p];
           A[j * kc + p] = tmp;
         }
-        __syncthreads();
       }
-      const T piv = A[k * kc + k];
       const int rows = K - k - 1;
-      for (int i = k + 1 + tid; i < K; i += W_THREADS)
-        A[k * kc + i] = (piv != T(0)) ? A[k * kc + i] / piv : T(0);
+      for (int i = k + 1 + tid; i < K; i += W_THREADS) {
+        const T v = i == p ? akk : A[k * kc + i];
+        A[k * kc + i] = (piv != T(0)) ? v / piv : T(0);
+      }
+      if (tid == 0) A[k * kc + k] = piv;
       __syncthreads();
       const int cols = Kt - k - 1;
       if (rows > 0 && cols > 0) {
@@ -494,12 +501,15 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
       for (int i = ln; i < K; i += 64) xs[g * kc + i] = A[(K + g) * kc + i];
     __syncthreads();
     // wavefronts take right-hand sides, lanes rows (no integer division)
+    // (each right-hand side belongs to one wavefront, so its lanes read
+    // x_k before lane 0 stores it, without a barrier in between)
     for (int k = K - 1; k >= 0; --k) {
-      if (tid < ng) xs[tid * kc + k] = xs[tid * kc + k] / static_cast<double>(A[k * kc + k]);
-      __syncthreads();
-      for (int g = wv; g < ng; g += NW)
-        for (int i = ln; i < k; i += 64)
-          xs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), xs[g * kc + k], xs[g * kc + i]);
+      const double ukk = static_cast<double>(A[k * kc + k]);
+      for (int g = wv; g < ng; g += NW) {
+        const double xk = xs[g * kc + k] / ukk;
+        for (int i = ln; i < k; i += 64) xs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), xk, xs[g * kc + i]);
+        if (ln == 0) xs[g * kc + k] = xk;
+      }
       __syncthreads();
     }
 
@@ -556,11 +566,12 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
         __syncthreads();
       }
       for (int k = K - 1; k >= 0; --k) {  // upper triangle
-        if (tid < ng) rs[tid * kc + k] = rs[tid * kc + k] / static_cast<double>(A[k * kc + k]);
-        __syncthreads();
-        for (int g = wv; g < ng; g += NW)
-          for (int i = ln; i < k; i += 64)
-            rs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), rs[g * kc + k], rs[g * kc + i]);
+        const double ukk = static_cast<double>(A[k * kc + k]);
+        for (int g = wv; g < ng; g += NW) {
+          const double xk = rs[g * kc + k] / ukk;
+          for (int i = ln; i < k; i += 64) rs[g * kc + i] = fma(-static_cast<double>(A[k * kc + i]), xk, rs[g * kc + i]);
+          if (ln == 0) rs[g * kc + k] = xk;
+        }
         __syncthreads();
       }
       // x += d; converged when |d| <= 2^-48 |x| (max norms over the group)
