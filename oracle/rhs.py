@@ -136,6 +136,9 @@ class NSModel:
         self.zwall[self.bnd_nodes[self.bnd_normal == 0]] = True
         self.xwall = np.zeros(self.n_active, bool)
         self.xwall[self.bnd_nodes[self.bnd_normal == 1]] = True
+        # the same differentiation matrices as sparse products, for long runs
+        n_tot = self.z.shape[0]
+        self.D = [dm_matrix(self.idx, W, n_tot) for W in (self.w_dx, self.w_dz, self.w_lap, self.w_hv)]
 
 
 def ghost_closure(model: NSModel, state: np.ndarray) -> np.ndarray:
@@ -161,16 +164,20 @@ def ghost_closure(model: NSModel, state: np.ndarray) -> np.ndarray:
     return s
 
 
-def ns_tendency(s, rows, idx, w_dx, w_dz, w_lap, w_hv, z, is_wall, consts, hv_coeff, is_xwall=None):
+def ns_tendency(s, rows, idx, w_dx, w_dz, w_lap, w_hv, z, is_wall, consts, hv_coeff, is_xwall=None,
+                derivs=None):
     """Eqs. uEq..piEq at the nodes ``rows`` of a closed state ``s`` [n_total][4]
     (ghost rows filled), given those rows' stencils and weights. ``is_wall``
     marks rows on walls normal to z (dw/dt = 0), ``is_xwall`` rows on walls
-    normal to x (du/dt = 0)."""
+    normal to x (du/dt = 0). ``derivs`` may supply the four stencil products
+    (Dx s, Dz s, Lap s, Lap^k s, each [rows][4]) computed elsewhere."""
     c = consts
     u, w, th, pi = (s[rows, f] for f in range(4))
     ua = u + c.get("u_bar", 0.0)     # background wind (translating density current)
-    D = lambda W: apply_dm(idx, W, s)                    # noqa: E731  [rows][4]
-    dx, dz, lap, hv = D(w_dx), D(w_dz), D(w_lap), D(w_hv)
+    if derivs is None:
+        D = lambda W: apply_dm(idx, W, s)                # noqa: E731  [rows][4]
+        derivs = (D(w_dx), D(w_dz), D(w_lap), D(w_hv))
+    dx, dz, lap, hv = derivs
     pibar = 1.0 - c["g"] * z / (c["c_p"] * c["theta_bar"])
     dpibar = -c["g"] / (c["c_p"] * c["theta_bar"])
     out = np.zeros((len(rows), 4))
@@ -196,5 +203,5 @@ def ns_rhs(model: NSModel, state: np.ndarray):
     out = np.zeros_like(s)
     out[:na] = ns_tendency(s, np.arange(na), model.idx, model.w_dx, model.w_dz, model.w_lap,
                            model.w_hv, model.z[:na], model.zwall, model.consts, model.hv_coeff,
-                           model.xwall)
+                           model.xwall, derivs=[Dm @ s for Dm in model.D])
     return out, s
