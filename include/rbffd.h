@@ -76,7 +76,7 @@ typedef struct {
   double period_x;          /* x period for the minimum image; 0 = not periodic.
                                With a period all x must lie in one interval of that
                                length.                                                  */
-  int64_t n_centers;        /* Nc: number of stencils                                  */
+  int64_t n_centers;        /* Nc: number of stencils (0: an empty batch, a no-op)     */
   const int32_t *centers;   /* [Nc] centre node indices, or NULL = 0..Nc-1             */
   int32_t n_max;            /* stencil row length of idx/w (1..120)                    */
   const int32_t *n_per;     /* [Nc] stencil size per centre (<= n_max), or NULL = n_max */

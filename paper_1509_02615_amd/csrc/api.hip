@@ -55,7 +55,7 @@ static int check_stencils(rbffd_ctx *ctx, const rbffd_stencils *st) {
   if (!st) return rbffd_fail(ctx, RBFFD_EINVAL, "null stencil description");
   if (st->n_nodes <= 0 || st->n_nodes >= (int64_t(1) << 31) || !st->xy)
     return rbffd_fail(ctx, RBFFD_EINVAL, "bad node set (n_nodes=%lld)", (long long)st->n_nodes);
-  if (st->n_centers <= 0 || st->n_centers >= (int64_t(1) << 31))
+  if (st->n_centers < 0 || st->n_centers >= (int64_t(1) << 31))
     return rbffd_fail(ctx, RBFFD_EINVAL, "bad n_centers=%lld", (long long)st->n_centers);
   if (st->n_max < 1 || st->n_max > 120)
     return rbffd_fail(ctx, RBFFD_EINVAL, "n_max=%d outside 1..120", st->n_max);
@@ -69,6 +69,7 @@ int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx) {
   if (!ctx) return RBFFD_EINVAL;
   int rc = check_stencils(ctx, st);
   if (rc) return rc;
+  if (st->n_centers == 0) return RBFFD_OK;  // empty batch: nothing to write
   if (!idx) return rbffd_fail(ctx, RBFFD_EINVAL, "null idx");
   RBFFD_HIP(ctx, hipSetDevice(ctx->device));
   return knn_run(ctx, st, idx);
@@ -80,8 +81,6 @@ int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops,
   int rc = check_stencils(ctx, st);
   if (rc) return rc;
   if (!ops || n_ops < 1 || n_ops > 8) return rbffd_fail(ctx, RBFFD_EINVAL, "n_ops=%d outside 1..8", n_ops);
-  if (!w) return rbffd_fail(ctx, RBFFD_EINVAL, "null w");
-  if (!st->idx_in && !idx) return rbffd_fail(ctx, RBFFD_EINVAL, "need idx output or idx_in");
   if (precision != RBFFD_SOLVE_FP64 && precision != RBFFD_SOLVE_FP32_IR)
     return rbffd_fail(ctx, RBFFD_EINVAL, "bad precision %d", precision);
   // Uniform parameters are checked here; per-centre ones are checked on the
@@ -109,6 +108,9 @@ int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops,
     if (st->n_max + M > 128)
       return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d above 128", st->n_max + M);
   }
+  if (st->n_centers == 0) return RBFFD_OK;  // empty batch: nothing to write
+  if (!w) return rbffd_fail(ctx, RBFFD_EINVAL, "null w");
+  if (!st->idx_in && !idx) return rbffd_fail(ctx, RBFFD_EINVAL, "need idx output or idx_in");
   RBFFD_HIP(ctx, hipSetDevice(ctx->device));
   const int32_t *use_idx = st->idx_in;
   if (!use_idx) {

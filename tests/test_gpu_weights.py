@@ -142,6 +142,23 @@ def test_weights_parity_channels(R, ctx, layout):
     _weights_parity(R, ctx, nd.xy, [(O.DZ, 0, 0), (O.DZZ, 0, 0)], 37, 7, 4, nd.period_x, nd.wall_nodes.ravel())
 
 
+def test_empty_batch_and_largest_system(R, ctx):
+    """Edge sizes: an empty batch of centres is a no-op for the search and
+    the weights; the largest system the library takes (n = 100, degree 6,
+    K = 128) matches the oracle on scattered nodes."""
+    import torch
+    say("weights: empty batch; K = 128 systems (n = 100, l = 6, r^7) on a jittered 24x24 square")
+    nd = jittered_square(24, seed=6)
+    xy = dev(nd.xy, torch.float64)
+    idx = R.rbffd_knn(ctx, xy, 37, 0.0, centers=dev(np.zeros(0, np.int32), torch.int32))
+    assert tuple(idx.shape) == (0, 37)
+    idx, W, status, rc = R.rbffd_weights(ctx, xy, [(O.DX, 0, 0)], 37, 7, 4,
+                                         centers=dev(np.zeros(0, np.int32), torch.int32))
+    assert rc == R.OK and W.numel() == 0
+    centers = np.array([0, 11, 300, 575, 290], np.int32)     # corner, edge, interior, corner, interior
+    _weights_parity(R, ctx, nd.xy, [(O.DX, 0, 0), (O.LAP, 0, 0), (O.HYPERLAP, 3, 0)], 100, 7, 6, 0.0, centers)
+
+
 @pytest.mark.parametrize("layout", ["cartesian", "hexagonal", "scattered"])
 def test_weights_parity_box(R, ctx, layout):
     """The closed box of the rising bubble (Section 6.5): interior operators,
