@@ -190,6 +190,25 @@ __device__ __forceinline__ dd dd_add(dd a, dd b) {
   s.lo += t.lo;
   return fast_two_sum(s.hi, s.lo);
 }
+// Sum without the second error-free step: the error is within a few
+// 2^-104 of |a| + |b| (not of |a + b|), which is what the residual sums and
+// sums of positive terms below need.
+__device__ __forceinline__ dd dd_add_terms(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  s.lo += a.lo + b.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ dd dd_sqr(dd a) {
+  dd p = two_prod(a.hi, a.hi);
+  p.lo += 2.0 * (a.hi * a.lo);
+  return fast_two_sum(p.hi, p.lo);
+}
+// (ah + al) - (bh + bl) for offsets of distinct stencil nodes
+__device__ __forceinline__ dd dd_diff(double ah, double al, double bh, double bl) {
+  dd s = two_sum(ah, -bh);
+  s.lo += al - bl;
+  return fast_two_sum(s.hi, s.lo);
+}
 __device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
 __device__ __forceinline__ dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
 __device__ __forceinline__ dd dd_mul(dd a, dd b) {
@@ -234,9 +253,9 @@ __device__ __forceinline__ dd dd_ipow(dd x, int p) {
 __device__ dd sys_entry_dd(int i, int j, int n, int m, const double *xh, const double *xl, const double *zh,
                            const double *zl) {
   if (i < n && j < n) {
-    dd dx = dd_sub(dd{xh[i], xl[i]}, dd{xh[j], xl[j]});
-    dd dz = dd_sub(dd{zh[i], zl[i]}, dd{zh[j], zl[j]});
-    dd r2 = dd_add(dd_mul(dx, dx), dd_mul(dz, dz));
+    const dd dx = dd_diff(xh[i], xl[i], xh[j], xl[j]);
+    const dd dz = dd_diff(zh[i], zl[i], zh[j], zl[j]);
+    const dd r2 = dd_add_terms(dd_sqr(dx), dd_sqr(dz));
     if (r2.hi == 0.0) return {0.0, 0.0};
     return dd_rpow(r2, dd_sqrt(r2), m);
   }
@@ -529,7 +548,7 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
             const dd aij = sys_entry_dd(i, j, n, mg, xi, xl, ze, zl);
 #pragma unroll
             for (int g = 0; g < 4; ++g)
-              if (g0 + g < ng) acc[g] = dd_add(acc[g], dd_mul_d(aij, xs[(g0 + g) * kc + j]));
+              if (g0 + g < ng) acc[g] = dd_add_terms(acc[g], dd_mul_d(aij, xs[(g0 + g) * kc + j]));
           }
 #pragma unroll
           for (int g = 0; g < 4; ++g) {
