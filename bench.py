@@ -25,6 +25,9 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3
+# without packed FP32 instructions (which this library does not emit): 256 CUs
+# x 4 SIMDs x 16 lanes x 2 flops per fused multiply-add x 2.4 GHz
+FP32_VALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 FP64_PEAK_TFLOPS = 78.6
 # closure network per node-sample: 149 inputs -> 128 -> 128 -> 4 outputs,
@@ -111,6 +114,7 @@ def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup, ensembl
         flops = nd.n_active * ensemble * (37 * (4 + 2 * 15) + 60)
         res["kernel_tflops"] = flops / k_avg_s / 1e12
         res["valu_frac_fp32_peak"] = res["kernel_tflops"] / FP32_VALU_PEAK_TFLOPS
+        res["valu_frac_fp32_nonpacked"] = res["kernel_tflops"] / FP32_VALU_NONPACKED_TFLOPS
     del model
     return res
 
