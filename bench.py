@@ -249,6 +249,30 @@ def closure_leg(R, ctx, calls=20, members=256):
                      "steps: 4-stage RK4 of 256 members, corrected = plain + forward + correction")
 
 
+def cpu_oracle_weights(min_seconds=10.0):
+    """The oracle's weights (extended-precision assembly, LU, refinement) on a
+    bounded sample of the mixed 1M batch: 120 stencils (every 997th centre;
+    their stencils found by the oracle's search beforehand, untimed), solved
+    repeatedly until min_seconds have passed; single thread."""
+    import oracle as O
+    from workloads import weights_config
+    cfg = weights_config(1024)
+    nd = cfg["nodes"]
+    sample = np.arange(0, nd.n_active, 997)[:120]
+    stencils = [O.knn(nd.xy, [c], int(cfg["n_per"][c]), 0.0)[0] for c in sample]
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.HYPERLAP, 0, 0)]
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < min_seconds:
+        for c, st in zip(sample, stencils):
+            O.stencil_weights(nd.xy, st, int(c), int(cfg["m_per"][c]), int(cfg["l_per"][c]), ops, 0.0)
+            done += 1
+    el = time.perf_counter() - t0
+    return dict(value=done / el, unit="stencils/s", cores=1, kind="oracle",
+                sample=f"{done} solves of 120 stencils of the mixed 1M batch (every 997th centre), "
+                       f"{el:.1f} s (numpy/scipy, single thread)")
+
+
 def cpu_baseline(cfg, min_seconds=10.0):
     """The oracle's RHS on a bounded sample: one 2048-node row of the same
     channel (row 128), stencils and weights from the oracle (untimed), then
@@ -370,6 +394,14 @@ def main():
         log(f"[bench] closure: {extras['closure_forward_256x2176']}")
         extras["precision_fullrun_900s"] = fullrun_leg(R, P, ctx, cfg, idx, W, Ww, xy)
         log(f"[bench] full runs to 900 s: {extras['precision_fullrun_900s']}")
+        # a 4x larger channel (4096 x 512 = 2,097,152 nodes, 2 GB per launch): the
+        # bandwidth is not an artefact of the 256 MB Infinity Cache
+        big = scale_config(4096, 512)
+        _, bidx, bW, bWw, _ = P.ns_weights(ctx, big)
+        extras["fp32_4096x512"] = run_rhs_leg(R, P, ctx, big, bidx, bW, bWw, None, R.F32, R.F32,
+                                              max(args.steps // 4, 10), 3)
+        del bidx, bW, bWw
+        log(f"[bench] fp32 4096x512: {extras['fp32_4096x512']}")
     extras["weights_scale_setup"] = dict(stencils=n_stencils, seconds=setup_s,
                                          stencils_per_s=n_stencils / setup_s,
                                          note="search + FP64 weights incl. host sync, 4+2 operators")
@@ -378,6 +410,9 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg)
         log(f"[bench] cpu baseline: {cpu}")
+        if not args.no_extras:
+            extras["cpu_oracle_weights"] = cpu_oracle_weights()
+            log(f"[bench] cpu oracle weights: {extras['cpu_oracle_weights']}")
 
     k = main_leg
     achieved = k["kernel_gbs"]

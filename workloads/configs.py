@@ -90,9 +90,12 @@ def bubble_config(layout: str = "cartesian", h: float = 200.0, seed: int = 0, mu
 
 def scale_config(nx: int = 2048, nz: int = 256, tableau: str = "rk4"):
     """Density current on a 2048 x 256 hexagonal-row channel at 25 m column
-    spacing (rows at 6400/255 m), 524,288 active nodes plus 2 x 2048 ghosts."""
+    spacing (rows at 6400/255 m), 524,288 active nodes plus 2 x 2048 ghosts.
+    Other sizes keep the domain; dt follows the column spacing (1/16 s at
+    25 m, as in Section 6.3's table)."""
     nodes = channel("hexagonal", nx, nz, -25600.0, 51200.0, 6400.0)
-    return _ns_config(nodes, f"density-current-hexagonal-{nx}x{nz}", 0.0625, tableau)
+    dt = 0.0625 * (51200.0 / nx) / 25.0
+    return _ns_config(nodes, f"density-current-hexagonal-{nx}x{nz}", dt, tableau)
 
 
 def _ns_config(nodes, name, dt, tableau):
