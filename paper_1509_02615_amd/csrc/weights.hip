@@ -266,15 +266,14 @@ __device__ dd sys_entry_dd(int i, int j, int n, int m, const double *xh, const d
   return dd_mul(dd_ipow(dd{xh[node], xl[node]}, a), dd_ipow(dd{zh[node], zl[node]}, b));
 }
 
-// Right-hand-side entry i of operator op in double-double.
-__device__ dd rhs_entry_dd(int i, int n, int m, const WOp &op, int k, const double *xh, const double *xl,
-                           const double *zh, const double *zl) {
+// Right-hand-side entry i of operator op in double-double, node offset (x, z)
+// for rows i < n.
+__device__ dd rhs_dd_at(int i, int n, int m, const WOp &op, int k, dd x, dd z) {
   if (i >= n) {
     int a, b;
     mono(i - n, a, b);
     return {poly_rhs(op.kind, k, a, b), 0.0};
   }
-  dd x{xh[i], xl[i]}, z{zh[i], zl[i]};
   dd r2 = dd_add(dd_mul(x, x), dd_mul(z, z));
   if (r2.hi == 0.0) return {0.0, 0.0};
   dd r = dd_sqrt(r2);
@@ -296,6 +295,11 @@ __device__ dd rhs_entry_dd(int i, int n, int m, const WOp &op, int k, const doub
     }
   }
   return {0.0, 0.0};
+}
+
+__device__ __forceinline__ dd rhs_entry_dd(int i, int n, int m, const WOp &op, int k, const double *xh,
+                                           const double *xl, const double *zh, const double *zl) {
+  return i < n ? rhs_dd_at(i, n, m, op, k, dd{xh[i], xl[i]}, dd{zh[i], zl[i]}) : rhs_dd_at(i, n, m, op, k, {}, {});
 }
 
 template <typename T>
@@ -640,6 +644,465 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
   if (tid == 0 && a.status) a.status[q] = status;
 }
 
+// ---- one wavefront per system, rows in registers (K <= 64) ----
+//
+// Lane i holds row i of A = [Phi P; P^T 0] in registers; column loops are
+// unrolled over a compile-time capacity KC (in guarded chunks of 8), so row
+// entries have static register indices, and column k of the running step is
+// fetched with a uniform switch. Partial pivoting moves no data: the lane
+// that supplies the pivot of step k leaves the active set and its row, row k
+// of U, is broadcast through LDS. A lane eliminated at step k keeps the
+// eliminated entry in column k (no later step touches it), so its multiplier
+// is that entry times 1 / pivot_k, applied in the substitutions. The
+// right-hand sides are solved after the factorisation, four at a time, so
+// registers hold one row and not [A | B].
+//
+// Iterative refinement evaluates the residual b - A x row by row with A and
+// b in double-double: lane i runs over the columns j with node j's offsets
+// and x_j broadcast from LDS. The first pass starts from x = 0, so the plain
+// solve and the refinement share one code path.
+
+// largest n (l + 1) with n + M(l) <= kc: entries of the power tables
+__host__ __device__ constexpr int pw_cap(int kc) {
+  int best = 0;
+  for (int l = 0; l <= 6; ++l) {
+    const int nn = kc - (l + 1) * (l + 2) / 2;
+    if (nn > 0 && nn * (l + 1) > best) best = nn * (l + 1);
+  }
+  return best;
+}
+
+template <int KC, typename T> struct WaveShared {
+  double off[KC][4];         // scaled node offsets: x hi, x lo, z hi, z lo
+  double pw[pw_cap(KC)][4];  // node t, power e at t (l + 1) + e: x^e (hi, lo), z^e (hi, lo)
+  double xs[KC][4];          // current solution of the right-hand sides in flight
+  double rps[KC];            // 1 / pivot of step k
+  T prow[KC];                // pivot row of the current step
+  int perm[KC];              // pivot lane of step k
+  int gl[MAX_OPS], kg[MAX_OPS];  // operators of the current group, their k
+};
+
+// Product of double-doubles with an unnormalised low part (three fused
+// terms): relative error within a few 2^-104.
+__device__ __forceinline__ dd dd_mulr(dd a, dd b) {
+  const double p = a.hi * b.hi;
+  double e = fma(a.hi, b.hi, -p);
+  e = fma(a.hi, b.lo, e);
+  e = fma(a.lo, b.hi, e);
+  return {p, e};
+}
+
+// acc + e x with the high parts summed error-free (Knuth's TwoSum) and the
+// low parts in plain FP64.
+__device__ __forceinline__ dd dd_acc(dd acc, dd e, double x) {
+  const double p = e.hi * x;
+  double pe = fma(e.hi, x, -p);
+  pe = fma(e.lo, x, pe);
+  const double s = acc.hi + p, bb = s - acc.hi;
+  const double err = (acc.hi - (s - bb)) + (p - bb);
+  return {s, acc.lo + (pe + err)};
+}
+
+// sqrt(s) for normal s > 0 within an ulp: reciprocal square root estimate,
+// one Goldschmidt step and a Newton correction (no range scaling: the
+// squared distances here lie between 2^-60 and 4).
+__device__ __forceinline__ double sqrt_pos(double s) {
+  const double y0 = __builtin_amdgcn_rsq(s);
+  double g = s * y0, h = 0.5 * y0;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  return fma(fma(-g, g, s), h, g);
+}
+
+// r^m for odd m >= 1 from r and r^2
+__device__ __forceinline__ double odd_pow(double r, double r2, int m) {
+  double v = r;
+  for (int i = 1; i < m; i += 2) v *= r2;
+  return v;
+}
+
+// |a - b|^m for distinct nodes, offsets in double-double, relative error
+// within about 2^-95: r^2 = s (1 + t) with s an FP64 number and t ~ 2^-52,
+// y = sqrt(s) within an ulp so that s - y^2 is exact, y^m in double-double
+// and (1 + t)^(m/2) to first order (the t^2 term is below 2^-100).
+__device__ __forceinline__ dd phi_dd(const double (&a)[4], const double (&b)[4], int m) {
+  dd dx = two_sum(a[0], -b[0]);
+  dx.lo += a[1] - b[1];
+  dd dz = two_sum(a[2], -b[2]);
+  dz.lo += a[3] - b[3];
+  const dd px = two_prod(dx.hi, dx.hi), pz = two_prod(dz.hi, dz.hi);
+  const dd s = two_sum(px.hi, pz.hi);
+  double slo = s.lo + (px.lo + pz.lo);
+  slo = fma(dx.hi + dx.hi, dx.lo, slo);
+  slo = fma(dz.hi + dz.hi, dz.lo, slo);
+  if (!(s.hi > 0.0)) return {0.0, 0.0};
+  const double y = sqrt_pos(s.hi);
+  double rs = __builtin_amdgcn_rcp(s.hi);
+  rs = fma(rs, fma(-s.hi, rs, 1.0), rs);  // one Newton step
+  const double t = (fma(-y, y, s.hi) + slo) * rs;
+  dd Y{y, 0.0};
+  const dd y2 = two_prod(y, y);
+  for (int i = 1; i < m; i += 2) Y = dd_mulr(Y, y2);
+  return {Y.hi, fma(Y.hi * (0.5 * m), t, Y.lo)};
+}
+
+__device__ __forceinline__ double rl(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ float rl(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, static_cast<unsigned>(__shfl_xor(static_cast<int>(v), off, 64)));
+  return v;
+}
+
+// ar[k] for a wave-uniform k: a switch on k becomes a tree of scalar
+// branches, so only one register pair is read
+template <int KC, typename T> __device__ __forceinline__ T pick(const T (&ar)[KC], int k) {
+  T r = ar[0];
+  switch (k) {
+#define RBFFD_PICK(i) \
+  case i:             \
+    if constexpr (i < KC) r = ar[i]; \
+    break;
+#define RBFFD_PICK8(i) RBFFD_PICK(i) RBFFD_PICK(i + 1) RBFFD_PICK(i + 2) RBFFD_PICK(i + 3) \
+                       RBFFD_PICK(i + 4) RBFFD_PICK(i + 5) RBFFD_PICK(i + 6) RBFFD_PICK(i + 7)
+    RBFFD_PICK8(0) RBFFD_PICK8(8) RBFFD_PICK8(16) RBFFD_PICK8(24)
+    RBFFD_PICK8(32) RBFFD_PICK8(40) RBFFD_PICK8(48) RBFFD_PICK8(56)
+#undef RBFFD_PICK8
+#undef RBFFD_PICK
+    default: break;
+  }
+  return r;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// wavefronts per SIMD the register budget is fitted to
+#ifndef RBFFD_WAVE_OCC64
+#define RBFFD_WAVE_OCC64 2
+#endif
+#ifndef RBFFD_WAVE_OCC48
+#define RBFFD_WAVE_OCC48 2
+#endif
+#ifndef RBFFD_WAVE_OCC32
+#define RBFFD_WAVE_OCC32 3
+#endif
+template <int KC> constexpr int wave_occ() {
+  return KC > 48 ? RBFFD_WAVE_OCC64 : KC > 32 ? RBFFD_WAVE_OCC48 : RBFFD_WAVE_OCC32;
+}
+
+template <int KC, typename T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>()))) void weights_wave_kernel(
+    WArgs a) {
+  static_assert(KC % 8 == 0 && KC <= 64, "capacity in chunks of 8, one row per lane");
+  __shared__ WaveShared<KC, T> S;
+  const int lane = threadIdx.x;
+  // per-stencil parameters are wave-uniform: kept in scalar registers
+  const int q = __builtin_amdgcn_readfirstlane(a.list ? a.list[blockIdx.x] : static_cast<int>(blockIdx.x));
+  const int c = __builtin_amdgcn_readfirstlane(a.centers ? a.centers[q] : q);
+  const int n = __builtin_amdgcn_readfirstlane(a.n_per ? a.n_per[q] : a.n_max);
+  const int m = __builtin_amdgcn_readfirstlane(a.m_per ? a.m_per[q] : a.m_uni);
+  const int l = __builtin_amdgcn_readfirstlane(a.l_per ? a.l_per[q] : a.l_uni);
+  const int M = n_terms(l);
+  const int K = n + M;
+  double *wrow = a.w + static_cast<int64_t>(q) * a.n_max;
+  const int64_t op_stride = static_cast<int64_t>(a.n_centers) * a.n_max;
+
+  bool bad = (c < 0 || c >= a.n_nodes || n < 1 || n > a.n_max || m < 1 || m > 15 || (m & 1) == 0 || l < 0 ||
+              l > 6 || n < M || K > KC);
+  int node = -1;
+  if (!bad && lane < n) node = a.idx[static_cast<int64_t>(q) * a.n_max + lane];
+  bad = bad || __ballot(lane < n && (node < 0 || node >= a.n_nodes)) != 0;
+  if (bad) {
+    for (int o = 0; o < a.n_ops; ++o)
+      for (int t = lane; t < a.n_max; t += 64) wrow[o * op_stride + t] = 0.0;
+    if (lane == 0 && a.status) a.status[q] = 2;
+    return;
+  }
+
+  // 1. offsets from the centre (exact double-double, minimum image in x),
+  // scaled by rho = the largest offset length
+  const double xc = a.xy[2 * c], zc = a.xy[2 * c + 1];
+  dd dx{0.0, 0.0}, dz{0.0, 0.0};
+  double d2 = 0.0;
+  if (lane < n) {
+    dx = two_sum(a.xy[2 * node], -xc);
+    if (a.period > 0.0) {
+      const double half = 0.5 * a.period, d64 = a.xy[2 * node] - xc;
+      if (d64 > half)
+        dx = dd_add(dx, dd{-a.period, 0.0});
+      else if (d64 < -half)
+        dx = dd_add(dx, dd{a.period, 0.0});
+    }
+    dz = two_sum(a.xy[2 * node + 1], -zc);
+    d2 = dx.hi * dx.hi + dz.hi * dz.hi;
+  }
+  const double rho = sqrt(wave_max(d2));
+  if (!(rho > 0.0)) {
+    for (int o = 0; o < a.n_ops; ++o)
+      for (int t = lane; t < a.n_max; t += 64) wrow[o * op_stride + t] = 0.0;
+    if (lane == 0 && a.status) a.status[q] = 1;
+    return;
+  }
+  const dd ex = lane < n ? dd_div(dx, dd{rho, 0.0}) : dd{0.0, 0.0};
+  const dd ez = lane < n ? dd_div(dz, dd{rho, 0.0}) : dd{0.0, 0.0};
+  const double own[4] = {ex.hi, ex.lo, ez.hi, ez.lo};
+  const int P = l + 1;
+  if (lane < n) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) S.off[lane][u] = own[u];
+    dd X{1.0, 0.0}, Z{1.0, 0.0};
+    for (int e = 0; e <= l; ++e) {
+      double *pe = S.pw[lane * P + e];
+      pe[0] = X.hi;
+      pe[1] = X.lo;
+      pe[2] = Z.hi;
+      pe[3] = Z.lo;
+      X = dd_mulr(X, ex);
+      Z = dd_mulr(Z, ez);
+    }
+  }
+  wave_sync_lds();
+  const bool is_node = lane < n, is_poly = lane >= n && lane < K;
+  int pa = 0, pb = 0;  // exponents of a polynomial row
+  if (is_poly) mono(lane - n, pa, pb);
+  const int own_pw = (is_node ? lane : 0) * P;   // own power table (node rows)
+  const int poly_a = pa, poly_b = pb;
+
+  const int n_ = n, K_ = K, P_ = P;
+  int status = 0;
+  unsigned done = 0;
+  // operators grouped by PHS order: one factorisation per group
+  while (done != (1u << a.n_ops) - 1u) {
+    int first = 0;
+    while (done & (1u << first)) ++first;
+    const int mg = a.ops[first].order ? a.ops[first].order : m;
+    int ng = 0;
+    bool group_bad = false;
+    for (int o = 0; o < a.n_ops; ++o) {
+      const int mo = a.ops[o].order ? a.ops[o].order : m;
+      if (!(done & (1u << o)) && mo == mg) {
+        const WOp &op = a.ops[o];
+        const int ke = (op.kind == RBFFD_HYPERLAP && op.k == 0) ? (mg - 1) / 2 : op.k;
+        if (op.kind == RBFFD_HYPERLAP && mg < 2 * ke + 1) group_bad = true;
+        if (lane == 0) {
+          S.gl[ng] = o;
+          S.kg[ng] = ke;
+        }
+        ++ng;
+        done |= 1u << o;
+      }
+    }
+    wave_sync_lds();
+    if (group_bad) {
+      status = 2;
+      for (int g = 0; g < ng; ++g)
+        for (int t = lane; t < a.n_max; t += 64) wrow[S.gl[g] * op_stride + t] = 0.0;
+      continue;
+    }
+
+    // 2. row `lane` of A in FP64 (columns >= K stay zero); branch-free per
+    // column: node rows take |x_i - x_j|^m or their own monomial, polynomial
+    // rows the monomial of node j
+    T ar[KC];
+    double amax = 0.0;
+    {
+      // opaque copies: keeps the per-column address arithmetic inside this
+      // loop instead of hoisted (and held in registers) across all groups
+      int n = n_, K = K_, P = P_;
+      asm volatile("" : "+s"(n), "+s"(K), "+s"(P));
+      int qa = 0, qb = 0;  // monomial of column j >= n, graded order
+#pragma unroll
+      for (int j = 0; j < KC; ++j) {
+        double v = 0.0;
+        if (j < K) {
+          const int jn = j < n ? j : n - 1;
+          const double ddx = own[0] - S.off[jn][0], ddz = own[2] - S.off[jn][2];
+          const double r2 = ddx * ddx + ddz * ddz;
+          const double phi = r2 > 0.0 ? odd_pow(sqrt_pos(r2), r2, mg) : 0.0;
+          const double mono_j = S.pw[jn * P + poly_a][0] * S.pw[jn * P + poly_b][2];
+          const double mono_i = S.pw[own_pw + qa][0] * S.pw[own_pw + qb][2];
+          v = j < n ? (is_node ? phi : (is_poly ? mono_j : 0.0)) : (is_node ? mono_i : 0.0);
+          if (j >= n) {
+            if (qa > 0) {
+              --qa;
+              ++qb;
+            } else {
+              qa = qb + 1;
+              qb = 0;
+            }
+          }
+        }
+        ar[j] = static_cast<T>(v);
+        amax = fmax(amax, fabs(v));
+      }
+    }
+    amax = wave_max(amax);
+
+    // 3. LU with partial pivoting, rows stay in their lanes
+    bool fr = lane < K;  // not yet chosen as a pivot row
+    int mystep = KC;     // elimination step at which this row became pivot
+    double rdg = 0.0;    // 1 / own pivot
+    double pmin = INFINITY;
+    for (int k = 0; k < K; ++k) {
+      const T ck = pick<KC>(ar, k);
+      // largest |a_ik| over the free rows, compared on 17 mantissa bits,
+      // ties to the highest lane; + 64 keeps free rows above the others
+      unsigned key = 0;
+      if (fr) key = ((__float_as_uint(static_cast<float>(fabs(static_cast<double>(ck)))) & ~63u) + 64u) | lane;
+      const int p = __builtin_amdgcn_readfirstlane(static_cast<int>(wave_max_u32(key) & 63u));
+      const T piv = rl(ck, p);
+      pmin = fmin(pmin, fabs(static_cast<double>(piv)));
+      const T rp = T(1) / piv;
+      if (lane == p) {
+        fr = false;
+        mystep = k;
+        rdg = static_cast<double>(rp);
+#pragma unroll
+        for (int j0 = 0; j0 < KC; j0 += 8)
+          if (j0 + 8 > k + 1 && j0 < K) {
+#pragma unroll
+            for (int j = j0; j < j0 + 8; ++j) S.prow[j] = ar[j];
+          }
+      }
+      if (lane <= k) S.prow[lane] = T(0);  // columns up to k take no update
+      wave_sync_lds();
+      const T lm = fr ? ck * rp : T(0);
+#pragma unroll
+      for (int j0 = 0; j0 < KC; j0 += 8)
+        if (j0 + 8 > k + 1 && j0 < K) {
+#pragma unroll
+          for (int j = j0; j < j0 + 8; ++j) ar[j] = fma(-lm, S.prow[j], ar[j]);
+        }
+      wave_sync_lds();
+    }
+    // lane k: pivot lane and 1 / pivot of step k
+    if (lane < K) {
+      S.perm[mystep] = lane;
+      S.rps[mystep] = rdg;
+    }
+    wave_sync_lds();
+    const int pv = lane < K ? S.perm[lane] : 0;
+    const double rpv = lane < K ? S.rps[lane] : 0.0;
+
+    // 4. right-hand sides four at a time: solve, then refine
+    for (int g0 = 0; g0 < ng; g0 += 4) {
+      const int G = min(4, ng - g0);
+      double x[4] = {0.0, 0.0, 0.0, 0.0};  // lane k: unknown k
+      bool converged = false;
+      for (int it = 0; it <= a.max_iter && !converged; ++it) {
+        // residual b - A x in double-double, rounded to FP64
+        dd acc[4] = {};
+        if (it > 0) {
+          for (int j = 0; j < n; ++j) {
+            const double oj[4] = {S.off[j][0], S.off[j][1], S.off[j][2], S.off[j][3]};
+            dd e{0.0, 0.0};
+            if (is_node) {
+              if (j != lane) e = phi_dd(own, oj, mg);
+            } else if (is_poly) {
+              const double *px = S.pw[j * P + poly_a], *pz = S.pw[j * P + poly_b];
+              e = dd_mulr(dd{px[0], px[1]}, dd{pz[2], pz[3]});
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g) acc[g] = dd_acc(acc[g], e, S.xs[j][g]);
+          }
+          int qa = 0, qb = 0;
+          for (int j = n; j < K; ++j) {
+            dd e{0.0, 0.0};
+            if (is_node) {
+              const double *px = S.pw[own_pw + qa], *pz = S.pw[own_pw + qb];
+              e = dd_mulr(dd{px[0], px[1]}, dd{pz[2], pz[3]});
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g) acc[g] = dd_acc(acc[g], e, S.xs[j][g]);
+            if (qa > 0) {
+              --qa;
+              ++qb;
+            } else {
+              qa = qb + 1;
+              qb = 0;
+            }
+          }
+        }
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          if (g < G && lane < K) {
+            const int o = __builtin_amdgcn_readfirstlane(S.gl[g0 + g]);
+            const dd b = rhs_dd_at(lane, n, mg, a.ops[o], __builtin_amdgcn_readfirstlane(S.kg[g0 + g]), ex, ez);
+            const dd r = two_sum(b.hi, -acc[g].hi);
+            v[g] = r.hi + (r.lo + (b.lo - acc[g].lo));
+          }
+        }
+        // forward substitution L y = P v: rows not yet pivot at step k
+        for (int k = 0; k < K; ++k) {
+          const int p = __builtin_amdgcn_readlane(pv, k);
+          const double r = rl(rpv, k);
+          const double lk = mystep > k ? static_cast<double>(pick<KC>(ar, k)) : 0.0;
+#pragma unroll
+          for (int g = 0; g < 4; ++g) v[g] = fma(-lk, rl(v[g], p) * r, v[g]);
+        }
+        // back substitution U d = y: rows pivoted before step k
+        for (int k = K - 1; k >= 0; --k) {
+          const int p = __builtin_amdgcn_readlane(pv, k);
+          const double r = rl(rpv, k);
+          const double uk = mystep < k ? static_cast<double>(pick<KC>(ar, k)) : 0.0;
+#pragma unroll
+          for (int g = 0; g < 4; ++g) v[g] = fma(-uk, rl(v[g], p) * r, v[g]);
+        }
+        // lane p_k holds y_k, so d_k = v * rdg there; lane k takes it
+        double dm = 0.0, xm = 0.0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const double dk = __shfl(v[g] * rdg, pv, 64);
+          const double d = lane < K ? dk : 0.0;
+          x[g] += d;
+          dm = fmax(dm, fabs(d));
+          xm = fmax(xm, fabs(x[g]));
+          if (lane < K) S.xs[lane][g] = x[g];
+        }
+        wave_sync_lds();
+        dm = wave_max(dm);
+        xm = wave_max(xm);
+        converged = dm <= 0x1p-48 * xm;
+      }
+
+      // 5. status and rescaled output
+      double xmax = 0.0;
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        if (g < G) xmax = fmax(xmax, fabs(x[g]));
+      const bool finite = isfinite(wave_max(xmax));
+      if (!(pmin >= 1e-13 * amax) || !converged || !finite) status = status ? status : 1;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        if (g < G) {
+          const int o = __builtin_amdgcn_readfirstlane(S.gl[g0 + g]);
+          const WOp &op = a.ops[o];
+          const int qd = (op.kind == RBFFD_DX || op.kind == RBFFD_DZ) ? 1
+                         : (op.kind == RBFFD_HYPERLAP)                ? 2 * __builtin_amdgcn_readfirstlane(S.kg[g0 + g])
+                                                                      : 2;
+          const double scale = 1.0 / ipow(rho, qd);
+          for (int t = lane; t < a.n_max; t += 64)
+            wrow[o * op_stride + t] = (t < n && finite) ? x[g] * scale : 0.0;
+        }
+      }
+    }
+  }
+  if (lane == 0 && a.status) a.status[q] = status;
+}
+
 // Launch buckets by system size: each bucket's launch reserves LDS for its
 // own largest K, so small systems do not pay for the largest one.
 constexpr int NBUCKET = 6;
@@ -774,6 +1237,16 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
     const int cap = cnt[2 * NBUCKET + b];  // the bucket's largest K
     a.k_cap = cap;
     a.list = used > 1 ? d_list.as<int>() + cnt[NBUCKET + b] : nullptr;
+    if (b <= 2) {  // systems of up to 64 unknowns: one wavefront each
+      const bool f64 = precision == RBFFD_SOLVE_FP64;
+      if (b == 0)
+        f64 ? weights_wave_kernel<32, double><<<cnt[b], 64, 0, s>>>(a) : weights_wave_kernel<32, float><<<cnt[b], 64, 0, s>>>(a);
+      else if (b == 1)
+        f64 ? weights_wave_kernel<48, double><<<cnt[b], 64, 0, s>>>(a) : weights_wave_kernel<48, float><<<cnt[b], 64, 0, s>>>(a);
+      else
+        f64 ? weights_wave_kernel<64, double><<<cnt[b], 64, 0, s>>>(a) : weights_wave_kernel<64, float><<<cnt[b], 64, 0, s>>>(a);
+      continue;
+    }
     const size_t head = sizeof(double) * (2 * static_cast<size_t>(n_ops) * cap + 4 * static_cast<size_t>(cap));
     if (precision == RBFFD_SOLVE_FP64) {
       const size_t lds = head + sizeof(double) * static_cast<size_t>(cap) * (cap + n_ops);
