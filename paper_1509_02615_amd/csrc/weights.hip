@@ -28,6 +28,7 @@
 // so the factorisation is written on the vector ALUs.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -302,6 +303,16 @@ __device__ __forceinline__ dd rhs_entry_dd(int i, int n, int m, const WOp &op, i
   return i < n ? rhs_dd_at(i, n, m, op, k, dd{xh[i], xl[i]}, dd{zh[i], zl[i]}) : rhs_dd_at(i, n, m, op, k, {}, {});
 }
 
+// Stopping rule of the iterative refinement, after a correction d computed
+// from a residual, with dprev the previous correction (the first solution
+// itself for the first refinement pass). The error contracts by a factor
+// g ~ |d| / |dprev| per pass, so about g |d| is left after adding d: stop
+// when that is below 2^-52 |x| while the corrections contract, or when d
+// itself is below 2^-48 |x|.
+__device__ __forceinline__ bool refined(double dm, double xm, double dprev) {
+  return dm <= 0x1p-48 * xm || (dm <= 0.5 * dprev && dm * dm <= 0x1p-52 * xm * dprev);
+}
+
 template <typename T>
 __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void weights_kernel(WArgs a) {
   extern __shared__ double smem[];
@@ -315,7 +326,7 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
   double *ze = xi + kc;                    // [kc] scaled z offsets (FP64)
   double *xl = ze + kc;                    // [kc] low parts of the double-double x offsets
   double *zl = xl + kc;                    // [kc] low parts of the double-double z offsets
-  __shared__ double s_red[4];
+  __shared__ double s_red[4];  // rho, converged flag, max |x|, previous correction
   __shared__ int s_piv[128];
   __shared__ int s_gl[MAX_OPS], s_kg[MAX_OPS];  // operators of the current group, their k
   __shared__ int s_flag, s_pivrow;
@@ -538,6 +549,7 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
 
     // 5. iterative refinement with double-double residuals
     bool converged = false;
+    if (tid == 0) s_red[3] = -1.0;  // no previous correction yet
     for (int it = 0; it < a.max_iter && !converged; ++it) {
       // r = b - A x in double-double: 4 lanes per row, partial sums over j,
       // right-hand sides in chunks of 4 (fixed trip counts keep the
@@ -611,7 +623,10 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
         }
         dmax = wave_max(dmax);
         xmax = wave_max(xmax);
-        if (tid == 0) s_red[1] = (dmax <= 0x1p-48 * xmax) ? 1.0 : 0.0;
+        if (tid == 0) {
+          s_red[1] = refined(dmax, xmax, s_red[3] >= 0.0 ? s_red[3] : xmax) ? 1.0 : 0.0;
+          s_red[3] = dmax;
+        }
       }
       __syncthreads();
       converged = s_red[1] != 0.0;
@@ -705,15 +720,29 @@ __device__ __forceinline__ dd dd_acc(dd acc, dd e, double x) {
 
 // sqrt(s) for normal s > 0 within an ulp: reciprocal square root estimate,
 // one Goldschmidt step and a Newton correction (no range scaling: the
-// squared distances here lie between 2^-60 and 4).
-__device__ __forceinline__ double sqrt_pos(double s) {
+// squared distances here lie between 2^-60 and 4); h returns ~1/(2 sqrt(s))
+// to about 2^-40.
+__device__ __forceinline__ double sqrt_pos(double s, double &h) {
   const double y0 = __builtin_amdgcn_rsq(s);
-  double g = s * y0, h = 0.5 * y0;
+  double g = s * y0;
+  h = 0.5 * y0;
   const double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
   return fma(fma(-g, g, s), h, g);
 }
+__device__ __forceinline__ double sqrt_pos(double s) {
+  double h;
+  return sqrt_pos(s, h);
+}
+
+// 1 / x: hardware estimate and two Newton steps (within an ulp or two)
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float x) { return 1.0f / x; }
 
 // r^m for odd m >= 1 from r and r^2
 __device__ __forceinline__ double odd_pow(double r, double r2, int m) {
@@ -737,10 +766,9 @@ __device__ __forceinline__ dd phi_dd(const double (&a)[4], const double (&b)[4],
   slo = fma(dx.hi + dx.hi, dx.lo, slo);
   slo = fma(dz.hi + dz.hi, dz.lo, slo);
   if (!(s.hi > 0.0)) return {0.0, 0.0};
-  const double y = sqrt_pos(s.hi);
-  double rs = __builtin_amdgcn_rcp(s.hi);
-  rs = fma(rs, fma(-s.hi, rs, 1.0), rs);  // one Newton step
-  const double t = (fma(-y, y, s.hi) + slo) * rs;
+  double h;
+  const double y = sqrt_pos(s.hi, h);
+  const double t = (fma(-y, y, s.hi) + slo) * (4.0 * h * h);  // (2h)^2 ~ 1/s
   dd Y{y, 0.0};
   const dd y2 = two_prod(y, y);
   for (int i = 1; i < m; i += 2) Y = dd_mulr(Y, y2);
@@ -757,27 +785,67 @@ __device__ __forceinline__ float rl(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// Largest value over the wavefront (full exec mask): data-parallel
+// primitives within rows of 16 (quad permutes, half-mirror, mirror), then the
+// row broadcasts 15 and 31 carry the maximum to lane 63.
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
-  for (int off = 32; off > 0; off >>= 1) v = max(v, static_cast<unsigned>(__shfl_xor(static_cast<int>(v), off, 64)));
-  return v;
+  auto step = [&](auto ctrl, auto rows) {
+    const unsigned o = static_cast<unsigned>(
+        __builtin_amdgcn_update_dpp(static_cast<int>(v), static_cast<int>(v), decltype(ctrl)::value,
+                                    decltype(rows)::value, 0xF, false));
+    v = max(v, o);
+  };
+  step(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});   // quad_perm 1,0,3,2
+  step(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});   // quad_perm 2,3,0,1
+  step(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});  // row_half_mirror
+  step(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});  // row_mirror
+  step(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});  // row_bcast:15
+  step(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});  // row_bcast:31
+  return static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
 }
 
-// ar[k] for a wave-uniform k: a switch on k becomes a tree of scalar
-// branches, so only one register pair is read
-template <int KC, typename T> __device__ __forceinline__ T pick(const T (&ar)[KC], int k) {
-  T r = ar[0];
-  switch (k) {
-#define RBFFD_PICK(i) \
-  case i:             \
-    if constexpr (i < KC) r = ar[i]; \
-    break;
-#define RBFFD_PICK8(i) RBFFD_PICK(i) RBFFD_PICK(i + 1) RBFFD_PICK(i + 2) RBFFD_PICK(i + 3) \
-                       RBFFD_PICK(i + 4) RBFFD_PICK(i + 5) RBFFD_PICK(i + 6) RBFFD_PICK(i + 7)
-    RBFFD_PICK8(0) RBFFD_PICK8(8) RBFFD_PICK8(16) RBFFD_PICK8(24)
-    RBFFD_PICK8(32) RBFFD_PICK8(40) RBFFD_PICK8(48) RBFFD_PICK8(56)
-#undef RBFFD_PICK8
-#undef RBFFD_PICK
-    default: break;
+// One matrix row in registers, in 16-element vector chunks: static indices
+// address registers directly, and a wave-uniform dynamic index k compiles to
+// indexed register moves (s_set_gpr_idx_on) into chunk k / 16.
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(16))); };
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(16))); };
+
+// A row is held in four such chunks (local vector values, chunk j / 16 holds
+// element j). They are only ever passed by value and written in the kernel
+// body through RBFFD_ROW_SET, so they stay SSA values in registers; element
+// stores through a pointer or reference would leave them in scratch memory.
+#define RBFFD_ROW_GET(j) ((j) < 16 ? ar0[(j) & 15] : (j) < 32 ? ar1[(j) & 15] : (j) < 48 ? ar2[(j) & 15] : ar3[(j) & 15])
+#define RBFFD_ROW_SET(j, x)   \
+  do {                        \
+    if ((j) < 16)             \
+      ar0[(j) & 15] = (x);    \
+    else if ((j) < 32)        \
+      ar1[(j) & 15] = (x);    \
+    else if ((j) < 48)        \
+      ar2[(j) & 15] = (x);    \
+    else                      \
+      ar3[(j) & 15] = (x);    \
+  } while (0)
+
+// Element k (wave-uniform) of a row: one indexed register read in the chunk
+// holding k; the empty asm keeps the chunk choice a branch.
+template <int KC, typename V>
+__device__ __forceinline__ auto pick4(V c0, V c1, V c2, V c3, int k) {
+  const int e = k & 15;
+  auto r = c0[0];
+  if (k < 16) {
+    r = c0[e];
+    asm volatile("" : "+v"(r));
+  } else if (KC <= 32 || k < 32) {
+    r = c1[e];
+    asm volatile("" : "+v"(r));
+  } else if (KC <= 48 || k < 48) {
+    r = c2[e];
+    asm volatile("" : "+v"(r));
+  } else {
+    r = c3[e];
+    asm volatile("" : "+v"(r));
   }
   return r;
 }
@@ -786,6 +854,110 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// State of one factorised system held by a wavefront (row `lane` of the
+// factors in four chunks, eliminated entries kept), and of its stencil.
+template <int KC, typename T> struct WaveRows {
+  typename Vec16<T>::type c0, c1, c2, c3;
+  int mystep;   // step at which this row was pivot
+  int pv;       // lane k: pivot lane of step k
+  double rpv;   // lane k: 1 / pivot of step k
+  double rdg;   // 1 / own pivot
+};
+struct WaveCtx {
+  int lane, n, K, mg, P, own_pw, poly_a, poly_b;
+  bool is_node, is_poly;
+  dd ex, ez;  // own scaled offset
+};
+
+// Solve for the G right-hand sides of operators S.gl[g0 ..], then refine
+// with double-double residuals until the stopping rule holds. Lane k ends
+// with unknown k in x[g].
+template <int KC, int G, typename T>
+__device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S, const WaveRows<KC, T> R,
+                                            const WaveCtx &c, int g0, double (&x)[4], bool &converged) {
+  const int lane = c.lane, n = c.n, K = c.K, P = c.P;
+  const double own[4] = {c.ex.hi, c.ex.lo, c.ez.hi, c.ez.lo};
+  double dprev = 0.0;  // previous correction (the plain solution after the first pass)
+  for (int it = 0; it <= a.max_iter && !converged; ++it) {
+    // residual b - A x in double-double, rounded to FP64 (b alone when x = 0)
+    dd acc[G] = {};
+    if (it > 0) {
+      for (int j = 0; j < n; ++j) {
+        const double oj[4] = {S.off[j][0], S.off[j][1], S.off[j][2], S.off[j][3]};
+        dd e{0.0, 0.0};
+        if (c.is_node) {
+          if (j != lane) e = phi_dd(own, oj, c.mg);
+        } else if (c.is_poly) {
+          const double *px = S.pw[j * P + c.poly_a], *pz = S.pw[j * P + c.poly_b];
+          e = dd_mulr(dd{px[0], px[1]}, dd{pz[2], pz[3]});
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = dd_acc(acc[g], e, S.xs[j][g]);
+      }
+      int qa = 0, qb = 0;
+      for (int j = n; j < K; ++j) {
+        dd e{0.0, 0.0};
+        if (c.is_node) {
+          const double *px = S.pw[c.own_pw + qa], *pz = S.pw[c.own_pw + qb];
+          e = dd_mulr(dd{px[0], px[1]}, dd{pz[2], pz[3]});
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = dd_acc(acc[g], e, S.xs[j][g]);
+        if (qa > 0) {
+          --qa;
+          ++qb;
+        } else {
+          qa = qb + 1;
+          qb = 0;
+        }
+      }
+    }
+    double v[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      v[g] = 0.0;
+      if (lane < K) {
+        const int o = __builtin_amdgcn_readfirstlane(S.gl[g0 + g]);
+        const dd b = rhs_dd_at(lane, n, c.mg, a.ops[o], __builtin_amdgcn_readfirstlane(S.kg[g0 + g]), c.ex, c.ez);
+        const dd r = two_sum(b.hi, -acc[g].hi);
+        v[g] = r.hi + (r.lo + (b.lo - acc[g].lo));
+      }
+    }
+    // forward substitution L y = P v: rows not yet pivot at step k
+    for (int k = 0; k < K; ++k) {
+      const int p = __builtin_amdgcn_readlane(R.pv, k);
+      const double r = rl(R.rpv, k);
+      const double lk = R.mystep > k ? static_cast<double>(pick4<KC>(R.c0, R.c1, R.c2, R.c3, k)) : 0.0;
+#pragma unroll
+      for (int g = 0; g < G; ++g) v[g] = fma(-lk, rl(v[g], p) * r, v[g]);
+    }
+    // back substitution U d = y: rows pivoted before step k
+    for (int k = K - 1; k >= 0; --k) {
+      const int p = __builtin_amdgcn_readlane(R.pv, k);
+      const double r = rl(R.rpv, k);
+      const double uk = R.mystep < k ? static_cast<double>(pick4<KC>(R.c0, R.c1, R.c2, R.c3, k)) : 0.0;
+#pragma unroll
+      for (int g = 0; g < G; ++g) v[g] = fma(-uk, rl(v[g], p) * r, v[g]);
+    }
+    // lane p_k holds y_k, so d_k = v * rdg there; lane k takes it
+    double dm = 0.0, xm = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const double dk = __shfl(v[g] * R.rdg, R.pv, 64);
+      const double d = lane < K ? dk : 0.0;
+      x[g] += d;
+      dm = fmax(dm, fabs(d));
+      xm = fmax(xm, fabs(x[g]));
+      if (lane < K) S.xs[lane][g] = x[g];
+    }
+    wave_sync_lds();
+    dm = wave_max(dm);
+    xm = wave_max(xm);
+    converged = it == 0 ? dm <= 0x1p-48 * xm : refined(dm, xm, dprev);
+    dprev = dm;
+  }
 }
 
 // wavefronts per SIMD the register budget is fitted to
@@ -915,7 +1087,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
     // 2. row `lane` of A in FP64 (columns >= K stay zero); branch-free per
     // column: node rows take |x_i - x_j|^m or their own monomial, polynomial
     // rows the monomial of node j
-    T ar[KC];
+    typename Vec16<T>::type ar0, ar1, ar2, ar3;
     double amax = 0.0;
     {
       // opaque copies: keeps the per-column address arithmetic inside this
@@ -944,7 +1116,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
             }
           }
         }
-        ar[j] = static_cast<T>(v);
+        RBFFD_ROW_SET(j, static_cast<T>(v));
         amax = fmax(amax, fabs(v));
       }
     }
@@ -956,7 +1128,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
     double rdg = 0.0;    // 1 / own pivot
     double pmin = INFINITY;
     for (int k = 0; k < K; ++k) {
-      const T ck = pick<KC>(ar, k);
+      const T ck = pick4<KC>(ar0, ar1, ar2, ar3, k);
       // largest |a_ik| over the free rows, compared on 17 mantissa bits,
       // ties to the highest lane; + 64 keeps free rows above the others
       unsigned key = 0;
@@ -964,7 +1136,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
       const int p = __builtin_amdgcn_readfirstlane(static_cast<int>(wave_max_u32(key) & 63u));
       const T piv = rl(ck, p);
       pmin = fmin(pmin, fabs(static_cast<double>(piv)));
-      const T rp = T(1) / piv;
+      const T rp = recip(piv);
       if (lane == p) {
         fr = false;
         mystep = k;
@@ -973,7 +1145,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
         for (int j0 = 0; j0 < KC; j0 += 8)
           if (j0 + 8 > k + 1 && j0 < K) {
 #pragma unroll
-            for (int j = j0; j < j0 + 8; ++j) S.prow[j] = ar[j];
+            for (int j = j0; j < j0 + 8; ++j) S.prow[j] = RBFFD_ROW_GET(j);
           }
       }
       if (lane <= k) S.prow[lane] = T(0);  // columns up to k take no update
@@ -983,7 +1155,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
       for (int j0 = 0; j0 < KC; j0 += 8)
         if (j0 + 8 > k + 1 && j0 < K) {
 #pragma unroll
-          for (int j = j0; j < j0 + 8; ++j) ar[j] = fma(-lm, S.prow[j], ar[j]);
+          for (int j = j0; j < j0 + 8; ++j) RBFFD_ROW_SET(j, fma(-lm, S.prow[j], RBFFD_ROW_GET(j)));
         }
       wave_sync_lds();
     }
@@ -1001,81 +1173,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
       const int G = min(4, ng - g0);
       double x[4] = {0.0, 0.0, 0.0, 0.0};  // lane k: unknown k
       bool converged = false;
-      for (int it = 0; it <= a.max_iter && !converged; ++it) {
-        // residual b - A x in double-double, rounded to FP64
-        dd acc[4] = {};
-        if (it > 0) {
-          for (int j = 0; j < n; ++j) {
-            const double oj[4] = {S.off[j][0], S.off[j][1], S.off[j][2], S.off[j][3]};
-            dd e{0.0, 0.0};
-            if (is_node) {
-              if (j != lane) e = phi_dd(own, oj, mg);
-            } else if (is_poly) {
-              const double *px = S.pw[j * P + poly_a], *pz = S.pw[j * P + poly_b];
-              e = dd_mulr(dd{px[0], px[1]}, dd{pz[2], pz[3]});
-            }
-#pragma unroll
-            for (int g = 0; g < 4; ++g) acc[g] = dd_acc(acc[g], e, S.xs[j][g]);
-          }
-          int qa = 0, qb = 0;
-          for (int j = n; j < K; ++j) {
-            dd e{0.0, 0.0};
-            if (is_node) {
-              const double *px = S.pw[own_pw + qa], *pz = S.pw[own_pw + qb];
-              e = dd_mulr(dd{px[0], px[1]}, dd{pz[2], pz[3]});
-            }
-#pragma unroll
-            for (int g = 0; g < 4; ++g) acc[g] = dd_acc(acc[g], e, S.xs[j][g]);
-            if (qa > 0) {
-              --qa;
-              ++qb;
-            } else {
-              qa = qb + 1;
-              qb = 0;
-            }
-          }
-        }
-        double v[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          if (g < G && lane < K) {
-            const int o = __builtin_amdgcn_readfirstlane(S.gl[g0 + g]);
-            const dd b = rhs_dd_at(lane, n, mg, a.ops[o], __builtin_amdgcn_readfirstlane(S.kg[g0 + g]), ex, ez);
-            const dd r = two_sum(b.hi, -acc[g].hi);
-            v[g] = r.hi + (r.lo + (b.lo - acc[g].lo));
-          }
-        }
-        // forward substitution L y = P v: rows not yet pivot at step k
-        for (int k = 0; k < K; ++k) {
-          const int p = __builtin_amdgcn_readlane(pv, k);
-          const double r = rl(rpv, k);
-          const double lk = mystep > k ? static_cast<double>(pick<KC>(ar, k)) : 0.0;
-#pragma unroll
-          for (int g = 0; g < 4; ++g) v[g] = fma(-lk, rl(v[g], p) * r, v[g]);
-        }
-        // back substitution U d = y: rows pivoted before step k
-        for (int k = K - 1; k >= 0; --k) {
-          const int p = __builtin_amdgcn_readlane(pv, k);
-          const double r = rl(rpv, k);
-          const double uk = mystep < k ? static_cast<double>(pick<KC>(ar, k)) : 0.0;
-#pragma unroll
-          for (int g = 0; g < 4; ++g) v[g] = fma(-uk, rl(v[g], p) * r, v[g]);
-        }
-        // lane p_k holds y_k, so d_k = v * rdg there; lane k takes it
-        double dm = 0.0, xm = 0.0;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const double dk = __shfl(v[g] * rdg, pv, 64);
-          const double d = lane < K ? dk : 0.0;
-          x[g] += d;
-          dm = fmax(dm, fabs(d));
-          xm = fmax(xm, fabs(x[g]));
-          if (lane < K) S.xs[lane][g] = x[g];
-        }
-        wave_sync_lds();
-        dm = wave_max(dm);
-        xm = wave_max(xm);
-        converged = dm <= 0x1p-48 * xm;
+      const WaveRows<KC, T> rows{ar0, ar1, ar2, ar3, mystep, pv, rpv, rdg};
+      const WaveCtx wc{lane, n, K, mg, P, own_pw, poly_a, poly_b, is_node, is_poly, ex, ez};
+      switch (G) {
+        case 1: wave_refine<KC, 1>(a, S, rows, wc, g0, x, converged); break;
+        case 2: wave_refine<KC, 2>(a, S, rows, wc, g0, x, converged); break;
+        case 3: wave_refine<KC, 3>(a, S, rows, wc, g0, x, converged); break;
+        default: wave_refine<KC, 4>(a, S, rows, wc, g0, x, converged); break;
       }
 
       // 5. status and rescaled output
@@ -1115,15 +1219,24 @@ __device__ __forceinline__ int bucket_of(int K) {
   return b;
 }
 
-// count[b] and the largest K in bucket b (kmax[b])
+// count[b] and the largest K in bucket b (kmax[b]); one atomic per
+// wavefront and bucket (lane-divergent addresses would serialise)
 __global__ void bucket_count_kernel(const int *n_per, int n_max, const int *l_per, int l_uni, int nc, int *count,
                                     int *kmax) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nc) return;
-  const int K = (n_per ? n_per[q] : n_max) + n_terms(l_per ? l_per[q] : l_uni);
-  const int b = bucket_of(K);
-  atomicAdd(&count[b], 1);
-  atomicMax(&kmax[b], K);
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int K = q < nc ? (n_per ? n_per[q] : n_max) + n_terms(l_per ? l_per[q] : l_uni) : 0;
+  const int b = q < nc ? bucket_of(K) : -1;
+  for (int bb = 0; bb < NBUCKET; ++bb) {
+    const uint64_t mask = __ballot(b == bb);
+    if (mask == 0) continue;
+    int km = b == bb ? K : 0;
+    for (int off = 32; off > 0; off >>= 1) km = max(km, __shfl_xor(km, off, 64));
+    if (lane == __ffsll(static_cast<unsigned long long>(mask)) - 1) {
+      atomicAdd(&count[bb], __popcll(mask));
+      atomicMax(&kmax[bb], km);
+    }
+  }
 }
 
 // cursor[b] starts at bucket b's offset in `list`. Each wavefront reserves
