@@ -46,7 +46,7 @@ const char *rbffd_last_error(rbffd_ctx *ctx) {
 
 int rbffd_sync(rbffd_ctx *ctx) {
   if (!ctx) return RBFFD_EINVAL;
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   RBFFD_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return RBFFD_OK;
 }
@@ -71,7 +71,7 @@ int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx) {
   if (rc) return rc;
   if (st->n_centers == 0) return RBFFD_OK;  // empty batch: nothing to write
   if (!idx) return rbffd_fail(ctx, RBFFD_EINVAL, "null idx");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return knn_run(ctx, st, idx);
 }
 
@@ -111,7 +111,7 @@ int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops,
   if (st->n_centers == 0) return RBFFD_OK;  // empty batch: nothing to write
   if (!w) return rbffd_fail(ctx, RBFFD_EINVAL, "null w");
   if (!st->idx_in && !idx) return rbffd_fail(ctx, RBFFD_EINVAL, "need idx output or idx_in");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   const int32_t *use_idx = st->idx_in;
   if (!use_idx) {
     rc = knn_run(ctx, st, idx);
@@ -133,7 +133,7 @@ int rbffd_model_create(rbffd_ctx *ctx, const rbffd_model_desc *desc, rbffd_model
   if (!ctx) return RBFFD_EINVAL;
   if (!desc || !out) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
   *out = nullptr;
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return model_create_impl(ctx, desc, out);
 }
 
@@ -142,14 +142,14 @@ int rbffd_model_destroy(rbffd_model *model) { return model_destroy_impl(model); 
 int rbffd_ghost(rbffd_ctx *ctx, rbffd_model *model, void *state) {
   if (!ctx) return RBFFD_EINVAL;
   if (!model || !state) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return model_ghost(ctx, model, state);
 }
 
 int rbffd_rhs(rbffd_ctx *ctx, rbffd_model *model, double t, void *state, void *tendency) {
   if (!ctx) return RBFFD_EINVAL;
   if (!model || !state || !tendency) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return model_rhs(ctx, model, t, state, tendency);
 }
 
@@ -162,7 +162,7 @@ int rbffd_step(rbffd_ctx *ctx, rbffd_model *model, void *state, double *t, doubl
   if (tableau != RBFFD_RK4 && tableau != RBFFD_WSRK3)
     return rbffd_fail(ctx, RBFFD_EINVAL, "bad tableau %d", tableau);
   if (!(dt > 0.0)) return rbffd_fail(ctx, RBFFD_EINVAL, "dt must be positive");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return model_step(ctx, model, state, t, dt, n_steps, tableau);
 }
 
@@ -183,7 +183,7 @@ int rbffd_model_profile_read(rbffd_model *model, double *total_ms, int64_t *laun
 int rbffd_model_tune(rbffd_ctx *ctx, rbffd_model *model, void *state, int *chosen, double *best_us) {
   if (!ctx) return RBFFD_EINVAL;
   if (!model || !state || !chosen || !best_us) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return model_tune(ctx, model, state, chosen, best_us);
 }
 
@@ -191,7 +191,7 @@ int rbffd_closure_create(rbffd_ctx *ctx, rbffd_model *model, const rbffd_closure
   if (!ctx) return RBFFD_EINVAL;
   if (!model || !desc || !out) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
   *out = nullptr;
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return closure_create(ctx, model, desc, out);
 }
 
@@ -202,7 +202,7 @@ float *rbffd_closure_params(rbffd_closure *cl) { return cl ? closure_params(cl) 
 int rbffd_closure_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, float *out) {
   if (!ctx) return RBFFD_EINVAL;
   if (!cl || !state || !out) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return closure_forward(ctx, cl, state, out);
 }
 
@@ -210,7 +210,7 @@ int rbffd_closure_gradient(rbffd_ctx *ctx, rbffd_closure *cl, const void *state,
                            double *loss) {
   if (!ctx) return RBFFD_EINVAL;
   if (!cl || !state || !target || !grad || !loss) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return closure_gradient(ctx, cl, state, target, grad, loss);
 }
 
@@ -219,7 +219,7 @@ int rbffd_closure_train_step(rbffd_ctx *ctx, rbffd_closure *cl, const void *stat
   if (!ctx) return RBFFD_EINVAL;
   if (!cl || !state || !target || !loss) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
   if (!(lr > 0.0)) return rbffd_fail(ctx, RBFFD_EINVAL, "learning rate must be positive");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return closure_train_step(ctx, cl, state, target, lr, loss);
 }
 
@@ -229,7 +229,7 @@ int rbffd_closure_step(rbffd_ctx *ctx, rbffd_closure *cl, void *state, double *t
   if (!cl || !state || !t) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
   if (n_steps < 0 || !(dt > 0.0) || (tableau != RBFFD_RK4 && tableau != RBFFD_WSRK3))
     return rbffd_fail(ctx, RBFFD_EINVAL, "bad step arguments");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return closure_step(ctx, cl, state, t, dt, n_steps, tableau, n_fallback);
 }
 
@@ -238,7 +238,7 @@ int rbffd_stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes)
   if (!dst || !src || bytes < 0 || bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 ||
       reinterpret_cast<uintptr_t>(src) % 16)
     return rbffd_fail(ctx, RBFFD_EINVAL, "stream copy needs 16-byte aligned pointers and size");
-  RBFFD_HIP(ctx, hipSetDevice(ctx->device));
+  RBFFD_ENTER(ctx);
   return stream_copy(ctx, dst, src, bytes);
 }
 

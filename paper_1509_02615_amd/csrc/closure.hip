@@ -447,14 +447,6 @@ __global__ void scale_out_kernel(const float *__restrict__ Y, int ys, int64_t S,
   out[s * 4 + 3] = Y[s * ys + 3] * sc.w;
 }
 
-// Stencil indices out of the model's slot-major records.
-__global__ void idx_from_rec_kernel(const RecF32 *__restrict__ r32, const RecBF16 *__restrict__ rbf, int64_t cnt,
-                                    int *__restrict__ out) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
-  out[t] = r32 ? r32[t].idx : rbf[t].idx;
-}
-
 __global__ void f64_to_f32_kernel(const double *__restrict__ a, int64_t n, float *__restrict__ b) {
   const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t < n) b[t] = static_cast<float>(a[t]);
@@ -648,13 +640,14 @@ int closure_create(rbffd_ctx *ctx, rbffd_model *m, const rbffd_closure_desc *d, 
   }
   f64_to_f32_kernel<<<grid_for(m->Na, 256), 256, 0, s>>>(d->node_feature, m->Na, cl->nodef.as<float>());
   const int64_t cnt = m->Na * m->n;
-  idx_from_rec_kernel<<<grid_for(cnt, 256), 256, 0, s>>>(m->wdt == RBFFD_F32 ? m->rec.as<RecF32>() : nullptr,
-                                                         m->wdt == RBFFD_BF16 ? m->rec.as<RecBF16>() : nullptr, cnt,
-                                                         cl->idx.as<int>());
+  const hipError_t e_idx = hipMemcpyAsync(cl->idx.p, m->idx_t.p, sizeof(int) * cnt, hipMemcpyDeviceToDevice, s);
   repack(cl, s);
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+  const hipError_t e_launch = hipGetLastError();
+  const hipError_t e_sync = hipStreamSynchronize(s);
+  if (e_idx != hipSuccess || e_launch != hipSuccess || e_sync != hipSuccess) {
     delete cl;
-    return rbffd_fail(ctx, RBFFD_EDEVICE, "closure set-up");
+    return rbffd_fail(ctx, RBFFD_EDEVICE, "closure set-up: index copy %s, launches %s, synchronisation %s",
+                      hipGetErrorString(e_idx), hipGetErrorString(e_launch), hipGetErrorString(e_sync));
   }
   *out = cl;
   return RBFFD_OK;

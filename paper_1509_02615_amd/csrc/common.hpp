@@ -28,6 +28,17 @@ int rbffd_fail(rbffd_ctx *ctx, int code, const char *fmt, ...);
                         hipGetErrorString(e_), __FILE__, __LINE__);                  \
   } while (0)
 
+// Entry into a library call: select the context's device and drop a stale
+// "last error" that an unrelated earlier call on this thread may have left
+// (the not-ready status of an event or stream query, for instance), so the
+// launch checks after our own launches report those launches only. A device
+// fault is not lost: it stays with the context and fails later calls.
+#define RBFFD_ENTER(ctx)                                  \
+  do {                                                    \
+    RBFFD_HIP((ctx), hipSetDevice((ctx)->device));        \
+    (void)hipGetLastError();                              \
+  } while (0)
+
 // Scoped device buffer (stream-ordered free is not needed: buffers live
 // until the owning call or object ends, after a synchronisation).
 struct DevBuf {

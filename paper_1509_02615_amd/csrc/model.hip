@@ -25,26 +25,49 @@
 
 namespace {
 
+// 16-bit offset j - i of a neighbour, or OFF_FAR
+__device__ __forceinline__ int16_t nb_offset(int j, int64_t i) {
+  const int64_t d = static_cast<int64_t>(j) - i;
+  return (d >= -32767 && d <= 32767) ? static_cast<int16_t>(d) : OFF_FAR;
+}
+
 __global__ void repack_f64(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n,
-                           int *__restrict__ idx_t, RecF64 *__restrict__ rec) {
+                           int *__restrict__ idx_t, int16_t *__restrict__ off, RecF64 *__restrict__ rec) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= na * n) return;
   int64_t i = t / n;
   int k = static_cast<int>(t % n);
   const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k) * na + i;
   idx_t[dst] = idx[src];
+  off[dst] = nb_offset(idx[src], i);
   rec[dst] = RecF64{w[src], w[plane + src], w[2 * plane + src], w[3 * plane + src]};
 }
 
 __global__ void repack_f32(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n,
-                           RecF32 *__restrict__ rec, double *__restrict__ hv) {
+                           int *__restrict__ idx_t, int16_t *__restrict__ off, RecF32 *__restrict__ rec,
+                           double *__restrict__ hv) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= na * n) return;
   int64_t i = t / n;
   int k = static_cast<int>(t % n);
   const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k) * na + i;
+  idx_t[dst] = idx[src];
+  off[dst] = nb_offset(idx[src], i);
   rec[dst] = RecF32{static_cast<float>(w[src]), static_cast<float>(w[plane + src]),
-                    static_cast<float>(w[2 * plane + src]), idx[src]};
+                    static_cast<float>(w[2 * plane + src])};
+  hv[dst] = w[3 * plane + src];
+}
+
+__global__ void repack_f32w(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n,
+                            int *__restrict__ idx_t, RecF32W *__restrict__ rec, double *__restrict__ hv) {
+  int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= na * n) return;
+  int64_t i = t / n;
+  int k = static_cast<int>(t % n);
+  const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k) * na + i;
+  idx_t[dst] = idx[src];
+  rec[dst] = RecF32W{static_cast<float>(w[src]), static_cast<float>(w[plane + src]),
+                     static_cast<float>(w[2 * plane + src]), idx[src]};
   hv[dst] = w[3 * plane + src];
 }
 
@@ -57,13 +80,14 @@ __device__ __forceinline__ uint16_t to_bf16(double v) {
 }
 
 __global__ void repack_bf16(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n,
-                            RecBF16 *__restrict__ rec, double *__restrict__ hv) {
+                            int *__restrict__ idx_t, RecBF16 *__restrict__ rec, double *__restrict__ hv) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= na * n) return;
   int64_t i = t / n;
   int k = static_cast<int>(t % n);
   const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k) * na + i;
-  rec[dst] = RecBF16{to_bf16(w[src]), to_bf16(w[plane + src]), to_bf16(w[2 * plane + src]), 0, idx[src]};
+  idx_t[dst] = idx[src];
+  rec[dst] = RecBF16{to_bf16(w[src]), to_bf16(w[plane + src]), to_bf16(w[2 * plane + src]), nb_offset(idx[src], i)};
   hv[dst] = w[3 * plane + src];
 }
 
@@ -290,17 +314,37 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
                                                     m->rec.as<RecAdv>());
     m->bytes_per_node = n * (4 + sizeof(RecAdv));
   } else if (m->wdt == RBFFD_F64) {
-    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecF64) * cnt) == hipSuccess;
+    // bytes the stage kernel streams per node: records, offsets, Lap^k
+    // weights (the full indices are read only for OFF_FAR neighbours); the
+    // offsets get one spare element, as a wave-uniform read takes the
+    // aligned dword around an offset
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->off16.alloc(sizeof(int16_t) * (cnt + 1)) == hipSuccess &&
+         m->rec.alloc(sizeof(RecF64) * cnt) == hipSuccess;
     if (ok)
-      repack_f64<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->rec.as<RecF64>());
-    m->bytes_per_node = n * (4 + sizeof(RecF64));
+      repack_f64<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->off16.as<int16_t>(),
+                                                     m->rec.as<RecF64>());
+    m->bytes_per_node = n * (sizeof(int16_t) + sizeof(RecF64));
+  } else if (m->wdt == RBFFD_F32 && m->E % 64 == 0) {
+    m->wide_rec = true;
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecF32W) * cnt) == hipSuccess &&
+         m->hv_t.alloc(sizeof(double) * cnt) == hipSuccess;
+    if (ok)
+      repack_f32w<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->rec.as<RecF32W>(),
+                                                      m->hv_t.as<double>());
+    m->bytes_per_node = n * (sizeof(RecF32W) + 8);
   } else if (m->wdt == RBFFD_F32) {
-    ok = m->rec.alloc(sizeof(RecF32) * cnt) == hipSuccess && m->hv_t.alloc(sizeof(double) * cnt) == hipSuccess;
-    if (ok) repack_f32<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->rec.as<RecF32>(), m->hv_t.as<double>());
-    m->bytes_per_node = n * (sizeof(RecF32) + 8);
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->off16.alloc(sizeof(int16_t) * (cnt + 1)) == hipSuccess &&
+         m->rec.alloc(sizeof(RecF32) * cnt) == hipSuccess && m->hv_t.alloc(sizeof(double) * cnt) == hipSuccess;
+    if (ok)
+      repack_f32<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->off16.as<int16_t>(),
+                                                     m->rec.as<RecF32>(), m->hv_t.as<double>());
+    m->bytes_per_node = n * (sizeof(RecF32) + sizeof(int16_t) + 8);
   } else {
-    ok = m->rec.alloc(sizeof(RecBF16) * cnt) == hipSuccess && m->hv_t.alloc(sizeof(double) * cnt) == hipSuccess;
-    if (ok) repack_bf16<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->rec.as<RecBF16>(), m->hv_t.as<double>());
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecBF16) * cnt) == hipSuccess &&
+         m->hv_t.alloc(sizeof(double) * cnt) == hipSuccess;
+    if (ok)
+      repack_bf16<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->rec.as<RecBF16>(),
+                                                      m->hv_t.as<double>());
     m->bytes_per_node = n * (sizeof(RecBF16) + 8);
   }
   if (!ok) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation (weights)");

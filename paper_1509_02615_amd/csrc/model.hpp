@@ -4,17 +4,25 @@
 
 #include "common.hpp"
 
-// Weight records, slot-major: record (k, i) holds slot k of node i.
+// Weight records, slot-major: record (k, i) holds slot k of node i. The
+// neighbour index j of a Navier-Stokes record travels as the 16-bit offset
+// j - i (int16 [n][Na], inline in the BF16 record); an offset outside
+// +-32767 (a ghost neighbour: ghosts are stored after the active nodes) is
+// OFF_FAR, and the kernel then reads j from the full index array idx_t.
+constexpr int16_t OFF_FAR = -32768;
 struct RecF64 {      // FP64 Navier-Stokes: Dx, Dz, Lap, Lap^k
   double dx, dz, lap, hv;
 };
-struct RecF32 {      // FP32 Navier-Stokes: Dx, Dz, Lap and the neighbour index
+struct RecF32 {      // FP32 Navier-Stokes: Dx, Dz, Lap
   float dx, dz, lap;
-  int idx;
 };
-struct RecBF16 {     // BF16 Navier-Stokes: Dx, Dz, Lap (bfloat16 bits) and the index
-  uint16_t dx, dz, lap, pad;
-  int idx;
+struct RecF32W {     // FP32 with the full index, for ensembles of 64k members: one
+  float dx, dz, lap; // record serves a wavefront of 64 members, so one aligned
+  int idx;           // 16-byte scalar load per slot beats the smaller record
+};
+struct RecBF16 {     // BF16 Navier-Stokes: Dx, Dz, Lap (bfloat16 bits) and the offset
+  uint16_t dx, dz, lap;
+  int16_t off;
 };
 struct RecAdv {      // transport: folded flux weights and Lap^k
   double adv, hv;
@@ -30,7 +38,9 @@ struct rbffd_model {
   int n = 0, E = 1, F = 1;
   int64_t N = 0, Na = 0;
   // slot-major differentiation matrices
-  DevBuf idx_t;     // int32 [n][Na] (F64 and transport layouts)
+  DevBuf idx_t;     // int32 [n][Na] full neighbour indices
+  DevBuf off16;     // int16 [n][Na] neighbour offsets j - i (F64 and F32 layouts)
+  bool wide_rec = false;  // FP32 records carry the full index (RecF32W)
   DevBuf rec;       // RecF64 / RecF32 / RecBF16 / RecAdv [n][Na]
   DevBuf hv_t;      // double [n][Na] (F32 / BF16 layouts)
   DevBuf kind;      // uint8 [N]: KIND_* bits (0: interior)

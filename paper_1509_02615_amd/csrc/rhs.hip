@@ -70,6 +70,13 @@ template <bool NT> __device__ __forceinline__ double2 stream_load2(const double2
   }
   return *p;
 }
+template <bool NT> __device__ __forceinline__ uint2 stream_load2u(const uint2 *p) {
+  if constexpr (NT) {
+    const unsigned *q = reinterpret_cast<const unsigned *>(p);
+    return make_uint2(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1));
+  }
+  return *p;
+}
 template <bool NT> __device__ __forceinline__ uint3 stream_load3(const uint3 *p) {
   if constexpr (NT) {
     const unsigned *q = reinterpret_cast<const unsigned *>(p);
@@ -77,6 +84,18 @@ template <bool NT> __device__ __forceinline__ uint3 stream_load3(const uint3 *p)
                       __builtin_nontemporal_load(q + 2));
   }
   return *p;
+}
+
+// Neighbour offset s. With a wave-uniform s (one node per wavefront) the
+// aligned dword holding it is loaded, so the load can go through the scalar
+// cache (scalar loads are dword-sized) instead of a vector load whose
+// latency would precede every gather address.
+template <bool NT, bool UNIFORM> __device__ __forceinline__ int load_off(const int16_t *off16, int64_t s) {
+  if constexpr (UNIFORM) {
+    const unsigned wd = reinterpret_cast<const unsigned *>(off16)[s >> 1];
+    return static_cast<int16_t>(wd >> (16 * static_cast<int>(s & 1)));
+  }
+  return stream_load<NT>(off16 + s);
 }
 
 template <int BLOCK = RHS_BLOCK> __device__ __forceinline__ int64_t xcd_thread() {
@@ -122,7 +141,8 @@ struct NSArgs {
   const void *yn;     // base of the stage update (y_n)
   void *out;          // tendency or next stage
   void *acc;          // RK4 accumulator
-  const int *idx_t;
+  const int *idx_t;      // full neighbour indices (read for OFF_FAR offsets only)
+  const int16_t *off16;  // neighbour offsets j - i (F64 and F32 records)
   const void *rec;
   const double *hv_t;
   const uint8_t *kind;
@@ -164,28 +184,43 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
     int j;
     FT wdx, wdz, wlp;
     double whv;
+    int off;
     if constexpr (WDT == RBFFD_F64) {
       const double2 r0 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s);
       const double2 r1 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s + 1);
-      j = stream_load<NT>(a.idx_t + s);
+      off = load_off<NT, MW>(a.off16, s);
       wdx = r0.x;
       wdz = r0.y;
       wlp = r1.x;
       whv = r1.y;
-    } else if constexpr (WDT == RBFFD_F32) {
-      const float4 r = stream_load4<NT>(reinterpret_cast<const float4 *>(a.rec) + s);
-      j = __float_as_int(r.w);
+    } else if constexpr (WDT == RBFFD_F32 && MW) {  // RecF32W: full index inline
+      const float4 r = reinterpret_cast<const float4 *>(a.rec)[s];
+      off = 0;
       wdx = r.x;
       wdz = r.y;
       wlp = r.z;
+      whv = a.hv_t[s];
+      j = __float_as_int(r.w);
+    } else if constexpr (WDT == RBFFD_F32) {
+      const uint3 r = stream_load3<NT>(reinterpret_cast<const uint3 *>(a.rec) + s);
+      off = load_off<NT, MW>(a.off16, s);
+      wdx = __uint_as_float(r.x);
+      wdz = __uint_as_float(r.y);
+      wlp = __uint_as_float(r.z);
       whv = stream_load<NT>(a.hv_t + s);
     } else {
-      const uint3 r = stream_load3<NT>(reinterpret_cast<const uint3 *>(a.rec) + s);
-      j = static_cast<int>(r.z);
+      const uint2 r = stream_load2u<NT>(reinterpret_cast<const uint2 *>(a.rec) + s);
       wdx = __uint_as_float(r.x << 16);
       wdz = __uint_as_float(r.x & 0xffff0000u);
       wlp = __uint_as_float(r.y << 16);
+      off = static_cast<int16_t>(r.y >> 16);
       whv = stream_load<NT>(a.hv_t + s);
+    }
+    if constexpr (!(WDT == RBFFD_F32 && MW)) {
+      if (__builtin_expect(off == OFF_FAR, 0))
+        j = a.idx_t[s];  // a ghost neighbour
+      else
+        j = static_cast<int>(i) + off;
     }
     const F4<FT> f = load4(ys + (static_cast<int64_t>(j) * E + e) * 4);
 #pragma unroll
@@ -597,6 +632,7 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.out = sp.out;
     a.acc = m->acc.p;
     a.idx_t = m->idx_t.as<int>();
+    a.off16 = m->off16.as<int16_t>();
     a.rec = m->rec.p;
     a.hv_t = m->hv_t.as<double>();
     a.kind = m->kind.as<uint8_t>();
