@@ -150,6 +150,41 @@ def weights_leg(R, ctx, cfg, precision):
                      "double-double refinement are extra work, not counted")
 
 
+def advection_leg(R, P, ctx):
+    """The scalar-transport workload (64 x 64 Cartesian nodes on the unit
+    square, r^5 + degree-4 polynomials, Dx, Dy and Lap^3, FP64): search and
+    weights, then the whole RK4 run to T = 5 (2,000 steps, one captured graph
+    per step) and the bell-return error against the initial field, which is
+    the exact solution at T. The 4,096-node state is cache-resident, so the
+    run measures per-step launch cost rather than bandwidth."""
+    import numpy as np
+    import torch
+    from workloads import advection_config
+    cfg = advection_config(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xy, idx, W, status = P.advection_weights(ctx, cfg)
+    model = P.advection_model(ctx, cfg, idx, W, xy=xy)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    psi0 = cfg["psi0"]
+    n = int(round(cfg["t_end"] / cfg["dt"]))
+    s = P.to_dev(psi0, torch.float64).reshape(model.state_shape()).contiguous()
+    s0 = s.clone()
+    R.rbffd_step(ctx, model, s, 0.0, cfg["dt"], 20, R.RK4)   # capture and warm up on the same buffer
+    s.copy_(s0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = R.rbffd_step(ctx, model, s, 0.0, cfg["dt"], n, R.RK4)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    y = s.double().cpu().numpy().ravel()
+    return dict(nodes=int(cfg["nodes"].n_active), steps=n, t_end=float(t), setup_s=setup, run_s=sec,
+                us_per_step=sec / n * 1e6, rhs_per_s=4 * n / sec, singular=int(status.abs().sum()),
+                bell_return_rel_l2=float(np.linalg.norm(y - psi0) / np.linalg.norm(psi0)),
+                bell_return_max_abs=float(np.abs(y - psi0).max()))
+
+
 def fullrun_leg(R, P, ctx, cfg, idx, W, Ww, xy, t_end=900.0, chunk=1800):
     """The density current on the 2048 x 256 channel run to t_end with FP64,
     FP32 and BF16-weight fields/weights from the same initial state (RK4,
@@ -392,6 +427,8 @@ def main():
         log(f"[bench] weights fp32+IR: {extras['weights_mixed_1M_fp32_ir']}")
         extras["closure_forward_256x2176"] = closure_leg(R, ctx)
         log(f"[bench] closure: {extras['closure_forward_256x2176']}")
+        extras["advection_64x64_fp64"] = advection_leg(R, P, ctx)
+        log(f"[bench] advection: {extras['advection_64x64_fp64']}")
         extras["precision_fullrun_900s"] = fullrun_leg(R, P, ctx, cfg, idx, W, Ww, xy)
         log(f"[bench] full runs to 900 s: {extras['precision_fullrun_900s']}")
         # a 4x larger channel (4096 x 512 = 2,097,152 nodes, 2 GB per launch): the
