@@ -276,12 +276,54 @@ def closure_leg(R, ctx, calls=20, members=256):
     ev1.record()
     torch.cuda.synchronize()
     corr_ms = ev0.elapsed_time(ev1) / n
+    speedup = closure_speedup(R, ctx, cc, params, nodef)
     return dict(samples=S, forward_us=fwd_s * 1e6, samples_per_s=S / fwd_s,
                 roofline={"bound": "mfma", "achieved": tflops, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                           "frac": tflops / BF16_MFMA_PEAK_TFLOPS, "flop_per_sample": CLOSURE_FLOP_PER_SAMPLE},
-                plain_step_ms=plain_ms, corrected_step_ms=corr_ms,
+                plain_step_ms=plain_ms, corrected_step_ms=corr_ms, vs_fine_run=speedup,
                 note="forward call = fused gather + 3-layer network kernel + output scaling; "
                      "steps: 4-stage RK4 of 256 members, corrected = plain + forward + correction")
+
+
+def closure_speedup(R, ctx, cc, params, nodef, members=64, seconds=30.0):
+    """Cost of the corrected coarse run against the fine run it stands in
+    for: the same members and the same simulated interval (30 s), each on
+    its own grid (fine 50 m, 1024 x 129 nodes, dt = 1/8 s; coarse 400 m,
+    128 x 17, dt = 1 s), timed after a warm-up that captures the graphs."""
+    import torch
+    from paper_1509_02615_amd import closure as CL
+    from paper_1509_02615_amd import pipeline as P
+    from workloads.fields import ensemble_amplitudes
+    amps = ensemble_amplitudes(members)
+    fine = cc["fine"]
+    xy, idx, W, Ww, _ = P.ns_weights(ctx, fine)
+    fm = P.ns_model(ctx, fine, idx, W, Ww, xy=xy, field_dtype=R.F32, weight_dtype=R.F32, ensemble=members)
+    fs = CL.ensemble_state(fine, amps)
+    cm, _ = CL.coarse_model(ctx, cc, members)
+    cs = CL.to_full(cm, CL.ensemble_state(cc["coarse"], amps)[:cm.Na])
+    cl = R.Closure(ctx, cm, params, nodef, [2.0, 2.0, 1.8, 3e-4], [1e-3, 1e-3, 7e-4, 3e-6], activation=R.ACT_RELU)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    nf = int(round(seconds / fine["dt"]))
+    nc = int(round(seconds / cc["coarse"]["dt"]))
+    f0, c0 = fs.clone(), cs.clone()
+    R.rbffd_step(ctx, fm, fs, 0.0, fine["dt"], 8, R.RK4)       # graph capture, warm-up
+    cl.step(cs, 0.0, cc["coarse"]["dt"], 4, R.RK4)
+    R.rbffd_step(ctx, cm, cs, 0.0, cc["coarse"]["dt"], 4, R.RK4)
+    fs.copy_(f0)
+    cs.copy_(c0)
+    fine_s = timed(lambda: R.rbffd_step(ctx, fm, fs, 0.0, fine["dt"], nf, R.RK4))
+    corr_s = timed(lambda: cl.step(cs, 0.0, cc["coarse"]["dt"], nc, R.RK4))
+    cs.copy_(c0)
+    plain_s = timed(lambda: R.rbffd_step(ctx, cm, cs, 0.0, cc["coarse"]["dt"], nc, R.RK4))
+    return dict(members=members, simulated_s=seconds, fine_steps=nf, coarse_steps=nc, fine_run_s=fine_s,
+                corrected_run_s=corr_s, plain_coarse_run_s=plain_s, speedup_corrected_vs_fine=fine_s / corr_s)
 
 
 def cpu_oracle_weights(min_seconds=10.0):
