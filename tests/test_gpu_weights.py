@@ -182,6 +182,28 @@ def test_weights_parity_mixed_batch(R, ctx, precision):
                     n_per=cfg["n_per"], m_per=cfg["m_per"], l_per=cfg["l_per"], precision=precision)
 
 
+def test_weights_parity_parameter_sweep(R, ctx):
+    """PHS orders 3..13 with their default hyperviscosity order (Lap^((m-1)/2)),
+    polynomial degrees 2..6 and stencils of 13..60 nodes mixed in one batch,
+    so that every system-size bucket runs (K = 19..88: the three one-
+    wavefront capacities and the block kernel); then r^1 with linear
+    polynomials (Section 3, Eq. weights). Every combination is well posed by
+    the oracle."""
+    say("weights: m = 3..13, l = 2..6, n = 13..60 mixed in one batch; then r^1, degree 1")
+    nd = jittered_square(24, seed=4)
+    combos = [(3, 2, 13), (3, 3, 21), (5, 2, 16), (9, 4, 30), (9, 3, 26), (11, 5, 40), (7, 5, 43),
+              (13, 6, 60), (5, 4, 49)]
+    N = nd.n_active
+    pick = np.arange(N) % len(combos)
+    m_per = np.array([combos[p][0] for p in pick], np.int32)
+    l_per = np.array([combos[p][1] for p in pick], np.int32)
+    n_per = np.array([combos[p][2] for p in pick], np.int32)
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0), (O.HYPERLAP, 0, 0)]
+    _weights_parity(R, ctx, nd.xy, ops, int(n_per.max()), 0, 0, 0.0, np.arange(N), sample=np.arange(0, N, 5),
+                    n_per=n_per, m_per=m_per, l_per=l_per)
+    _weights_parity(R, ctx, nd.xy, ops[:3], 7, 1, 1, 0.0, np.arange(N), sample=np.arange(0, N, 11))
+
+
 def test_weights_full_size_mixed_samples(R, ctx):
     say("weights: 1,048,576 scattered nodes, mixed l in {3,4,5}, one launch, 120 sampled stencils")
     cfg = weights_config(1024)
