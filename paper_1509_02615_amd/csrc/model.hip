@@ -17,6 +17,7 @@
 // row's own position), so the GPU finds each entry's row by arithmetic.
 // Each Runge-Kutta stage applies the windows.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -44,18 +45,32 @@ __global__ void repack_f64(const int *__restrict__ idx, const double *__restrict
 }
 
 __global__ void repack_f32(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n,
-                           int *__restrict__ idx_t, int16_t *__restrict__ off, RecF32 *__restrict__ rec,
-                           double *__restrict__ hv) {
+                           int *__restrict__ idx_t, uint32_t *__restrict__ aux, RecF32 *__restrict__ rec,
+                           int *__restrict__ bad) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= na * n) return;
   int64_t i = t / n;
   int k = static_cast<int>(t % n);
   const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k) * na + i;
   idx_t[dst] = idx[src];
-  off[dst] = nb_offset(idx[src], i);
+  // Lap^k weight = hi (1 + q 2^-39): hi its FP32 rounding (|w - hi| <=
+  // 2^-24 |hi|, and w - hi is exact in FP64), q the relative remainder on a
+  // 2^-39 grid
+  const double hv = w[3 * plane + src];
+  const float hi = static_cast<float>(hv);
+  int q = 0;
+  if (hv != 0.0) {
+    if (!(fabsf(hi) >= FLT_MIN && fabsf(hi) <= FLT_MAX)) {
+      atomicOr(bad, 1);  // outside the FP32 normal range
+    } else {
+      q = static_cast<int>(rint((hv - static_cast<double>(hi)) / static_cast<double>(hi) * 0x1p39));
+      q = max(-32767, min(32767, q));
+    }
+  }
   rec[dst] = RecF32{static_cast<float>(w[src]), static_cast<float>(w[plane + src]),
-                    static_cast<float>(w[2 * plane + src])};
-  hv[dst] = w[3 * plane + src];
+                    static_cast<float>(w[2 * plane + src]), hi};
+  aux[dst] = static_cast<uint32_t>(static_cast<uint16_t>(q)) |
+             (static_cast<uint32_t>(static_cast<uint16_t>(nb_offset(idx[src], i))) << 16);
 }
 
 __global__ void repack_f32w(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n,
@@ -333,12 +348,22 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
                                                       m->hv_t.as<double>());
     m->bytes_per_node = n * (sizeof(RecF32W) + 8);
   } else if (m->wdt == RBFFD_F32) {
-    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->off16.alloc(sizeof(int16_t) * (cnt + 1)) == hipSuccess &&
-         m->rec.alloc(sizeof(RecF32) * cnt) == hipSuccess && m->hv_t.alloc(sizeof(double) * cnt) == hipSuccess;
-    if (ok)
-      repack_f32<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->off16.as<int16_t>(),
-                                                     m->rec.as<RecF32>(), m->hv_t.as<double>());
-    m->bytes_per_node = n * (sizeof(RecF32) + sizeof(int16_t) + 8);
+    DevBuf bad;
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->aux32.alloc(sizeof(uint32_t) * cnt) == hipSuccess &&
+         m->rec.alloc(sizeof(RecF32) * cnt) == hipSuccess && bad.alloc(sizeof(int)) == hipSuccess;
+    if (ok) {
+      int hb = 0;
+      if (hipMemsetAsync(bad.p, 0, sizeof(int), s) != hipSuccess) return fail_model(ctx, m, RBFFD_EDEVICE, "memset");
+      repack_f32<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->aux32.as<uint32_t>(),
+                                                     m->rec.as<RecF32>(), bad.as<int>());
+      if (hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail_model(ctx, m, RBFFD_EDEVICE, "weight repack");
+      if (hb)
+        return fail_model(ctx, m, RBFFD_EINVAL,
+                          "hyperviscosity weights outside the FP32 normal range: use FP64 weights for this node set");
+    }
+    m->bytes_per_node = n * (sizeof(RecF32) + sizeof(uint32_t));
   } else {
     ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecBF16) * cnt) == hipSuccess &&
          m->hv_t.alloc(sizeof(double) * cnt) == hipSuccess;

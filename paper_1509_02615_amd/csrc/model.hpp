@@ -13,9 +13,14 @@ constexpr int16_t OFF_FAR = -32768;
 struct RecF64 {      // FP64 Navier-Stokes: Dx, Dz, Lap, Lap^k
   double dx, dz, lap, hv;
 };
-struct RecF32 {      // FP32 Navier-Stokes: Dx, Dz, Lap
-  float dx, dz, lap;
+struct RecF32 {      // FP32 Navier-Stokes: Dx, Dz, Lap and the high part of Lap^k
+  float dx, dz, lap, hv;
 };
+// The FP32 layout's second stream, one 32-bit word per record: the low 16
+// bits a correction q of the Lap^k weight, which is hv (1 + q 2^-39) (within
+// about 2^-40 of the FP64 weight, below the weights' own error), the high 16
+// bits the neighbour offset.
+constexpr double HV_Q_SCALE = 0x1p-39;
 struct RecF32W {     // FP32 with the full index, for ensembles of 64k members: one
   float dx, dz, lap; // record serves a wavefront of 64 members, so one aligned
   int idx;           // 16-byte scalar load per slot beats the smaller record
@@ -39,7 +44,8 @@ struct rbffd_model {
   int64_t N = 0, Na = 0;
   // slot-major differentiation matrices
   DevBuf idx_t;     // int32 [n][Na] full neighbour indices
-  DevBuf off16;     // int16 [n][Na] neighbour offsets j - i (F64 and F32 layouts)
+  DevBuf off16;     // int16 [n][Na] neighbour offsets j - i (F64 layout)
+  DevBuf aux32;     // uint32 [n][Na] Lap^k correction and neighbour offset (FP32 layout)
   bool wide_rec = false;  // FP32 records carry the full index (RecF32W)
   DevBuf rec;       // RecF64 / RecF32 / RecBF16 / RecAdv [n][Na]
   DevBuf hv_t;      // double [n][Na] (F32 / BF16 layouts)

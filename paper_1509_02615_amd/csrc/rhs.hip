@@ -142,7 +142,8 @@ struct NSArgs {
   void *out;          // tendency or next stage
   void *acc;          // RK4 accumulator
   const int *idx_t;      // full neighbour indices (read for OFF_FAR offsets only)
-  const int16_t *off16;  // neighbour offsets j - i (F64 and F32 records)
+  const int16_t *off16;  // neighbour offsets j - i (F64 records)
+  const uint32_t *aux32; // Lap^k correction and neighbour offset (FP32 records)
   const void *rec;
   const double *hv_t;
   const uint8_t *kind;
@@ -202,12 +203,14 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
       whv = a.hv_t[s];
       j = __float_as_int(r.w);
     } else if constexpr (WDT == RBFFD_F32) {
-      const uint3 r = stream_load3<NT>(reinterpret_cast<const uint3 *>(a.rec) + s);
-      off = load_off<NT, MW>(a.off16, s);
-      wdx = __uint_as_float(r.x);
-      wdz = __uint_as_float(r.y);
-      wlp = __uint_as_float(r.z);
-      whv = stream_load<NT>(a.hv_t + s);
+      const float4 r = stream_load4<NT>(reinterpret_cast<const float4 *>(a.rec) + s);
+      const uint32_t x = stream_load<NT>(a.aux32 + s);
+      off = static_cast<int16_t>(x >> 16);
+      wdx = r.x;
+      wdz = r.y;
+      wlp = r.z;
+      const double hi = r.w;  // Lap^k weight hi (1 + q 2^-39)
+      whv = fma(hi, static_cast<double>(static_cast<int16_t>(x & 0xffffu)) * HV_Q_SCALE, hi);
     } else {
       const uint2 r = stream_load2u<NT>(reinterpret_cast<const uint2 *>(a.rec) + s);
       wdx = __uint_as_float(r.x << 16);
@@ -633,6 +636,7 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.acc = m->acc.p;
     a.idx_t = m->idx_t.as<int>();
     a.off16 = m->off16.as<int16_t>();
+    a.aux32 = m->aux32.as<uint32_t>();
     a.rec = m->rec.p;
     a.hv_t = m->hv_t.as<double>();
     a.kind = m->kind.as<uint8_t>();
