@@ -128,7 +128,10 @@ int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx);
  * Outputs: idx [Nc][n_max] (may be NULL when idx_in is given),
  *          w [n_ops][Nc][n_max] FP64 (zero past n_c),
  *          status [Nc] (NULL allowed): 0 ok, 1 singular (smallest pivot below
- *          1e-13 max|A|, or refinement did not converge).
+ *          1e-13 max|A|, or refinement did not converge: it stops when the
+ *          error left after a correction d, estimated as |d|^2 / |d_prev|
+ *          from the contraction of successive corrections, is below
+ *          2^-52 |x|, or when |d| <= 2^-48 |x|).
  * Returns RBFFD_ESINGULAR (after writing everything) when any status is 1;
  * synchronises to read the status count. EINVAL: even m, l > 6, n_c < M,
  * K = n_c + M > 128, Laplacian^k with m < 2k+1, n_ops outside 1..8. */
@@ -142,7 +145,10 @@ typedef struct {
   int32_t field_dtype;    /* RBFFD_F64 or RBFFD_F32 (state element type)                */
   int32_t weight_dtype;   /* RBFFD_F64, RBFFD_F32 or RBFFD_BF16 for the first-derivative
                              and Laplacian weights; hyperviscosity and closure weights
-                             stay FP64. F32/BF16 need field_dtype F32.                   */
+                             stay FP64 (with F32, hyperviscosity weights are stored as
+                             an FP32 value and a 16-bit relative correction, within
+                             about 2^-40 of FP64; they must lie in the FP32 normal
+                             range). F32/BF16 need field_dtype F32.                      */
   int32_t n;              /* stencil length (row length of idx and w)                    */
   int64_t n_total;        /* N: all nodes including ghosts                               */
   int64_t n_active;       /* nodes 0..n_active-1 carry stencils and prognostic values;
@@ -192,8 +198,9 @@ typedef struct {
  * groups of rows that share no ghost) once on the host, keeping each inverse
  * row to rounding accuracy as its entries above a certified cut-off.
  * Synchronises. The caller's arrays may be freed after. EINVAL:
- * inconsistent sizes or indices, a ghost listed twice or missing;
- * ESINGULAR: a singular W_G. */
+ * inconsistent sizes or indices, a ghost listed twice or missing, F32
+ * hyperviscosity weights outside the FP32 normal range; ESINGULAR: a
+ * singular W_G. */
 int rbffd_model_create(rbffd_ctx *ctx, const rbffd_model_desc *desc, rbffd_model **out);
 int rbffd_model_destroy(rbffd_model *model);
 
