@@ -238,6 +238,20 @@ def test_rhs_parity_reduced_precision(R, ctx, wdt, tol, h):
     assert max(errs) <= tol
 
 
+def test_fp32_model_rejects_hyperviscosity_weights_beyond_fp32(R, ctx):
+    """The FP32 layout stores the Lap^k weights as an FP32 value plus a
+    relative correction, so weights outside the FP32 normal range are
+    rejected at model creation (EINVAL); FP64 weights take them."""
+    say("model: FP32 layout rejects Lap^k weights beyond the FP32 range, FP64 accepts them")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", 400.0)
+    Wbig = W.copy()
+    Wbig[3] *= 1e60   # weights of about 1e-16 at 400 m end beyond 3.4e38
+    with pytest.raises(R.RbffdError) as e:
+        gpu_ns(R, ctx, cfg, idx, Wbig, Ww, fdt=1, wdt=1)
+    assert e.value.code == R.EINVAL
+    gpu_ns(R, ctx, cfg, idx, Wbig, Ww, fdt=0, wdt=0).close()
+
+
 def test_rhs_rest_state_is_zero(R, ctx):
     import torch
     say("rhs: hydrostatic rest gives exactly zero tendency (FP64 and FP32)")
