@@ -252,6 +252,51 @@ def test_fp32_model_rejects_hyperviscosity_weights_beyond_fp32(R, ctx):
     gpu_ns(R, ctx, cfg, idx, Wbig, Ww, fdt=0, wdt=0).close()
 
 
+def test_rhs_independent_of_node_order(R, ctx):
+    """Neighbour indices travel as 16-bit offsets j - i, with an escape to the
+    full index beyond +-32767. A random order of the active nodes of the 50 m
+    hexagonal channel (about 150k nodes, most offsets beyond that range)
+    gives the same tendency node for node, bit for bit (FP64, FP32 and BF16
+    weights)."""
+    import torch
+    from paper_1509_02615_amd import pipeline as P
+    say("rhs: random order of the 50 m hexagonal channel's active nodes, same tendency bit for bit")
+    cfg = density_current_config("hexagonal", 50.0)
+    nd = cfg["nodes"]
+    na, N = nd.n_active, nd.n_total
+    xy, idx, W, Ww, _ = P.ns_weights(ctx, cfg)
+    rng = np.random.default_rng(12)
+    order = rng.permutation(na)                    # new node k is old node order[k]
+    new_of_old = np.arange(N)
+    new_of_old[order] = np.arange(na)
+    order_t, map_t = dev(order, torch.int64), dev(new_of_old, torch.int64)
+    idx2 = map_t[idx.long()[order_t]].int().contiguous()
+    W2 = W[:, order_t].contiguous()
+    xy2 = xy.clone()
+    xy2[:na] = xy[order_t]
+    far = (idx2.long() - torch.arange(na, device="cuda")[:, None]).abs() > 32767
+    say(f"   {float(far.float().mean()):.0%} of the offsets beyond +-32767")
+    assert float(far.float().mean()) > 0.5
+    st = smooth_ns_state(nd, seed=5)
+    st2 = st.copy()
+    st2[:na] = st[order]
+    Wwall = Ww.reshape(2, -1, idx.shape[1])
+    for fdt, wdt, dt in ((R.F64, R.F64, torch.float64), (R.F32, R.F32, torch.float32),
+                         (R.F32, R.BF16, torch.float32)):
+        outs = []
+        for ix, w, x, s, bn in ((idx, W, xy, st, nd.bnd_nodes), (idx2, W2, xy2, st2, new_of_old[nd.bnd_nodes])):
+            m = R.Model(ctx, R.PHYS_NS, ix, w, x, na, field_dtype=fdt, weight_dtype=wdt, hv_coeff=cfg["hv_coeff"],
+                        consts=cfg["consts"], bnd_nodes=dev(bn, torch.int32),
+                        bnd_ghosts=dev(nd.bnd_ghosts, torch.int32), bnd_normal=dev(nd.bnd_normal, torch.int32),
+                        bnd_d1=Wwall[0].contiguous(), bnd_d2=Wwall[1].contiguous())
+            sv = dev(s, dt).reshape(m.state_shape()).contiguous()
+            o = torch.empty_like(sv)
+            R.rbffd_rhs(ctx, m, 0.0, sv, o)
+            outs.append(o.reshape(N, 4))
+            m.close()
+        assert torch.equal(outs[1][:na], outs[0][:na][order_t]), (fdt, wdt)
+
+
 def test_rhs_rest_state_is_zero(R, ctx):
     import torch
     say("rhs: hydrostatic rest gives exactly zero tendency (FP64 and FP32)")
