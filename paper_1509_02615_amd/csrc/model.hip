@@ -121,6 +121,15 @@ __global__ void repack_adv(const int *__restrict__ idx, const double *__restrict
   rec[dst] = RecAdv{w[src] * U[j] + w[plane + src] * V[j], w[2 * plane + src]};
 }
 
+// out[r][k] = idx[rows[r]][k]: rows of a row-major [.][n] index array
+__global__ void gather_rows_kernel(const int *__restrict__ idx, const int *__restrict__ rows, int R, int n,
+                                   int *__restrict__ out) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<int64_t>(R) * n) return;
+  const int64_t r = t / n;
+  out[t] = idx[static_cast<int64_t>(rows[r]) * n + (t - r * n)];
+}
+
 __global__ void check_idx(const int *__restrict__ idx, int64_t count, int64_t n_total, int *__restrict__ bad) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= count) return;
@@ -419,11 +428,21 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
       int &c = gcol[h_ghost[r] - static_cast<int>(na)];
       if (c >= 0) return fail_model(ctx, m, RBFFD_EINVAL, "ghost node listed twice");
       c = r;
-      if (hipMemcpyAsync(&h_widx[static_cast<size_t>(r) * n], d->idx + static_cast<int64_t>(h_node[r]) * n,
-                         sizeof(int) * n, hipMemcpyDeviceToHost, s) != hipSuccess)
+    }
+    {  // the boundary rows' stencils: one gather on the device, one copy
+      DevBuf d_rows, d_widx;
+      if (d_rows.alloc(sizeof(int) * R) != hipSuccess || d_widx.alloc(sizeof(int) * h_widx.size()) != hipSuccess)
+        return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation");
+      const int64_t cnt_w = static_cast<int64_t>(R) * n;
+      if (hipMemcpyAsync(d_rows.p, h_node.data(), sizeof(int) * R, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail_model(ctx, m, RBFFD_EDEVICE, "boundary stencil copy");
+      gather_rows_kernel<<<grid_for(cnt_w, 256), 256, 0, s>>>(d->idx, d_rows.as<int>(), R, static_cast<int>(n),
+                                                             d_widx.as<int>());
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(h_widx.data(), d_widx.p, sizeof(int) * h_widx.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
         return fail_model(ctx, m, RBFFD_EDEVICE, "boundary stencil copy");
     }
-    if (hipStreamSynchronize(s) != hipSuccess) return fail_model(ctx, m, RBFFD_EDEVICE, "boundary stencil copy");
     // per field's operator: u takes d1 on z-normal rows and d2 on x-normal
     // rows, w the reverse, theta' and pi' d1 everywhere
     auto weight = [&](int mat, int r, int k) {

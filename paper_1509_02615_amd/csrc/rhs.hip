@@ -386,7 +386,10 @@ __device__ __forceinline__ void resid_store(const GArgs &a, int64_t row, int e, 
 }
 
 // B1 part 1: boundary-row residuals r = bc - (W_I u_I + W_B u_B).
-// One wavefront per (boundary row, member); lanes take stencil slots.
+// One wavefront per (boundary row, member); lanes take stencil slots. The
+// launch is short and latency-bound, so every load that does not depend on
+// a gathered value is issued first: the row's normal, its wall node and that
+// node's theta' (which the closure never writes), beside the slot records.
 template <class FT>
 __global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_kernel(GArgs a) {
   const int64_t item = static_cast<int64_t>(blockIdx.x) * (RHS_BLOCK / 64) + (threadIdx.x >> 6);
@@ -394,14 +397,29 @@ __global__ __launch_bounds__(RHS_BLOCK) void ghost_resid_kernel(GArgs a) {
   if (item >= static_cast<int64_t>(a.R) * a.E) return;
   const int64_t row = item / a.E;
   const int e = static_cast<int>(item - row * a.E);
+  FT *y = static_cast<FT *>(a.y);
   const int nrm = a.bnd_normal[row];
+  const int64_t o = (static_cast<int64_t>(a.bnd_nodes[row]) * a.E + e) * 4;
+  const double thb = static_cast<double>(y[o + 2]);
   double ru = 0.0, rw = 0.0, rt = 0.0, rp = 0.0;
   for (int k = lane; k < a.n; k += 64) resid_slot<FT>(a, row, k, e, nrm, ru, rw, rt, rp);
   ru = wave_sum(ru);
   rw = wave_sum(rw);
   rt = wave_sum(rt);
   rp = wave_sum(rp);
-  if (lane == 0) resid_store<FT>(a, row, e, nrm, ru, rw, rt, rp);
+  if (lane == 0) {
+    if (nrm == 0) {
+      rp += a.bc_scale * thb / (a.theta_bar + thb);
+      y[o + 1] = FT(0);
+    } else {
+      y[o + 0] = FT(0);
+    }
+    double *g = a.gres + (row * a.E + e) * 4;
+    g[0] = ru;
+    g[1] = rw;
+    g[2] = rt;
+    g[3] = rp;
+  }
 }
 
 // One W_G^-1 row (matrix `mat`, boundary row `row`): the cyclic window of
@@ -423,7 +441,45 @@ __device__ __forceinline__ int64_t win_row(const InvRow &w, int q) {
 }
 
 // B1 part 2: ghost values u_G = W_G^-1 r through the inverse windows.
-// One wavefront per (ghost row, member); lanes take window positions.
+// One wavefront per (ghost row, member); lanes take window positions, two
+// positions per lane at a time with both positions' loads issued before
+// either is summed (the sums per lane stay in window order).
+struct ApplyTerms {
+  double ct, t0, t2, t3;  // theta' / pi' (and u when shared): W_G^-1 entry, residuals
+  double cw, r1;          // w
+  double cu, r0;          // u
+};
+__device__ __forceinline__ ApplyTerms apply_load(const GArgs &a, const InvRow &wt, const InvRow &ww, const InvRow &wu,
+                                                 int q, int e) {
+  ApplyTerms t{};
+  if (q < wt.len) {
+    t.ct = wt.val[q];
+    const double *r = a.gres + (win_row(wt, q) * a.E + e) * 4;
+    if (a.u_shared) t.t0 = r[0];
+    t.t2 = r[2];
+    t.t3 = r[3];
+  }
+  if (q < ww.len) {
+    t.cw = ww.val[q];
+    t.r1 = a.gres[(win_row(ww, q) * a.E + e) * 4 + 1];
+  }
+  if (q < wu.len) {
+    t.cu = wu.val[q];
+    t.r0 = a.gres[(win_row(wu, q) * a.E + e) * 4];
+  }
+  return t;
+}
+__device__ __forceinline__ void apply_sum(const GArgs &a, const InvRow &wt, const InvRow &ww, const InvRow &wu, int q,
+                                          const ApplyTerms &t, double (&v)[4]) {
+  if (q < wt.len) {
+    if (a.u_shared) v[0] = fma(t.ct, t.t0, v[0]);
+    v[2] = fma(t.ct, t.t2, v[2]);
+    v[3] = fma(t.ct, t.t3, v[3]);
+  }
+  if (q < ww.len) v[1] = fma(t.cw, t.r1, v[1]);
+  if (q < wu.len) v[0] = fma(t.cu, t.r0, v[0]);
+}
+
 template <class FT>
 __global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_kernel(GArgs a) {
   const int64_t item = static_cast<int64_t>(blockIdx.x) * (RHS_BLOCK / 64) + (threadIdx.x >> 6);
@@ -431,25 +487,19 @@ __global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_kernel(GArgs a) {
   if (item >= static_cast<int64_t>(a.R) * a.E) return;
   const int64_t row = item / a.E;
   const int e = static_cast<int>(item - row * a.E);
+  const int64_t go = (static_cast<int64_t>(a.bnd_ghosts[row]) * a.E + e) * 4;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  // the rows' window descriptors first (independent loads), then one pass
-  // over the longest window
   const InvRow wt = inv_row(a, 2, row), ww = inv_row(a, 1, row);
   const InvRow wu = a.u_shared ? InvRow{nullptr, 0, 1, 0, 0} : inv_row(a, 0, row);
   const int L = max(max(wt.len, ww.len), wu.len);
-  for (int q = lane; q < L; q += 64) {
-    if (q < wt.len) {
-      const double c = wt.val[q];
-      const double *r = a.gres + (win_row(wt, q) * a.E + e) * 4;
-      if (a.u_shared) v[0] = fma(c, r[0], v[0]);
-      v[2] = fma(c, r[2], v[2]);
-      v[3] = fma(c, r[3], v[3]);
-    }
-    if (q < ww.len) v[1] = fma(ww.val[q], a.gres[(win_row(ww, q) * a.E + e) * 4 + 1], v[1]);
-    if (q < wu.len) v[0] = fma(wu.val[q], a.gres[(win_row(wu, q) * a.E + e) * 4], v[0]);
+  for (int q = lane; q < L; q += 128) {
+    const ApplyTerms t0 = apply_load(a, wt, ww, wu, q, e);
+    const ApplyTerms t1 = apply_load(a, wt, ww, wu, q + 64, e);
+    apply_sum(a, wt, ww, wu, q, t0, v);
+    apply_sum(a, wt, ww, wu, q + 64, t1, v);
   }
   for (int f = 0; f < 4; ++f) v[f] = wave_sum(v[f]);
-  if (lane == 0) store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.bnd_ghosts[row]) * a.E + e) * 4, v);
+  if (lane == 0) store4(static_cast<FT *>(a.y) + go, v);
 }
 
 // Ensembles (E >= GHOST_MEMBER_LANES): the same two steps with one thread
