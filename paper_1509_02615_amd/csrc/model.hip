@@ -32,27 +32,29 @@ __device__ __forceinline__ int16_t nb_offset(int j, int64_t i) {
   return (d >= -32767 && d <= 32767) ? static_cast<int16_t>(d) : OFF_FAR;
 }
 
-__global__ void repack_f64(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n,
+__global__ void repack_f64(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n, int k0,
                            int *__restrict__ idx_t, int16_t *__restrict__ off, RecF64 *__restrict__ rec) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= na * n) return;
   int64_t i = t / n;
   int k = static_cast<int>(t % n);
-  const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k) * na + i;
-  idx_t[dst] = idx[src];
+  const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k - k0) * na + i;
+  idx_t[static_cast<int64_t>(k) * na + i] = idx[src];
+  if (k < k0) return;  // the centre slot: every centre-subtracted sum skips it
   off[dst] = nb_offset(idx[src], i);
   rec[dst] = RecF64{w[src], w[plane + src], w[2 * plane + src], w[3 * plane + src]};
 }
 
-__global__ void repack_f32(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n,
+__global__ void repack_f32(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n, int k0,
                            int *__restrict__ idx_t, uint32_t *__restrict__ aux, RecF32 *__restrict__ rec,
                            int *__restrict__ bad) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= na * n) return;
   int64_t i = t / n;
   int k = static_cast<int>(t % n);
-  const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k) * na + i;
-  idx_t[dst] = idx[src];
+  const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k - k0) * na + i;
+  idx_t[static_cast<int64_t>(k) * na + i] = idx[src];
+  if (k < k0) return;  // the centre slot: every centre-subtracted sum skips it
   // Lap^k weight = hi (1 + q 2^-39): hi its FP32 rounding (|w - hi| <=
   // 2^-24 |hi|, and w - hi is exact in FP64), q the relative remainder on a
   // 2^-39 grid
@@ -73,14 +75,15 @@ __global__ void repack_f32(const int *__restrict__ idx, const double *__restrict
              (static_cast<uint32_t>(static_cast<uint16_t>(nb_offset(idx[src], i))) << 16);
 }
 
-__global__ void repack_f32w(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n,
+__global__ void repack_f32w(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n, int k0,
                             int *__restrict__ idx_t, RecF32W *__restrict__ rec, double *__restrict__ hv) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= na * n) return;
   int64_t i = t / n;
   int k = static_cast<int>(t % n);
-  const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k) * na + i;
-  idx_t[dst] = idx[src];
+  const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k - k0) * na + i;
+  idx_t[static_cast<int64_t>(k) * na + i] = idx[src];
+  if (k < k0) return;  // the centre slot: every centre-subtracted sum skips it
   rec[dst] = RecF32W{static_cast<float>(w[src]), static_cast<float>(w[plane + src]),
                      static_cast<float>(w[2 * plane + src]), idx[src]};
   hv[dst] = w[3 * plane + src];
@@ -94,14 +97,15 @@ __device__ __forceinline__ uint16_t to_bf16(double v) {
   return static_cast<uint16_t>(u >> 16);
 }
 
-__global__ void repack_bf16(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n,
+__global__ void repack_bf16(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n, int k0,
                             int *__restrict__ idx_t, RecBF16 *__restrict__ rec, double *__restrict__ hv) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= na * n) return;
   int64_t i = t / n;
   int k = static_cast<int>(t % n);
-  const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k) * na + i;
-  idx_t[dst] = idx[src];
+  const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k - k0) * na + i;
+  idx_t[static_cast<int64_t>(k) * na + i] = idx[src];
+  if (k < k0) return;  // the centre slot: every centre-subtracted sum skips it
   rec[dst] = RecBF16{to_bf16(w[src]), to_bf16(w[plane + src]), to_bf16(w[2 * plane + src]), nb_offset(idx[src], i)};
   hv[dst] = w[3 * plane + src];
 }
@@ -128,6 +132,12 @@ __global__ void gather_rows_kernel(const int *__restrict__ idx, const int *__res
   if (t >= static_cast<int64_t>(R) * n) return;
   const int64_t r = t / n;
   out[t] = idx[static_cast<int64_t>(rows[r]) * n + (t - r * n)];
+}
+
+// Clears *first unless every node's stencil starts with the node itself.
+__global__ void centre_first_kernel(const int *__restrict__ idx, int64_t na, int n, int *__restrict__ first) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < na && idx[i * n] != i) atomicAnd(first, 0);
 }
 
 __global__ void check_idx(const int *__restrict__ idx, int64_t count, int64_t n_total, int *__restrict__ bad) {
@@ -329,6 +339,23 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
     if (hb) return fail_model(ctx, m, RBFFD_EINVAL, "stencil index outside the node set");
   }
 
+  // Navier-Stokes sums are centre-subtracted, so a centre slot adds exactly
+  // 0: when every stencil starts with its own node, the stream leaves that
+  // slot out (the full index array keeps it)
+  if (m->physics == RBFFD_PHYS_NS && n > 1) {
+    DevBuf first;
+    int hf = 0;
+    if (first.alloc(sizeof(int)) != hipSuccess) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation");
+    if (hipMemsetAsync(first.p, 0xff, sizeof(int), s) != hipSuccess) return fail_model(ctx, m, RBFFD_EDEVICE, "memset");
+    centre_first_kernel<<<grid_for(na, 256), 256, 0, s>>>(d->idx, na, m->n, first.as<int>());
+    if (hipMemcpyAsync(&hf, first.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail_model(ctx, m, RBFFD_EDEVICE, "stencil centre check");
+    m->k0 = hf ? 1 : 0;
+  }
+  const int k0 = m->k0;
+  const int64_t cs = (n - k0) * na;  // stream records
+
   // slot-major repack
   bool ok = true;
   if (m->physics == RBFFD_PHYS_ADVECTION) {
@@ -342,28 +369,28 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
     // weights (the full indices are read only for OFF_FAR neighbours); the
     // offsets get one spare element, as a wave-uniform read takes the
     // aligned dword around an offset
-    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->off16.alloc(sizeof(int16_t) * (cnt + 1)) == hipSuccess &&
-         m->rec.alloc(sizeof(RecF64) * cnt) == hipSuccess;
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->off16.alloc(sizeof(int16_t) * (cs + 1)) == hipSuccess &&
+         m->rec.alloc(sizeof(RecF64) * cs) == hipSuccess;
     if (ok)
-      repack_f64<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->off16.as<int16_t>(),
+      repack_f64<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, k0, m->idx_t.as<int>(), m->off16.as<int16_t>(),
                                                      m->rec.as<RecF64>());
-    m->bytes_per_node = n * (sizeof(int16_t) + sizeof(RecF64));
+    m->bytes_per_node = (n - k0) * (sizeof(int16_t) + sizeof(RecF64));
   } else if (m->wdt == RBFFD_F32 && m->E % 64 == 0) {
     m->wide_rec = true;
-    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecF32W) * cnt) == hipSuccess &&
-         m->hv_t.alloc(sizeof(double) * cnt) == hipSuccess;
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecF32W) * cs) == hipSuccess &&
+         m->hv_t.alloc(sizeof(double) * cs) == hipSuccess;
     if (ok)
-      repack_f32w<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->rec.as<RecF32W>(),
+      repack_f32w<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, k0, m->idx_t.as<int>(), m->rec.as<RecF32W>(),
                                                       m->hv_t.as<double>());
-    m->bytes_per_node = n * (sizeof(RecF32W) + 8);
+    m->bytes_per_node = (n - k0) * (sizeof(RecF32W) + 8);
   } else if (m->wdt == RBFFD_F32) {
     DevBuf bad;
-    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->aux32.alloc(sizeof(uint32_t) * cnt) == hipSuccess &&
-         m->rec.alloc(sizeof(RecF32) * cnt) == hipSuccess && bad.alloc(sizeof(int)) == hipSuccess;
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->aux32.alloc(sizeof(uint32_t) * cs) == hipSuccess &&
+         m->rec.alloc(sizeof(RecF32) * cs) == hipSuccess && bad.alloc(sizeof(int)) == hipSuccess;
     if (ok) {
       int hb = 0;
       if (hipMemsetAsync(bad.p, 0, sizeof(int), s) != hipSuccess) return fail_model(ctx, m, RBFFD_EDEVICE, "memset");
-      repack_f32<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->aux32.as<uint32_t>(),
+      repack_f32<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, k0, m->idx_t.as<int>(), m->aux32.as<uint32_t>(),
                                                      m->rec.as<RecF32>(), bad.as<int>());
       if (hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess)
@@ -372,14 +399,14 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
         return fail_model(ctx, m, RBFFD_EINVAL,
                           "hyperviscosity weights outside the FP32 normal range: use FP64 weights for this node set");
     }
-    m->bytes_per_node = n * (sizeof(RecF32) + sizeof(uint32_t));
+    m->bytes_per_node = (n - k0) * (sizeof(RecF32) + sizeof(uint32_t));
   } else {
-    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecBF16) * cnt) == hipSuccess &&
-         m->hv_t.alloc(sizeof(double) * cnt) == hipSuccess;
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecBF16) * cs) == hipSuccess &&
+         m->hv_t.alloc(sizeof(double) * cs) == hipSuccess;
     if (ok)
-      repack_bf16<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, m->idx_t.as<int>(), m->rec.as<RecBF16>(),
+      repack_bf16<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, k0, m->idx_t.as<int>(), m->rec.as<RecBF16>(),
                                                       m->hv_t.as<double>());
-    m->bytes_per_node = n * (sizeof(RecBF16) + 8);
+    m->bytes_per_node = (n - k0) * (sizeof(RecBF16) + 8);
   }
   if (!ok) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation (weights)");
   if (m->physics == RBFFD_PHYS_NS) {

@@ -44,11 +44,13 @@ struct rbffd_model {
   int64_t N = 0, Na = 0;
   // slot-major differentiation matrices
   DevBuf idx_t;     // int32 [n][Na] full neighbour indices
-  DevBuf off16;     // int16 [n][Na] neighbour offsets j - i (F64 layout)
-  DevBuf aux32;     // uint32 [n][Na] Lap^k correction and neighbour offset (FP32 layout)
+  DevBuf off16;     // int16 [n - k0][Na] neighbour offsets j - i (F64 layout)
+  DevBuf aux32;     // uint32 [n - k0][Na] Lap^k correction and neighbour offset (FP32 layout)
   bool wide_rec = false;  // FP32 records carry the full index (RecF32W)
-  DevBuf rec;       // RecF64 / RecF32 / RecBF16 / RecAdv [n][Na]
-  DevBuf hv_t;      // double [n][Na] (F32 / BF16 layouts)
+  int k0 = 0;             // first slot in the stream (1: every stencil starts with its centre, which
+                          // centre-subtracted sums skip); the stream arrays hold slots k0..n-1
+  DevBuf rec;       // RecF64 / RecF32 / RecBF16 [n - k0][Na], RecAdv [n][Na]
+  DevBuf hv_t;      // double [n - k0][Na] (F32 / BF16 layouts)
   DevBuf kind;      // uint8 [N]: KIND_* bits (0: interior)
   DevBuf pibar;     // double [Na]
   double hv_coeff = 0.0, vel_period = 1.0;

@@ -684,7 +684,7 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.yn = sp.yn;
     a.out = sp.out;
     a.acc = m->acc.p;
-    a.idx_t = m->idx_t.as<int>();
+    a.idx_t = m->idx_t.as<int>() + m->k0 * m->Na;  // stream slot k is stencil slot k0 + k
     a.off16 = m->off16.as<int16_t>();
     a.aux32 = m->aux32.as<uint32_t>();
     a.rec = m->rec.p;
@@ -692,7 +692,7 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.kind = m->kind.as<uint8_t>();
     a.pibar = m->pibar.as<double>();
     a.Na = m->Na;
-    a.n = m->n;
+    a.n = m->n - m->k0;
     a.E = m->E;
     a.c_p = m->c_p;
     a.rcv = m->R_d / m->c_v;

@@ -297,6 +297,38 @@ def test_rhs_independent_of_node_order(R, ctx):
         assert torch.equal(outs[1][:na], outs[0][:na][order_t]), (fdt, wdt)
 
 
+def test_centre_slot_skip_is_exact(R, ctx):
+    """Centre-subtracted sums give the centre slot a zero term, so a model
+    whose stencils all start with their own node streams only the other
+    slots. Swapping the first two slots of one interior stencil makes the
+    model keep every slot (more bytes per node); the tendency is the same
+    bit for bit (FP64, FP32, BF16 weights)."""
+    import torch
+    say("rhs: centre slot left out of the stream vs kept, same tendency bit for bit")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", 400.0)
+    nd = cfg["nodes"]
+    assert (idx[:, 0] == np.arange(idx.shape[0])).all()
+    k = nd.n_active // 2
+    assert k not in set(nd.bnd_nodes.tolist())
+    idx2, W2 = idx.copy(), W.copy()
+    idx2[k, [0, 1]] = idx2[k, [1, 0]]
+    W2[:, k, [0, 1]] = W2[:, k, [1, 0]]
+    st = smooth_ns_state(nd, seed=21)
+    for fdt, wdt, dt in ((R.F64, R.F64, torch.float64), (R.F32, R.F32, torch.float32),
+                         (R.F32, R.BF16, torch.float32)):
+        outs, bpn = [], []
+        for ix, w in ((idx, W), (idx2, W2)):
+            m = gpu_ns(R, ctx, cfg, ix, w, Ww, fdt=fdt, wdt=wdt)
+            s = dev(st, dt).reshape(m.state_shape()).contiguous()
+            o = torch.empty_like(s)
+            R.rbffd_rhs(ctx, m, 0.0, s, o)
+            outs.append(o)
+            bpn.append(m.bytes_per_node())
+            m.close()
+        assert bpn[0] < bpn[1], (fdt, wdt, bpn)
+        assert torch.equal(outs[0], outs[1]), (fdt, wdt)
+
+
 def test_rhs_rest_state_is_zero(R, ctx):
     import torch
     say("rhs: hydrostatic rest gives exactly zero tendency (FP64 and FP32)")
