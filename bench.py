@@ -231,6 +231,39 @@ def fullrun_leg(R, P, ctx, cfg, idx, W, Ww, xy, t_end=900.0, chunk=1800):
     return out
 
 
+def device_peaks_leg(R, ctx):
+    """The device's practical ceilings beside the published peaks: a plain
+    streaming copy of 512 MiB (read + write bytes per second) and the
+    matrix-core probe (dense BF16 16x16x32 products on registers)."""
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    R.rbffd_stream_copy(ctx, dst, src)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(5):
+        R.rbffd_stream_copy(ctx, dst, src)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    del src, dst
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    out = torch.empty(1024 * n_cu, dtype=torch.float32, device="cuda")
+    res = dict(stream_copy_512MiB_gbs=copy_gbs, stream_copy_frac_of_peak=copy_gbs / HBM_PEAK_GBS)
+    for shape, name in ((0, "16x16x32"), (1, "32x32x16")):
+        R.rbffd_mfma_probe(ctx, out, 100, shape)
+        torch.cuda.synchronize()
+        ev0.record()
+        flops = R.rbffd_mfma_probe(ctx, out, 20000, shape)
+        ev1.record()
+        torch.cuda.synchronize()
+        tf = flops / (ev0.elapsed_time(ev1) / 1e3) / 1e12
+        res[f"mfma_bf16_{name}_tflops"] = tf
+        res[f"mfma_bf16_{name}_frac_of_peak"] = tf / BF16_MFMA_PEAK_TFLOPS
+    return res
+
+
 def closure_leg(R, ctx, calls=20, members=256):
     """Learned closure on its coarse grid (400 m Cartesian channel, 128 x 17
     nodes) for 256 members: 557,056 node-samples per fused forward call
@@ -471,6 +504,8 @@ def main():
         log(f"[bench] weights fp32+IR: {extras['weights_mixed_1M_fp32_ir']}")
         extras["closure_forward_256x2176"] = closure_leg(R, ctx)
         log(f"[bench] closure: {extras['closure_forward_256x2176']}")
+        extras["device_peaks"] = device_peaks_leg(R, ctx)
+        log(f"[bench] device peaks: {extras['device_peaks']}")
         extras["advection_64x64_fp64"] = advection_leg(R, P, ctx)
         log(f"[bench] advection: {extras['advection_64x64_fp64']}")
         extras["precision_fullrun_900s"] = fullrun_leg(R, P, ctx, cfg, idx, W, Ww, xy)

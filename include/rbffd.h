@@ -310,6 +310,17 @@ int rbffd_closure_step(rbffd_ctx *ctx, rbffd_closure *cl, void *state, double *t
  * memory counters can be calibrated against a kernel of known traffic. */
 int rbffd_stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes);
 
+/* Measurement helper: a matrix-core throughput probe. Every wavefront of
+ * 4 x (number of compute units) 256-thread blocks runs `iters` rounds of four
+ * independent BF16 matrix products on register operands (no memory
+ * traffic), of shape 16x16x32 (shape 0) or 32x32x16 (shape 1), so the
+ * launch's rate (timed by the caller on the context stream) is that shape's
+ * dense BF16 ceiling on this device. out: device, at least
+ * 1024 x (number of compute units) floats, one value per thread is written;
+ * *flops (host) receives the launch's flop count. RBFFD_EINVAL for another
+ * shape, a short out or iters < 1. */
+int rbffd_mfma_probe(rbffd_ctx *ctx, int shape, float *out, int64_t n_out, int iters, int64_t *flops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -242,4 +242,10 @@ int rbffd_stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes)
   return stream_copy(ctx, dst, src, bytes);
 }
 
+int rbffd_mfma_probe(rbffd_ctx *ctx, int shape, float *out, int64_t n_out, int iters, int64_t *flops) {
+  if (!ctx || !flops) return RBFFD_EINVAL;
+  RBFFD_ENTER(ctx);
+  return mfma_probe(ctx, shape, out, n_out, iters, flops);
+}
+
 }  // extern "C"

@@ -287,6 +287,40 @@ mlp_forward_kernel(
   }
 }
 
+// Matrix-core throughput probe: every wavefront runs `iters` rounds of four
+// independent BF16 products on register operands (no memory traffic), of
+// shape 16x16x32 (SHAPE 0) or 32x32x16 (SHAPE 1); each lane stores one sum so
+// that none of them is dead.
+template <int SHAPE> __global__ __launch_bounds__(256) void mfma_probe_kernel(float *__restrict__ out, int iters) {
+  typedef __attribute__((ext_vector_type(16))) float f16v;
+  const int tid = threadIdx.x;
+  bf8v a, b;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    a[q] = static_cast<__bf16>(1.0f + 0.001f * static_cast<float>((tid + q) & 7));
+    b[q] = static_cast<__bf16>(0.5f - 0.001f * static_cast<float>((tid * 3 + q) & 7));
+  }
+  float v = 0.0f;
+  if constexpr (SHAPE == 0) {
+    f4v acc[4] = {};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[u], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v += acc[u][0] + acc[u][1] + acc[u][2] + acc[u][3];
+  } else {
+    f16v acc[4] = {};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[u], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v += acc[u][0] + acc[u][5] + acc[u][10] + acc[u][15];
+  }
+  out[static_cast<int64_t>(blockIdx.x) * 256 + tid] = v;
+}
+
 // Input features, one thread per (sample, 4-value group): slot 0 = own
 // fields, slots 1..36 = differences, group 37 = node value + zeros, 38..39 = 0.
 __global__ void features_kernel(const float *__restrict__ y, const int *__restrict__ idx_t, int64_t Na, int n, int E,
@@ -720,5 +754,22 @@ int closure_step(rbffd_ctx *ctx, rbffd_closure *cl, void *state, double *t, doub
     }
   }
   if (n_fallback) *n_fallback = fb;
+  return RBFFD_OK;
+}
+
+// Launch the matrix-core probe: four 256-thread blocks per compute unit.
+int mfma_probe(rbffd_ctx *ctx, int shape, float *out, int64_t n_out, int iters, int64_t *flops) {
+  const int64_t blocks = 4 * static_cast<int64_t>(ctx->n_cu);
+  if (!out || iters < 1 || (shape != 0 && shape != 1) || n_out < blocks * 256)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "mfma probe: needs shape 0 or 1, iters >= 1 and %lld output floats",
+                      static_cast<long long>(blocks * 256));
+  if (shape == 0)
+    mfma_probe_kernel<0><<<static_cast<unsigned>(blocks), 256, 0, ctx->stream>>>(out, iters);
+  else
+    mfma_probe_kernel<1><<<static_cast<unsigned>(blocks), 256, 0, ctx->stream>>>(out, iters);
+  RBFFD_HIP(ctx, hipGetLastError());
+  // 4 wavefronts per block, 4 products per round of 16 x 16 x 32 or 32 x 32 x 16 multiply-adds
+  const int64_t per = shape == 0 ? 2 * 16 * 16 * 32 : 2 * 32 * 32 * 16;
+  *flops = blocks * 4 * static_cast<int64_t>(iters) * 4 * per;
   return RBFFD_OK;
 }

@@ -81,6 +81,7 @@ int model_profile(rbffd_model *m, int enable);
 int model_profile_read(rbffd_model *m, double *total_ms, int64_t *launches);
 int stream_copy(rbffd_ctx *ctx, void *dst, const void *src, int64_t bytes);
 int model_tune(rbffd_ctx *ctx, rbffd_model *m, void *state, int *chosen, double *best_us);
+int mfma_probe(rbffd_ctx *ctx, int shape, float *out, int64_t n_out, int iters, int64_t *flops);
 int closure_create(rbffd_ctx *ctx, rbffd_model *m, const rbffd_closure_desc *d, rbffd_closure **out);
 int closure_destroy(rbffd_closure *cl);
 float *closure_params(rbffd_closure *cl);

@@ -68,6 +68,7 @@ _lib.rbffd_model_bytes_per_node.restype = _i64
 _lib.rbffd_model_profile.argtypes = [_vp, ctypes.c_int]
 _lib.rbffd_model_profile_read.argtypes = [_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
 _lib.rbffd_stream_copy.argtypes = [_vp, _vp, _vp, _i64]
+_lib.rbffd_mfma_probe.argtypes = [_vp, ctypes.c_int, _vp, _i64, ctypes.c_int, ctypes.POINTER(_i64)]
 _lib.rbffd_model_tune.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_f64)]
 
 
@@ -92,7 +93,7 @@ _lib.rbffd_closure_step.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_f64), _f64, _
 EXPORTS = ["rbffd_create", "rbffd_destroy", "rbffd_last_error", "rbffd_sync", "rbffd_knn",
            "rbffd_weights", "rbffd_model_create", "rbffd_model_destroy", "rbffd_ghost",
            "rbffd_rhs", "rbffd_step", "rbffd_model_bytes_per_node", "rbffd_model_profile",
-           "rbffd_model_profile_read", "rbffd_stream_copy", "rbffd_model_tune", "rbffd_closure_create",
+           "rbffd_model_profile_read", "rbffd_stream_copy", "rbffd_mfma_probe", "rbffd_model_tune", "rbffd_closure_create",
            "rbffd_closure_destroy", "rbffd_closure_params", "rbffd_closure_forward", "rbffd_closure_gradient",
            "rbffd_closure_train_step", "rbffd_closure_step"]
 
@@ -288,6 +289,17 @@ def rbffd_stream_copy(ctx: Context, dst, src):
     if dst.numel() * dst.element_size() != nb:
         raise ValueError("size mismatch")
     ctx.check(_lib.rbffd_stream_copy(ctx.h, dst.data_ptr(), src.data_ptr(), nb))
+
+
+def rbffd_mfma_probe(ctx: Context, out, iters, shape=1):
+    """Matrix-core throughput probe (shape 0: 16x16x32, 1: 32x32x16 BF16
+    products) into `out` (float32 device tensor of at least 1024 x CUs
+    values); returns the launch's flop count."""
+    if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()):
+        raise ValueError("contiguous float32 device tensor required")
+    fl = _i64(0)
+    ctx.check(_lib.rbffd_mfma_probe(ctx.h, int(shape), out.data_ptr(), out.numel(), int(iters), ctypes.byref(fl)))
+    return fl.value
 
 
 def rbffd_step(ctx: Context, model: Model, state, t, dt, n_steps, tableau=RK4):

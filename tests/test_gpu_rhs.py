@@ -531,3 +531,24 @@ def test_tuned_shape_gives_identical_results(R, ctx, fdt, wdt):
     s1 = s.clone()
     R.rbffd_step(ctx, gm, s1, 0.0, cfg["dt"], 3, R.RK4)     # graph recaptured with the new shape
     assert torch.isfinite(s1).all()
+
+
+def test_measurement_helpers(R, ctx):
+    """The streaming copy copies; the matrix-core probe rejects a short
+    output, writes a finite value per thread and reports its flop count."""
+    import torch
+    say("measurement helpers: stream copy and matrix-core probe")
+    src = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    R.rbffd_stream_copy(ctx, dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    with pytest.raises(R.RbffdError):
+        R.rbffd_mfma_probe(ctx, torch.empty(16, dtype=torch.float32, device="cuda"), 1)
+    for shape in (0, 1):
+        out = torch.full((1024 * n_cu,), float("nan"), dtype=torch.float32, device="cuda")
+        flops = R.rbffd_mfma_probe(ctx, out, 10, shape)
+        torch.cuda.synchronize()
+        assert flops == 4 * n_cu * 4 * 10 * 4 * 2 * 16 * 16 * 32 * (1 if shape == 0 else 2)
+        assert bool(torch.isfinite(out).all())
