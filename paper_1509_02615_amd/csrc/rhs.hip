@@ -339,9 +339,28 @@ struct GArgs {
   double bc_scale, theta_bar;  // dpi/dz = bc_scale * th / (theta_bar + th) on walls normal to z
 };
 
+// Sum over the wavefront (full exec mask), returned in every lane: adds of
+// data-parallel moves within rows of 16 lanes (quad permutes, half-mirror,
+// mirror), then the row broadcasts 15 and 31 carry the row sums to lane 63,
+// which is read back. A few cycles per step, against a cross-lane permute
+// through the LDS unit per step and half; one fixed order for every caller.
+template <int CTRL, int ROWS> __device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWS, 0xF, false);
+  return v + __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v = dpp_add<0xB1, 0xF>(v);   // quad_perm 1,0,3,2
+  v = dpp_add<0x4E, 0xF>(v);   // quad_perm 2,3,0,1
+  v = dpp_add<0x141, 0xF>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xF>(v);  // row_mirror: every lane holds its row's sum
+  v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), 63);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), 63);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
 
 // One stencil slot's contribution to the residuals of a boundary row with
