@@ -140,12 +140,14 @@ def weights_leg(R, ctx, cfg, precision):
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
-    bad = int((status != 0).sum().item())
+    bad = int(((status == 1) | (status == 2)).sum().item())
+    fallback = int((status == 3).sum().item())   # solved again in FP64 (FP32 factorisation only)
     # algorithmic flops of the solves: LU of K x K (2/3 K^3) and the forward and
     # back substitution of the 3 right-hand sides (2 K^2 each); K = n + M
     K = cfg["n_per"].astype(np.float64) + (cfg["l_per"] + 1) * (cfg["l_per"] + 2) / 2
     flops = float(np.sum(2.0 / 3.0 * K ** 3 + 2.0 * K ** 2 * 3))
     return dict(stencils=nd.n_active, ms=ms, stencils_per_s=nd.n_active / (ms / 1e3), singular=bad,
+                fp64_fallback=fallback,
                 solve_tflops=flops / (ms / 1e3) / 1e12,
                 fp64_peak_frac=flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
                 note="solve flops only (2/3 K^3 + 2 K^2 per right-hand side); assembly and "

@@ -131,7 +131,9 @@ int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx);
  *          1e-13 max|A|, or refinement did not converge: it stops when the
  *          error left after a correction d, estimated as |d|^2 / |d_prev|
  *          from the contraction of successive corrections, is below
- *          2^-52 |x|, or when |d| <= 2^-48 |x|).
+ *          2^-52 |x|, or when |d| <= 2^-48 |x|), 3 ok after an FP64 solve
+ *          (RBFFD_SOLVE_FP32_IR only: stencils whose FP32-factorisation
+ *          refinement stalls are solved again with the FP64 factorisation).
  * Returns RBFFD_ESINGULAR (after writing everything) when any status is 1;
  * synchronises to read the status count. EINVAL: even m, l > 6, n_c < M,
  * K = n_c + M > 128, Laplacian^k with m < 2k+1, n_ops outside 1..8. */

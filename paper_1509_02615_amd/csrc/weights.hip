@@ -1272,6 +1272,26 @@ __global__ void ksize_kernel(const int *n_per, int n_max, const int *l_per, int 
   atomicMax(kmax, n + n_terms(l));
 }
 
+// Stencils whose FP32-factorisation refinement stalled (status 1), for an
+// FP64 solve: systems of up to 64 unknowns from the front of `list`, larger
+// ones from the back; counts[0] and counts[1] count them.
+__global__ void stalled_list_kernel(const int *status, const int *n_per, int n_max, const int *l_per, int l_uni,
+                                    int nc, int *list, int *counts) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc || status[q] != 1) return;
+  const int K = (n_per ? n_per[q] : n_max) + n_terms(l_per ? l_per[q] : l_uni);
+  if (K <= 64)
+    list[atomicAdd(&counts[0], 1)] = q;
+  else
+    list[nc - 1 - atomicAdd(&counts[1], 1)] = q;
+}
+
+// Listed stencils that the FP64 solve did solve: status 3.
+__global__ void mark_fallback_kernel(int *status, const int *list, int count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count && status[list[t]] == 0) status[list[t]] = 3;
+}
+
 __global__ void count_status_kernel(const int *status, int nc, int *counts) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nc) return;
@@ -1375,6 +1395,43 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
     }
   }
   RBFFD_HIP(ctx, hipGetLastError());
+  // FP32 factorisation: the stencils whose refinement stalled are solved
+  // again in FP64 (the same kernels, over a list of them) and marked 3
+  if (precision == RBFFD_SOLVE_FP32_IR) {
+    DevBuf d_fl;
+    RBFFD_HIP(ctx, d_fl.alloc(sizeof(int) * nc));
+    RBFFD_HIP(ctx, hipMemsetAsync(d_k.p, 0, 4 * sizeof(int), s));
+    stalled_list_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
+                                                          d_fl.as<int>(), d_k.as<int>());
+    RBFFD_HIP(ctx, hipGetLastError());
+    int hc[2];
+    RBFFD_HIP(ctx, hipMemcpyAsync(hc, d_k.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+    RBFFD_HIP(ctx, hipStreamSynchronize(s));
+    if (hc[0] + hc[1] > 0) {
+      WArgs f = a;
+      f.max_iter = 3;  // the FP64 setting
+      if (hc[0] > 0) {
+        f.list = d_fl.as<int>();
+        f.k_cap = 64;
+        weights_wave_kernel<64, double><<<hc[0], 64, 0, s>>>(f);
+      }
+      if (hc[1] > 0) {
+        f.list = d_fl.as<int>() + nc - hc[1];
+        f.k_cap = kc;
+        const size_t lds = sizeof(double) * (2 * static_cast<size_t>(n_ops) * kc + 4 * static_cast<size_t>(kc)) +
+                           sizeof(double) * static_cast<size_t>(kc) * (kc + n_ops);
+        if (lds > 156 * 1024) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d too large for LDS", kc);
+        RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<double>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+        weights_kernel<double><<<hc[1], W_THREADS, lds, s>>>(f);
+      }
+      RBFFD_HIP(ctx, hipGetLastError());
+      if (hc[0] > 0) mark_fallback_kernel<<<grid_for(hc[0], 256), 256, 0, s>>>(st_out, d_fl.as<int>(), hc[0]);
+      if (hc[1] > 0)
+        mark_fallback_kernel<<<grid_for(hc[1], 256), 256, 0, s>>>(st_out, d_fl.as<int>() + nc - hc[1], hc[1]);
+      RBFFD_HIP(ctx, hipGetLastError());
+    }
+  }
   RBFFD_HIP(ctx, hipMemsetAsync(d_k.p, 0, 4 * sizeof(int), s));
   count_status_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, nc, d_k.as<int>());
   RBFFD_HIP(ctx, hipGetLastError());

@@ -104,7 +104,8 @@ def _weights_parity(R, ctx, xy, ops_o, n, m, l, period, centers, sample=None, n_
         m_per=None if m_per is None else dev(m_per, torch.int32),
         l_per=None if l_per is None else dev(l_per, torch.int32), precision=precision)
     idx, W, status = host(idx), host(W), host(status)
-    assert rc == R.OK and np.all(status == 0)
+    # 3: solved again in FP64 after the FP32 factorisation's refinement stalled
+    assert rc == R.OK and np.all((status == 0) | ((status == 3) & (precision == 1)))
     cs = range(len(centers)) if sample is None else sample
     worst = 0.0
     for a in cs:
@@ -234,6 +235,49 @@ def test_weights_reproduce_polynomials(R, ctx):
             for o, (kind, k, _) in enumerate(ops):
                 exact = O.poly_apply(kind, 3 if kind == O.HYPERLAP else k, a, b)
                 assert abs(W[o, c] @ vals - exact) <= 1e-10 * (np.abs(W[o, c] * vals).sum() + abs(exact))
+
+
+def test_fp32_factorisation_falls_back_to_fp64(R, ctx):
+    """Ill-conditioned systems (r^13, degree 6, n = 34 on a jittered 8 x 8
+    lattice squeezed 5x in z: condition numbers around 1e9, far beyond what
+    FP32 refinement can handle) under the FP32 factorisation: the stencils
+    whose refinement stalls are solved again in FP64 and marked 3. Their
+    weights equal the FP64 run's bit for bit, and every stencil matches the
+    oracle."""
+    import torch
+    say("weights: FP32 factorisation falls back to FP64 where its refinement stalls (cond ~1e9)")
+    rng = np.random.default_rng(5)
+    g, sq = 8, 0.2
+    X, Z = np.meshgrid(np.arange(g), np.arange(g))
+    xy = np.stack([X.ravel(), Z.ravel() * sq], 1).astype(np.float64)
+    xy += rng.uniform(-0.2, 0.2, xy.shape) * np.array([1.0, sq])
+    centers = np.arange(g * g, dtype=np.int32)
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0)]
+    runs = {}
+    for prec in (0, 1):
+        idx, W, status, rc = R.rbffd_weights(ctx, dev(xy, torch.float64), ops, 34, 13, 6,
+                                             centers=dev(centers, torch.int32), precision=prec)
+        runs[prec] = (host(idx), host(W), host(status), rc)
+    idx, W64, s64, rc64 = runs[0]
+    _, W32, s32, rc32 = runs[1]
+    assert rc64 == R.OK and np.all(s64 == 0)
+    assert rc32 == R.OK and np.all((s32 == 0) | (s32 == 3))
+    fell = np.flatnonzero(s32 == 3)
+    say(f"   {len(fell)} of {len(centers)} stencils solved again in FP64")
+    assert len(fell) > 0
+    assert np.array_equal(W32[:, fell], W64[:, fell])
+    worst = 0.0
+    for a, c in enumerate(centers):
+        st = O.knn(xy, [int(c)], 34, 0.0)[0]
+        assert np.array_equal(idx[a], st)
+        Wo, so = O.stencil_weights(xy, st, int(c), 13, 6, ops, 0.0)
+        assert so == 0
+        for W in (W64, W32):
+            for o in range(len(ops)):
+                err = np.linalg.norm(W[o, a] - Wo[o]) / np.linalg.norm(Wo[o])
+                worst = max(worst, err)
+                assert err <= TOL_W, (a, o, err)
+    say(f"   worst norm-wise relative weight error {worst:.2e}")
 
 
 def test_weights_singular_and_invalid(R, ctx):
