@@ -431,6 +431,21 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
     if (m->mirror_src.alloc(sizeof(int) * ng) != hipSuccess) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation");
     if (hipMemcpy(m->mirror_src.p, h_src.data(), sizeof(int) * ng, hipMemcpyHostToDevice) != hipSuccess)
       return fail_model(ctx, m, RBFFD_EDEVICE, "mirror source upload");
+    // the same map from the sources' side, so that a stage can write each
+    // updated value into its ghosts as well
+    std::vector<int> h_off(static_cast<size_t>(na) + 1, 0), h_list(static_cast<size_t>(ng));
+    for (int v : h_src) ++h_off[static_cast<size_t>(v) + 1];
+    for (int64_t i = 0; i < na; ++i) h_off[i + 1] += h_off[i];
+    {
+      std::vector<int> fill(h_off.begin(), h_off.end() - 1);
+      for (int64_t k = 0; k < ng; ++k) h_list[fill[h_src[k]]++] = static_cast<int>(k);
+    }
+    if (m->mirror_off.alloc(sizeof(int) * h_off.size()) != hipSuccess ||
+        m->mirror_list.alloc(sizeof(int) * h_list.size()) != hipSuccess)
+      return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation");
+    if (hipMemcpy(m->mirror_off.p, h_off.data(), sizeof(int) * h_off.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->mirror_list.p, h_list.data(), sizeof(int) * h_list.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return fail_model(ctx, m, RBFFD_EDEVICE, "mirror source upload");
     m->n_mirror = ng;
   }
 

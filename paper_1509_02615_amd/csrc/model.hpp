@@ -72,6 +72,7 @@ struct rbffd_model {
   // transport mirror ghosts
   int64_t n_mirror = 0;
   DevBuf mirror_src;               // int32 [N - Na]
+  DevBuf mirror_off, mirror_list;  // per active node, its ghosts k (node Na + k): list[off[i] .. off[i+1])
   // time stepping
   DevBuf ya, yb, acc;              // [N][E][F] stage buffers
   DevBuf dev_misc;                 // {int nonfinite_step, int step_ctr, double t0}

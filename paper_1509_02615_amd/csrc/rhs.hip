@@ -284,6 +284,7 @@ struct AdvArgs {
   int mode, acc_mode;
   DevMisc *misc;
   int check;
+  const int *mir_off, *mir_list;  // stage updates: also write each node's mirror ghosts (or null)
 };
 
 template <class FT>
@@ -321,6 +322,10 @@ __global__ __launch_bounds__(RHS_BLOCK) void adv_stage_kernel(AdvArgs a) {
     }
   }
   static_cast<FT *>(a.out)[o] = static_cast<FT>(r);
+  if (a.mir_off) {  // the value the mirror boundary would copy into this node's ghosts
+    for (int g = a.mir_off[i]; g < a.mir_off[i + 1]; ++g)
+      static_cast<FT *>(a.out)[(Na + a.mir_list[g]) * E + e] = static_cast<FT>(r);
+  }
   if (a.check && !isfinite(r)) atomicMin(&a.misc->nonfinite_step, a.misc->step_ctr);
 }
 
@@ -756,6 +761,10 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.acc_mode = sp.acc_mode;
     a.misc = use_misc ? misc : nullptr;
     a.check = sp.check;
+    if (sp.mode != 0 && m->n_mirror > 0) {
+      a.mir_off = m->mirror_off.as<int>();
+      a.mir_list = m->mirror_list.as<int>();
+    }
     if (m->fdt == RBFFD_F64)
       adv_stage_kernel<double><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(a);
     else
@@ -772,6 +781,13 @@ __global__ void zero_rows_kernel(void *p, int64_t first_byte, int64_t n_bytes) {
   if (t < n_bytes / 4) static_cast<uint32_t *>(p)[first_byte / 4 + t] = 0u;
 }
 
+// Whether a stage's input needs the boundary launch first: always for the
+// Navier-Stokes closure; for transport only the step's input, since every
+// stage update writes its mirror ghosts itself.
+bool needs_ghost(const rbffd_model *m, const StageSpec &sp, const void *y) {
+  return m->physics != RBFFD_PHYS_ADVECTION || sp.ys == y;
+}
+
 // One full time step, as a sequence of launches on the context stream.
 int enqueue_step(rbffd_ctx *ctx, rbffd_model *m, void *y, double dt, int tableau) {
   int rc;
@@ -784,7 +800,7 @@ int enqueue_step(rbffd_ctx *ctx, rbffd_model *m, void *y, double dt, int tableau
         {ya, nullptr, y, dt / 6.0, 0.0, dt, 2, 0, 1},
     };
     for (const StageSpec &sp : st) {
-      if ((rc = launch_ghost(ctx, m, const_cast<void *>(sp.ys)))) return rc;
+      if (needs_ghost(m, sp, y) && (rc = launch_ghost(ctx, m, const_cast<void *>(sp.ys)))) return rc;
       if ((rc = launch_stage(ctx, m, sp, 0.0, true, dt))) return rc;
     }
   } else {
@@ -794,7 +810,7 @@ int enqueue_step(rbffd_ctx *ctx, rbffd_model *m, void *y, double dt, int tableau
         {yb, y, y, dt, 0.0, dt / 2.0, 1, 0, 1},
     };
     for (const StageSpec &sp : st) {
-      if ((rc = launch_ghost(ctx, m, const_cast<void *>(sp.ys)))) return rc;
+      if (needs_ghost(m, sp, y) && (rc = launch_ghost(ctx, m, const_cast<void *>(sp.ys)))) return rc;
       if ((rc = launch_stage(ctx, m, sp, 0.0, true, dt))) return rc;
     }
   }
