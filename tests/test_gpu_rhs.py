@@ -481,7 +481,9 @@ def test_step_reports_nonfinite(R, ctx):
 def test_full_size_scale_rhs_sampled(R, ctx):
     """2048 x 256 hexagonal channel (524,288 nodes): the whole GPU path
     (search, weights, closure, fused RHS) against the oracle evaluated
-    node by node at sampled nodes away from the walls."""
+    node by node at sampled nodes away from the walls, in FP64, FP32 and
+    with BF16 weights, each in the launch shape the tuner picks (as the
+    benchmark runs it)."""
     import torch
     from paper_1509_02615_amd import pipeline as P
     say("full size: 2048x256 channel, GPU search+weights+rhs, 160 sampled nodes, FP64 and FP32")
@@ -498,14 +500,17 @@ def test_full_size_scale_rhs_sampled(R, ctx):
     ref = O.ns_tendency(state, rows, o_idx, o_W[0], o_W[1], o_W[2], o_W[3], nd.xy[rows, 1],
                         np.zeros(len(rows), bool), cfg["consts"], cfg["hv_coeff"])
     assert np.array_equal(idx[torch.from_numpy(rows).cuda()].cpu().numpy(), o_idx)
-    for fdt, wdt, dt, tol in ((0, 0, torch.float64, 1e-12), (1, 1, torch.float32, 1e-6)):
+    for fdt, wdt, dt, tol in ((0, 0, torch.float64, 1e-12), (1, 1, torch.float32, 1e-6),
+                              (1, 2, torch.float32, 1e-2)):
         gm = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
         s = dev(state, dt).reshape(gm.state_shape()).contiguous()
         out = torch.empty_like(s)
+        shape, _ = R.rbffd_model_tune(ctx, gm, s)
         R.rbffd_rhs(ctx, gm, 0.0, s, out)
         got = host(out).reshape(-1, 4)[rows]
         errs = [np.linalg.norm(got[:, f] - ref[:, f]) / np.linalg.norm(ref[:, f]) for f in range(4)]
-        say(f"   field dtype {fdt}: rel-l2 per field over samples {['%.2e' % e for e in errs]}")
+        say(f"   field dtype {fdt}, weight dtype {wdt}, shape {shape}: rel-l2 per field over samples "
+            f"{['%.2e' % e for e in errs]}")
         assert max(errs) <= tol
 
 
