@@ -557,3 +557,41 @@ def test_measurement_helpers(R, ctx):
         torch.cuda.synchronize()
         assert flops == 4 * n_cu * 4 * 10 * 4 * 2 * 16 * 16 * 32 * (1 if shape == 0 else 2)
         assert bool(torch.isfinite(out).all())
+
+
+def test_full_size_ghost_closure_holds_the_wall_conditions(R, ctx):
+    """2048 x 256 channel (2 x 2,048 wall rows): after the ghost closure
+    every wall row's own conditions hold to rounding with the model's wall
+    weights (Section 5.2: the ghost values are what makes them hold):
+    du/dz = dtheta'/dz = 0, dpi'/dz = g theta'_B / (c_p theta_bar (theta_bar +
+    theta'_B)), w_B = 0 and d2w/dz2 = 0. A property that holds at any size:
+    it checks the windowed W_G^-1 solve on the full walls, FP64 and FP32."""
+    import torch
+    from paper_1509_02615_amd import pipeline as P
+    say("full size: ghost closure on 2 x 2048 wall rows, wall conditions to rounding (FP64, FP32)")
+    cfg = scale_config()
+    nd = cfg["nodes"]
+    c = cfg["consts"]
+    xy, idx, W, Ww, _ = P.ns_weights(ctx, cfg)
+    n = idx.shape[1]
+    rows = nd.bnd_nodes
+    assert np.all(nd.bnd_normal == 0)  # channel: both walls normal to z
+    I = idx.cpu().numpy()[rows]                           # the wall rows' stencils (ghosts included)
+    D = host(Ww).reshape(2, -1, n)                        # Dz and Dzz weights of the wall rows
+    base = smooth_ns_state(nd, seed=7)
+    for fdt, dt, tol in ((R.F64, torch.float64, 1e-12), (R.F32, torch.float32, 1e-5)):
+        gm = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=fdt)
+        s = dev(base, dt).reshape(gm.state_shape()).contiguous()
+        R.rbffd_ghost(ctx, gm, s)
+        y = host(s).reshape(-1, 4).astype(np.float64)
+        assert np.all(y[rows, 1] == 0.0)                  # w on the walls
+        thb = y[rows, 2]
+        bc = c["g"] * thb / (c["c_p"] * c["theta_bar"] * (c["theta_bar"] + thb))
+        worst = 0.0
+        for f, d, target in ((0, D[0], 0.0), (1, D[1], 0.0), (2, D[0], 0.0), (3, D[0], bc)):
+            terms = d * y[I, f]
+            r = np.abs(terms.sum(1) - target) / (np.abs(terms).sum(1) + np.abs(target))
+            worst = max(worst, float(r.max()))
+            assert r.max() <= tol, (fdt, f, float(r.max()))
+        say(f"   field dtype {fdt}: worst relative wall-condition residual {worst:.2e}")
+        gm.close()
