@@ -64,6 +64,9 @@ struct WArgs {
   int k_cap;
   int max_iter;
   const int *list;  // stencils of this launch (NULL: blockIdx.x itself)
+  int n_list;       // two systems per wavefront: stencils in the launch
+  int *defer;       // two systems per wavefront: stencils left to the one-system kernel
+  int *n_defer;     // their count
 };
 
 __device__ __forceinline__ int n_terms(int l) { return (l + 1) * (l + 2) / 2; }
@@ -804,6 +807,44 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   return static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
 }
 
+// Maxima over the lanes of each system when a wavefront holds H systems
+// (lanes [h 64/H, (h + 1) 64/H)); every lane receives its group's value.
+template <int H> __device__ __forceinline__ double group_max(double v) {
+  for (int off = 32 / H; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Largest key of each group with the full exec mask: the same data-parallel
+// steps as wave_max_u32; after the row broadcast 15, lane 31 holds the
+// maximum of lanes 0-31 and lane 63 that of lanes 32-63.
+template <int H> __device__ __forceinline__ void group_max_key(unsigned v, unsigned &k0, unsigned &k1) {
+  if constexpr (H == 1) {
+    k0 = k1 = wave_max_u32(v);
+  } else {
+    auto step = [&](auto ctrl, auto rows) {
+      const unsigned o = static_cast<unsigned>(
+          __builtin_amdgcn_update_dpp(static_cast<int>(v), static_cast<int>(v), decltype(ctrl)::value,
+                                      decltype(rows)::value, 0xF, false));
+      v = max(v, o);
+    };
+    step(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});
+    step(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});
+    step(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});
+    step(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});
+    step(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});
+    k0 = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 31));
+    k1 = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
+  }
+}
+
+// Value of lane l of the own group (l wave-uniform; l0 for group 0 and l1
+// for group 1 when they differ).
+template <int H, typename V> __device__ __forceinline__ V group_rl(V v, int l0, int l1, int h) {
+  if constexpr (H == 1) return rl(v, l0);
+  const V a = rl(v, l0), b = rl(v, 32 + l1);
+  return h ? b : a;
+}
+
 // One matrix row in registers, in 16-element vector chunks: static indices
 // address registers directly, and a wave-uniform dynamic index k compiles to
 // indexed register moves (s_set_gpr_idx_on) into chunk k / 16.
@@ -872,15 +913,23 @@ struct WaveCtx {
 };
 
 // Solve for the G right-hand sides of operators S.gl[g0 ..], then refine
-// with double-double residuals until the stopping rule holds. Lane k ends
-// with unknown k in x[g].
-template <int KC, int G, typename T>
+// with double-double residuals until the stopping rule holds. Lane k of a
+// system's lanes ends with unknown k in x[g]. With two systems per
+// wavefront (H = 2, group h), a system that has converged keeps its
+// solution while the other one refines.
+template <int KC, int G, typename T, int H>
 __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S, const WaveRows<KC, T> R,
-                                            const WaveCtx &c, int g0, double (&x)[4], bool &converged) {
+                                            const WaveCtx &c, int g0, double (&x)[4], bool &converged, int h) {
   const int lane = c.lane, n = c.n, K = c.K, P = c.P;
   const double own[4] = {c.ex.hi, c.ex.lo, c.ez.hi, c.ez.lo};
   double dprev = 0.0;  // previous correction (the plain solution after the first pass)
-  for (int it = 0; it <= a.max_iter && !converged; ++it) {
+  for (int it = 0; it <= a.max_iter; ++it) {
+    if constexpr (H == 1) {
+      if (converged) break;
+    } else {
+      if (__ballot(!converged) == 0) break;
+    }
+    const bool live = !converged;
     // residual b - A x in double-double, rounded to FP64 (b alone when x = 0)
     dd acc[G] = {};
     if (it > 0) {
@@ -927,36 +976,38 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
     }
     // forward substitution L y = P v: rows not yet pivot at step k
     for (int k = 0; k < K; ++k) {
-      const int p = __builtin_amdgcn_readlane(R.pv, k);
-      const double r = rl(R.rpv, k);
+      const int p0 = __builtin_amdgcn_readlane(R.pv, k), p1 = H == 1 ? p0 : __builtin_amdgcn_readlane(R.pv, 32 + k);
+      const double r = group_rl<H>(R.rpv, k, k, h);
       const double lk = R.mystep > k ? static_cast<double>(pick4<KC>(R.c0, R.c1, R.c2, R.c3, k)) : 0.0;
 #pragma unroll
-      for (int g = 0; g < G; ++g) v[g] = fma(-lk, rl(v[g], p) * r, v[g]);
+      for (int g = 0; g < G; ++g) v[g] = fma(-lk, group_rl<H>(v[g], p0, p1, h) * r, v[g]);
     }
     // back substitution U d = y: rows pivoted before step k
     for (int k = K - 1; k >= 0; --k) {
-      const int p = __builtin_amdgcn_readlane(R.pv, k);
-      const double r = rl(R.rpv, k);
+      const int p0 = __builtin_amdgcn_readlane(R.pv, k), p1 = H == 1 ? p0 : __builtin_amdgcn_readlane(R.pv, 32 + k);
+      const double r = group_rl<H>(R.rpv, k, k, h);
       const double uk = R.mystep < k ? static_cast<double>(pick4<KC>(R.c0, R.c1, R.c2, R.c3, k)) : 0.0;
 #pragma unroll
-      for (int g = 0; g < G; ++g) v[g] = fma(-uk, rl(v[g], p) * r, v[g]);
+      for (int g = 0; g < G; ++g) v[g] = fma(-uk, group_rl<H>(v[g], p0, p1, h) * r, v[g]);
     }
     // lane p_k holds y_k, so d_k = v * rdg there; lane k takes it
     double dm = 0.0, xm = 0.0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const double dk = __shfl(v[g] * R.rdg, R.pv, 64);
-      const double d = lane < K ? dk : 0.0;
+      const double dk = __shfl(v[g] * R.rdg, R.pv + (64 / H) * h, 64);
+      const double d = lane < K && live ? dk : 0.0;
       x[g] += d;
       dm = fmax(dm, fabs(d));
       xm = fmax(xm, fabs(x[g]));
       if (lane < K) S.xs[lane][g] = x[g];
     }
     wave_sync_lds();
-    dm = wave_max(dm);
-    xm = wave_max(xm);
-    converged = it == 0 ? dm <= 0x1p-48 * xm : refined(dm, xm, dprev);
-    dprev = dm;
+    dm = group_max<H>(dm);
+    xm = group_max<H>(xm);
+    if (live) {
+      converged = it == 0 ? dm <= 0x1p-48 * xm : refined(dm, xm, dprev);
+      dprev = dm;
+    }
   }
 }
 
@@ -974,28 +1025,68 @@ template <int KC> constexpr int wave_occ() {
   return KC > 48 ? RBFFD_WAVE_OCC64 : KC > 32 ? RBFFD_WAVE_OCC48 : RBFFD_WAVE_OCC32;
 }
 
-template <int KC, typename T>
+// Stencils q and r have the same n, m and l (hence the same system shape).
+__device__ __forceinline__ bool same_shape(const WArgs &a, int q, int r) {
+  return (!a.n_per || a.n_per[q] == a.n_per[r]) && (!a.m_per || a.m_per[q] == a.m_per[r]) &&
+         (!a.l_per || a.l_per[q] == a.l_per[r]);
+}
+
+// H systems per wavefront: H = 1, or H = 2 for systems of up to 32 unknowns
+// (lanes 0-31 and 32-63). The two systems of a wavefront have the same n, m
+// and l, so every loop bound and branch on them stays wave-uniform; a
+// second stencil of another shape, and a pair with an invalid or degenerate
+// stencil, go to a.defer for the one-system kernel.
+template <int KC, typename T, int H = 1>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>()))) void weights_wave_kernel(
     WArgs a) {
-  static_assert(KC % 8 == 0 && KC <= 64, "capacity in chunks of 8, one row per lane");
-  __shared__ WaveShared<KC, T> S;
-  const int lane = threadIdx.x;
-  // per-stencil parameters are wave-uniform: kept in scalar registers
-  const int q = __builtin_amdgcn_readfirstlane(a.list ? a.list[blockIdx.x] : static_cast<int>(blockIdx.x));
-  const int c = __builtin_amdgcn_readfirstlane(a.centers ? a.centers[q] : q);
-  const int n = __builtin_amdgcn_readfirstlane(a.n_per ? a.n_per[q] : a.n_max);
-  const int m = __builtin_amdgcn_readfirstlane(a.m_per ? a.m_per[q] : a.m_uni);
-  const int l = __builtin_amdgcn_readfirstlane(a.l_per ? a.l_per[q] : a.l_uni);
+  static_assert(KC % 8 == 0 && KC <= 64 / H && (H == 1 || H == 2), "capacity in chunks of 8, one row per lane");
+  constexpr int L = 64 / H;  // lanes per system
+  __shared__ WaveShared<KC, T> SS[H];
+  const int h = H == 1 ? 0 : static_cast<int>(threadIdx.x) / L;  // the lane's system
+  const int lane = static_cast<int>(threadIdx.x) % L;             // the matrix row it holds
+  WaveShared<KC, T> &S = SS[h];
+  // per-stencil parameters: n, m and l are wave-uniform (scalar registers)
+  int q, q0;
+  bool writer = true;  // this lane's system writes results (not a stand-in copy)
+  if constexpr (H == 1) {
+    q = __builtin_amdgcn_readfirstlane(a.list ? a.list[blockIdx.x] : static_cast<int>(blockIdx.x));
+    q0 = q;
+  } else {
+    const int i0 = 2 * static_cast<int>(blockIdx.x);
+    q0 = __builtin_amdgcn_readfirstlane(a.list ? a.list[i0] : i0);
+    int q1 = q0;
+    if (i0 + 1 < a.n_list) {
+      q1 = __builtin_amdgcn_readfirstlane(a.list ? a.list[i0 + 1] : i0 + 1);
+      if (!same_shape(a, q0, q1)) {
+        if (threadIdx.x == 0) a.defer[atomicAdd(a.n_defer, 1)] = q1;
+        q1 = q0;  // the upper lanes repeat system q0 without writing
+      }
+    }
+    writer = h == 0 || q1 != q0;
+    q = h ? q1 : q0;
+  }
+  const int c = H == 1 ? __builtin_amdgcn_readfirstlane(a.centers ? a.centers[q] : q) : (a.centers ? a.centers[q] : q);
+  const int n = __builtin_amdgcn_readfirstlane(a.n_per ? a.n_per[q0] : a.n_max);
+  const int m = __builtin_amdgcn_readfirstlane(a.m_per ? a.m_per[q0] : a.m_uni);
+  const int l = __builtin_amdgcn_readfirstlane(a.l_per ? a.l_per[q0] : a.l_uni);
   const int M = n_terms(l);
   const int K = n + M;
   double *wrow = a.w + static_cast<int64_t>(q) * a.n_max;
   const int64_t op_stride = static_cast<int64_t>(a.n_centers) * a.n_max;
+  // a pair with a system the checks below reject: both to the one-system kernel
+  auto defer_pair = [&]() {
+    if (lane == 0 && writer) a.defer[atomicAdd(a.n_defer, 1)] = q;
+  };
 
   bool bad = (c < 0 || c >= a.n_nodes || n < 1 || n > a.n_max || m < 1 || m > 15 || (m & 1) == 0 || l < 0 ||
               l > 6 || n < M || K > KC);
   int node = -1;
   if (!bad && lane < n) node = a.idx[static_cast<int64_t>(q) * a.n_max + lane];
-  bad = bad || __ballot(lane < n && (node < 0 || node >= a.n_nodes)) != 0;
+  bad = __ballot(bad || (lane < n && (node < 0 || node >= a.n_nodes))) != 0;
+  if (H == 2 && bad) {
+    defer_pair();
+    return;
+  }
   if (bad) {
     for (int o = 0; o < a.n_ops; ++o)
       for (int t = lane; t < a.n_max; t += 64) wrow[o * op_stride + t] = 0.0;
@@ -1020,7 +1111,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
     dz = two_sum(a.xy[2 * node + 1], -zc);
     d2 = dx.hi * dx.hi + dz.hi * dz.hi;
   }
-  const double rho = sqrt(wave_max(d2));
+  const double rho = sqrt(group_max<H>(d2));
+  if (H == 2 && __ballot(!(rho > 0.0)) != 0) {
+    defer_pair();
+    return;
+  }
   if (!(rho > 0.0)) {
     for (int o = 0; o < a.n_ops; ++o)
       for (int t = lane; t < a.n_max; t += 64) wrow[o * op_stride + t] = 0.0;
@@ -1080,7 +1175,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
     if (group_bad) {
       status = 2;
       for (int g = 0; g < ng; ++g)
-        for (int t = lane; t < a.n_max; t += 64) wrow[S.gl[g] * op_stride + t] = 0.0;
+        for (int t = lane; t < a.n_max; t += L)
+          if (writer) wrow[S.gl[g] * op_stride + t] = 0.0;
       continue;
     }
 
@@ -1120,7 +1216,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
         amax = fmax(amax, fabs(v));
       }
     }
-    amax = wave_max(amax);
+    amax = group_max<H>(amax);
 
     // 3. LU with partial pivoting, rows stay in their lanes
     bool fr = lane < K;  // not yet chosen as a pivot row
@@ -1133,8 +1229,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
       // ties to the highest lane; + 64 keeps free rows above the others
       unsigned key = 0;
       if (fr) key = ((__float_as_uint(static_cast<float>(fabs(static_cast<double>(ck)))) & ~63u) + 64u) | lane;
-      const int p = __builtin_amdgcn_readfirstlane(static_cast<int>(wave_max_u32(key) & 63u));
-      const T piv = rl(ck, p);
+      unsigned k0, k1;
+      group_max_key<H>(key, k0, k1);
+      const int p0 = __builtin_amdgcn_readfirstlane(static_cast<int>(k0 & 63u));
+      const int p1 = __builtin_amdgcn_readfirstlane(static_cast<int>(k1 & 63u));
+      const int p = h ? p1 : p0;
+      const T piv = group_rl<H>(ck, p0, p1, h);
       pmin = fmin(pmin, fabs(static_cast<double>(piv)));
       const T rp = recip(piv);
       if (lane == p) {
@@ -1176,10 +1276,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
       const WaveRows<KC, T> rows{ar0, ar1, ar2, ar3, mystep, pv, rpv, rdg};
       const WaveCtx wc{lane, n, K, mg, P, own_pw, poly_a, poly_b, is_node, is_poly, ex, ez};
       switch (G) {
-        case 1: wave_refine<KC, 1>(a, S, rows, wc, g0, x, converged); break;
-        case 2: wave_refine<KC, 2>(a, S, rows, wc, g0, x, converged); break;
-        case 3: wave_refine<KC, 3>(a, S, rows, wc, g0, x, converged); break;
-        default: wave_refine<KC, 4>(a, S, rows, wc, g0, x, converged); break;
+        case 1: wave_refine<KC, 1, T, H>(a, S, rows, wc, g0, x, converged, h); break;
+        case 2: wave_refine<KC, 2, T, H>(a, S, rows, wc, g0, x, converged, h); break;
+        case 3: wave_refine<KC, 3, T, H>(a, S, rows, wc, g0, x, converged, h); break;
+        default: wave_refine<KC, 4, T, H>(a, S, rows, wc, g0, x, converged, h); break;
       }
 
       // 5. status and rescaled output
@@ -1187,7 +1287,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
 #pragma unroll
       for (int g = 0; g < 4; ++g)
         if (g < G) xmax = fmax(xmax, fabs(x[g]));
-      const bool finite = isfinite(wave_max(xmax));
+      const bool finite = isfinite(group_max<H>(xmax));
       if (!(pmin >= 1e-13 * amax) || !converged || !finite) status = status ? status : 1;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
@@ -1198,13 +1298,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
                          : (op.kind == RBFFD_HYPERLAP)                ? 2 * __builtin_amdgcn_readfirstlane(S.kg[g0 + g])
                                                                       : 2;
           const double scale = 1.0 / ipow(rho, qd);
-          for (int t = lane; t < a.n_max; t += 64)
-            wrow[o * op_stride + t] = (t < n && finite) ? x[g] * scale : 0.0;
+          for (int t = lane; t < a.n_max; t += L)
+            if (writer) wrow[o * op_stride + t] = (t < n && finite) ? x[g] * scale : 0.0;
         }
       }
     }
   }
-  if (lane == 0 && a.status) a.status[q] = status;
+  if (lane == 0 && writer && a.status) a.status[q] = status;
 }
 
 // Launch buckets by system size: each bucket's launch reserves LDS for its
@@ -1365,16 +1465,30 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   RBFFD_HIP(ctx, hipGetLastError());
   int used = 0;
   for (int b = 0; b < NBUCKET; ++b) used += cnt[b] > 0;
+  // systems of up to 32 unknowns: two per wavefront; the stencils that
+  // kernel leaves (a shape other than its partner's, invalid or degenerate
+  // ones) are solved one per wavefront after the other buckets
+  DevBuf d_def;
+  const bool f64 = precision == RBFFD_SOLVE_FP64;
+  if (cnt[0] > 0) {
+    RBFFD_HIP(ctx, d_def.alloc(sizeof(int) * (static_cast<size_t>(cnt[0]) + 1)));
+    RBFFD_HIP(ctx, hipMemsetAsync(d_def.p, 0, sizeof(int), s));
+  }
   for (int b = 0; b < NBUCKET; ++b) {
     if (cnt[b] == 0) continue;
     const int cap = cnt[2 * NBUCKET + b];  // the bucket's largest K
     a.k_cap = cap;
     a.list = used > 1 ? d_list.as<int>() + cnt[NBUCKET + b] : nullptr;
     if (b <= 2) {  // systems of up to 64 unknowns: one wavefront each
-      const bool f64 = precision == RBFFD_SOLVE_FP64;
-      if (b == 0)
-        f64 ? weights_wave_kernel<32, double><<<cnt[b], 64, 0, s>>>(a) : weights_wave_kernel<32, float><<<cnt[b], 64, 0, s>>>(a);
-      else if (b == 1)
+      if (b == 0) {
+        WArgs p = a;
+        p.n_list = cnt[0];
+        p.n_defer = d_def.as<int>();
+        p.defer = d_def.as<int>() + 1;
+        const int waves = (cnt[0] + 1) / 2;
+        f64 ? weights_wave_kernel<32, double, 2><<<waves, 64, 0, s>>>(p)
+            : weights_wave_kernel<32, float, 2><<<waves, 64, 0, s>>>(p);
+      } else if (b == 1)
         f64 ? weights_wave_kernel<48, double><<<cnt[b], 64, 0, s>>>(a) : weights_wave_kernel<48, float><<<cnt[b], 64, 0, s>>>(a);
       else
         f64 ? weights_wave_kernel<64, double><<<cnt[b], 64, 0, s>>>(a) : weights_wave_kernel<64, float><<<cnt[b], 64, 0, s>>>(a);
@@ -1395,6 +1509,18 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
     }
   }
   RBFFD_HIP(ctx, hipGetLastError());
+  if (cnt[0] > 0) {
+    int nd = 0;
+    RBFFD_HIP(ctx, hipMemcpyAsync(&nd, d_def.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    RBFFD_HIP(ctx, hipStreamSynchronize(s));
+    if (nd > 0) {
+      WArgs f = a;
+      f.list = d_def.as<int>() + 1;
+      f.k_cap = 32;
+      f64 ? weights_wave_kernel<32, double><<<nd, 64, 0, s>>>(f) : weights_wave_kernel<32, float><<<nd, 64, 0, s>>>(f);
+      RBFFD_HIP(ctx, hipGetLastError());
+    }
+  }
   // FP32 factorisation: the stencils whose refinement stalled are solved
   // again in FP64 (the same kernels, over a list of them) and marked 3
   if (precision == RBFFD_SOLVE_FP32_IR) {

@@ -205,6 +205,28 @@ def test_weights_parity_parameter_sweep(R, ctx):
     _weights_parity(R, ctx, nd.xy, ops[:3], 7, 1, 1, 0.0, np.arange(N), sample=np.arange(0, N, 11))
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_two_systems_per_wavefront(R, ctx, precision):
+    """Systems of up to 32 unknowns run two per wavefront, and the two share
+    n, m and l; a stencil whose partner has another shape is solved on its
+    own afterwards. An odd count (the last wavefront holds one system), runs
+    of one shape and alternating shapes (same n and l, different m
+    included), against the oracle."""
+    say(f"weights: K <= 32 systems two per wavefront, 4 shapes in runs and alternations, 23 stencils, "
+        f"precision {precision}")
+    nd = jittered_square(24, seed=8)
+    shapes = [(3, 2, 13), (5, 3, 21), (3, 3, 21), (5, 2, 20)]      # (m, l, n): K = 19, 31, 31, 26
+    pattern = [0, 0, 0, 0, 0, 1, 1, 0, 2, 3, 2, 3, 0, 1, 1, 1, 2, 2, 3, 0, 0, 1, 2]
+    rng = np.random.default_rng(12)
+    centers = rng.choice(nd.n_active, len(pattern), replace=False).astype(np.int32)
+    m_per = np.array([shapes[p][0] for p in pattern], np.int32)
+    l_per = np.array([shapes[p][1] for p in pattern], np.int32)
+    n_per = np.array([shapes[p][2] for p in pattern], np.int32)
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0)]
+    _weights_parity(R, ctx, nd.xy, ops, int(n_per.max()), 0, 0, 0.0, centers, n_per=n_per, m_per=m_per,
+                    l_per=l_per, precision=precision)
+
+
 def test_weights_full_size_mixed_samples(R, ctx):
     say("weights: 1,048,576 scattered nodes, mixed l in {3,4,5}, one launch, 120 sampled stencils")
     cfg = weights_config(1024)
