@@ -1319,57 +1319,86 @@ __device__ __forceinline__ int bucket_of(int K) {
   return b;
 }
 
-// count[b] and the largest K in bucket b (kmax[b]); one atomic per
-// wavefront and bucket (lane-divergent addresses would serialise)
-__global__ void bucket_count_kernel(const int *n_per, int n_max, const int *l_per, int l_uni, int nc, int *count,
-                                    int *kmax) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const int K = q < nc ? (n_per ? n_per[q] : n_max) + n_terms(l_per ? l_per[q] : l_uni) : 0;
-  const int b = q < nc ? bucket_of(K) : -1;
-  for (int bb = 0; bb < NBUCKET; ++bb) {
+// Bucketing runs in blocks of 1024 threads: per-wavefront ballots are summed
+// over the block in LDS, and each block takes one atomic per bucket
+// (same-address atomics serialise, so one per wavefront cost 1.1 ms on the
+// 1M-stencil batch).
+constexpr int BK_BLOCK = 1024;
+constexpr int BK_WAVES = BK_BLOCK / 64;
+
+// Bucket of stencil q and its system size K, or NBUCKET (K = 0) when its n
+// or l is invalid.
+__device__ __forceinline__ int stencil_bucket(const int *n_per, int n_max, const int *l_per, int l_uni, int q,
+                                              int &K) {
+  const int n = n_per ? n_per[q] : n_max;
+  const int l = l_per ? l_per[q] : l_uni;
+  K = 0;
+  if (l < 0 || l > 6 || n < 1 || n > n_max) return NBUCKET;
+  K = n + n_terms(l);
+  return bucket_of(K);
+}
+
+// count[b] and the largest K kmax[b] of each bucket b; count[NBUCKET]
+// counts the stencils with an invalid n or l.
+__global__ __launch_bounds__(BK_BLOCK) void bucket_count_kernel(const int *n_per, int n_max, const int *l_per,
+                                                                int l_uni, int nc, int *count, int *kmax) {
+  __shared__ int s_cnt[BK_WAVES][NBUCKET + 1], s_km[BK_WAVES][NBUCKET + 1];
+  const int q = static_cast<int>(blockIdx.x) * BK_BLOCK + static_cast<int>(threadIdx.x);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int K = 0;
+  const int b = q < nc ? stencil_bucket(n_per, n_max, l_per, l_uni, q, K) : -1;
+  for (int bb = 0; bb <= NBUCKET; ++bb) {
     const uint64_t mask = __ballot(b == bb);
-    if (mask == 0) continue;
     int km = b == bb ? K : 0;
     for (int off = 32; off > 0; off >>= 1) km = max(km, __shfl_xor(km, off, 64));
-    if (lane == __ffsll(static_cast<unsigned long long>(mask)) - 1) {
-      atomicAdd(&count[bb], __popcll(mask));
-      atomicMax(&kmax[bb], km);
+    if (lane == 0) {
+      s_cnt[wv][bb] = __popcll(mask);
+      s_km[wv][bb] = km;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x <= NBUCKET) {
+    int c = 0, km = 0;
+    for (int w = 0; w < BK_WAVES; ++w) {
+      c += s_cnt[w][threadIdx.x];
+      km = max(km, s_km[w][threadIdx.x]);
+    }
+    if (c) {
+      atomicAdd(&count[threadIdx.x], c);
+      atomicMax(&kmax[threadIdx.x], km);
     }
   }
 }
 
-// cursor[b] starts at bucket b's offset in `list`. Each wavefront reserves
-// one run per bucket and fills it in ascending stencil order, so stencils
-// that are neighbours in memory stay neighbours in a launch.
-__global__ void bucket_fill_kernel(const int *n_per, int n_max, const int *l_per, int l_uni, int nc, int *cursor,
-                                   int *list) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const bool ok = q < nc;
-  const int b = ok ? bucket_of((n_per ? n_per[q] : n_max) + n_terms(l_per ? l_per[q] : l_uni)) : -1;
+// cursor[b] starts at bucket b's offset in `list`. Each block reserves one
+// run per bucket and fills it in ascending stencil order, so stencils that
+// are neighbours in memory stay neighbours in a launch. Every stencil is
+// valid here (the count rejects a batch with invalid ones).
+__global__ __launch_bounds__(BK_BLOCK) void bucket_fill_kernel(const int *n_per, int n_max, const int *l_per,
+                                                               int l_uni, int nc, int *cursor, int *list) {
+  __shared__ int s_cnt[BK_WAVES][NBUCKET], s_base[NBUCKET];
+  const int q = static_cast<int>(blockIdx.x) * BK_BLOCK + static_cast<int>(threadIdx.x);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int K = 0;
+  const int b = q < nc ? stencil_bucket(n_per, n_max, l_per, l_uni, q, K) : -1;
+  uint64_t mine = 0;
   for (int bb = 0; bb < NBUCKET; ++bb) {
     const uint64_t mask = __ballot(b == bb);
-    if (mask == 0) continue;
-    int base = 0;
-    if (lane == __ffsll(static_cast<unsigned long long>(mask)) - 1) base = atomicAdd(&cursor[bb], __popcll(mask));
-    base = __shfl(base, __ffsll(static_cast<unsigned long long>(mask)) - 1, 64);
-    if (b == bb) list[base + __popcll(mask & ((uint64_t(1) << lane) - 1))] = q;
+    if (lane == 0) s_cnt[wv][bb] = __popcll(mask);
+    if (b == bb) mine = mask;
   }
-}
-
-// Per-stencil system size K = n + M and a count of invalid parameter sets.
-__global__ void ksize_kernel(const int *n_per, int n_max, const int *l_per, int l_uni, int nc,
-                             int *kmax, int *n_invalid) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nc) return;
-  int n = n_per ? n_per[q] : n_max;
-  int l = l_per ? l_per[q] : l_uni;
-  if (l < 0 || l > 6 || n < 1 || n > n_max) {
-    atomicAdd(n_invalid, 1);
-    return;
+  __syncthreads();
+  if (threadIdx.x < NBUCKET) {
+    int t = 0;
+    for (int w = 0; w < BK_WAVES; ++w) t += s_cnt[w][threadIdx.x];
+    s_base[threadIdx.x] = t ? atomicAdd(&cursor[threadIdx.x], t) : 0;
   }
-  atomicMax(kmax, n + n_terms(l));
+  __syncthreads();
+  if (b >= 0 && b < NBUCKET) {
+    int base = s_base[b];
+    for (int w = 0; w < wv; ++w) base += s_cnt[w][b];
+    list[base + __popcll(mine & ((uint64_t(1) << lane) - 1))] = q;
+  }
 }
 
 // Stencils whose FP32-factorisation refinement stalled (status 1), for an
@@ -1408,15 +1437,22 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   const int nc = static_cast<int>(st->n_centers);
   DevBuf d_k;
   RBFFD_HIP(ctx, d_k.alloc(4 * sizeof(int)));
-  RBFFD_HIP(ctx, hipMemsetAsync(d_k.p, 0, 4 * sizeof(int), s));
-  ksize_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
-                                                 d_k.as<int>(), d_k.as<int>() + 1);
+  // stencils bucketed by K (and the invalid ones counted), one launch per
+  // non-empty bucket
+  constexpr int C_START = NBUCKET + 1, C_KMAX = 2 * NBUCKET + 1, C_ALL = 3 * NBUCKET + 2;
+  DevBuf d_cnt, d_list;
+  RBFFD_HIP(ctx, d_cnt.alloc(C_ALL * sizeof(int)));
+  RBFFD_HIP(ctx, d_list.alloc(sizeof(int) * std::max(nc, 1)));
+  RBFFD_HIP(ctx, hipMemsetAsync(d_cnt.p, 0, C_ALL * sizeof(int), s));
+  bucket_count_kernel<<<grid_for(nc, BK_BLOCK), BK_BLOCK, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform,
+                                                                  nc, d_cnt.as<int>(), d_cnt.as<int>() + C_KMAX);
   RBFFD_HIP(ctx, hipGetLastError());
-  int hk[2];
-  RBFFD_HIP(ctx, hipMemcpyAsync(hk, d_k.p, sizeof(hk), hipMemcpyDeviceToHost, s));
+  int cnt[C_ALL];  // counts (and the invalid count), starts, largest K per bucket
+  RBFFD_HIP(ctx, hipMemcpyAsync(cnt, d_cnt.p, C_ALL * sizeof(int), hipMemcpyDeviceToHost, s));
   RBFFD_HIP(ctx, hipStreamSynchronize(s));
-  if (hk[1] > 0) return rbffd_fail(ctx, RBFFD_EINVAL, "%d stencils with invalid n or l", hk[1]);
-  const int kc = hk[0];
+  if (cnt[NBUCKET] > 0) return rbffd_fail(ctx, RBFFD_EINVAL, "%d stencils with invalid n or l", cnt[NBUCKET]);
+  int kc = 0;
+  for (int b = 0; b < NBUCKET; ++b) kc = std::max(kc, cnt[C_KMAX + b]);
   if (kc > 128) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d above 128", kc);
 
   DevBuf d_status;
@@ -1443,25 +1479,14 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   a.w = w;
   a.status = st_out;
   a.max_iter = precision == RBFFD_SOLVE_FP64 ? 3 : 30;
-  // stencils bucketed by K, one launch per non-empty bucket
-  DevBuf d_cnt, d_list;
-  RBFFD_HIP(ctx, d_cnt.alloc(3 * NBUCKET * sizeof(int)));
-  RBFFD_HIP(ctx, d_list.alloc(sizeof(int) * std::max(nc, 1)));
-  RBFFD_HIP(ctx, hipMemsetAsync(d_cnt.p, 0, 3 * NBUCKET * sizeof(int), s));
-  bucket_count_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
-                                                        d_cnt.as<int>(), d_cnt.as<int>() + 2 * NBUCKET);
-  RBFFD_HIP(ctx, hipGetLastError());
-  int cnt[3 * NBUCKET];   // counts, starts, largest K
-  RBFFD_HIP(ctx, hipMemcpyAsync(cnt, d_cnt.p, 3 * NBUCKET * sizeof(int), hipMemcpyDeviceToHost, s));
-  RBFFD_HIP(ctx, hipStreamSynchronize(s));
   for (int b = 0, off = 0; b < NBUCKET; ++b) {
-    cnt[NBUCKET + b] = off;  // start of bucket b
+    cnt[C_START + b] = off;  // start of bucket b
     off += cnt[b];
   }
-  RBFFD_HIP(ctx, hipMemcpyAsync(d_cnt.as<int>() + NBUCKET, cnt + NBUCKET, NBUCKET * sizeof(int),
+  RBFFD_HIP(ctx, hipMemcpyAsync(d_cnt.as<int>() + C_START, cnt + C_START, NBUCKET * sizeof(int),
                                 hipMemcpyHostToDevice, s));
-  bucket_fill_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
-                                                       d_cnt.as<int>() + NBUCKET, d_list.as<int>());
+  bucket_fill_kernel<<<grid_for(nc, BK_BLOCK), BK_BLOCK, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
+                                                                 d_cnt.as<int>() + C_START, d_list.as<int>());
   RBFFD_HIP(ctx, hipGetLastError());
   int used = 0;
   for (int b = 0; b < NBUCKET; ++b) used += cnt[b] > 0;
@@ -1476,9 +1501,9 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   }
   for (int b = 0; b < NBUCKET; ++b) {
     if (cnt[b] == 0) continue;
-    const int cap = cnt[2 * NBUCKET + b];  // the bucket's largest K
+    const int cap = cnt[C_KMAX + b];  // the bucket's largest K
     a.k_cap = cap;
-    a.list = used > 1 ? d_list.as<int>() + cnt[NBUCKET + b] : nullptr;
+    a.list = used > 1 ? d_list.as<int>() + cnt[C_START + b] : nullptr;
     if (b <= 2) {  // systems of up to 64 unknowns: one wavefront each
       if (b == 0) {
         WArgs p = a;
@@ -1561,6 +1586,7 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   RBFFD_HIP(ctx, hipMemsetAsync(d_k.p, 0, 4 * sizeof(int), s));
   count_status_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, nc, d_k.as<int>());
   RBFFD_HIP(ctx, hipGetLastError());
+  int hk[2];
   RBFFD_HIP(ctx, hipMemcpyAsync(hk, d_k.p, sizeof(hk), hipMemcpyDeviceToHost, s));
   RBFFD_HIP(ctx, hipStreamSynchronize(s));
   *n_bad = hk[1] > 0 ? -hk[1] : hk[0];
