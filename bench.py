@@ -122,7 +122,8 @@ def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup, ensembl
 
 
 def weights_leg(R, ctx, cfg, precision):
-    """One rbffd_weights launch over a node set; returns stencils/s."""
+    """One rbffd_weights call over a node set, after an untimed one; returns
+    stencils/s."""
     import torch
     from paper_1509_02615_amd import pipeline as P
     nd = cfg["nodes"]
@@ -132,6 +133,11 @@ def weights_leg(R, ctx, cfg, precision):
     l_per = P.to_dev(cfg["l_per"], torch.int32)
     ops = [(R.DX, 0, 0), (R.DZ, 0, 0), (R.HYPERLAP, 0, 0)]
     idx = R.rbffd_knn(ctx, xy, cfg["n_max"], 0.0, n_per=n_per)
+    # one untimed call first: the timed call then finds its output blocks
+    # (1.5 GB of weights) in torch's allocator, as a steady-state caller would
+    W = R.rbffd_weights(ctx, xy, ops, cfg["n_max"], n_per=n_per, m_per=m_per, l_per=l_per, idx_in=idx,
+                        precision=precision)
+    del W
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
