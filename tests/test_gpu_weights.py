@@ -316,3 +316,8 @@ def test_weights_singular_and_invalid(R, ctx):
             R.rbffd_weights(ctx, xy, bad.get("ops", [(O.DX, 0, 0)]), bad.get("n", 37), bad["m"], bad["l"],
                             centers=dev(centers, torch.int32))
         assert e.value.code == R.EINVAL
+    # a per-stencil degree outside 0..6: found by the bucketing pass on the device
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_weights(ctx, xy, [(O.DX, 0, 0)], 37, 7, 0, centers=dev(centers, torch.int32),
+                        l_per=dev(np.array([4, 7], np.int32), torch.int32))
+    assert e.value.code == R.EINVAL
