@@ -1372,11 +1372,16 @@ __global__ __launch_bounds__(BK_BLOCK) void bucket_count_kernel(const int *n_per
 
 // cursor[b] starts at bucket b's offset in `list`. Each block reserves one
 // run per bucket and fills it in ascending stencil order, so stencils that
-// are neighbours in memory stay neighbours in a launch. Every stencil is
-// valid here (the count rejects a batch with invalid ones).
-__global__ __launch_bounds__(BK_BLOCK) void bucket_fill_kernel(const int *n_per, int n_max, const int *l_per,
-                                                               int l_uni, int nc, int *cursor, int *list) {
+// are neighbours in memory stay neighbours in a launch. In the run of the
+// K <= 32 bucket, whose systems are solved two per wavefront, stencils of
+// one shape (n, m, l) are made adjacent (by shape, then stencil) when the
+// block holds more than one shape. Every stencil is valid here (the count
+// rejects a batch with invalid ones).
+__global__ __launch_bounds__(BK_BLOCK) void bucket_fill_kernel(const int *n_per, int n_max, const int *m_per,
+                                                               int m_uni, const int *l_per, int l_uni, int nc,
+                                                               int *cursor, int *list) {
   __shared__ int s_cnt[BK_WAVES][NBUCKET], s_base[NBUCKET];
+  __shared__ unsigned s_key[BK_BLOCK];
   const int q = static_cast<int>(blockIdx.x) * BK_BLOCK + static_cast<int>(threadIdx.x);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int K = 0;
@@ -1387,14 +1392,46 @@ __global__ __launch_bounds__(BK_BLOCK) void bucket_fill_kernel(const int *n_per,
     if (lane == 0) s_cnt[wv][bb] = __popcll(mask);
     if (b == bb) mine = mask;
   }
+  // shape key of a K <= 32 stencil (n < 64, l <= 6, m <= 15), else all ones
+  unsigned key = 0xFFFFFFFFu;
+  if (b == 0) {
+    const unsigned n = static_cast<unsigned>(n_per ? n_per[q] : n_max);
+    const unsigned m = static_cast<unsigned>(m_per ? m_per[q] : m_uni) & 15u;
+    const unsigned l = static_cast<unsigned>(l_per ? l_per[q] : l_uni);
+    key = ((n | (l << 6) | (m << 9)) << 10) | threadIdx.x;
+  }
   __syncthreads();
   if (threadIdx.x < NBUCKET) {
     int t = 0;
     for (int w = 0; w < BK_WAVES; ++w) t += s_cnt[w][threadIdx.x];
     s_base[threadIdx.x] = t ? atomicAdd(&cursor[threadIdx.x], t) : 0;
   }
+  // more than one shape in this block's K <= 32 run: sort the run's keys
+  const unsigned shape = b == 0 ? key >> 10 : 0u;
+  if (b == 0) s_key[0] = shape;  // any one of the run's shapes
   __syncthreads();
-  if (b >= 0 && b < NBUCKET) {
+  const bool mixed = __syncthreads_or(b == 0 && shape != s_key[0]);
+  if (mixed) {
+    s_key[threadIdx.x] = key;
+    __syncthreads();
+    for (int size = 2; size <= BK_BLOCK; size <<= 1)  // bitonic sort, ascending
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const int t = threadIdx.x, u = t ^ stride;
+        if (u > t) {
+          const unsigned x = s_key[t], y = s_key[u];
+          if ((x > y) == ((t & size) == 0)) {
+            s_key[t] = y;
+            s_key[u] = x;
+          }
+        }
+        __syncthreads();
+      }
+    // the run's stencils are now the first entries, by shape, then stencil
+    const unsigned k = s_key[threadIdx.x];
+    if (k != 0xFFFFFFFFu)
+      list[s_base[0] + static_cast<int>(threadIdx.x)] = static_cast<int>(blockIdx.x) * BK_BLOCK + static_cast<int>(k & 1023u);
+  }
+  if ((b > 0 && b < NBUCKET) || (b == 0 && !mixed)) {
     int base = s_base[b];
     for (int w = 0; w < wv; ++w) base += s_cnt[w][b];
     list[base + __popcll(mine & ((uint64_t(1) << lane) - 1))] = q;
@@ -1485,7 +1522,8 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   }
   RBFFD_HIP(ctx, hipMemcpyAsync(d_cnt.as<int>() + C_START, cnt + C_START, NBUCKET * sizeof(int),
                                 hipMemcpyHostToDevice, s));
-  bucket_fill_kernel<<<grid_for(nc, BK_BLOCK), BK_BLOCK, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
+  bucket_fill_kernel<<<grid_for(nc, BK_BLOCK), BK_BLOCK, 0, s>>>(st->n_per, st->n_max, st->m_per, st->m_uniform,
+                                                                 st->l_per, st->l_uniform, nc,
                                                                  d_cnt.as<int>() + C_START, d_list.as<int>());
   RBFFD_HIP(ctx, hipGetLastError());
   int used = 0;
@@ -1507,6 +1545,7 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
     if (b <= 2) {  // systems of up to 64 unknowns: one wavefront each
       if (b == 0) {
         WArgs p = a;
+        p.list = d_list.as<int>() + cnt[C_START];  // ordered by shape within blocks, even as the only bucket
         p.n_list = cnt[0];
         p.n_defer = d_def.as<int>();
         p.defer = d_def.as<int>() + 1;
