@@ -220,7 +220,9 @@ int rbffd_rhs(rbffd_ctx *ctx, rbffd_model *model, double t, void *state, void *t
 /* B1-B4: advance `state` in place by n_steps steps of size dt with the
  * tableau (RBFFD_RK4: classical RK4; RBFFD_WSRK3: y1 = y + dt/3 f(y),
  * y2 = y + dt/2 f(y1), y + dt f(y2)). Each stage is closure -> fused
- * RHS + stage update; one step is captured once as a HIP graph and replayed.
+ * RHS + stage update. One step and eight steps are captured once as HIP
+ * graphs (recaptured when state, dt or the tableau change); a call replays
+ * the eight-step graph n_steps / 8 times and the one-step graph for the rest.
  * *t (host) is advanced. Synchronises at the end to check for non-finite
  * values: returns RBFFD_ENONFINITE and names the first bad step in
  * rbffd_last_error. */

@@ -630,6 +630,8 @@ int model_destroy_impl(rbffd_model *m) {
   }
   if (m->exec) (void)hipGraphExecDestroy(m->exec);
   if (m->graph) (void)hipGraphDestroy(m->graph);
+  if (m->exec_n) (void)hipGraphExecDestroy(m->exec_n);
+  if (m->graph_n) (void)hipGraphDestroy(m->graph_n);
   delete m;
   return RBFFD_OK;
 }

@@ -76,8 +76,10 @@ struct rbffd_model {
   // time stepping
   DevBuf ya, yb, acc;              // [N][E][F] stage buffers
   DevBuf dev_misc;                 // {int nonfinite_step, int step_ctr, double t0}
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;      // one captured step
   hipGraphExec_t exec = nullptr;
+  hipGraph_t graph_n = nullptr;    // GRAPH_STEPS captured steps
+  hipGraphExec_t exec_n = nullptr;
   void *graph_state = nullptr;
   double graph_dt = 0.0;
   int graph_tableau = -1;

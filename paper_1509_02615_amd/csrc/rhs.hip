@@ -838,6 +838,54 @@ int model_rhs(rbffd_ctx *ctx, rbffd_model *m, double t, void *state, void *tende
   return RBFFD_OK;
 }
 
+namespace {
+
+// Steps per replay of the larger captured graph: consecutive graph launches
+// leave the device idle for about 8 us, so a run replays GRAPH_STEPS steps per
+// launch and single steps for the remainder.
+constexpr int GRAPH_STEPS = 8;
+
+void drop_graphs(rbffd_model *m) {
+  if (m->exec) (void)hipGraphExecDestroy(m->exec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  if (m->exec_n) (void)hipGraphExecDestroy(m->exec_n);
+  if (m->graph_n) (void)hipGraphDestroy(m->graph_n);
+  m->exec = m->exec_n = nullptr;
+  m->graph = m->graph_n = nullptr;
+}
+
+// Captures k steps into one graph and instantiates it.
+int capture_steps(rbffd_ctx *ctx, rbffd_model *m, void *state, double dt, int tableau, int k, hipGraph_t *graph_out,
+                  hipGraphExec_t *exec_out) {
+  hipStream_t cs = ctx->stream;
+  bool own_stream = false;
+  if (cs == nullptr) {  // the null stream cannot be captured
+    RBFFD_HIP(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    own_stream = true;
+  }
+  hipStream_t saved = ctx->stream;
+  ctx->stream = cs;
+  hipError_t eb = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  int rc = RBFFD_OK;
+  hipGraph_t graph = nullptr;
+  hipError_t ec = eb;
+  if (eb == hipSuccess) {
+    for (int i = 0; i < k && rc == RBFFD_OK; ++i) rc = enqueue_step(ctx, m, state, dt, tableau);
+    ec = hipStreamEndCapture(cs, &graph);
+  }
+  ctx->stream = saved;
+  if (own_stream) (void)hipStreamDestroy(cs);
+  if (rc || ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc ? rc : rbffd_fail(ctx, RBFFD_EDEVICE, "graph capture: %s", hipGetErrorString(ec));
+  }
+  *graph_out = graph;
+  RBFFD_HIP(ctx, hipGraphInstantiate(exec_out, graph, nullptr, nullptr, 0));
+  return RBFFD_OK;
+}
+
+}  // namespace
+
 int model_step(rbffd_ctx *ctx, rbffd_model *m, void *state, double *t, double dt, int64_t n_steps, int tableau) {
   if (n_steps == 0) return RBFFD_OK;
   hipStream_t s = ctx->stream;
@@ -848,39 +896,23 @@ int model_step(rbffd_ctx *ctx, rbffd_model *m, void *state, double *t, double dt
       int rc = enqueue_step(ctx, m, state, dt, tableau);
       if (rc) return rc;
     }
-  } else if (!m->exec || m->graph_state != state || m->graph_dt != dt || m->graph_tableau != tableau) {
-    if (m->exec) {
-      RBFFD_HIP(ctx, hipGraphExecDestroy(m->exec));
-      m->exec = nullptr;
+  } else {
+    if (!m->exec || !m->exec_n || m->graph_state != state || m->graph_dt != dt || m->graph_tableau != tableau) {
+      drop_graphs(m);
+      int rc = capture_steps(ctx, m, state, dt, tableau, 1, &m->graph, &m->exec);
+      if (rc == RBFFD_OK) rc = capture_steps(ctx, m, state, dt, tableau, GRAPH_STEPS, &m->graph_n, &m->exec_n);
+      if (rc) {
+        drop_graphs(m);
+        return rc;
+      }
+      m->graph_state = state;
+      m->graph_dt = dt;
+      m->graph_tableau = tableau;
     }
-    if (m->graph) {
-      RBFFD_HIP(ctx, hipGraphDestroy(m->graph));
-      m->graph = nullptr;
-    }
-    hipStream_t cs = s;
-    bool own_stream = false;
-    if (cs == nullptr) {  // the null stream cannot be captured
-      RBFFD_HIP(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-      own_stream = true;
-    }
-    hipStream_t saved = ctx->stream;
-    ctx->stream = cs;
-    RBFFD_HIP(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_step(ctx, m, state, dt, tableau);
-    hipGraph_t graph = nullptr;
-    hipError_t ec = hipStreamEndCapture(cs, &graph);
-    ctx->stream = saved;
-    if (own_stream) (void)hipStreamDestroy(cs);
-    if (rc) return rc;
-    if (ec != hipSuccess) return rbffd_fail(ctx, RBFFD_EDEVICE, "graph capture: %s", hipGetErrorString(ec));
-    m->graph = graph;
-    RBFFD_HIP(ctx, hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));
-    m->graph_state = state;
-    m->graph_dt = dt;
-    m->graph_tableau = tableau;
+    int64_t k = 0;
+    for (; k + GRAPH_STEPS <= n_steps; k += GRAPH_STEPS) RBFFD_HIP(ctx, hipGraphLaunch(m->exec_n, s));
+    for (; k < n_steps; ++k) RBFFD_HIP(ctx, hipGraphLaunch(m->exec, s));
   }
-  if (!m->profile)
-    for (int64_t k = 0; k < n_steps; ++k) RBFFD_HIP(ctx, hipGraphLaunch(m->exec, s));
   DevMisc h{};
   RBFFD_HIP(ctx, hipMemcpyAsync(&h, m->dev_misc.p, sizeof(h), hipMemcpyDeviceToHost, s));
   RBFFD_HIP(ctx, hipStreamSynchronize(s));
@@ -971,12 +1003,7 @@ int model_tune(rbffd_ctx *ctx, rbffd_model *m, void *state, int *chosen, double 
   (void)hipEventDestroy(e1);
   m->shape = best_s;
   m->profile = saved_profile;
-  if (m->exec) {  // a captured graph holds the old shape
-    (void)hipGraphExecDestroy(m->exec);
-    m->exec = nullptr;
-    (void)hipGraphDestroy(m->graph);
-    m->graph = nullptr;
-  }
+  drop_graphs(m);  // a captured graph holds the old shape
   *chosen = best_s;
   *best_us = best;
   return rc;
