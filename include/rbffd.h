@@ -111,8 +111,11 @@ int rbffd_sync(rbffd_ctx *ctx);
  * minimum image for a periodic x (shifted by one period when |dx| > period/2).
  * Section 6 uses the n = 37 nearest nodes (a complete symmetric set on
  * Cartesian and hexagonal lattices, Appendix A).
- * Output idx [Nc][n_max] int32, entries past n_c set to -1. Uses m/l only for
- * validation. Synchronises once (grid set-up). EINVAL if n_c > N. */
+ * Output idx [Nc][n_max] int32, entries past n_c set to -1. Ignores m and l.
+ * Synchronises (argument checks, grid set-up). EINVAL (nothing written): a
+ * centre outside the node set, n_c outside 1..min(n_max, N), non-finite
+ * coordinates. Dense clusters (more candidates near a centre than the
+ * search holds on chip) are searched by a slower exact kernel. */
 int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx);
 
 /* ---- A1-A4: batched weights -------------------------------------------- */
@@ -135,8 +138,11 @@ int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx);
  *          (RBFFD_SOLVE_FP32_IR only: stencils whose FP32-factorisation
  *          refinement stalls are solved again with the FP64 factorisation).
  * Returns RBFFD_ESINGULAR (after writing everything) when any status is 1;
- * synchronises to read the status count. EINVAL: even m, l > 6, n_c < M,
- * K = n_c + M > 128, Laplacian^k with m < 2k+1, n_ops outside 1..8. */
+ * synchronises to read the status count. EINVAL (nothing written: every
+ * per-stencil parameter and given index is checked on the device before the
+ * search or a solve starts): even m, l > 6, n_c < M, K = n_c + M > 128,
+ * Laplacian^k with m < 2k+1, n_ops outside 1..8, a centre or given stencil
+ * index outside the node set. */
 int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
                   int precision, int32_t *idx, double *w, int32_t *status);
 
@@ -145,12 +151,16 @@ int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops,
 typedef struct {
   int32_t physics;        /* RBFFD_PHYS_ADVECTION or RBFFD_PHYS_NS                      */
   int32_t field_dtype;    /* RBFFD_F64 or RBFFD_F32 (state element type)                */
-  int32_t weight_dtype;   /* RBFFD_F64, RBFFD_F32 or RBFFD_BF16 for the first-derivative
-                             and Laplacian weights; hyperviscosity and closure weights
-                             stay FP64 (with F32, hyperviscosity weights are stored as
-                             an FP32 value and a 16-bit relative correction, within
-                             about 2^-40 of FP64; they must lie in the FP32 normal
-                             range). F32/BF16 need field_dtype F32.                      */
+  int32_t weight_dtype;   /* RBFFD_F64, RBFFD_F32 or RBFFD_BF16 storage of the weights
+                             (closure weights stay FP64). F32: every weight as its FP32
+                             rounding plus a small correction of Lap^k (within about
+                             2^-30 of FP64), Dx and Dz (about 2^-29). BF16: Dx and Dz as
+                             bfloat16 plus an 8-bit correction (about 2^-16), Lap as
+                             bfloat16, Lap^k as FP32 plus a 16-bit correction (about
+                             2^-40). With F32 and BF16 the hyperviscosity sums and the
+                             divergence u_x + w_z run in FP64 on the corrected
+                             weights, the other sums in FP32; Lap^k weights must lie
+                             in the FP32 normal range. F32/BF16 need field_dtype F32. */
   int32_t n;              /* stencil length (row length of idx and w)                    */
   int64_t n_total;        /* N: all nodes including ghosts                               */
   int64_t n_active;       /* nodes 0..n_active-1 carry stencils and prognostic values;
@@ -220,9 +230,10 @@ int rbffd_rhs(rbffd_ctx *ctx, rbffd_model *model, double t, void *state, void *t
 /* B1-B4: advance `state` in place by n_steps steps of size dt with the
  * tableau (RBFFD_RK4: classical RK4; RBFFD_WSRK3: y1 = y + dt/3 f(y),
  * y2 = y + dt/2 f(y1), y + dt f(y2)). Each stage is closure -> fused
- * RHS + stage update. One step and eight steps are captured once as HIP
- * graphs (recaptured when state, dt or the tableau change); a call replays
- * the eight-step graph n_steps / 8 times and the one-step graph for the rest.
+ * RHS + stage update. Eight steps and one step are captured as HIP graphs
+ * when a call first needs them (recaptured when state, dt or the tableau
+ * change); a call replays the eight-step graph n_steps / 8 times and the
+ * one-step graph for the rest.
  * *t (host) is advanced. Synchronises at the end to check for non-finite
  * values: returns RBFFD_ENONFINITE and names the first bad step in
  * rbffd_last_error. */

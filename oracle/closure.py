@@ -11,9 +11,12 @@ samples and outputs of (y - target)^2.
 
 Everything here is FP64. With ``emulate=True`` the values the GPU stores in
 bfloat16 (inputs, weights, hidden activations and back-propagated
-activations) are rounded to bfloat16 at the same places, so the GPU can be
-compared at FP32-accumulation accuracy; with ``emulate=False`` it is the
-plain FP64 network, whose analytic gradient is pinned by finite differences.
+activations) are rounded to bfloat16 at the same places, and the output-layer
+gradient to FP32, so the GPU can be compared at FP32-accumulation accuracy;
+with ``emulate=False`` it is the plain FP64 network, whose analytic gradient
+is pinned by finite differences. The two differ only by those roundings
+(pinned: with the roundings replaced by the identity they agree bit for bit,
+and a hand-computed two-sample case fixes where each rounding happens).
 """
 
 import numpy as np
@@ -47,6 +50,22 @@ def bf16(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def fp32(x):
+    """Round to the nearest FP32, returned as FP64."""
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def _exact(x):
+    return np.asarray(x, dtype=np.float64)
+
+
+def _rounders(emulate):
+    """(r16, r32): the roundings applied where the GPU stores a value --
+    bfloat16 for the matrix-core operands and activations, FP32 for the
+    output-layer gradient -- or no rounding for the plain network."""
+    return (bf16, fp32) if emulate else (_exact, _exact)
+
+
 def unpack(p):
     p = np.asarray(p, dtype=np.float64)
     return (p[OW1:OB1].reshape(HID, KIN), p[OB1:OW2], p[OW2:OB2].reshape(HID, HID), p[OB2:OW3],
@@ -70,7 +89,7 @@ def features(state, idx, node_feature, in_scale):
 
 def forward(p, X, emulate=False, act=TANH):
     W1, b1, W2, b2, W3, b3 = unpack(p)
-    r = bf16 if emulate else (lambda v: np.asarray(v, dtype=np.float64))
+    r, _ = _rounders(emulate)
     Xr, W1r, W2r, W3r = r(X), r(W1), r(W2), r(W3)
     H1 = r(_act(Xr @ W1r.T + b1, act))
     H2 = r(_act(H1 @ W2r.T + b2, act))
@@ -81,15 +100,14 @@ def forward(p, X, emulate=False, act=TANH):
 def loss_and_grad(p, X, T, emulate=False, act=TANH):
     """Loss and its gradient for targets T [S][4] (only outputs 0..3 enter)."""
     W1, b1, W2, b2, W3, b3 = unpack(p)
-    r = bf16 if emulate else (lambda v: np.asarray(v, dtype=np.float64))
+    r, r32 = _rounders(emulate)
     Y, H1, H2, Xr = forward(p, X, emulate, act)
     S = X.shape[0]
     D = Y[:, :4] - T
     loss = float(np.sum(D * D) / (4 * S))
     dY32 = np.zeros((S, NOUT))
     dY32[:, :4] = 2.0 * D / (4 * S)
-    if emulate:
-        dY32 = np.asarray(dY32, dtype=np.float32).astype(np.float64)
+    dY32 = r32(dY32)
     dY = r(dY32)
     dH2 = r((dY @ r(W3)) * _dact(H2, act))
     dH1 = r((dH2 @ r(W2)) * _dact(H1, act))

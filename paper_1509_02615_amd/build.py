@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "librbffd.so")
 ARCH = os.environ.get("RBFFD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "knn.hip", "weights.hip", "model.hip", "rhs.hip", "closure.hip"]
+SOURCES = ["api.hip", "check.hip", "knn.hip", "weights.hip", "model.hip", "rhs.hip", "closure.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]

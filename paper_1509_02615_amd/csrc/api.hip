@@ -4,18 +4,6 @@
 
 #include "common.hpp"
 
-int rbffd_fail(rbffd_ctx *ctx, int code, const char *fmt, ...) {
-  if (ctx) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    ctx->last_error = buf;
-  }
-  return code;
-}
-
 extern "C" {
 
 int rbffd_create(rbffd_ctx **out, int device, void *hip_stream) {
@@ -72,19 +60,22 @@ int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx) {
   if (st->n_centers == 0) return RBFFD_OK;  // empty batch: nothing to write
   if (!idx) return rbffd_fail(ctx, RBFFD_EINVAL, "null idx");
   RBFFD_ENTER(ctx);
-  return knn_run(ctx, st, idx);
+  Workspace ws;
+  rc = check_stencils_device(ctx, st, nullptr, 0, false, ws);
+  if (rc) return rc;
+  return knn_run(ctx, st, idx, ws);
 }
 
-int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
-                  int precision, int32_t *idx, double *w, int32_t *status) {
-  if (!ctx) return RBFFD_EINVAL;
+// Checks of the uniform arguments of a weights call that need no device.
+static int check_weights_host(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
+                              int precision) {
   int rc = check_stencils(ctx, st);
   if (rc) return rc;
   if (!ops || n_ops < 1 || n_ops > 8) return rbffd_fail(ctx, RBFFD_EINVAL, "n_ops=%d outside 1..8", n_ops);
   if (precision != RBFFD_SOLVE_FP64 && precision != RBFFD_SOLVE_FP32_IR)
     return rbffd_fail(ctx, RBFFD_EINVAL, "bad precision %d", precision);
-  // Uniform parameters are checked here; per-centre ones are checked on the
-  // device (a bad entry gives status 2 and EINVAL).
+  // Uniform parameters are checked here; per-centre ones on the device
+  // before anything is written.
   if (!st->m_per && (st->m_uniform < 1 || st->m_uniform > 15 || st->m_uniform % 2 == 0))
     return rbffd_fail(ctx, RBFFD_EINVAL, "PHS order m=%d must be odd in 1..15", st->m_uniform);
   if (!st->l_per && (st->l_uniform < 0 || st->l_uniform > 6))
@@ -108,13 +99,18 @@ int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops,
     if (st->n_max + M > 128)
       return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d above 128", st->n_max + M);
   }
-  if (st->n_centers == 0) return RBFFD_OK;  // empty batch: nothing to write
-  if (!w) return rbffd_fail(ctx, RBFFD_EINVAL, "null w");
-  if (!st->idx_in && !idx) return rbffd_fail(ctx, RBFFD_EINVAL, "need idx output or idx_in");
-  RBFFD_ENTER(ctx);
+  return RBFFD_OK;
+}
+
+// A1-A4 on a workspace: device argument checks (nothing is written before
+// they pass), the search (or a copy of the given stencils), then the solves.
+static int weights_impl(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops, int precision,
+                        int32_t *idx, double *w, int32_t *status, Workspace &ws) {
+  int rc = check_stencils_device(ctx, st, ops, n_ops, true, ws);
+  if (rc) return rc;
   const int32_t *use_idx = st->idx_in;
   if (!use_idx) {
-    rc = knn_run(ctx, st, idx);
+    rc = knn_run(ctx, st, idx, ws);
     if (rc) return rc;
     use_idx = idx;
   } else if (idx) {
@@ -122,11 +118,24 @@ int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops,
                                   hipMemcpyDeviceToDevice, ctx->stream));
   }
   int32_t n_bad = 0;
-  rc = weights_run(ctx, st, ops, n_ops, precision, use_idx, w, status, &n_bad);
+  rc = weights_run(ctx, st, ops, n_ops, precision, use_idx, w, status, &n_bad, ws);
   if (rc) return rc;
   if (n_bad < 0) return rbffd_fail(ctx, RBFFD_EINVAL, "%d stencils have invalid m, l or n", -n_bad);
   if (n_bad > 0) return rbffd_fail(ctx, RBFFD_ESINGULAR, "%d singular stencil systems", n_bad);
   return RBFFD_OK;
+}
+
+int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
+                  int precision, int32_t *idx, double *w, int32_t *status) {
+  if (!ctx) return RBFFD_EINVAL;
+  int rc = check_weights_host(ctx, st, ops, n_ops, precision);
+  if (rc) return rc;
+  if (st->n_centers == 0) return RBFFD_OK;  // empty batch: nothing to write
+  if (!w) return rbffd_fail(ctx, RBFFD_EINVAL, "null w");
+  if (!st->idx_in && !idx) return rbffd_fail(ctx, RBFFD_EINVAL, "need idx output or idx_in");
+  RBFFD_ENTER(ctx);
+  Workspace ws;
+  return weights_impl(ctx, st, ops, n_ops, precision, idx, w, status, ws);
 }
 
 int rbffd_model_create(rbffd_ctx *ctx, const rbffd_model_desc *desc, rbffd_model **out) {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -26,6 +27,18 @@ int rbffd_fail(rbffd_ctx *ctx, int code, const char *fmt, ...);
     if (e_ != hipSuccess)                                                            \
       return rbffd_fail((ctx), RBFFD_EDEVICE, "%s failed: %s (%s:%d)", #call,        \
                         hipGetErrorString(e_), __FILE__, __LINE__);                  \
+  } while (0)
+
+// A workspace request: a failed allocation is ENOMEM; a request beyond a
+// fixed region (which the callers' size checks rule out) is reported as such.
+#define RBFFD_WS(ctx, ws, call)                                                                   \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return rbffd_fail((ctx), (ws).fixed() ? RBFFD_EINVAL : RBFFD_ENOMEM,                        \
+                        (ws).fixed() ? "scratch region exhausted (%s:%d)" : "device allocation "  \
+                                                                            "failed (%s:%d)",     \
+                        __FILE__, __LINE__);                                                      \
   } while (0)
 
 // Entry into a library call: select the context's device and drop a stale
@@ -61,12 +74,97 @@ struct DevBuf {
   template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Device scratch of one search or weights call. Without a region every
+// request is a hipMalloc, released when the call ends; with a fixed region
+// requests are carved from it in order, 256-byte aligned, and a request
+// beyond its end fails without allocating.
+class Workspace {
+ public:
+  Workspace() = default;
+  Workspace(void *region, size_t cap) : base_(static_cast<char *>(region)), cap_(cap) {}
+  Workspace(const Workspace &) = delete;
+  Workspace &operator=(const Workspace &) = delete;
+  ~Workspace() {
+    for (void *p : owned_) (void)hipFree(p);
+  }
+  bool fixed() const { return base_ != nullptr; }
+  size_t used() const { return used_; }
+  // `bytes` of device memory in *out (null for zero bytes)
+  hipError_t get(size_t bytes, void **out) {
+    *out = nullptr;
+    if (bytes == 0) return hipSuccess;
+    if (base_) {
+      const size_t at = (used_ + 255) & ~size_t(255);
+      if (at > cap_ || bytes > cap_ - at) return hipErrorOutOfMemory;
+      *out = base_ + at;
+      used_ = at + bytes;
+      return hipSuccess;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipSuccess) owned_.push_back(p);
+    *out = p;
+    used_ += bytes;
+    return e;
+  }
+  template <class T> hipError_t get(size_t count, T **out) {
+    void *p = nullptr;
+    hipError_t e = get(count * sizeof(T), &p);
+    *out = static_cast<T *>(p);
+    return e;
+  }
+
+ private:
+  char *base_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+  std::vector<void *> owned_;
+};
+
+// Device scratch of the search for n nodes and nc centres, of the argument
+// checks, and of the weights (after the search) for nc centres, as the
+// Workspace requests them (each rounded up to 256 bytes): the size a fixed
+// region needs. The constants are the search's box blocks and scan tile and
+// the weights' count array.
+constexpr int KNN_BOX_BLOCKS = 512;
+constexpr int KNN_SCAN_TILE = 4096;
+constexpr int WEIGHTS_COUNTS = 20;
+constexpr size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t knn_scratch_bytes(int64_t n_nodes, int64_t n_centers) {
+  // box partials, box + overflow count, cell counts, cell starts, scan tile
+  // sums, nodes by cell, centres left to the dense-cluster kernel
+  const size_t n = static_cast<size_t>(n_nodes), cells = n + 16;
+  const size_t tiles = (cells + KNN_SCAN_TILE - 1) / KNN_SCAN_TILE;
+  const size_t nc = static_cast<size_t>(n_centers > 1 ? n_centers : 1);
+  return round256(sizeof(double) * 4 * KNN_BOX_BLOCKS) + round256(sizeof(double) * 8) +
+         round256(sizeof(int) * cells) + round256(sizeof(int) * (cells + 1)) + round256(sizeof(int) * tiles) +
+         round256(sizeof(int) * n) + round256(sizeof(int) * nc);
+}
+constexpr size_t CHECK_SCRATCH_BYTES = 256;
+constexpr size_t weights_scratch_bytes(int64_t n_centers) {
+  // status counts, bucket counts, bucket lists, status (when the caller
+  // passes none), stencils left by the two-systems-per-wavefront kernel,
+  // FP32-factorisation stencils to solve again
+  const size_t nc = static_cast<size_t>(n_centers > 1 ? n_centers : 1);
+  return round256(4 * sizeof(int)) + round256(WEIGHTS_COUNTS * sizeof(int)) + round256(nc * sizeof(int)) +
+         round256(nc * sizeof(int32_t)) + round256((nc + 1) * sizeof(int)) + round256(nc * sizeof(int));
+}
+
+// ---- argument checks on the device (check.hip) ----
+// Every per-stencil parameter and index of a search (`weights` false) or a
+// weights call is checked before anything is written: centre indices, n, and
+// for weights m, l, n >= M(l), n + M <= 128, Laplacian^k continuity and the
+// given stencils' indices. Synchronises; RBFFD_EINVAL names the first bad
+// stencil.
+int check_stencils_device(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops, bool weights,
+                          Workspace &ws);
+
 // ---- stencil search (knn.hip) ----
-int knn_run(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx);
+int knn_run(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx, Workspace &ws);
 
 // ---- weights (weights.hip) ----
 int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
-                int precision, const int32_t *idx, double *w, int32_t *status, int32_t *n_bad);
+                int precision, const int32_t *idx, double *w, int32_t *status, int32_t *n_bad,
+                Workspace &ws);
 
 // ---- right-hand side model (model.hip / rhs.hip) ----
 struct StageArgs;

@@ -45,6 +45,25 @@ __global__ void repack_f64(const int *__restrict__ idx, const double *__restrict
   rec[dst] = RecF64{w[src], w[plane + src], w[2 * plane + src], w[3 * plane + src]};
 }
 
+// Signed correction q of the FP32 rounding hi of w on a grid of `scale`
+// (relative), clamped to `bits` bits: w ~ hi (1 + q scale). |w - hi| <= 2^-24
+// |hi| and w - hi is exact in FP64. No correction for a zero or subnormal hi.
+__device__ __forceinline__ int rel_q(double w, double hi, double inv_scale, int bits) {
+  if (!(fabs(hi) >= static_cast<double>(FLT_MIN))) return 0;
+  const int lim = (1 << (bits - 1)) - 1;
+  const int q = static_cast<int>(rint((w - hi) / hi * inv_scale));
+  return max(-lim - 1, min(lim, q));
+}
+
+// FP32 rounding of a Lap^k weight, which must lie in the FP32 normal range
+// (else *bad is set): the stage kernel's Lap^k sums run in FP64 on
+// hi (1 + q scale).
+__device__ __forceinline__ float hv_hi(double hv, int *bad) {
+  const float hi = static_cast<float>(hv);
+  if (hv != 0.0 && !(fabsf(hi) >= FLT_MIN && fabsf(hi) <= FLT_MAX)) atomicOr(bad, 1);
+  return hi;
+}
+
 __global__ void repack_f32(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n, int k0,
                            int *__restrict__ idx_t, uint32_t *__restrict__ aux, RecF32 *__restrict__ rec,
                            int *__restrict__ bad) {
@@ -55,28 +74,18 @@ __global__ void repack_f32(const int *__restrict__ idx, const double *__restrict
   const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k - k0) * na + i;
   idx_t[static_cast<int64_t>(k) * na + i] = idx[src];
   if (k < k0) return;  // the centre slot: every centre-subtracted sum skips it
-  // Lap^k weight = hi (1 + q 2^-39): hi its FP32 rounding (|w - hi| <=
-  // 2^-24 |hi|, and w - hi is exact in FP64), q the relative remainder on a
-  // 2^-39 grid
-  const double hv = w[3 * plane + src];
-  const float hi = static_cast<float>(hv);
-  int q = 0;
-  if (hv != 0.0) {
-    if (!(fabsf(hi) >= FLT_MIN && fabsf(hi) <= FLT_MAX)) {
-      atomicOr(bad, 1);  // outside the FP32 normal range
-    } else {
-      q = static_cast<int>(rint((hv - static_cast<double>(hi)) / static_cast<double>(hi) * 0x1p39));
-      q = max(-32767, min(32767, q));
-    }
-  }
-  rec[dst] = RecF32{static_cast<float>(w[src]), static_cast<float>(w[plane + src]),
-                    static_cast<float>(w[2 * plane + src]), hi};
-  aux[dst] = static_cast<uint32_t>(static_cast<uint16_t>(q)) |
-             (static_cast<uint32_t>(static_cast<uint16_t>(nb_offset(idx[src], i))) << 16);
+  const double wx = w[src], wz = w[plane + src], hv = w[3 * plane + src];
+  const float hx = static_cast<float>(wx), hz = static_cast<float>(wz), hh = hv_hi(hv, bad);
+  const int qh = rel_q(hv, hh, 1.0 / HV_Q_SCALE, HV_Q_BITS);
+  const int qx = rel_q(wx, hx, 1.0 / D_Q_SCALE, D_Q_BITS), qz = rel_q(wz, hz, 1.0 / D_Q_SCALE, D_Q_BITS);
+  rec[dst] = RecF32{hx, hz, static_cast<float>(w[2 * plane + src]), hh};
+  aux[dst] = (static_cast<uint32_t>(static_cast<uint16_t>(nb_offset(idx[src], i))) << 16) |
+             ((static_cast<uint32_t>(qh) & 63u) << 10) | ((static_cast<uint32_t>(qx) & 31u) << 5) |
+             (static_cast<uint32_t>(qz) & 31u);
 }
 
-__global__ void repack_f32w(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n, int k0,
-                            int *__restrict__ idx_t, RecF32W *__restrict__ rec, double *__restrict__ hv) {
+__global__ void repack_mw(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n, int k0,
+                          int *__restrict__ idx_t, RecMW *__restrict__ rec) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= na * n) return;
   int64_t i = t / n;
@@ -84,9 +93,7 @@ __global__ void repack_f32w(const int *__restrict__ idx, const double *__restric
   const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k - k0) * na + i;
   idx_t[static_cast<int64_t>(k) * na + i] = idx[src];
   if (k < k0) return;  // the centre slot: every centre-subtracted sum skips it
-  rec[dst] = RecF32W{static_cast<float>(w[src]), static_cast<float>(w[plane + src]),
-                     static_cast<float>(w[2 * plane + src]), idx[src]};
-  hv[dst] = w[3 * plane + src];
+  rec[dst] = RecMW{w[src], w[plane + src], w[3 * plane + src], static_cast<float>(w[2 * plane + src]), idx[src]};
 }
 
 __device__ __forceinline__ uint16_t to_bf16(double v) {
@@ -97,8 +104,17 @@ __device__ __forceinline__ uint16_t to_bf16(double v) {
   return static_cast<uint16_t>(u >> 16);
 }
 
+// 8-bit correction of a bfloat16 weight b: w ~ b (1 + q 2^-15)
+__device__ __forceinline__ int8_t bf_q(double w, uint16_t b) {
+  const double hb = static_cast<double>(__uint_as_float(static_cast<uint32_t>(b) << 16));
+  if (!(fabs(hb) >= static_cast<double>(FLT_MIN))) return 0;
+  const int q = static_cast<int>(rint((w - hb) / hb * 0x1p15));
+  return static_cast<int8_t>(max(-127, min(127, q)));
+}
+
 __global__ void repack_bf16(const int *__restrict__ idx, const double *__restrict__ w, int64_t na, int n, int k0,
-                            int *__restrict__ idx_t, RecBF16 *__restrict__ rec, double *__restrict__ hv) {
+                            int *__restrict__ idx_t, RecBF16 *__restrict__ rec, RecBF16X *__restrict__ rec2,
+                            int *__restrict__ bad) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= na * n) return;
   int64_t i = t / n;
@@ -106,8 +122,11 @@ __global__ void repack_bf16(const int *__restrict__ idx, const double *__restric
   const int64_t src = i * n + k, plane = na * n, dst = static_cast<int64_t>(k - k0) * na + i;
   idx_t[static_cast<int64_t>(k) * na + i] = idx[src];
   if (k < k0) return;  // the centre slot: every centre-subtracted sum skips it
-  rec[dst] = RecBF16{to_bf16(w[src]), to_bf16(w[plane + src]), to_bf16(w[2 * plane + src]), nb_offset(idx[src], i)};
-  hv[dst] = w[3 * plane + src];
+  const double wx = w[src], wz = w[plane + src], hv = w[3 * plane + src];
+  const uint16_t bx = to_bf16(wx), bz = to_bf16(wz);
+  rec[dst] = RecBF16{bx, bz, to_bf16(w[2 * plane + src]), nb_offset(idx[src], i)};
+  const float hh = hv_hi(hv, bad);
+  rec2[dst] = RecBF16X{hh, static_cast<int16_t>(rel_q(hv, hh, 1.0 / HV_Q16_SCALE, 16)), bf_q(wx, bx), bf_q(wz, bz)};
 }
 
 // Transport, flux form (Section 6.1): (D_x (U psi) + D_z (V psi))_i
@@ -377,21 +396,25 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
     m->bytes_per_node = (n - k0) * (sizeof(int16_t) + sizeof(RecF64));
   } else if (m->wdt == RBFFD_F32 && m->E % 64 == 0) {
     m->wide_rec = true;
-    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecF32W) * cs) == hipSuccess &&
-         m->hv_t.alloc(sizeof(double) * cs) == hipSuccess;
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecMW) * cs) == hipSuccess;
     if (ok)
-      repack_f32w<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, k0, m->idx_t.as<int>(), m->rec.as<RecF32W>(),
-                                                      m->hv_t.as<double>());
-    m->bytes_per_node = (n - k0) * (sizeof(RecF32W) + 8);
-  } else if (m->wdt == RBFFD_F32) {
+      repack_mw<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, k0, m->idx_t.as<int>(), m->rec.as<RecMW>());
+    m->bytes_per_node = (n - k0) * sizeof(RecMW);
+  } else {
+    const bool f32 = m->wdt == RBFFD_F32;
     DevBuf bad;
-    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->aux32.alloc(sizeof(uint32_t) * cs) == hipSuccess &&
-         m->rec.alloc(sizeof(RecF32) * cs) == hipSuccess && bad.alloc(sizeof(int)) == hipSuccess;
+    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && bad.alloc(sizeof(int)) == hipSuccess &&
+         (f32 ? m->aux32.alloc(sizeof(uint32_t) * cs) == hipSuccess && m->rec.alloc(sizeof(RecF32) * cs) == hipSuccess
+              : m->rec.alloc(sizeof(RecBF16) * cs) == hipSuccess && m->rec2.alloc(sizeof(RecBF16X) * cs) == hipSuccess);
     if (ok) {
       int hb = 0;
       if (hipMemsetAsync(bad.p, 0, sizeof(int), s) != hipSuccess) return fail_model(ctx, m, RBFFD_EDEVICE, "memset");
-      repack_f32<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, k0, m->idx_t.as<int>(), m->aux32.as<uint32_t>(),
-                                                     m->rec.as<RecF32>(), bad.as<int>());
+      if (f32)
+        repack_f32<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, k0, m->idx_t.as<int>(),
+                                                       m->aux32.as<uint32_t>(), m->rec.as<RecF32>(), bad.as<int>());
+      else
+        repack_bf16<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, k0, m->idx_t.as<int>(),
+                                                        m->rec.as<RecBF16>(), m->rec2.as<RecBF16X>(), bad.as<int>());
       if (hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess)
         return fail_model(ctx, m, RBFFD_EDEVICE, "weight repack");
@@ -399,14 +422,7 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
         return fail_model(ctx, m, RBFFD_EINVAL,
                           "hyperviscosity weights outside the FP32 normal range: use FP64 weights for this node set");
     }
-    m->bytes_per_node = (n - k0) * (sizeof(RecF32) + sizeof(uint32_t));
-  } else {
-    ok = m->idx_t.alloc(sizeof(int) * cnt) == hipSuccess && m->rec.alloc(sizeof(RecBF16) * cs) == hipSuccess &&
-         m->hv_t.alloc(sizeof(double) * cs) == hipSuccess;
-    if (ok)
-      repack_bf16<<<grid_for(cnt, 256), 256, 0, s>>>(d->idx, d->w, na, m->n, k0, m->idx_t.as<int>(), m->rec.as<RecBF16>(),
-                                                      m->hv_t.as<double>());
-    m->bytes_per_node = (n - k0) * (sizeof(RecBF16) + 8);
+    m->bytes_per_node = (n - k0) * (f32 ? sizeof(RecF32) + sizeof(uint32_t) : sizeof(RecBF16) + sizeof(RecBF16X));
   }
   if (!ok) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation (weights)");
   if (m->physics == RBFFD_PHYS_NS) {

@@ -13,22 +13,35 @@ constexpr int16_t OFF_FAR = -32768;
 struct RecF64 {      // FP64 Navier-Stokes: Dx, Dz, Lap, Lap^k
   double dx, dz, lap, hv;
 };
-struct RecF32 {      // FP32 Navier-Stokes: Dx, Dz, Lap and the high part of Lap^k
-  float dx, dz, lap, hv;
+struct RecF32 {      // FP32 Navier-Stokes: Dx, Dz, Lap and Lap^k, each the FP32 rounding hi
+  float dx, dz, lap, hv;  // of the FP64 weight
 };
-// The FP32 layout's second stream, one 32-bit word per record: the low 16
-// bits a correction q of the Lap^k weight, which is hv (1 + q 2^-39) (within
-// about 2^-40 of the FP64 weight, below the weights' own error), the high 16
-// bits the neighbour offset.
-constexpr double HV_Q_SCALE = 0x1p-39;
-struct RecF32W {     // FP32 with the full index, for ensembles of 64k members: one
-  float dx, dz, lap; // record serves a wavefront of 64 members, so one aligned
-  int idx;           // 16-byte scalar load per slot beats the smaller record
+// The FP32 layout's second stream, one 32-bit word per record: bits 31-16
+// the neighbour offset; bits 15-10, 9-5 and 4-0 signed corrections q of the
+// Lap^k, Dx and Dz weights, each weight being hi (1 + q s) with s = 2^-29
+// (Lap^k, within about 2^-30 of the FP64 weight) and 2^-28 (Dx, Dz, within
+// about 2^-29). The corrected Dx and Dz weights enter only the divergence
+// u_x + w_z, which the stage kernel sums in FP64: the pressure tendency is
+// the small difference of that term and w dpi-bar/dz in a developed flow.
+constexpr double HV_Q_SCALE = 0x1p-29;
+constexpr double D_Q_SCALE = 0x1p-28;
+constexpr int HV_Q_BITS = 6, D_Q_BITS = 5;
+struct RecMW {       // ensembles of 64k members (one record per wavefront of 64 members,
+  double dx, dz, hv; // through the scalar cache: bytes per member are negligible, so the
+  float lap;         // weights the FP64 sums take stay FP64 and the full index is inline;
+  int idx;           // one aligned 32-byte scalar load per slot)
 };
 struct RecBF16 {     // BF16 Navier-Stokes: Dx, Dz, Lap (bfloat16 bits) and the offset
   uint16_t dx, dz, lap;
   int16_t off;
 };
+struct RecBF16X {    // the BF16 layout's second stream: the Lap^k weight as FP32 hi and
+  float hv;          // a correction (hv (1 + hvq 2^-39), about 2^-40), and 8-bit
+  int16_t hvq;       // corrections of the Dx and Dz weights, each bf16 (1 + q 2^-15),
+  int8_t dxq, dzq;   // so that they keep about 16 significant bits
+};
+constexpr double HV_Q16_SCALE = 0x1p-39;
+constexpr float BF_Q_SCALE = 0x1p-15f;
 struct RecAdv {      // transport: folded flux weights and Lap^k
   double adv, hv;
 };
@@ -45,12 +58,12 @@ struct rbffd_model {
   // slot-major differentiation matrices
   DevBuf idx_t;     // int32 [n][Na] full neighbour indices
   DevBuf off16;     // int16 [n - k0][Na] neighbour offsets j - i (F64 layout)
-  DevBuf aux32;     // uint32 [n - k0][Na] Lap^k correction and neighbour offset (FP32 layout)
-  bool wide_rec = false;  // FP32 records carry the full index (RecF32W)
+  DevBuf aux32;     // uint32 [n - k0][Na] neighbour offset and weight corrections (FP32 layout)
+  bool wide_rec = false;  // FP32 records carry the full index (RecMW)
   int k0 = 0;             // first slot in the stream (1: every stencil starts with its centre, which
                           // centre-subtracted sums skip); the stream arrays hold slots k0..n-1
-  DevBuf rec;       // RecF64 / RecF32 / RecBF16 [n - k0][Na], RecAdv [n][Na]
-  DevBuf hv_t;      // double [n - k0][Na] (F32 / BF16 layouts)
+  DevBuf rec;       // RecF64 / RecF32 / RecMW / RecBF16 [n - k0][Na], RecAdv [n][Na]
+  DevBuf rec2;      // RecBF16X [n - k0][Na] (BF16 layout)
   DevBuf kind;      // uint8 [N]: KIND_* bits (0: interior)
   DevBuf pibar;     // double [Na]
   double hv_coeff = 0.0, vel_period = 1.0;

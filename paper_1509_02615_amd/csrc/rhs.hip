@@ -15,8 +15,12 @@
 //
 // Reduced precision: FP32 fields use centre-subtracted sums
 // sum_k w_k (f_j - f_i), which equal sum_k w_k f_j because derivative
-// weights sum to zero (they reproduce constants, Section 3); hyperviscosity
-// weights stay FP64 and accumulate in FP64 (their sums cancel strongly).
+// weights sum to zero (they reproduce constants, Section 3). Two kinds of sum
+// run in FP64 on weights corrected towards their FP64 values: the
+// hyperviscosity sums (they cancel strongly), and the divergence u_x + w_z,
+// whose term in the pressure equation (Eq. piEq) nearly cancels w dpi-bar/dz
+// in a developed flow, so that its FP32 rounding would dominate the pressure
+// tendency's error.
 //
 // Launch geometry: 256-thread blocks, thread = (node, member); block ids are
 // remapped so that each of the 8 XCDs (which take block ids round-robin)
@@ -143,9 +147,9 @@ struct NSArgs {
   void *acc;          // RK4 accumulator
   const int *idx_t;      // full neighbour indices (read for OFF_FAR offsets only)
   const int16_t *off16;  // neighbour offsets j - i (F64 records)
-  const uint32_t *aux32; // Lap^k correction and neighbour offset (FP32 records)
+  const uint32_t *aux32; // neighbour offset and weight corrections (FP32 records)
   const void *rec;
-  const double *hv_t;
+  const void *rec2;      // second record stream (BF16 layout)
   const uint8_t *kind;
   const double *pibar;
   int64_t Na;
@@ -177,6 +181,11 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
   const F4<FT> own = load4(ys + (i * E + e) * 4);
   FT sdx[4] = {0, 0, 0, 0}, sdz[4] = {0, 0, 0, 0}, slp[3] = {0, 0, 0};
   double shv[4] = {0.0, 0.0, 0.0, 0.0};
+  // reduced-precision layouts: the divergence u_x + w_z in FP64, from exact
+  // differences and weights corrected towards FP64 (FP64 layout: sdx[0], sdz[1])
+  double sux = 0.0, swz = 0.0;
+  constexpr bool DIV64 = WDT != RBFFD_F64;
+  const double own_u = static_cast<double>(own.v[0]), own_w = static_cast<double>(own.v[1]);
   const int n = a.n;
   const int64_t Na = a.Na;
 #pragma unroll SH::unroll
@@ -184,7 +193,7 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
     const int64_t s = static_cast<int64_t>(k) * Na + i;
     int j;
     FT wdx, wdz, wlp;
-    double whv;
+    double whv, wdx64 = 0.0, wdz64 = 0.0;
     int off;
     if constexpr (WDT == RBFFD_F64) {
       const double2 r0 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s);
@@ -194,14 +203,16 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
       wdz = r0.y;
       wlp = r1.x;
       whv = r1.y;
-    } else if constexpr (WDT == RBFFD_F32 && MW) {  // RecF32W: full index inline
-      const float4 r = reinterpret_cast<const float4 *>(a.rec)[s];
+    } else if constexpr (WDT == RBFFD_F32 && MW) {  // RecMW: FP64 weights, full index inline
+      const RecMW r = reinterpret_cast<const RecMW *>(a.rec)[s];
       off = 0;
-      wdx = r.x;
-      wdz = r.y;
-      wlp = r.z;
-      whv = a.hv_t[s];
-      j = __float_as_int(r.w);
+      wdx64 = r.dx;
+      wdz64 = r.dz;
+      wdx = static_cast<float>(r.dx);
+      wdz = static_cast<float>(r.dz);
+      wlp = r.lap;
+      whv = r.hv;
+      j = r.idx;
     } else if constexpr (WDT == RBFFD_F32) {
       const float4 r = stream_load4<NT>(reinterpret_cast<const float4 *>(a.rec) + s);
       const uint32_t x = stream_load<NT>(a.aux32 + s);
@@ -209,15 +220,26 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
       wdx = r.x;
       wdz = r.y;
       wlp = r.z;
-      const double hi = r.w;  // Lap^k weight hi (1 + q 2^-39)
-      whv = fma(hi, static_cast<double>(static_cast<int16_t>(x & 0xffffu)) * HV_Q_SCALE, hi);
+      // corrections: bits 15-10 (Lap^k), 9-5 (Dx), 4-0 (Dz), signed
+      const int qh = static_cast<int>(x << 16) >> 26, qx = static_cast<int>(x << 22) >> 27,
+                qz = static_cast<int>(x << 27) >> 27;
+      const double hh = r.w, hx = r.x, hz = r.y;
+      whv = fma(hh, static_cast<double>(qh) * HV_Q_SCALE, hh);
+      wdx64 = fma(hx, static_cast<double>(qx) * D_Q_SCALE, hx);
+      wdz64 = fma(hz, static_cast<double>(qz) * D_Q_SCALE, hz);
     } else {
       const uint2 r = stream_load2u<NT>(reinterpret_cast<const uint2 *>(a.rec) + s);
-      wdx = __uint_as_float(r.x << 16);
-      wdz = __uint_as_float(r.x & 0xffff0000u);
+      const uint2 x = stream_load2u<NT>(reinterpret_cast<const uint2 *>(a.rec2) + s);
+      // RecBF16X: {float hv, int16 hvq, int8 dxq, int8 dzq}
+      const float bx = __uint_as_float(r.x << 16), bz = __uint_as_float(r.x & 0xffff0000u);
+      wdx = fmaf(bx, static_cast<float>(static_cast<int>(x.y << 8) >> 24) * BF_Q_SCALE, bx);
+      wdz = fmaf(bz, static_cast<float>(static_cast<int>(x.y) >> 24) * BF_Q_SCALE, bz);
       wlp = __uint_as_float(r.y << 16);
       off = static_cast<int16_t>(r.y >> 16);
-      whv = stream_load<NT>(a.hv_t + s);
+      const double hh = __uint_as_float(x.x);
+      whv = fma(hh, static_cast<double>(static_cast<int16_t>(x.y & 0xffffu)) * HV_Q16_SCALE, hh);
+      wdx64 = wdx;
+      wdz64 = wdz;
     }
     if constexpr (!(WDT == RBFFD_F32 && MW)) {
       if (__builtin_expect(off == OFF_FAR, 0))
@@ -229,23 +251,29 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const FT d = f.v[c] - own.v[c];
-      sdx[c] = fma(wdx, d, sdx[c]);
-      sdz[c] = fma(wdz, d, sdz[c]);
+      if (!DIV64 || c != 0) sdx[c] = fma(wdx, d, sdx[c]);
+      if (!DIV64 || c != 1) sdz[c] = fma(wdz, d, sdz[c]);
       if (c < 3) slp[c] = fma(wlp, d, slp[c]);
       shv[c] = fma(whv, static_cast<double>(d), shv[c]);
     }
+    if constexpr (DIV64) {
+      sux = fma(wdx64, static_cast<double>(f.v[0]) - own_u, sux);
+      swz = fma(wdz64, static_cast<double>(f.v[1]) - own_w, swz);
+    }
   }
+  const double ux = DIV64 ? sux : static_cast<double>(sdx[0]);
+  const double wz = DIV64 ? swz : static_cast<double>(sdz[1]);
   // Eqs. uEq..piEq (perturbation form), evaluated in FP64; a uniform
   // background wind u_bar joins u in the advective terms
   const double u = own.v[0], w = own.v[1], th = own.v[2], pi = own.v[3];
   const double ua = u + a.u_bar;
   const double cp_th = a.c_p * (a.theta_bar + th);
   double f[4];
-  f[0] = -ua * sdx[0] - w * sdz[0] - cp_th * sdx[3] + a.mu * slp[0] + a.hv * shv[0];
-  f[1] = -ua * sdx[1] - w * sdz[1] - cp_th * sdz[3] + a.g * th / a.theta_bar + a.mu * slp[1] + a.hv * shv[1];
+  f[0] = -ua * ux - w * sdz[0] - cp_th * sdx[3] + a.mu * slp[0] + a.hv * shv[0];
+  f[1] = -ua * sdx[1] - w * wz - cp_th * sdz[3] + a.g * th / a.theta_bar + a.mu * slp[1] + a.hv * shv[1];
   f[2] = -ua * sdx[2] - w * sdz[2] + a.mu * slp[2] + a.hv * shv[2];
-  f[3] = -ua * sdx[3] - w * (a.dpibar + static_cast<double>(sdz[3])) -
-         a.rcv * (a.pibar[i] + pi) * (static_cast<double>(sdx[0]) + static_cast<double>(sdz[1])) + a.hv * shv[3];
+  f[3] = -ua * sdx[3] - w * (a.dpibar + static_cast<double>(sdz[3])) - a.rcv * (a.pibar[i] + pi) * (ux + wz) +
+         a.hv * shv[3];
   const uint8_t kd = a.kind[i];
   if (kd & KIND_ZWALL) f[1] = 0.0;  // w stays 0 on walls normal to z
   if (kd & KIND_XWALL) f[0] = 0.0;  // u stays 0 on walls normal to x
@@ -712,7 +740,7 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.off16 = m->off16.as<int16_t>();
     a.aux32 = m->aux32.as<uint32_t>();
     a.rec = m->rec.p;
-    a.hv_t = m->hv_t.as<double>();
+    a.rec2 = m->rec2.p;
     a.kind = m->kind.as<uint8_t>();
     a.pibar = m->pibar.as<double>();
     a.Na = m->Na;
@@ -897,17 +925,24 @@ int model_step(rbffd_ctx *ctx, rbffd_model *m, void *state, double *t, double dt
       if (rc) return rc;
     }
   } else {
-    if (!m->exec || !m->exec_n || m->graph_state != state || m->graph_dt != dt || m->graph_tableau != tableau) {
+    // graphs are captured for one (state, dt, tableau) and only when a call
+    // needs them: the eight-step graph for n_steps >= 8, the one-step graph
+    // for a remainder
+    if (m->graph_state != state || m->graph_dt != dt || m->graph_tableau != tableau) {
       drop_graphs(m);
-      int rc = capture_steps(ctx, m, state, dt, tableau, 1, &m->graph, &m->exec);
-      if (rc == RBFFD_OK) rc = capture_steps(ctx, m, state, dt, tableau, GRAPH_STEPS, &m->graph_n, &m->exec_n);
-      if (rc) {
-        drop_graphs(m);
-        return rc;
-      }
       m->graph_state = state;
       m->graph_dt = dt;
       m->graph_tableau = tableau;
+    }
+    int rc = RBFFD_OK;
+    if (n_steps >= GRAPH_STEPS && !m->exec_n)
+      rc = capture_steps(ctx, m, state, dt, tableau, GRAPH_STEPS, &m->graph_n, &m->exec_n);
+    if (rc == RBFFD_OK && n_steps % GRAPH_STEPS != 0 && !m->exec)
+      rc = capture_steps(ctx, m, state, dt, tableau, 1, &m->graph, &m->exec);
+    if (rc) {
+      drop_graphs(m);
+      m->graph_state = nullptr;
+      return rc;
     }
     int64_t k = 0;
     for (; k + GRAPH_STEPS <= n_steps; k += GRAPH_STEPS) RBFFD_HIP(ctx, hipGraphLaunch(m->exec_n, s));

@@ -1468,36 +1468,36 @@ __global__ void count_status_kernel(const int *status, int nc, int *counts) {
 
 }  // namespace
 
+namespace {
+constexpr int C_START = NBUCKET + 1, C_KMAX = 2 * NBUCKET + 1, C_ALL = 3 * NBUCKET + 2;
+static_assert(C_ALL == WEIGHTS_COUNTS, "scratch size formula");
+}  // namespace
+
 int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops, int precision,
-                const int32_t *idx, double *w, int32_t *status, int32_t *n_bad) {
+                const int32_t *idx, double *w, int32_t *status, int32_t *n_bad, Workspace &ws) {
   hipStream_t s = ctx->stream;
   const int nc = static_cast<int>(st->n_centers);
-  DevBuf d_k;
-  RBFFD_HIP(ctx, d_k.alloc(4 * sizeof(int)));
+  int *d_k, *d_cnt, *d_list;
+  RBFFD_WS(ctx, ws, ws.get(4, &d_k));
   // stencils bucketed by K (and the invalid ones counted), one launch per
   // non-empty bucket
-  constexpr int C_START = NBUCKET + 1, C_KMAX = 2 * NBUCKET + 1, C_ALL = 3 * NBUCKET + 2;
-  DevBuf d_cnt, d_list;
-  RBFFD_HIP(ctx, d_cnt.alloc(C_ALL * sizeof(int)));
-  RBFFD_HIP(ctx, d_list.alloc(sizeof(int) * std::max(nc, 1)));
-  RBFFD_HIP(ctx, hipMemsetAsync(d_cnt.p, 0, C_ALL * sizeof(int), s));
+  RBFFD_WS(ctx, ws, ws.get(C_ALL, &d_cnt));
+  RBFFD_WS(ctx, ws, ws.get(std::max(nc, 1), &d_list));
+  RBFFD_HIP(ctx, hipMemsetAsync(d_cnt, 0, C_ALL * sizeof(int), s));
   bucket_count_kernel<<<grid_for(nc, BK_BLOCK), BK_BLOCK, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform,
-                                                                  nc, d_cnt.as<int>(), d_cnt.as<int>() + C_KMAX);
+                                                                  nc, d_cnt, d_cnt + C_KMAX);
   RBFFD_HIP(ctx, hipGetLastError());
   int cnt[C_ALL];  // counts (and the invalid count), starts, largest K per bucket
-  RBFFD_HIP(ctx, hipMemcpyAsync(cnt, d_cnt.p, C_ALL * sizeof(int), hipMemcpyDeviceToHost, s));
+  RBFFD_HIP(ctx, hipMemcpyAsync(cnt, d_cnt, C_ALL * sizeof(int), hipMemcpyDeviceToHost, s));
   RBFFD_HIP(ctx, hipStreamSynchronize(s));
+  // n and l were checked before anything was written; this is a safeguard
   if (cnt[NBUCKET] > 0) return rbffd_fail(ctx, RBFFD_EINVAL, "%d stencils with invalid n or l", cnt[NBUCKET]);
   int kc = 0;
   for (int b = 0; b < NBUCKET; ++b) kc = std::max(kc, cnt[C_KMAX + b]);
   if (kc > 128) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d above 128", kc);
 
-  DevBuf d_status;
   int32_t *st_out = status;
-  if (!st_out) {
-    RBFFD_HIP(ctx, d_status.alloc(sizeof(int32_t) * nc));
-    st_out = d_status.as<int32_t>();
-  }
+  if (!st_out) RBFFD_WS(ctx, ws, ws.get(nc, &st_out));
   WArgs a{};
   a.xy = st->xy;
   a.period = st->period_x;
@@ -1520,35 +1520,34 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
     cnt[C_START + b] = off;  // start of bucket b
     off += cnt[b];
   }
-  RBFFD_HIP(ctx, hipMemcpyAsync(d_cnt.as<int>() + C_START, cnt + C_START, NBUCKET * sizeof(int),
-                                hipMemcpyHostToDevice, s));
+  RBFFD_HIP(ctx, hipMemcpyAsync(d_cnt + C_START, cnt + C_START, NBUCKET * sizeof(int), hipMemcpyHostToDevice, s));
   bucket_fill_kernel<<<grid_for(nc, BK_BLOCK), BK_BLOCK, 0, s>>>(st->n_per, st->n_max, st->m_per, st->m_uniform,
-                                                                 st->l_per, st->l_uniform, nc,
-                                                                 d_cnt.as<int>() + C_START, d_list.as<int>());
+                                                                 st->l_per, st->l_uniform, nc, d_cnt + C_START,
+                                                                 d_list);
   RBFFD_HIP(ctx, hipGetLastError());
   int used = 0;
   for (int b = 0; b < NBUCKET; ++b) used += cnt[b] > 0;
   // systems of up to 32 unknowns: two per wavefront; the stencils that
   // kernel leaves (a shape other than its partner's, invalid or degenerate
   // ones) are solved one per wavefront after the other buckets
-  DevBuf d_def;
+  int *d_def = nullptr;
   const bool f64 = precision == RBFFD_SOLVE_FP64;
   if (cnt[0] > 0) {
-    RBFFD_HIP(ctx, d_def.alloc(sizeof(int) * (static_cast<size_t>(cnt[0]) + 1)));
-    RBFFD_HIP(ctx, hipMemsetAsync(d_def.p, 0, sizeof(int), s));
+    RBFFD_WS(ctx, ws, ws.get(static_cast<size_t>(cnt[0]) + 1, &d_def));
+    RBFFD_HIP(ctx, hipMemsetAsync(d_def, 0, sizeof(int), s));
   }
   for (int b = 0; b < NBUCKET; ++b) {
     if (cnt[b] == 0) continue;
     const int cap = cnt[C_KMAX + b];  // the bucket's largest K
     a.k_cap = cap;
-    a.list = used > 1 ? d_list.as<int>() + cnt[C_START + b] : nullptr;
+    a.list = used > 1 ? d_list + cnt[C_START + b] : nullptr;
     if (b <= 2) {  // systems of up to 64 unknowns: one wavefront each
       if (b == 0) {
         WArgs p = a;
-        p.list = d_list.as<int>() + cnt[C_START];  // ordered by shape within blocks, even as the only bucket
+        p.list = d_list + cnt[C_START];  // ordered by shape within blocks, even as the only bucket
         p.n_list = cnt[0];
-        p.n_defer = d_def.as<int>();
-        p.defer = d_def.as<int>() + 1;
+        p.n_defer = d_def;
+        p.defer = d_def + 1;
         const int waves = (cnt[0] + 1) / 2;
         f64 ? weights_wave_kernel<32, double, 2><<<waves, 64, 0, s>>>(p)
             : weights_wave_kernel<32, float, 2><<<waves, 64, 0, s>>>(p);
@@ -1575,11 +1574,11 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   RBFFD_HIP(ctx, hipGetLastError());
   if (cnt[0] > 0) {
     int nd = 0;
-    RBFFD_HIP(ctx, hipMemcpyAsync(&nd, d_def.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    RBFFD_HIP(ctx, hipMemcpyAsync(&nd, d_def, sizeof(int), hipMemcpyDeviceToHost, s));
     RBFFD_HIP(ctx, hipStreamSynchronize(s));
     if (nd > 0) {
       WArgs f = a;
-      f.list = d_def.as<int>() + 1;
+      f.list = d_def + 1;
       f.k_cap = 32;
       f64 ? weights_wave_kernel<32, double><<<nd, 64, 0, s>>>(f) : weights_wave_kernel<32, float><<<nd, 64, 0, s>>>(f);
       RBFFD_HIP(ctx, hipGetLastError());
@@ -1588,25 +1587,25 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   // FP32 factorisation: the stencils whose refinement stalled are solved
   // again in FP64 (the same kernels, over a list of them) and marked 3
   if (precision == RBFFD_SOLVE_FP32_IR) {
-    DevBuf d_fl;
-    RBFFD_HIP(ctx, d_fl.alloc(sizeof(int) * nc));
-    RBFFD_HIP(ctx, hipMemsetAsync(d_k.p, 0, 4 * sizeof(int), s));
+    int *d_fl;
+    RBFFD_WS(ctx, ws, ws.get(nc, &d_fl));
+    RBFFD_HIP(ctx, hipMemsetAsync(d_k, 0, 4 * sizeof(int), s));
     stalled_list_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
-                                                          d_fl.as<int>(), d_k.as<int>());
+                                                          d_fl, d_k);
     RBFFD_HIP(ctx, hipGetLastError());
     int hc[2];
-    RBFFD_HIP(ctx, hipMemcpyAsync(hc, d_k.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+    RBFFD_HIP(ctx, hipMemcpyAsync(hc, d_k, sizeof(hc), hipMemcpyDeviceToHost, s));
     RBFFD_HIP(ctx, hipStreamSynchronize(s));
     if (hc[0] + hc[1] > 0) {
       WArgs f = a;
       f.max_iter = 3;  // the FP64 setting
       if (hc[0] > 0) {
-        f.list = d_fl.as<int>();
+        f.list = d_fl;
         f.k_cap = 64;
         weights_wave_kernel<64, double><<<hc[0], 64, 0, s>>>(f);
       }
       if (hc[1] > 0) {
-        f.list = d_fl.as<int>() + nc - hc[1];
+        f.list = d_fl + nc - hc[1];
         f.k_cap = kc;
         const size_t lds = sizeof(double) * (2 * static_cast<size_t>(n_ops) * kc + 4 * static_cast<size_t>(kc)) +
                            sizeof(double) * static_cast<size_t>(kc) * (kc + n_ops);
@@ -1616,17 +1615,17 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
         weights_kernel<double><<<hc[1], W_THREADS, lds, s>>>(f);
       }
       RBFFD_HIP(ctx, hipGetLastError());
-      if (hc[0] > 0) mark_fallback_kernel<<<grid_for(hc[0], 256), 256, 0, s>>>(st_out, d_fl.as<int>(), hc[0]);
+      if (hc[0] > 0) mark_fallback_kernel<<<grid_for(hc[0], 256), 256, 0, s>>>(st_out, d_fl, hc[0]);
       if (hc[1] > 0)
-        mark_fallback_kernel<<<grid_for(hc[1], 256), 256, 0, s>>>(st_out, d_fl.as<int>() + nc - hc[1], hc[1]);
+        mark_fallback_kernel<<<grid_for(hc[1], 256), 256, 0, s>>>(st_out, d_fl + nc - hc[1], hc[1]);
       RBFFD_HIP(ctx, hipGetLastError());
     }
   }
-  RBFFD_HIP(ctx, hipMemsetAsync(d_k.p, 0, 4 * sizeof(int), s));
-  count_status_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, nc, d_k.as<int>());
+  RBFFD_HIP(ctx, hipMemsetAsync(d_k, 0, 4 * sizeof(int), s));
+  count_status_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, nc, d_k);
   RBFFD_HIP(ctx, hipGetLastError());
   int hk[2];
-  RBFFD_HIP(ctx, hipMemcpyAsync(hk, d_k.p, sizeof(hk), hipMemcpyDeviceToHost, s));
+  RBFFD_HIP(ctx, hipMemcpyAsync(hk, d_k, sizeof(hk), hipMemcpyDeviceToHost, s));
   RBFFD_HIP(ctx, hipStreamSynchronize(s));
   *n_bad = hk[1] > 0 ? -hk[1] : hk[0];
   return RBFFD_OK;

@@ -2,10 +2,16 @@
 backward kernels) against the CPU oracle, and of what the trained network
 gains over the plain coarse run.
 
-Parity is with the oracle emulating the GPU's bfloat16 storage (inputs,
-weights, activations): the remaining differences are FP32 accumulation and
-tanh rounding, which can flip single bfloat16 roundings; forward outputs
-agree to 5e-3 relative l2 and gradients to 3e-2 per parameter block."""
+Parity is checked twice:
+- against the oracle emulating the GPU's bfloat16 storage (inputs, weights,
+  activations, back-propagated activations): the remaining differences are
+  FP32 accumulation order and tanh rounding, which can flip single bfloat16
+  roundings. Bars about 10x the measured differences (1e-5..4e-5): forward
+  5e-4 relative l2, loss 1e-5 relative, each gradient block 3e-4;
+- against the plain FP64 network (no rounding anywhere, its gradient pinned
+  by finite differences): the GPU may be no farther from it than the
+  bfloat16 storage itself puts the emulated network (computed in the test),
+  plus 25% and an FP32-accumulation floor of 2e-4."""
 
 import numpy as np
 import pytest
@@ -52,10 +58,19 @@ IN_SCALE = [10.0, 10.0, 5.0, 1e-3]
 OUT_SCALE = [0.05, 0.05, 0.02, 1e-5]
 
 
+BLOCKS = [("W1", OC.OW1, OC.OB1), ("b1", OC.OB1, OC.OW2), ("W2", OC.OW2, OC.OB2), ("b2", OC.OB2, OC.OW3),
+          ("W3", OC.OW3, OC.OW3 + 4 * OC.HID), ("b3", OC.OB3, OC.OB3 + 4)]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
 @pytest.mark.parametrize("act", [OC.TANH, OC.RELU])
 def test_closure_forward_and_gradient_parity(setup, act):
     """The fused forward kernel (closure_forward) and the layer-by-layer
-    kernels of the gradient against the oracle."""
+    kernels of the gradient against the oracle: the bfloat16-emulating one
+    (tight bars) and the plain FP64 network (bars from the bfloat16 effect)."""
     import torch
     st = setup
     say(f"closure: forward and gradient vs the oracle, cartesian 400 m, E = 3, activation {act}")
@@ -64,27 +79,31 @@ def test_closure_forward_and_gradient_parity(setup, act):
     p[OC.OB1:OC.OW2] = rng.normal(0, 0.1, OC.HID)
     p[OC.OB3:OC.OB3 + 4] = rng.normal(0, 0.1, 4)
     p = p.astype(np.float32)
+    p64 = p.astype(np.float64)
     cl, nodef = _closure(st, p, IN_SCALE, OUT_SCALE, act)
     s = torch.from_numpy(st["closed"].astype(np.float32)).cuda().contiguous()
     na, E = st["nd"].n_active, st["E"]
     X = OC.features(st["closed"], st["o_idx"], nodef, IN_SCALE)
-    Y, *_ = OC.forward(p.astype(np.float64), X, emulate=True, act=act)
+    Ye = OC.forward(p64, X, emulate=True, act=act)[0][:, :4]
+    Yp = OC.forward(p64, X, emulate=False, act=act)[0][:, :4]
     got = cl.forward(s).cpu().numpy().reshape(na * E, 4) / np.array(OUT_SCALE)
-    err = np.linalg.norm(got - Y[:, :4]) / np.linalg.norm(Y[:, :4])
-    say(f"   forward rel-l2 {err:.2e}")
-    assert err < 5e-3
+    e_em, e_pl, e_bf = _rel(got, Ye), _rel(got, Yp), _rel(Ye, Yp)
+    say(f"   forward rel-l2: vs emulated {e_em:.2e}, vs plain FP64 {e_pl:.2e} (bfloat16 effect {e_bf:.2e})")
+    assert e_em < 5e-4
+    assert e_pl <= 1.25 * e_bf + 2e-4
     T = rng.normal(0, 1, (na * E, 4))
-    loss_o, g_o = OC.loss_and_grad(p.astype(np.float64), X, T, emulate=True, act=act)
+    loss_e, g_e = OC.loss_and_grad(p64, X, T, emulate=True, act=act)
+    loss_p, g_p = OC.loss_and_grad(p64, X, T, emulate=False, act=act)
     g, loss = cl.gradient(s, torch.from_numpy(T.astype(np.float32)).cuda().reshape(na, E, 4).contiguous())
     g = g.cpu().numpy().astype(np.float64)
-    say(f"   loss gpu {loss:.6f} oracle {loss_o:.6f}")
-    assert abs(loss - loss_o) <= 1e-3 * loss_o
-    blocks = [("W1", OC.OW1, OC.OB1), ("b1", OC.OB1, OC.OW2), ("W2", OC.OW2, OC.OB2), ("b2", OC.OB2, OC.OW3),
-              ("W3", OC.OW3, OC.OW3 + 4 * OC.HID), ("b3", OC.OB3, OC.OB3 + 4)]
-    for name, a, b in blocks:
-        e = np.linalg.norm(g[a:b] - g_o[a:b]) / np.linalg.norm(g_o[a:b])
-        say(f"   grad {name}: rel-l2 {e:.2e}")
-        assert e < 3e-2, name
+    say(f"   loss gpu {loss:.8f} emulated {loss_e:.8f} plain {loss_p:.8f}")
+    assert abs(loss - loss_e) <= 1e-5 * loss_e
+    assert abs(loss - loss_p) <= 1.25 * abs(loss_e - loss_p) + 1e-5 * loss_p
+    for name, a, b in BLOCKS:
+        e_em, e_pl, e_bf = _rel(g[a:b], g_e[a:b]), _rel(g[a:b], g_p[a:b]), _rel(g_e[a:b], g_p[a:b])
+        say(f"   grad {name}: vs emulated {e_em:.2e}, vs plain FP64 {e_pl:.2e} (bfloat16 effect {e_bf:.2e})")
+        assert e_em < 3e-4, name
+        assert e_pl <= 1.25 * e_bf + 2e-4, name
     assert np.all(g[OC.OW3 + 4 * OC.HID:OC.OB3] == 0.0)
 
 

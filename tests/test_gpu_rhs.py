@@ -3,10 +3,11 @@ stages against the CPU oracle, through the C ABI.
 
 Tolerances: FP64 paths agree with the oracle to 1e-12 relative l2 per field
 for one evaluation (rounding-order differences only) and to 1e-9 after a
-multi-step run; the FP32-field path (FP32 first-derivative and Laplacian
-weights, FP64 hyperviscosity weights) meets 1e-6 per field on FP32
-representable inputs; BF16 weights are held to 1e-2 (bfloat16 keeps 8
-significant bits)."""
+multi-step run; the FP32-field path (FP32 weights, the divergence and the
+hyperviscosity sums in FP64 on corrected weights) meets 1e-6 per field on
+FP32-representable inputs, also on a developed flow; BF16 weights (Dx and Dz
+with an 8-bit correction, about 16 significant bits; Lap 8 bits) are held to
+2e-3 per field."""
 
 import numpy as np
 import pytest
@@ -220,7 +221,7 @@ def test_rhs_parity_fp64(R, ctx, layout, h):
     assert np.all(got[na:] == 0.0)
 
 
-@pytest.mark.parametrize("wdt,tol", [(1, 1e-6), (2, 1e-2)])
+@pytest.mark.parametrize("wdt,tol", [(1, 1e-6), (2, 2e-3)])
 @pytest.mark.parametrize("h", [400.0, 200.0])
 def test_rhs_parity_reduced_precision(R, ctx, wdt, tol, h):
     import torch
@@ -238,17 +239,47 @@ def test_rhs_parity_reduced_precision(R, ctx, wdt, tol, h):
     assert max(errs) <= tol
 
 
+@pytest.mark.parametrize("h", [400.0, 200.0])
+def test_rhs_parity_developed_state(R, ctx, h):
+    """One right-hand side on a developed flow: the hexagonal density
+    current integrated by the oracle to t = 300 s (stored by
+    tests/golden/make_developed_states.py; Section 6.4), in FP64, FP32 fields
+    and weights (on the FP32-rounded state) and BF16 weights, against the
+    oracle on the same input."""
+    import os
+    import torch
+    say(f"rhs: developed hexagonal {h} m state at t = 300 s (oracle run), FP64 / FP32 / BF16 weights")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", h)
+    path = os.path.join(os.path.dirname(__file__), "golden", f"developed_hexagonal_{int(h)}m_300s.npz")
+    st64 = np.load(path)["state"]
+    na = cfg["nodes"].n_active
+    assert st64.shape == (cfg["nodes"].n_total, 4) and np.abs(st64[:na, 2]).max() > 5.0
+    for fdt, wdt, tol in ((0, 0, 1e-12), (1, 1, 1e-6), (1, 2, 2e-3)):
+        st = st64 if fdt == 0 else st64.astype(np.float32).astype(np.float64)
+        ref, _ = O.ns_rhs(om, st)
+        gm = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=fdt, wdt=wdt)
+        s = dev(st, torch.float64 if fdt == 0 else torch.float32).reshape(gm.state_shape()).contiguous()
+        out = torch.full_like(s, float("nan"))
+        R.rbffd_rhs(ctx, gm, 300.0, s, out)
+        got = host(out).reshape(st.shape)
+        errs = rel_fields(got, ref, np.arange(na))
+        say(f"   fields {fdt} weights {wdt}: rel-l2 per field {['%.2e' % e for e in errs]} (bar {tol})")
+        assert max(errs) <= tol
+        del gm
+
+
 def test_fp32_model_rejects_hyperviscosity_weights_beyond_fp32(R, ctx):
-    """The FP32 layout stores the Lap^k weights as an FP32 value plus a
-    relative correction, so weights outside the FP32 normal range are
+    """The FP32 and BF16 layouts store the Lap^k weights as an FP32 value
+    plus a relative correction, so weights outside the FP32 normal range are
     rejected at model creation (EINVAL); FP64 weights take them."""
-    say("model: FP32 layout rejects Lap^k weights beyond the FP32 range, FP64 accepts them")
+    say("model: FP32 and BF16 layouts reject Lap^k weights beyond the FP32 range, FP64 accepts them")
     cfg, om, idx, W, Ww = ns_case("hexagonal", 400.0)
     Wbig = W.copy()
     Wbig[3] *= 1e60   # weights of about 1e-16 at 400 m end beyond 3.4e38
-    with pytest.raises(R.RbffdError) as e:
-        gpu_ns(R, ctx, cfg, idx, Wbig, Ww, fdt=1, wdt=1)
-    assert e.value.code == R.EINVAL
+    for wdt in (1, 2):
+        with pytest.raises(R.RbffdError) as e:
+            gpu_ns(R, ctx, cfg, idx, Wbig, Ww, fdt=1, wdt=wdt)
+        assert e.value.code == R.EINVAL
     gpu_ns(R, ctx, cfg, idx, Wbig, Ww, fdt=0, wdt=0).close()
 
 
@@ -501,7 +532,7 @@ def test_full_size_scale_rhs_sampled(R, ctx):
                         np.zeros(len(rows), bool), cfg["consts"], cfg["hv_coeff"])
     assert np.array_equal(idx[torch.from_numpy(rows).cuda()].cpu().numpy(), o_idx)
     for fdt, wdt, dt, tol in ((0, 0, torch.float64, 1e-12), (1, 1, torch.float32, 1e-6),
-                              (1, 2, torch.float32, 1e-2)):
+                              (1, 2, torch.float32, 2e-3)):
         gm = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
         s = dev(state, dt).reshape(gm.state_shape()).contiguous()
         out = torch.empty_like(s)

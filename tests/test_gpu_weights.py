@@ -227,8 +227,12 @@ def test_two_systems_per_wavefront(R, ctx, precision):
                     l_per=l_per, precision=precision)
 
 
-def test_weights_full_size_mixed_samples(R, ctx):
-    say("weights: 1,048,576 scattered nodes, mixed l in {3,4,5}, one launch, 120 sampled stencils")
+@pytest.mark.parametrize("precision", [0, 1])
+def test_weights_full_size_mixed_samples(R, ctx, precision):
+    """The 1M mixed batch in both solve precisions (FP64 LU, and the FP32
+    factorisation with FP64 refinement, which is accepted only at the
+    oracle's accuracy: Section 3, Eq. weights), 120 sampled stencils."""
+    say(f"weights: 1,048,576 scattered nodes, mixed l in {{3,4,5}}, 120 sampled stencils, precision {precision}")
     cfg = weights_config(1024)
     nd = cfg["nodes"]
     rng = np.random.default_rng(11)
@@ -236,7 +240,7 @@ def test_weights_full_size_mixed_samples(R, ctx):
     samp = np.concatenate([samp, np.nonzero(cfg["n_per"] == cfg["n_max"])[0][:6]])
     ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.HYPERLAP, 0, 0)]
     _weights_parity(R, ctx, nd.xy, ops, cfg["n_max"], 0, 0, 0.0, np.arange(nd.n_active), sample=samp,
-                    n_per=cfg["n_per"], m_per=cfg["m_per"], l_per=cfg["l_per"])
+                    n_per=cfg["n_per"], m_per=cfg["m_per"], l_per=cfg["l_per"], precision=precision)
 
 
 def test_weights_reproduce_polynomials(R, ctx):
@@ -316,8 +320,87 @@ def test_weights_singular_and_invalid(R, ctx):
             R.rbffd_weights(ctx, xy, bad.get("ops", [(O.DX, 0, 0)]), bad.get("n", 37), bad["m"], bad["l"],
                             centers=dev(centers, torch.int32))
         assert e.value.code == R.EINVAL
-    # a per-stencil degree outside 0..6: found by the bucketing pass on the device
+    # a per-stencil degree outside 0..6: found by the device checks
     with pytest.raises(R.RbffdError) as e:
         R.rbffd_weights(ctx, xy, [(O.DX, 0, 0)], 37, 7, 0, centers=dev(centers, torch.int32),
                         l_per=dev(np.array([4, 7], np.int32), torch.int32))
     assert e.value.code == R.EINVAL
+
+
+def test_invalid_arguments_write_nothing(R, ctx):
+    """EINVAL leaves every output as it was (rbffd.h conventions): the
+    per-stencil parameters and indices are checked on the device before the
+    search or any solve writes. Outputs are filled with sentinels; one bad
+    entry at a time -- a degree above 6, an even PHS order, a stencil too
+    small for its polynomial terms, a centre outside the node set, a given
+    stencil index outside it, Laplacian^3 of r^5 -- must leave them alone."""
+    import torch
+    say("weights/knn: invalid per-stencil arguments -> EINVAL with idx, w and status untouched")
+    nd = jittered_square(24, seed=9)
+    xy = dev(nd.xy, torch.float64)
+    nc, n = 40, 37
+    centers = np.arange(100, 100 + nc, dtype=np.int32)
+    good = dict(n_per=np.full(nc, n, np.int32), m_per=np.full(nc, 7, np.int32), l_per=np.full(nc, 4, np.int32))
+    idx_ok = R.rbffd_knn(ctx, xy, n, 0.0, centers=dev(centers, torch.int32))
+    cases = []
+    for key, at, val in (("l_per", 5, 7), ("m_per", 17, 6), ("n_per", 30, 12), ("centers", 39, nd.n_active),
+                         ("idx_in", 3, -4), ("m_per", 0, 5)):
+        cases.append((key, at, val))
+    for key, at, val in cases:
+        args = {k: v.copy() for k, v in good.items()}
+        cen = centers.copy()
+        idx_in = None
+        ops = [(O.DX, 0, 0), (O.LAP, 0, 0)]
+        if key == "centers":
+            cen[at] = val
+        elif key == "idx_in":
+            idx_in = host(idx_ok).copy()
+            idx_in[at, 20] = val
+        else:
+            args[key][at] = val
+        if key == "m_per" and val == 5:
+            ops = [(O.DX, 0, 0), (O.HYPERLAP, 3, 0)]          # Laplacian^3 of r^5: not continuous
+        idx = torch.full((nc, n), -77, dtype=torch.int32, device="cuda")
+        w = torch.full((len(ops), nc, n), 12345.0, dtype=torch.float64, device="cuda")
+        status = torch.full((nc,), 99, dtype=torch.int32, device="cuda")
+        with pytest.raises(R.RbffdError) as e:
+            R.rbffd_weights(ctx, xy, ops, n, 0, 0, centers=dev(cen, torch.int32),
+                            n_per=dev(args["n_per"], torch.int32), m_per=dev(args["m_per"], torch.int32),
+                            l_per=dev(args["l_per"], torch.int32),
+                            idx_in=None if idx_in is None else dev(idx_in, torch.int32), out=(idx, w, status))
+        assert e.value.code == R.EINVAL, (key, e.value)
+        assert f"stencil {at}" in str(e.value), (key, str(e.value))
+        assert bool((idx == -77).all()) and bool((w == 12345.0).all()) and bool((status == 99).all()), key
+        say(f"   {key}[{at}] = {val}: {e.value}")
+    # the search alone: a bad centre or stencil size writes nothing either
+    for cen, n_per in ((np.array([0, 5, nd.n_active + 3], np.int32), None),
+                       (np.array([0, 5, 9], np.int32), np.array([37, 0, 37], np.int32))):
+        out = torch.full((3, n), -77, dtype=torch.int32, device="cuda")
+        with pytest.raises(R.RbffdError) as e:
+            R.rbffd_knn(ctx, xy, n, 0.0, centers=dev(cen, torch.int32),
+                        n_per=None if n_per is None else dev(n_per, torch.int32), out=out)
+        assert e.value.code == R.EINVAL and bool((out == -77).all())
+
+
+def test_knn_dense_cluster(R, ctx):
+    """A cluster of 3,000 nodes inside one grid cell of a sparse set (more
+    candidates than the search keeps in LDS): those centres, and sparse
+    centres whose search block reaches the cluster, are finished by the exact
+    selection kernel; bit-exact against the oracle's brute-force search,
+    also with a periodic x."""
+    import torch
+    say("knn: 3,000-node cluster inside one cell of 400 sparse nodes (exact fallback), plain and periodic")
+    rng = np.random.default_rng(21)
+    sparse = rng.uniform(0.0, 1.0, (400, 2))
+    cluster = np.array([0.5, 0.5]) + rng.uniform(-1e-3, 1e-3, (3000, 2))
+    xy = np.concatenate([sparse, cluster])
+    for period in (0.0, 1.0):
+        samp = np.concatenate([np.arange(0, 400, 9), 400 + rng.choice(3000, 40, replace=False)])
+        got = host(R.rbffd_knn(ctx, dev(xy, torch.float64), 37, period, centers=dev(samp.astype(np.int32), torch.int32)))
+        for a, c in enumerate(samp):
+            ref = O.knn(xy, [int(c)], 37, period)[0]
+            assert np.array_equal(got[a], ref), (period, c)
+    # a ragged n_per with the same cluster
+    n_per = rng.integers(1, 61, 60).astype(np.int32)
+    samp = 400 + rng.choice(3000, 60, replace=False).astype(np.int32)
+    _knn_case(R, ctx, xy, 60, 0.0, centers=samp, n_per=n_per)
