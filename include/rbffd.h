@@ -146,6 +146,23 @@ int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx);
 int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
                   int precision, int32_t *idx, double *w, int32_t *status);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * operation as rbffd_weights (same arguments, outputs, status codes and
+ * kernels, bit-identical results) without any device allocation. Its scratch
+ * (search grid, bucket lists, status when `status` is NULL) is a fixed
+ * region of about 64 MiB that the library holds on every device it runs on
+ * until the process ends, set up by rbffd_create. Limits: n_nodes <=
+ * RBFFD_NOALLOC_MAX_NODES and n_centers <= RBFFD_NOALLOC_MAX_CENTERS, else
+ * RBFFD_EINVAL with nothing written. Every call on a device shares that
+ * device's region: calls that overlap on one device (from several contexts
+ * or threads) race and must be serialised by the caller. It still
+ * synchronises like rbffd_weights. */
+#define RBFFD_NOALLOC_MAX_NODES 2097152
+#define RBFFD_NOALLOC_MAX_CENTERS 2097152
+int rbffd_weights_noalloc(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
+                          int precision, int32_t *idx, double *w, int32_t *status);
+
 /* ---- B1-B4: right-hand side model -------------------------------------- */
 
 typedef struct {

@@ -1,8 +1,59 @@
 // extern "C" entry points of librbffd: argument checks and dispatch.
 #include <cstdarg>
+#include <mutex>
 #include <new>
 
 #include "common.hpp"
+
+// ---- scratch of the allocation-free weights entry point ----
+//
+// rbffd_weights_noalloc takes its device scratch from this array instead of
+// allocating. Each device holds its own copy (for as long as the process
+// runs); host code never passes the array's name to a kernel or a copy --
+// in host code it is only a stand-in -- but the device address that
+// hipGetSymbolAddress returns for the current device, taken once per device
+// by rbffd_create. The size covers the search and the weights at the
+// documented limits (RBFFD_NOALLOC_MAX_NODES, RBFFD_NOALLOC_MAX_CENTERS).
+namespace {
+constexpr size_t NOALLOC_BYTES = CHECK_SCRATCH_BYTES +
+                                 knn_scratch_bytes(RBFFD_NOALLOC_MAX_NODES, RBFFD_NOALLOC_MAX_CENTERS) +
+                                 weights_scratch_bytes(RBFFD_NOALLOC_MAX_CENTERS);
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on `device` (which must be current),
+// looked up on first use.
+hipError_t scratch_for(int device, void **out) {
+  *out = nullptr;
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
+
+int rbffd_fail(rbffd_ctx *ctx, int code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return code;
+}
 
 extern "C" {
 
@@ -19,6 +70,11 @@ int rbffd_create(rbffd_ctx **out, int device, void *hip_stream) {
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
+  // set-up of the allocation-free entry point's scratch on this device
+  if (scratch_for(device, &ctx->scratch) != hipSuccess) {
+    delete ctx;
+    return RBFFD_EDEVICE;
+  }
   *out = ctx;
   return RBFFD_OK;
 }
@@ -135,6 +191,24 @@ int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops,
   if (!st->idx_in && !idx) return rbffd_fail(ctx, RBFFD_EINVAL, "need idx output or idx_in");
   RBFFD_ENTER(ctx);
   Workspace ws;
+  return weights_impl(ctx, st, ops, n_ops, precision, idx, w, status, ws);
+}
+
+int rbffd_weights_noalloc(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
+                          int precision, int32_t *idx, double *w, int32_t *status) {
+  if (!ctx) return RBFFD_EINVAL;
+  int rc = check_weights_host(ctx, st, ops, n_ops, precision);
+  if (rc) return rc;
+  if (st->n_nodes > RBFFD_NOALLOC_MAX_NODES || st->n_centers > RBFFD_NOALLOC_MAX_CENTERS)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "%lld nodes / %lld centres beyond the allocation-free limits (%d / %d)",
+                      (long long)st->n_nodes, (long long)st->n_centers, RBFFD_NOALLOC_MAX_NODES,
+                      RBFFD_NOALLOC_MAX_CENTERS);
+  if (st->n_centers == 0) return RBFFD_OK;  // empty batch: nothing to write
+  if (!w) return rbffd_fail(ctx, RBFFD_EINVAL, "null w");
+  if (!st->idx_in && !idx) return rbffd_fail(ctx, RBFFD_EINVAL, "need idx output or idx_in");
+  if (!ctx->scratch) return rbffd_fail(ctx, RBFFD_EDEVICE, "no scratch region on device %d", ctx->device);
+  RBFFD_ENTER(ctx);
+  Workspace ws(ctx->scratch, NOALLOC_BYTES);
   return weights_impl(ctx, st, ops, n_ops, precision, idx, w, status, ws);
 }
 

@@ -16,6 +16,7 @@ struct rbffd_ctx {
   hipStream_t stream = nullptr;
   std::string last_error;
   int n_cu = 256;
+  void *scratch = nullptr;  // this device's scratch of rbffd_weights_noalloc
 };
 
 // Error helper: records a message and returns the code.

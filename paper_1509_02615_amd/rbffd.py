@@ -58,6 +58,8 @@ _lib.rbffd_sync.argtypes = [_vp]
 _lib.rbffd_knn.argtypes = [_vp, ctypes.POINTER(Stencils), _vp]
 _lib.rbffd_weights.argtypes = [_vp, ctypes.POINTER(Stencils), ctypes.POINTER(Op), ctypes.c_int,
                                ctypes.c_int, _vp, _vp, _vp]
+_lib.rbffd_weights_noalloc.argtypes = [_vp, ctypes.POINTER(Stencils), ctypes.POINTER(Op), ctypes.c_int,
+                                       ctypes.c_int, _vp, _vp, _vp]
 _lib.rbffd_model_create.argtypes = [_vp, ctypes.POINTER(ModelDesc), ctypes.POINTER(_vp)]
 _lib.rbffd_model_destroy.argtypes = [_vp]
 _lib.rbffd_ghost.argtypes = [_vp, _vp, _vp]
@@ -91,7 +93,7 @@ _lib.rbffd_closure_step.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_f64), _f64, _
                                     ctypes.POINTER(_i64)]
 
 EXPORTS = ["rbffd_create", "rbffd_destroy", "rbffd_last_error", "rbffd_sync", "rbffd_knn",
-           "rbffd_weights", "rbffd_model_create", "rbffd_model_destroy", "rbffd_ghost",
+           "rbffd_weights", "rbffd_weights_noalloc", "rbffd_model_create", "rbffd_model_destroy", "rbffd_ghost",
            "rbffd_rhs", "rbffd_step", "rbffd_model_bytes_per_node", "rbffd_model_profile",
            "rbffd_model_profile_read", "rbffd_stream_copy", "rbffd_mfma_probe", "rbffd_model_tune", "rbffd_closure_create",
            "rbffd_closure_destroy", "rbffd_closure_params", "rbffd_closure_forward", "rbffd_closure_gradient",
@@ -174,10 +176,15 @@ def rbffd_knn(ctx: Context, xy, n_max, period_x=0.0, centers=None, n_per=None, o
     return out
 
 
+NOALLOC_MAX_NODES = NOALLOC_MAX_CENTERS = 2097152
+
+
 def rbffd_weights(ctx: Context, xy, ops, n_max, m=0, l=0, period_x=0.0, centers=None, n_per=None,
-                  m_per=None, l_per=None, idx_in=None, precision=SOLVE_FP64, out=None, n_centers=None):
+                  m_per=None, l_per=None, idx_in=None, precision=SOLVE_FP64, out=None, n_centers=None,
+                  _entry=None):
     """A1-A4: returns (idx [Nc][n_max], w [n_ops][Nc][n_max] FP64, status [Nc], rc).
     ops: list of (kind, k, phs_order). rc is OK or ESINGULAR."""
+    entry = _lib.rbffd_weights if _entry is None else _entry
     st, nc = _stencils(xy, n_max, period_x, centers, n_per, m, l, m_per, l_per, idx_in, n_centers)
     dev = xy.device
     op_arr = (Op * len(ops))(*[Op(kind, k, order, 0) for (kind, k, order) in ops])
@@ -188,10 +195,17 @@ def rbffd_weights(ctx: Context, xy, ops, n_max, m=0, l=0, period_x=0.0, centers=
     else:
         idx, w, status = out
     idx_out = None if idx_in is not None else _ptr(idx, torch.int32, (nc, n_max), "idx")
-    rc = ctx.check(_lib.rbffd_weights(ctx.h, ctypes.byref(st), op_arr, len(ops), int(precision), idx_out,
+    rc = ctx.check(entry(ctx.h, ctypes.byref(st), op_arr, len(ops), int(precision), idx_out,
                                       _ptr(w, torch.float64, (len(ops), nc, n_max), "w"),
                                       _ptr(status, torch.int32, (nc,), "status")), allow=(ESINGULAR,))
     return idx, w, status, rc
+
+
+def rbffd_weights_noalloc(ctx: Context, xy, ops, n_max, out, **kw):
+    """rbffd_weights without any device allocation inside the library (its
+    scratch is a fixed per-device region): the outputs ``out`` = (idx, w,
+    status) are the caller's. Same results as rbffd_weights."""
+    return rbffd_weights(ctx, xy, ops, n_max, out=out, _entry=_lib.rbffd_weights_noalloc, **kw)
 
 
 class Model:
