@@ -35,6 +35,13 @@ FP64_PEAK_TFLOPS = 78.6
 CLOSURE_FLOP_PER_SAMPLE = 2 * (149 * 128 + 128 * 128 + 128 * 4)
 ROOT = os.path.dirname(os.path.abspath(__file__))
 COUNTERS = os.path.join(ROOT, "profiles", "ns_stage_kernel_hbm_counters.json")
+# Fixed algorithmic bytes per node-update of one RHS evaluation (all four
+# fields read and written once, int32 indices, 37 slots): FP32 Dx, Dz, Lap +
+# FP64 Lap^k weights 920 B; FP64 everything 1,396 B; BF16 Dx, Dz, Lap + FP64
+# Lap^k 698 B. The kernels stream fewer bytes (16-bit offsets, the centre slot
+# left out, Lap^k as FP32 + correction); `frac` uses their own count, and
+# `frac_fixed_count` this fixed one.
+FIXED_BYTES_PER_NODE = {"fp32": 920.0, "fp64": 1396.0, "bf16": 698.0}
 METRIC = "RHS node-updates/s & % HBM peak, FP32 vs FP64 at stated rel-L2; stencils/s"
 
 
@@ -49,20 +56,41 @@ def field_bytes_per_node_stage(tableau, fb, F=4, E=1):
     return v * (2 + 3 + 3) / 3.0
 
 
-def measured_traffic(bytes_per_launch):
-    """HBM bytes per launch of the FP32 stage kernel from the committed
-    counter passes, if the kernel sources still hash as when counted."""
+def measured_traffic(leg, bytes_per_launch):
+    """HBM bytes per launch (GB) of the stage kernel of one bench leg (fp32,
+    fp64, bf16, ensemble64_fp32) from the committed counter passes, if the
+    kernel sources still hash as when counted and the algorithmic count is
+    the same."""
     import hashlib
     try:
         d = json.load(open(COUNTERS))
         src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in d["sources"])
+        rec = d["legs"][leg]
     except (OSError, ValueError, KeyError):
         return None
     if hashlib.sha256(src).hexdigest() != d["source_sha256"]:
         return None
-    if abs(d["algorithmic_bytes_per_launch"] - bytes_per_launch) > 1.0:
+    if abs(rec["algorithmic_bytes_per_launch"] - bytes_per_launch) > 1.0:
         return None
-    return d["traffic_bytes_per_launch"] / 1e9          # GB per launch, like `achieved` per second
+    return rec["traffic_bytes_per_launch"] / 1e9          # GB per launch, like `achieved` per second
+
+
+def leg_roofline(leg, res, n_active):
+    """Roofline of one stage-kernel leg: algorithmic bytes per launch (the
+    kernel's own count, and the fixed count where one is defined) over the
+    HIP-event average launch duration, against the 8 TB/s HBM peak, with the
+    counter-measured traffic where committed."""
+    k_s = res["kernel_avg_ms"] / 1e3
+    out = {"bound": "hbm", "achieved": res["bytes_per_launch"] / k_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": res["bytes_per_launch"] / k_s / 1e9 / HBM_PEAK_GBS,
+           "traffic": measured_traffic(leg, res["bytes_per_launch"]),
+           "traffic_unit": "GB per launch (HBM counters, calibrated)", "kernel": "ns_stage_kernel",
+           "bytes_per_launch": res["bytes_per_launch"], "kernel_avg_ms": res["kernel_avg_ms"]}
+    fixed = FIXED_BYTES_PER_NODE.get(leg)
+    if fixed is not None:
+        out["fixed_bytes_per_node"] = fixed
+        out["frac_fixed_count"] = fixed * n_active / k_s / 1e9 / HBM_PEAK_GBS
+    return out
 
 
 def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup, ensemble=1):
@@ -76,7 +104,15 @@ def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup, ensembl
         s0 = s0 * (ensemble_amplitudes(ensemble) / -15.0)[None, :, None]
     state = P.to_dev(s0, dt_t).reshape(model.state_shape()).contiguous()
     shape, tune_us = R.rbffd_model_tune(ctx, model, state)
-    t = R.rbffd_step(ctx, model, state, 0.0, cfg["dt"], warmup, R.RK4)   # warm-up; captures the step graph
+    t = R.rbffd_step(ctx, model, state, 0.0, cfg["dt"], warmup, R.RK4)   # warm-up
+    # set-up outside the timed region: rbffd_step captures its eight-step and
+    # one-step graphs when a call first needs them, so eight more steps from a
+    # saved copy capture the first; the state then goes back to the copy (the
+    # graphs are bound to this buffer, not to its contents)
+    saved = state.clone()
+    R.rbffd_step(ctx, model, state, t, cfg["dt"], 8 + (1 if warmup % 8 == 0 else 0), R.RK4)
+    state.copy_(saved)
+    del saved
     # timed region: K steps, each one replay of the captured step graph
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -121,9 +157,10 @@ def run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, steps, warmup, ensembl
     return res
 
 
-def weights_leg(R, ctx, cfg, precision):
+def weights_leg(R, ctx, cfg, precision, ref=None):
     """One rbffd_weights call over a node set, after an untimed one; returns
-    stencils/s."""
+    stencils/s (and, given the oracle's weights of sampled stencils, the
+    worst sampled error)."""
     import torch
     from paper_1509_02615_amd import pipeline as P
     nd = cfg["nodes"]
@@ -133,10 +170,13 @@ def weights_leg(R, ctx, cfg, precision):
     l_per = P.to_dev(cfg["l_per"], torch.int32)
     ops = [(R.DX, 0, 0), (R.DZ, 0, 0), (R.HYPERLAP, 0, 0)]
     idx = R.rbffd_knn(ctx, xy, cfg["n_max"], 0.0, n_per=n_per)
-    # one untimed call first: the timed call then finds its output blocks
-    # (1.5 GB of weights) in torch's allocator, as a steady-state caller would
-    W = R.rbffd_weights(ctx, xy, ops, cfg["n_max"], n_per=n_per, m_per=m_per, l_per=l_per, idx_in=idx,
-                        precision=precision)
+    # one untimed tuning call first (each size bucket's launch shape, kept in
+    # the context); the timed call then also finds its output blocks (1.5 GB
+    # of weights) in torch's allocator, as a steady-state caller would
+    t0 = time.perf_counter()
+    _, W, _, _, shapes, bucket_ms = R.rbffd_weights_tune(ctx, xy, ops, cfg["n_max"], n_per=n_per, m_per=m_per,
+                                                         l_per=l_per, idx_in=idx, precision=precision)
+    tune_s = time.perf_counter() - t0
     del W
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -148,12 +188,18 @@ def weights_leg(R, ctx, cfg, precision):
     ms = ev0.elapsed_time(ev1)
     bad = int(((status == 1) | (status == 2)).sum().item())
     fallback = int((status == 3).sum().item())   # solved again in FP64 (FP32 factorisation only)
+    err = None
+    if ref:
+        rows = torch.tensor(sorted(ref), device=W.device)
+        err = sampled_weights_error(idx[rows].cpu().numpy(), W[:, rows].cpu().numpy(), ref)
     # algorithmic flops of the solves: LU of K x K (2/3 K^3) and the forward and
     # back substitution of the 3 right-hand sides (2 K^2 each); K = n + M
     K = cfg["n_per"].astype(np.float64) + (cfg["l_per"] + 1) * (cfg["l_per"] + 2) / 2
     flops = float(np.sum(2.0 / 3.0 * K ** 3 + 2.0 * K ** 2 * 3))
     return dict(stencils=nd.n_active, ms=ms, stencils_per_s=nd.n_active / (ms / 1e3), singular=bad,
-                fp64_fallback=fallback,
+                fp64_fallback=fallback, sampled_worst_rel_err_vs_oracle=err,
+                tuned_shapes=shapes, tuned_bucket_ms=bucket_ms, tune_s=tune_s,
+                sampled=None if not ref else f"{len(ref)} stencils (every 997th centre)",
                 solve_tflops=flops / (ms / 1e3) / 1e12,
                 fp64_peak_frac=flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
                 note="solve flops only (2/3 K^3 + 2 K^2 per right-hand side); assembly and "
@@ -297,6 +343,7 @@ def closure_leg(R, ctx, calls=20, members=256):
     cl = R.Closure(ctx, cm, params, nodef, [2.0, 2.0, 1.8, 3e-4], [1e-3, 1e-3, 7e-4, 3e-6],
                    activation=R.ACT_RELU)
     S = cm.Na * members
+    shape, tune_us = cl.tune(state)
     for _ in range(3):
         cl.forward(state)
     torch.cuda.synchronize()
@@ -320,7 +367,7 @@ def closure_leg(R, ctx, calls=20, members=256):
     torch.cuda.synchronize()
     corr_ms = ev0.elapsed_time(ev1) / n
     speedup = closure_speedup(R, ctx, cc, params, nodef)
-    return dict(samples=S, forward_us=fwd_s * 1e6, samples_per_s=S / fwd_s,
+    return dict(samples=S, forward_us=fwd_s * 1e6, samples_per_s=S / fwd_s, tuned_shape=shape, tune_us=tune_us,
                 roofline={"bound": "mfma", "achieved": tflops, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                           "frac": tflops / BF16_MFMA_PEAK_TFLOPS, "flop_per_sample": CLOSURE_FLOP_PER_SAMPLE},
                 plain_step_ms=plain_ms, corrected_step_ms=corr_ms, vs_fine_run=speedup,
@@ -373,7 +420,9 @@ def cpu_oracle_weights(min_seconds=10.0):
     """The oracle's weights (extended-precision assembly, LU, refinement) on a
     bounded sample of the mixed 1M batch: 120 stencils (every 997th centre;
     their stencils found by the oracle's search beforehand, untimed), solved
-    repeatedly until min_seconds have passed; single thread."""
+    repeatedly until min_seconds have passed; single thread. Also returns the
+    sample's oracle stencils and weights, against which the GPU weights legs
+    report their accuracy."""
     import oracle as O
     from workloads import weights_config
     cfg = weights_config(1024)
@@ -382,15 +431,34 @@ def cpu_oracle_weights(min_seconds=10.0):
     stencils = [O.knn(nd.xy, [c], int(cfg["n_per"][c]), 0.0)[0] for c in sample]
     ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.HYPERLAP, 0, 0)]
     done = 0
+    ref = {}
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < min_seconds:
         for c, st in zip(sample, stencils):
-            O.stencil_weights(nd.xy, st, int(c), int(cfg["m_per"][c]), int(cfg["l_per"][c]), ops, 0.0)
+            W, _ = O.stencil_weights(nd.xy, st, int(c), int(cfg["m_per"][c]), int(cfg["l_per"][c]), ops, 0.0)
+            ref.setdefault(int(c), (st, W))
             done += 1
     el = time.perf_counter() - t0
-    return dict(value=done / el, unit="stencils/s", cores=1, kind="oracle",
-                sample=f"{done} solves of 120 stencils of the mixed 1M batch (every 997th centre), "
-                       f"{el:.1f} s (numpy/scipy, single thread)")
+    res = dict(value=done / el, unit="stencils/s", cores=1, kind="oracle",
+               sample=f"{done} solves of 120 stencils of the mixed 1M batch (every 997th centre), "
+                      f"{el:.1f} s (numpy/scipy, single thread)")
+    return res, ref
+
+
+def sampled_weights_error(idx, W, ref):
+    """Worst norm-wise relative error, per stencil and operator, of GPU
+    weights against the oracle's at the sampled centres: idx [S][n_max] and
+    W [ops][S][n_max] hold the GPU rows of the centres in sorted order (None
+    when a sampled stencil differs)."""
+    worst = 0.0
+    for a, c in enumerate(sorted(ref)):
+        st, Wo = ref[c]
+        n = len(st)
+        if not np.array_equal(idx[a, :n], st):
+            return None
+        for o in range(Wo.shape[0]):
+            worst = max(worst, float(np.linalg.norm(W[o, a, :n] - Wo[o]) / np.linalg.norm(Wo[o])))
+    return worst
 
 
 def cpu_baseline(cfg, min_seconds=10.0):
@@ -474,7 +542,10 @@ def main():
                     help="run only the FP64/FP32/BF16 runs to t = 900 s and print their comparison")
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for hardware-counter passes: 2 RK4 steps of the chosen precision "
-                         "and 3 plain copies of 512 MiB (counter calibration); prints no JSON line")
+                         "(and --ensemble) and 3 plain copies of 512 MiB (counter calibration); prints no "
+                         "JSON line")
+    ap.add_argument("--ensemble", type=int, default=1, help="members of the --pmc-run model")
+    ap.add_argument("--no-fullrun", action="store_true", help="skip the runs to t = 900 s (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the multi-GPU path is not built (see the sharding notes); "
@@ -483,13 +554,13 @@ def main():
 
     # The oracle baselines run first, on the host alone: their worker
     # processes start before this process touches the GPU.
-    cpu, cpu_weights = None, None
+    cpu, cpu_weights, oracle_ref = None, None, None
     if not (args.no_cpu_baseline or args.closure_only or args.weights_only or args.fullrun_only or args.pmc_run):
         from workloads import scale_config as _scale
         cpu = cpu_baseline(_scale())
         print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
         if not args.no_extras:
-            cpu_weights = cpu_oracle_weights()
+            cpu_weights, oracle_ref = cpu_oracle_weights()
             print(f"[bench] cpu oracle weights: {cpu_weights}", file=sys.stderr, flush=True)
 
     import torch
@@ -528,8 +599,10 @@ def main():
     fdt = {"fp32": R.F32, "fp64": R.F64, "bf16": R.F32}[args.precision]
     wdt = {"fp32": R.F32, "fp64": R.F64, "bf16": R.BF16}[args.precision]
     if args.pmc_run:
-        model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
-        state = P.to_dev(cfg["state0"], torch.float64 if fdt == R.F64 else torch.float32)
+        E = args.ensemble
+        model = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt, ensemble=E)
+        s0 = np.repeat(cfg["state0"][:, None, :], E, axis=1)
+        state = P.to_dev(s0, torch.float64 if fdt == R.F64 else torch.float32)
         state = state.reshape(model.state_shape()).contiguous()
         shape, _ = R.rbffd_model_tune(ctx, model, state)     # same launch shape as the timed region
         R.rbffd_step(ctx, model, state, 0.0, cfg["dt"], 2, R.RK4)
@@ -538,8 +611,8 @@ def main():
         for _ in range(3):
             R.rbffd_stream_copy(ctx, dst, src)
         torch.cuda.synchronize()
-        log(f"[bench] pmc run done: stage kernel shape {shape}, {model.bytes_per_node()} B/node stencil stream, "
-            f"copy kernel 2 x {512 << 20} bytes per launch")
+        log(f"[bench] pmc run done: E = {E}, stage kernel shape {shape}, {model.bytes_per_node()} B/node stencil "
+            f"stream, copy kernel 2 x {512 << 20} bytes per launch")
         return
     main_leg = run_rhs_leg(R, P, ctx, cfg, idx, W, Ww, xy, fdt, wdt, args.steps, args.warmup)
     log(f"[bench] {args.precision}: {main_leg}")
@@ -555,9 +628,9 @@ def main():
                                                 max(args.steps // 10, 5), 2, ensemble=64)
         log(f"[bench] ensemble 64: {extras['ensemble64_fp32']}")
         wcfg = weights_config(1024)
-        extras["weights_mixed_1M_fp64"] = weights_leg(R, ctx, wcfg, R.SOLVE_FP64)
+        extras["weights_mixed_1M_fp64"] = weights_leg(R, ctx, wcfg, R.SOLVE_FP64, oracle_ref)
         log(f"[bench] weights fp64: {extras['weights_mixed_1M_fp64']}")
-        extras["weights_mixed_1M_fp32_ir"] = weights_leg(R, ctx, wcfg, R.SOLVE_FP32_IR)
+        extras["weights_mixed_1M_fp32_ir"] = weights_leg(R, ctx, wcfg, R.SOLVE_FP32_IR, oracle_ref)
         log(f"[bench] weights fp32+IR: {extras['weights_mixed_1M_fp32_ir']}")
         extras["closure_forward_256x2176"] = closure_leg(R, ctx)
         log(f"[bench] closure: {extras['closure_forward_256x2176']}")
@@ -565,8 +638,9 @@ def main():
         log(f"[bench] device peaks: {extras['device_peaks']}")
         extras["advection_64x64_fp64"] = advection_leg(R, P, ctx)
         log(f"[bench] advection: {extras['advection_64x64_fp64']}")
-        extras["precision_fullrun_900s"] = fullrun_leg(R, P, ctx, cfg, idx, W, Ww, xy)
-        log(f"[bench] full runs to 900 s: {extras['precision_fullrun_900s']}")
+        if not args.no_fullrun:
+            extras["precision_fullrun_900s"] = fullrun_leg(R, P, ctx, cfg, idx, W, Ww, xy)
+            log(f"[bench] full runs to 900 s: {extras['precision_fullrun_900s']}")
         # a 4x larger channel (4096 x 512 = 2,097,152 nodes, 2 GB per launch): the
         # bandwidth is not an artefact of the 256 MB Infinity Cache
         big = scale_config(4096, 512)
@@ -582,8 +656,10 @@ def main():
     if cpu_weights is not None:
         extras["cpu_oracle_weights"] = cpu_weights
 
+    for name in ("fp64", "fp32", "bf16", "ensemble64_fp32"):
+        if name in extras:
+            extras[name]["roofline"] = leg_roofline(name, extras[name], nd.n_active)
     k = main_leg
-    achieved = k["kernel_gbs"]
     line = {
         "metric": METRIC,
         "value": k["node_updates_per_s"],
@@ -600,12 +676,7 @@ def main():
         "config": {"workload": f"{cfg['name']}: density current, 524,288 active + 4,096 ghost nodes, "
                                f"r^7 + degree-4 polynomials, n=37, RK4 dt=1/16 s, E=1",
                    "stages_per_step": 4, "precision": args.precision},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(k["bytes_per_launch"]) if args.precision == "fp32" else None,
-                     "traffic_unit": "GB per launch (HBM counters, calibrated)",
-                     "kernel": "ns_stage_kernel", "bytes_per_launch": k["bytes_per_launch"],
-                     "kernel_avg_ms": k["kernel_avg_ms"]},
+        "roofline": leg_roofline(args.precision, k, nd.n_active),
         "cpu_baseline": cpu,
         "accuracy": None if "precision_fullrun_900s" not in extras else {
             "theta_rel_l2_at_900s_vs_fp64": {k: extras["precision_fullrun_900s"][k]["theta_rel_l2_vs_fp64"]

@@ -146,6 +146,33 @@ int rbffd_knn(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx);
 int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
                   int precision, int32_t *idx, double *w, int32_t *status);
 
+/* Autotuning of the batched weights (Section 3's O(n^3 N) preprocessing):
+ * stencils are grouped by system size K = n + M into RBFFD_WEIGHT_BUCKETS
+ * buckets (K <= 32, 48, 64, 80, 96, 128), each solved by one launch that
+ * drains the bucket's queue; stencils the two-systems-per-wavefront kernel
+ * cannot pair, and (FP32 factorisation) systems whose refinement stalls, go
+ * to further device-side queues drained without a host round trip. A launch
+ * shape per bucket sets the grid (workgroups per compute unit of a
+ * persistent grid, or one workgroup per system) and, for K <= 32, two systems
+ * per wavefront or one; shapes never change a system's arithmetic, so every
+ * shape gives bit-identical results. This call computes the same outputs as
+ * rbffd_weights; for every bucket whose shapes[b] is -1 it runs each of the
+ * bucket's shapes (the batch is solved once per shape), times the bucket's
+ * launches with HIP events and keeps the fastest in the context for later
+ * rbffd_weights calls; shapes[b] >= 0 forces that shape (0 is the default).
+ * shapes (host, [RBFFD_WEIGHT_BUCKETS], in/out, or NULL = tune all) returns
+ * the chosen shapes, bucket_ms (host or NULL) the chosen shapes' times.
+ * Shape counts: 4 for bucket 0 (two systems per wavefront with one wavefront
+ * per pair (0) or a persistent grid (1); one system per wavefront, one
+ * wavefront per system (2) or persistent (3)), 2 for buckets 1-2 (one
+ * wavefront per system, or persistent), 4 for buckets 3-5 (one workgroup per
+ * system, or 1, 2, 4 persistent workgroups per compute unit). A persistent
+ * grid holds as many wavefronts as the compute units keep resident. Synchronises. Errors as rbffd_weights; EINVAL
+ * for a shape outside its bucket's range. */
+#define RBFFD_WEIGHT_BUCKETS 6
+int rbffd_weights_tune(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops, int precision,
+                       int32_t *idx, double *w, int32_t *status, int32_t *shapes, double *bucket_ms);
+
 /* For callers that cannot allocate device memory -- code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc: the same
  * operation as rbffd_weights (same arguments, outputs, status codes and
@@ -319,6 +346,14 @@ float *rbffd_closure_params(rbffd_closure *cl);
 /* Correction y * out_scale for every active node and member of `state`
  * ([N][E][4] FP32, ghost rows filled): out [n_active][E][4] FP32. */
 int rbffd_closure_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, float *out);
+/* Autotuning of the fused forward pass: times each compiled launch shape
+ * (16-sample tiles per wavefront 1 or 2, wavefronts per block 4, 8 or 16,
+ * wavefronts per SIMD 2 or 4: shapes 0-4) on `state` and keeps the fastest for
+ * later forward, step and training calls; every shape computes the same
+ * correction bit for bit. *chosen (host, in/out): -1 on entry tunes, a shape
+ * 0-4 is timed and kept as given; on return the shape kept and its time per
+ * call (us). Synchronises. EINVAL for a shape above 4. */
+int rbffd_closure_tune(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int *chosen, double *best_us);
 /* Loss and its gradient with respect to the parameters for targets
  * [n_active][E][4] FP32 (already divided by out_scale); grad
  * [RBFFD_CLOSURE_NPARAMS] FP32 device (overwritten); *loss on the host.

@@ -159,9 +159,12 @@ static int check_weights_host(rbffd_ctx *ctx, const rbffd_stencils *st, const rb
 }
 
 // A1-A4 on a workspace: device argument checks (nothing is written before
-// they pass), the search (or a copy of the given stencils), then the solves.
+// they pass), the search (or a copy of the given stencils), then the solves
+// (tuned: one run per candidate launch shape, the fastest shape per size
+// bucket kept in the context).
 static int weights_impl(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops, int precision,
-                        int32_t *idx, double *w, int32_t *status, Workspace &ws) {
+                        int32_t *idx, double *w, int32_t *status, Workspace &ws, bool tune = false,
+                        int32_t *shapes = nullptr, double *ms = nullptr) {
   int rc = check_stencils_device(ctx, st, ops, n_ops, true, ws);
   if (rc) return rc;
   const int32_t *use_idx = st->idx_in;
@@ -174,7 +177,8 @@ static int weights_impl(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op
                                   hipMemcpyDeviceToDevice, ctx->stream));
   }
   int32_t n_bad = 0;
-  rc = weights_run(ctx, st, ops, n_ops, precision, use_idx, w, status, &n_bad, ws);
+  rc = tune ? weights_tune(ctx, st, ops, n_ops, precision, use_idx, w, status, &n_bad, shapes, ms)
+            : weights_run(ctx, st, ops, n_ops, precision, use_idx, w, status, &n_bad, ws);
   if (rc) return rc;
   if (n_bad < 0) return rbffd_fail(ctx, RBFFD_EINVAL, "%d stencils have invalid m, l or n", -n_bad);
   if (n_bad > 0) return rbffd_fail(ctx, RBFFD_ESINGULAR, "%d singular stencil systems", n_bad);
@@ -192,6 +196,24 @@ int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops,
   RBFFD_ENTER(ctx);
   Workspace ws;
   return weights_impl(ctx, st, ops, n_ops, precision, idx, w, status, ws);
+}
+
+int rbffd_weights_tune(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops, int precision,
+                       int32_t *idx, double *w, int32_t *status, int32_t *shapes, double *bucket_ms) {
+  if (!ctx) return RBFFD_EINVAL;
+  int rc = check_weights_host(ctx, st, ops, n_ops, precision);
+  if (rc) return rc;
+  if (shapes)
+    for (int b = 0; b < RBFFD_WEIGHT_BUCKETS; ++b)
+      if (shapes[b] < -1 || shapes[b] >= weights_shape_count(b))
+        return rbffd_fail(ctx, RBFFD_EINVAL, "shape %d of bucket %d outside -1..%d", shapes[b], b,
+                          weights_shape_count(b) - 1);
+  if (st->n_centers == 0) return RBFFD_OK;  // empty batch: nothing to write
+  if (!w) return rbffd_fail(ctx, RBFFD_EINVAL, "null w");
+  if (!st->idx_in && !idx) return rbffd_fail(ctx, RBFFD_EINVAL, "need idx output or idx_in");
+  RBFFD_ENTER(ctx);
+  Workspace ws;
+  return weights_impl(ctx, st, ops, n_ops, precision, idx, w, status, ws, true, shapes, bucket_ms);
 }
 
 int rbffd_weights_noalloc(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
@@ -287,6 +309,13 @@ int rbffd_closure_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, 
   if (!cl || !state || !out) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
   RBFFD_ENTER(ctx);
   return closure_forward(ctx, cl, state, out);
+}
+
+int rbffd_closure_tune(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int *chosen, double *best_us) {
+  if (!ctx) return RBFFD_EINVAL;
+  if (!cl || !state || !chosen || !best_us) return rbffd_fail(ctx, RBFFD_EINVAL, "null argument");
+  RBFFD_ENTER(ctx);
+  return closure_tune(ctx, cl, state, chosen, best_us);
 }
 
 int rbffd_closure_gradient(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target, float *grad,

@@ -163,23 +163,14 @@ __device__ __forceinline__ bf8v gather_block(const float *__restrict__ y, const 
 }
 
 // Y[s][0..3] for S samples, T tiles of 16 samples per wavefront; blocks of
-// MLP_WAVES wavefronts share one LDS copy of the weights and loop over
-// contiguous unit ranges (XCD-aware block order); MLP_OCC wavefronts per SIMD
-// bound the registers. Measured on 557,056 samples: one 16-wavefront block
-// per compute unit at four wavefronts per SIMD and T = 1 is fastest (more
-// wavefronts hide the gather latency better than larger tiles save LDS
-// reads of the weight fragments).
-#ifndef RBFFD_MLP_T
-#define RBFFD_MLP_T 1
-#endif
-#ifndef RBFFD_MLP_WAVES
-#define RBFFD_MLP_WAVES 16
-#endif
-#ifndef RBFFD_MLP_OCC
-#define RBFFD_MLP_OCC 4
-#endif
-constexpr int MLP_WAVES = RBFFD_MLP_WAVES, MLP_OCC = RBFFD_MLP_OCC;
-template <int T, int ACT>
+// W wavefronts share one LDS copy of the weights and loop over contiguous
+// unit ranges (XCD-aware block order); OCC wavefronts per SIMD bound the
+// registers. The launch shapes (T, W, OCC) rbffd_closure_tune chooses from
+// are kMlpShapes; a sample's arithmetic is the same in every shape. Measured
+// on 557,056 samples: one 16-wavefront block per compute unit at four
+// wavefronts per SIMD and T = 1 is fastest (more wavefronts hide the gather
+// latency better than larger tiles save LDS reads of the weight fragments).
+template <int T, int MLP_WAVES, int MLP_OCC, int ACT>
 __global__ __launch_bounds__(64 * MLP_WAVES) __attribute__((amdgpu_waves_per_eu(MLP_OCC, MLP_OCC))) void
 mlp_forward_kernel(
     const float *__restrict__ y, const int *__restrict__ idx_t, int64_t Na, int n, int E,
@@ -500,6 +491,7 @@ struct rbffd_closure {
   DevBuf loss, bad;
   int64_t step = 0;
   int act = RBFFD_ACT_TANH;
+  int shape = 0;  // fused forward launch shape (rbffd_closure_tune)
 };
 
 namespace {
@@ -581,32 +573,56 @@ void repack(rbffd_closure *cl, hipStream_t s) {
   frag_pack_kernel<<<grid_for(NFRAG * 512, 256), 256, 0, s>>>(cl->params.as<float>(), cl->frag.as<__bf16>());
 }
 
-constexpr int MLP_T = RBFFD_MLP_T;
+struct MlpShape {
+  int T, waves, occ;
+};
+constexpr MlpShape kMlpShapes[] = {{1, 16, 4}, {1, 8, 4}, {1, 4, 4}, {2, 8, 2}, {2, 4, 2}};
+constexpr int kNumMlpShapes = sizeof(kMlpShapes) / sizeof(kMlpShapes[0]);
 
-template <int ACT> void set_mlp_lds(bool &ok) {
-  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void *>(&mlp_forward_kernel<MLP_T, ACT>),
+template <int S, int ACT> auto mlp_kernel() {
+  return mlp_forward_kernel<kMlpShapes[S].T, kMlpShapes[S].waves, kMlpShapes[S].occ, ACT>;
+}
+
+template <int S> void set_mlp_lds_shape(bool &ok) {
+  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void *>(mlp_kernel<S, RBFFD_ACT_RELU>()),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(MLP_LDS)) == hipSuccess;
+  ok = ok && hipFuncSetAttribute(reinterpret_cast<const void *>(mlp_kernel<S, RBFFD_ACT_TANH>()),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(MLP_LDS)) == hipSuccess;
 }
 
-// Fused forward pass into cl->Yc [S][4]. Resident blocks per compute unit:
-// as many as LDS (160 KB, 77 KB of packed weights each) and the SIMDs'
-// wavefront slots allow; the grid is one wave of them.
-int forward_fused(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int64_t S) {
+void set_mlp_lds(bool &ok) {
+  set_mlp_lds_shape<0>(ok);
+  set_mlp_lds_shape<1>(ok);
+  set_mlp_lds_shape<2>(ok);
+  set_mlp_lds_shape<3>(ok);
+  set_mlp_lds_shape<4>(ok);
+}
+
+// Fused forward pass into cl->Yc [S][4] in launch shape S. Resident blocks per
+// compute unit: as many as LDS (160 KB, 77 KB of packed weights each) and the
+// SIMDs' wavefront slots allow; the grid is one wave of them.
+template <int SH>
+void launch_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int64_t S) {
+  constexpr MlpShape sh = kMlpShapes[SH];
   rbffd_model *m = cl->model;
-  constexpr int per_cu = std::min<int>(static_cast<int>((160 * 1024) / MLP_LDS), 4 * MLP_OCC / MLP_WAVES);
+  constexpr int per_cu = std::min<int>(static_cast<int>((160 * 1024) / MLP_LDS), 4 * sh.occ / sh.waves);
   static_assert(per_cu >= 1, "fused forward launch shape");
-  const int64_t units = (S + 16 * MLP_T - 1) / (16 * MLP_T);
+  const int64_t units = (S + 16 * sh.T - 1) / (16 * sh.T);
   const unsigned nb = static_cast<unsigned>(
-      std::max<int64_t>(1, std::min<int64_t>(256 * per_cu, (units + MLP_WAVES - 1) / MLP_WAVES)));
-  auto launch = [&](auto kern) {
-    kern<<<nb, 64 * MLP_WAVES, MLP_LDS, ctx->stream>>>(static_cast<const float *>(state), cl->idx.as<int>(), m->Na, m->n, m->E,
-                                            cl->nodef.as<float>(), cl->inv_in, cl->frag.as<__bf16>(),
-                                            cl->params.as<float>(), cl->Yc.as<float>(), S);
-  };
-  if (cl->act == RBFFD_ACT_RELU) {
-    launch(mlp_forward_kernel<MLP_T, RBFFD_ACT_RELU>);
-  } else {
-    launch(mlp_forward_kernel<MLP_T, RBFFD_ACT_TANH>);
+      std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(ctx->n_cu) * per_cu, (units + sh.waves - 1) / sh.waves)));
+  auto kern = cl->act == RBFFD_ACT_RELU ? mlp_kernel<SH, RBFFD_ACT_RELU>() : mlp_kernel<SH, RBFFD_ACT_TANH>();
+  kern<<<nb, 64 * sh.waves, MLP_LDS, ctx->stream>>>(static_cast<const float *>(state), cl->idx.as<int>(), m->Na, m->n,
+                                                    m->E, cl->nodef.as<float>(), cl->inv_in, cl->frag.as<__bf16>(),
+                                                    cl->params.as<float>(), cl->Yc.as<float>(), S);
+}
+
+int forward_fused(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int64_t S) {
+  switch (cl->shape) {
+    case 1: launch_forward<1>(ctx, cl, state, S); break;
+    case 2: launch_forward<2>(ctx, cl, state, S); break;
+    case 3: launch_forward<3>(ctx, cl, state, S); break;
+    case 4: launch_forward<4>(ctx, cl, state, S); break;
+    default: launch_forward<0>(ctx, cl, state, S); break;
   }
   RBFFD_HIP(ctx, hipGetLastError());
   return RBFFD_OK;
@@ -656,8 +672,7 @@ int closure_create(rbffd_ctx *ctx, rbffd_model *m, const rbffd_closure_desc *d, 
     return rbffd_fail(ctx, RBFFD_ENOMEM, "device allocation (closure)");
   }
   bool lds_ok = true;
-  set_mlp_lds<RBFFD_ACT_TANH>(lds_ok);
-  set_mlp_lds<RBFFD_ACT_RELU>(lds_ok);
+  set_mlp_lds(lds_ok);
   if (!lds_ok) {
     delete cl;
     return rbffd_fail(ctx, RBFFD_EDEVICE, "closure: LDS size of the fused forward kernel");
@@ -700,6 +715,45 @@ int closure_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, float 
   if (rc) return rc;
   scale_out_kernel<<<grid_for(S, 256), 256, 0, ctx->stream>>>(cl->Yc.as<float>(), 4, S, cl->out_sc, out);
   RBFFD_HIP(ctx, hipGetLastError());
+  return RBFFD_OK;
+}
+
+// Time every launch shape of the fused forward kernel on `state` (one
+// untimed call, then three timed ones each) and keep the fastest; with
+// *chosen >= 0 on entry, time and keep that shape only.
+int closure_tune(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int *chosen, double *best_us) {
+  const int64_t S = cl->model->Na * cl->model->E;
+  if (*chosen >= kNumMlpShapes) return rbffd_fail(ctx, RBFFD_EINVAL, "closure shape %d outside -1..%d", *chosen,
+                                                  kNumMlpShapes - 1);
+  const int first = *chosen >= 0 ? *chosen : 0, last = *chosen >= 0 ? *chosen : kNumMlpShapes - 1;
+  hipEvent_t e0, e1;
+  RBFFD_HIP(ctx, hipEventCreate(&e0));
+  RBFFD_HIP(ctx, hipEventCreate(&e1));
+  int best = first;
+  double best_t = -1.0;
+  int rc = RBFFD_OK;
+  for (int sh = first; sh <= last && rc == RBFFD_OK; ++sh) {
+    cl->shape = sh;
+    rc = forward_fused(ctx, cl, state, S);
+    if (rc) break;
+    if (hipEventRecord(e0, ctx->stream) != hipSuccess) rc = RBFFD_EDEVICE;
+    for (int r = 0; r < 3 && rc == RBFFD_OK; ++r) rc = forward_fused(ctx, cl, state, S);
+    float ms = 0.0f;
+    if (rc == RBFFD_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = rbffd_fail(ctx, RBFFD_EDEVICE, "closure tuning: event timing");
+    const double us = 1e3 * ms / 3.0;
+    if (rc == RBFFD_OK && (best_t < 0.0 || us < best_t)) {
+      best_t = us;
+      best = sh;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  cl->shape = best;
+  if (rc) return rc;
+  *chosen = best;
+  *best_us = best_t;
   return RBFFD_OK;
 }
 

@@ -17,6 +17,7 @@ struct rbffd_ctx {
   std::string last_error;
   int n_cu = 256;
   void *scratch = nullptr;  // this device's scratch of rbffd_weights_noalloc
+  int wshape[RBFFD_WEIGHT_BUCKETS] = {};  // weights launch shape per size bucket (rbffd_weights_tune)
 };
 
 // Error helper: records a message and returns the code.
@@ -128,7 +129,7 @@ class Workspace {
 // the weights' count array.
 constexpr int KNN_BOX_BLOCKS = 512;
 constexpr int KNN_SCAN_TILE = 4096;
-constexpr int WEIGHTS_COUNTS = 20;
+constexpr int WEIGHTS_COUNTS = 40;
 constexpr size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 constexpr size_t knn_scratch_bytes(int64_t n_nodes, int64_t n_centers) {
   // box partials, box + overflow count, cell counts, cell starts, scan tile
@@ -142,12 +143,12 @@ constexpr size_t knn_scratch_bytes(int64_t n_nodes, int64_t n_centers) {
 }
 constexpr size_t CHECK_SCRATCH_BYTES = 256;
 constexpr size_t weights_scratch_bytes(int64_t n_centers) {
-  // status counts, bucket counts, bucket lists, status (when the caller
-  // passes none), stencils left by the two-systems-per-wavefront kernel,
+  // counts and queues, bucket lists, status (when the caller passes none),
+  // stencils left by the two-systems-per-wavefront kernel,
   // FP32-factorisation stencils to solve again
   const size_t nc = static_cast<size_t>(n_centers > 1 ? n_centers : 1);
-  return round256(4 * sizeof(int)) + round256(WEIGHTS_COUNTS * sizeof(int)) + round256(nc * sizeof(int)) +
-         round256(nc * sizeof(int32_t)) + round256((nc + 1) * sizeof(int)) + round256(nc * sizeof(int));
+  return round256(WEIGHTS_COUNTS * sizeof(int)) + round256(nc * sizeof(int)) + round256(nc * sizeof(int32_t)) +
+         round256(nc * sizeof(int)) + round256(nc * sizeof(int));
 }
 
 // ---- argument checks on the device (check.hip) ----
@@ -163,9 +164,14 @@ int check_stencils_device(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_
 int knn_run(rbffd_ctx *ctx, const rbffd_stencils *st, int32_t *idx, Workspace &ws);
 
 // ---- weights (weights.hip) ----
+// `shapes`: launch shape per size bucket (NULL: the context's tuned ones);
+// `bucket_ev`: NULL, or two events per bucket recorded around its launches.
 int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops,
                 int precision, const int32_t *idx, double *w, int32_t *status, int32_t *n_bad,
-                Workspace &ws);
+                Workspace &ws, const int *shapes = nullptr, hipEvent_t *bucket_ev = nullptr);
+int weights_tune(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops, int precision,
+                 const int32_t *idx, double *w, int32_t *status, int32_t *n_bad, int32_t *shapes, double *ms);
+int weights_shape_count(int bucket);
 
 // ---- right-hand side model (model.hip / rhs.hip) ----
 struct StageArgs;
@@ -185,6 +191,7 @@ int closure_create(rbffd_ctx *ctx, rbffd_model *m, const rbffd_closure_desc *d, 
 int closure_destroy(rbffd_closure *cl);
 float *closure_params(rbffd_closure *cl);
 int closure_forward(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, float *out);
+int closure_tune(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, int *chosen, double *best_us);
 int closure_gradient(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target, float *grad,
                      double *loss);
 int closure_train_step(rbffd_ctx *ctx, rbffd_closure *cl, const void *state, const float *target, double lr,

@@ -292,6 +292,42 @@ static int fail_model(rbffd_ctx *ctx, rbffd_model *m, int code, const char *msg)
   return rbffd_fail(ctx, code, "%s", msg);
 }
 
+// Traversal order of the member-wavefront stage kernel (ensembles of 64k
+// members, where a node's member vector is 1 KiB per 64 members): the active
+// nodes in Morton (Z) order of their coordinates, so that the nodes one XCD
+// works on at a time form a compact patch whose neighbours' member vectors
+// stay in its L2 instead of being fetched again for every stencil that
+// reaches them (row-major order spans several full rows per patch).
+static int build_order(rbffd_ctx *ctx, rbffd_model *m, const double *xy_dev) {
+  const int64_t na = m->Na;
+  std::vector<double> xy(static_cast<size_t>(2 * na));
+  if (hipMemcpy(xy.data(), xy_dev, sizeof(double) * 2 * na, hipMemcpyDeviceToHost) != hipSuccess)
+    return RBFFD_EDEVICE;
+  double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+  for (int64_t i = 0; i < na; ++i)
+    for (int c = 0; c < 2; ++c) {
+      lo[c] = std::min(lo[c], xy[2 * i + c]);
+      hi[c] = std::max(hi[c], xy[2 * i + c]);
+    }
+  std::vector<std::pair<uint32_t, int>> key(static_cast<size_t>(na));
+  for (int64_t i = 0; i < na; ++i) {
+    uint32_t code = 0;
+    for (int c = 0; c < 2; ++c) {
+      const double span = hi[c] > lo[c] ? hi[c] - lo[c] : 1.0;
+      const uint32_t v = static_cast<uint32_t>(std::min(65535.0, std::max(0.0, (xy[2 * i + c] - lo[c]) / span * 65535.0)));
+      for (int b = 0; b < 16; ++b) code |= ((v >> b) & 1u) << (2 * b + c);
+    }
+    key[static_cast<size_t>(i)] = {code, static_cast<int>(i)};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int> order(static_cast<size_t>(na));
+  for (int64_t i = 0; i < na; ++i) order[static_cast<size_t>(i)] = key[static_cast<size_t>(i)].second;
+  if (m->order.alloc(sizeof(int) * na) != hipSuccess) return RBFFD_ENOMEM;
+  if (hipMemcpy(m->order.p, order.data(), sizeof(int) * na, hipMemcpyHostToDevice) != hipSuccess) return RBFFD_EDEVICE;
+  (void)ctx;
+  return RBFFD_OK;
+}
+
 int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **out) {
   hipStream_t s = ctx->stream;
   if (d->physics != RBFFD_PHYS_ADVECTION && d->physics != RBFFD_PHYS_NS)
@@ -430,6 +466,10 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
     m->bytes_per_node += 8 + 1;  // pi-bar and the node kind
     if (m->pibar.alloc(sizeof(double) * na) != hipSuccess) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation");
     pibar_kernel<<<grid_for(na, 256), 256, 0, s>>>(d->xy, na, d->g / (d->c_p * d->theta_bar), m->pibar.as<double>());
+  }
+  if (m->physics == RBFFD_PHYS_NS && m->E % 64 == 0) {
+    const int rc = build_order(ctx, m, d->xy);
+    if (rc) return fail_model(ctx, m, rc, "traversal order");
   }
   if (m->kind.alloc(m->N) != hipSuccess) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation");
   kind_kernel<<<grid_for(m->N, 256), 256, 0, s>>>(m->kind.as<uint8_t>(), m->N, na);

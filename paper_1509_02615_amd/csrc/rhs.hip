@@ -152,6 +152,7 @@ struct NSArgs {
   const void *rec2;      // second record stream (BF16 layout)
   const uint8_t *kind;
   const double *pibar;
+  const int *order;   // member-wavefront mode: node of each wavefront-sized unit (or NULL)
   int64_t Na;
   int n, E;
   double c_p, rcv, g, theta_bar, mu, hv, dpibar, u_bar;
@@ -175,8 +176,11 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
   if (t >= a.Na * a.E) return;
   const int E = a.E;
   int64_t i = E == 1 ? t : t / E;
-  if constexpr (MW) i = __builtin_amdgcn_readfirstlane(static_cast<int>(i));
-  const int e = static_cast<int>(t - i * E);
+  const int e = static_cast<int>(t - i * E);  // the member
+  if constexpr (MW) {  // a wave-uniform node, taken in the model's traversal order
+    const int li = __builtin_amdgcn_readfirstlane(static_cast<int>(i));
+    i = a.order ? a.order[li] : li;
+  }
   const FT *ys = static_cast<const FT *>(a.ys);
   const F4<FT> own = load4(ys + (i * E + e) * 4);
   FT sdx[4] = {0, 0, 0, 0}, sdz[4] = {0, 0, 0, 0}, slp[3] = {0, 0, 0};
@@ -743,6 +747,7 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.rec2 = m->rec2.p;
     a.kind = m->kind.as<uint8_t>();
     a.pibar = m->pibar.as<double>();
+    a.order = m->order.as<int>();
     a.Na = m->Na;
     a.n = m->n - m->k0;
     a.E = m->E;

@@ -63,11 +63,32 @@ struct WArgs {
   int *status;
   int k_cap;
   int max_iter;
-  const int *list;  // stencils of this launch (NULL: blockIdx.x itself)
-  int n_list;       // two systems per wavefront: stencils in the launch
-  int *defer;       // two systems per wavefront: stencils left to the one-system kernel
-  int *n_defer;     // their count
+  const int *list;    // the launch's queue of stencils, list[base .. base + count)
+                      // (NULL: the stencils base .. base + count - 1 themselves)
+  const int2 *qinfo;  // device {base, count} of the queue (NULL: {0, n_centers}); a
+                      // negative base: the queue fills `list` from its end, so its
+                      // entries are list[n_centers - count .. n_centers)
+  int *defer;         // two systems per wavefront: stencils left to the one-system kernel
+  int *n_defer;       // their count (the deferred queue's count, device)
 };
+
+// The queue a launch drains: item t is stencil list[base + t]. Launches are
+// persistent or one workgroup per item; a workgroup takes items
+// blockIdx.x, blockIdx.x + gridDim.x, ...
+struct QueueView {
+  const int *list;
+  int base, count;
+  __device__ __forceinline__ int stencil(int t) const { return list ? list[base + t] : base + t; }
+};
+__device__ __forceinline__ QueueView queue_view(const WArgs &a) {
+  QueueView v{a.list, 0, a.n_centers};
+  if (a.qinfo) {
+    const int2 qi = *a.qinfo;
+    v.count = qi.y;
+    v.base = qi.x >= 0 ? qi.x : a.n_centers - qi.y;
+  }
+  return v;
+}
 
 __device__ __forceinline__ int n_terms(int l) { return (l + 1) * (l + 2) / 2; }
 
@@ -316,10 +337,7 @@ __device__ __forceinline__ bool refined(double dm, double xm, double dprev) {
   return dm <= 0x1p-48 * xm || (dm <= 0.5 * dprev && dm * dm <= 0x1p-52 * xm * dprev);
 }
 
-template <typename T>
-__global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void weights_kernel(WArgs a) {
-  extern __shared__ double smem[];
-  const int q = a.list ? a.list[blockIdx.x] : blockIdx.x;
+template <typename T> __device__ void block_solve(const WArgs &a, double *smem, const int q) {
   const int tid = threadIdx.x;
   const int kc = a.k_cap;
   // LDS carve-up, sized by the launch's largest system kc and operator count
@@ -660,6 +678,16 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
     __syncthreads();
   }
   if (tid == 0 && a.status) a.status[q] = status;
+}
+
+template <typename T>
+__global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void weights_kernel(WArgs a) {
+  extern __shared__ double smem[];
+  const QueueView qv = queue_view(a);
+  for (int t = blockIdx.x; t < qv.count; t += gridDim.x) {
+    __syncthreads();  // the previous system's LDS reads are done
+    block_solve<T>(a, smem, qv.stencil(t));
+  }
 }
 
 // ---- one wavefront per system, rows in registers (K <= 64) ----
@@ -1031,17 +1059,11 @@ __device__ __forceinline__ bool same_shape(const WArgs &a, int q, int r) {
          (!a.l_per || a.l_per[q] == a.l_per[r]);
 }
 
-// H systems per wavefront: H = 1, or H = 2 for systems of up to 32 unknowns
-// (lanes 0-31 and 32-63). The two systems of a wavefront have the same n, m
-// and l, so every loop bound and branch on them stays wave-uniform; a
-// second stencil of another shape, and a pair with an invalid or degenerate
-// stencil, go to a.defer for the one-system kernel.
-template <int KC, typename T, int H = 1>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>()))) void weights_wave_kernel(
-    WArgs a) {
+template <int KC, typename T, int H>
+__device__ __forceinline__ void wave_solve(const WArgs &a, WaveShared<KC, T> (&SS)[H], const QueueView &qv,
+                                           const int item) {
   static_assert(KC % 8 == 0 && KC <= 64 / H && (H == 1 || H == 2), "capacity in chunks of 8, one row per lane");
   constexpr int L = 64 / H;  // lanes per system
-  __shared__ WaveShared<KC, T> SS[H];
   const int h = H == 1 ? 0 : static_cast<int>(threadIdx.x) / L;  // the lane's system
   const int lane = static_cast<int>(threadIdx.x) % L;             // the matrix row it holds
   WaveShared<KC, T> &S = SS[h];
@@ -1049,14 +1071,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
   int q, q0;
   bool writer = true;  // this lane's system writes results (not a stand-in copy)
   if constexpr (H == 1) {
-    q = __builtin_amdgcn_readfirstlane(a.list ? a.list[blockIdx.x] : static_cast<int>(blockIdx.x));
+    q = __builtin_amdgcn_readfirstlane(qv.stencil(item));
     q0 = q;
   } else {
-    const int i0 = 2 * static_cast<int>(blockIdx.x);
-    q0 = __builtin_amdgcn_readfirstlane(a.list ? a.list[i0] : i0);
+    const int i0 = 2 * item;
+    q0 = __builtin_amdgcn_readfirstlane(qv.stencil(i0));
     int q1 = q0;
-    if (i0 + 1 < a.n_list) {
-      q1 = __builtin_amdgcn_readfirstlane(a.list ? a.list[i0 + 1] : i0 + 1);
+    if (i0 + 1 < qv.count) {
+      q1 = __builtin_amdgcn_readfirstlane(qv.stencil(i0 + 1));
       if (!same_shape(a, q0, q1)) {
         if (threadIdx.x == 0) a.defer[atomicAdd(a.n_defer, 1)] = q1;
         q1 = q0;  // the upper lanes repeat system q0 without writing
@@ -1307,6 +1329,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>
   if (lane == 0 && writer && a.status) a.status[q] = status;
 }
 
+// H systems per wavefront: H = 1, or H = 2 for systems of up to 32 unknowns
+// (lanes 0-31 and 32-63). The two systems of a wavefront have the same n, m
+// and l, so every loop bound and branch on them stays wave-uniform; a
+// second stencil of another shape, and a pair with an invalid or degenerate
+// stencil, go to a.defer for the one-system kernel. The wavefront drains its
+// share of the launch's queue (items of H systems).
+template <int KC, typename T, int H = 1, bool PERSIST = false>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>()))) void weights_wave_kernel(
+    WArgs a) {
+  __shared__ WaveShared<KC, T> SS[H];
+  QueueView qv = queue_view(a);
+  qv.base = __builtin_amdgcn_readfirstlane(qv.base);
+  qv.count = __builtin_amdgcn_readfirstlane(qv.count);
+  const int items = H == 2 ? (qv.count + 1) / 2 : qv.count;
+  if constexpr (PERSIST) {
+    for (int t = blockIdx.x; t < items; t += gridDim.x) {
+      wave_sync_lds();  // the previous system's LDS reads are done
+      wave_solve<KC, T, H>(a, SS, qv, t);
+    }
+  } else {  // one wavefront per item: no loop for the compiler to hoist work out of
+    if (static_cast<int>(blockIdx.x) < items) wave_solve<KC, T, H>(a, SS, qv, blockIdx.x);
+  }
+}
+
 // Launch buckets by system size: each bucket's launch reserves LDS for its
 // own largest K, so small systems do not pay for the largest one.
 constexpr int NBUCKET = 6;
@@ -1439,23 +1485,25 @@ __global__ __launch_bounds__(BK_BLOCK) void bucket_fill_kernel(const int *n_per,
 }
 
 // Stencils whose FP32-factorisation refinement stalled (status 1), for an
-// FP64 solve: systems of up to 64 unknowns from the front of `list`, larger
-// ones from the back; counts[0] and counts[1] count them.
+// FP64 solve: systems of up to 64 unknowns into the front of `list` (queue
+// lo), larger ones into its end (queue hi); the queues' counts grow here.
 __global__ void stalled_list_kernel(const int *status, const int *n_per, int n_max, const int *l_per, int l_uni,
-                                    int nc, int *list, int *counts) {
+                                    int nc, int *list, int2 *lo, int2 *hi) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nc || status[q] != 1) return;
   const int K = (n_per ? n_per[q] : n_max) + n_terms(l_per ? l_per[q] : l_uni);
   if (K <= 64)
-    list[atomicAdd(&counts[0], 1)] = q;
+    list[atomicAdd(&lo->y, 1)] = q;
   else
-    list[nc - 1 - atomicAdd(&counts[1], 1)] = q;
+    list[nc - 1 - atomicAdd(&hi->y, 1)] = q;
 }
 
-// Listed stencils that the FP64 solve did solve: status 3.
-__global__ void mark_fallback_kernel(int *status, const int *list, int count) {
+// Stencils of both stalled queues that the FP64 solve did solve: status 3.
+__global__ void mark_fallback_kernel(int *status, const int *list, int nc, const int2 *lo, const int2 *hi) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < count && status[list[t]] == 0) status[list[t]] = 3;
+  if (t >= nc) return;
+  const bool in = t < lo->y || t >= nc - hi->y;
+  if (in && status[list[t]] == 0) status[list[t]] = 3;
 }
 
 __global__ void count_status_kernel(const int *status, int nc, int *counts) {
@@ -1466,38 +1514,107 @@ __global__ void count_status_kernel(const int *status, int nc, int *counts) {
   if (s == 2) atomicAdd(&counts[1], 1);
 }
 
-}  // namespace
+// Launch shapes of the solve kernels, chosen per size bucket by
+// rbffd_weights_tune. Wavefront buckets: one wavefront per queue item, or a
+// persistent grid of as many wavefronts as the compute units hold at the
+// kernel's occupancy, each draining items in turn; for systems of up to 32
+// unknowns also two systems per wavefront or one. Block buckets: one
+// workgroup per system or 1, 2, 4 persistent workgroups per compute unit. A
+// shape never changes a system's arithmetic.
+struct WShape {
+  bool persist, pair;
+};
+constexpr WShape kWaveShapes[] = {{false, true}, {true, true}, {false, false}, {true, false}};
+constexpr int kBlockShapes[] = {0, 1, 2, 4};
+constexpr int shape_count(int b) { return b == 0 ? 4 : b <= 2 ? 2 : 4; }
+constexpr int MAX_SHAPES = 4;
 
-namespace {
-constexpr int C_START = NBUCKET + 1, C_KMAX = 2 * NBUCKET + 1, C_ALL = 3 * NBUCKET + 2;
+// Count array layout (device, int): bucket counts and the invalid count,
+// largest K per bucket, fill cursors, queues {base, count} (the six buckets,
+// the stencils the pair kernel defers, the stalled systems of up to 64 and
+// of more unknowns), status counts.
+constexpr int Q_DEFER = NBUCKET, Q_STALL_LO = NBUCKET + 1, Q_STALL_HI = NBUCKET + 2, NQUEUE = NBUCKET + 3;
+constexpr int C_KMAX = NBUCKET + 1, C_CURSOR = 2 * NBUCKET + 1, C_Q = 3 * NBUCKET + 2,
+              C_STATUS = C_Q + 2 * NQUEUE, C_ALL = C_STATUS + 2;
+static_assert(C_Q % 2 == 0, "queues are int2");
 static_assert(C_ALL == WEIGHTS_COUNTS, "scratch size formula");
+
+inline unsigned grid_of(int64_t items, int per_cu, int n_cu) {
+  const int64_t g = per_cu > 0 ? std::min<int64_t>(items, static_cast<int64_t>(per_cu) * n_cu) : items;
+  return static_cast<unsigned>(std::max<int64_t>(g, 1));
+}
+
+// A wavefront-bucket launch: one wavefront per item, or persistent (the
+// compute units' resident wavefronts at the kernel's occupancy).
+template <int KC, typename T, int H>
+void launch_wave(const WArgs &a, int64_t items, bool persist, int n_cu, hipStream_t s) {
+  if (persist)
+    weights_wave_kernel<KC, T, H, true><<<grid_of(items, 4 * wave_occ<KC>(), n_cu), 64, 0, s>>>(a);
+  else
+    weights_wave_kernel<KC, T, H, false><<<grid_of(items, 0, n_cu), 64, 0, s>>>(a);
+}
+
+template <typename T> int launch_block(rbffd_ctx *ctx, const WArgs &a, int cap, int n_ops, unsigned grid) {
+  const size_t head = sizeof(double) * (2 * static_cast<size_t>(n_ops) * cap + 4 * static_cast<size_t>(cap));
+  const size_t lds = head + sizeof(T) * static_cast<size_t>(cap) * (cap + n_ops);
+  if (lds > 156 * 1024) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d too large for LDS", cap);
+  RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  weights_kernel<T><<<grid, W_THREADS, lds, ctx->stream>>>(a);
+  return RBFFD_OK;
+}
+
 }  // namespace
 
 int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops, int precision,
-                const int32_t *idx, double *w, int32_t *status, int32_t *n_bad, Workspace &ws) {
+                const int32_t *idx, double *w, int32_t *status, int32_t *n_bad, Workspace &ws, const int *shapes,
+                hipEvent_t *bucket_ev) {
   hipStream_t s = ctx->stream;
   const int nc = static_cast<int>(st->n_centers);
-  int *d_k, *d_cnt, *d_list;
-  RBFFD_WS(ctx, ws, ws.get(4, &d_k));
-  // stencils bucketed by K (and the invalid ones counted), one launch per
-  // non-empty bucket
+  const int n_cu = ctx->n_cu;
+  if (!shapes) shapes = ctx->wshape;
+  int *d_cnt, *d_list;
   RBFFD_WS(ctx, ws, ws.get(C_ALL, &d_cnt));
   RBFFD_WS(ctx, ws, ws.get(std::max(nc, 1), &d_list));
   RBFFD_HIP(ctx, hipMemsetAsync(d_cnt, 0, C_ALL * sizeof(int), s));
+  // stencils bucketed by K (and the invalid ones counted)
   bucket_count_kernel<<<grid_for(nc, BK_BLOCK), BK_BLOCK, 0, s>>>(st->n_per, st->n_max, st->l_per, st->l_uniform,
                                                                   nc, d_cnt, d_cnt + C_KMAX);
   RBFFD_HIP(ctx, hipGetLastError());
-  int cnt[C_ALL];  // counts (and the invalid count), starts, largest K per bucket
-  RBFFD_HIP(ctx, hipMemcpyAsync(cnt, d_cnt, C_ALL * sizeof(int), hipMemcpyDeviceToHost, s));
+  int cnt[C_ALL];  // counts (and the invalid count), largest K per bucket, cursors, queues
+  RBFFD_HIP(ctx, hipMemcpyAsync(cnt, d_cnt, C_CURSOR * sizeof(int), hipMemcpyDeviceToHost, s));
   RBFFD_HIP(ctx, hipStreamSynchronize(s));
   // n and l were checked before anything was written; this is a safeguard
   if (cnt[NBUCKET] > 0) return rbffd_fail(ctx, RBFFD_EINVAL, "%d stencils with invalid n or l", cnt[NBUCKET]);
-  int kc = 0;
-  for (int b = 0; b < NBUCKET; ++b) kc = std::max(kc, cnt[C_KMAX + b]);
+  int kc = 0, n_small = 0, n_large = 0;
+  for (int b = 0; b < NBUCKET; ++b) {
+    kc = std::max(kc, cnt[C_KMAX + b]);
+    (b <= 2 ? n_small : n_large) += cnt[b];
+  }
   if (kc > 128) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d above 128", kc);
 
   int32_t *st_out = status;
   if (!st_out) RBFFD_WS(ctx, ws, ws.get(nc, &st_out));
+  // queues: bucket b at its prefix offset in the list (its fill cursor starts
+  // there), the deferred and stalled queues empty
+  for (int b = 0, off = 0; b < NBUCKET; ++b) {
+    cnt[C_CURSOR + b] = off;
+    cnt[C_Q + 2 * b] = off;
+    cnt[C_Q + 2 * b + 1] = cnt[b];
+    off += cnt[b];
+  }
+  for (int q = NBUCKET; q < NQUEUE; ++q) {
+    cnt[C_Q + 2 * q] = q == Q_STALL_HI ? -1 : 0;
+    cnt[C_Q + 2 * q + 1] = 0;
+  }
+  RBFFD_HIP(ctx, hipMemcpyAsync(d_cnt + C_CURSOR, cnt + C_CURSOR, (C_STATUS - C_CURSOR) * sizeof(int),
+                                hipMemcpyHostToDevice, s));
+  bucket_fill_kernel<<<grid_for(nc, BK_BLOCK), BK_BLOCK, 0, s>>>(st->n_per, st->n_max, st->m_per, st->m_uniform,
+                                                                 st->l_per, st->l_uniform, nc, d_cnt + C_CURSOR,
+                                                                 d_list);
+  RBFFD_HIP(ctx, hipGetLastError());
+  int2 *queue = reinterpret_cast<int2 *>(d_cnt + C_Q);
+
   WArgs a{};
   a.xy = st->xy;
   a.period = st->period_x;
@@ -1516,117 +1633,130 @@ int weights_run(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, i
   a.w = w;
   a.status = st_out;
   a.max_iter = precision == RBFFD_SOLVE_FP64 ? 3 : 30;
-  for (int b = 0, off = 0; b < NBUCKET; ++b) {
-    cnt[C_START + b] = off;  // start of bucket b
-    off += cnt[b];
-  }
-  RBFFD_HIP(ctx, hipMemcpyAsync(d_cnt + C_START, cnt + C_START, NBUCKET * sizeof(int), hipMemcpyHostToDevice, s));
-  bucket_fill_kernel<<<grid_for(nc, BK_BLOCK), BK_BLOCK, 0, s>>>(st->n_per, st->n_max, st->m_per, st->m_uniform,
-                                                                 st->l_per, st->l_uniform, nc, d_cnt + C_START,
-                                                                 d_list);
-  RBFFD_HIP(ctx, hipGetLastError());
-  int used = 0;
-  for (int b = 0; b < NBUCKET; ++b) used += cnt[b] > 0;
-  // systems of up to 32 unknowns: two per wavefront; the stencils that
-  // kernel leaves (a shape other than its partner's, invalid or degenerate
-  // ones) are solved one per wavefront after the other buckets
-  int *d_def = nullptr;
+  a.list = d_list;
   const bool f64 = precision == RBFFD_SOLVE_FP64;
-  if (cnt[0] > 0) {
-    RBFFD_WS(ctx, ws, ws.get(static_cast<size_t>(cnt[0]) + 1, &d_def));
-    RBFFD_HIP(ctx, hipMemsetAsync(d_def, 0, sizeof(int), s));
-  }
+  int *d_def = nullptr;
+  if (cnt[0] > 0) RBFFD_WS(ctx, ws, ws.get(cnt[0], &d_def));
   for (int b = 0; b < NBUCKET; ++b) {
-    if (cnt[b] == 0) continue;
-    const int cap = cnt[C_KMAX + b];  // the bucket's largest K
-    a.k_cap = cap;
-    a.list = used > 1 ? d_list + cnt[C_START + b] : nullptr;
-    if (b <= 2) {  // systems of up to 64 unknowns: one wavefront each
+    if (bucket_ev) RBFFD_HIP(ctx, hipEventRecord(bucket_ev[2 * b], s));
+    if (cnt[b] > 0) {
+      a.qinfo = queue + b;
+      a.k_cap = cnt[C_KMAX + b];  // the bucket's largest K
       if (b == 0) {
-        WArgs p = a;
-        p.list = d_list + cnt[C_START];  // ordered by shape within blocks, even as the only bucket
-        p.n_list = cnt[0];
-        p.n_defer = d_def;
-        p.defer = d_def + 1;
-        const int waves = (cnt[0] + 1) / 2;
-        f64 ? weights_wave_kernel<32, double, 2><<<waves, 64, 0, s>>>(p)
-            : weights_wave_kernel<32, float, 2><<<waves, 64, 0, s>>>(p);
-      } else if (b == 1)
-        f64 ? weights_wave_kernel<48, double><<<cnt[b], 64, 0, s>>>(a) : weights_wave_kernel<48, float><<<cnt[b], 64, 0, s>>>(a);
-      else
-        f64 ? weights_wave_kernel<64, double><<<cnt[b], 64, 0, s>>>(a) : weights_wave_kernel<64, float><<<cnt[b], 64, 0, s>>>(a);
-      continue;
-    }
-    const size_t head = sizeof(double) * (2 * static_cast<size_t>(n_ops) * cap + 4 * static_cast<size_t>(cap));
-    if (precision == RBFFD_SOLVE_FP64) {
-      const size_t lds = head + sizeof(double) * static_cast<size_t>(cap) * (cap + n_ops);
-      if (lds > 156 * 1024) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d too large for LDS", cap);
-      RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<double>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-      weights_kernel<double><<<cnt[b], W_THREADS, lds, s>>>(a);
-    } else {
-      const size_t lds = head + sizeof(float) * static_cast<size_t>(cap) * (cap + n_ops);
-      RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<float>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-      weights_kernel<float><<<cnt[b], W_THREADS, lds, s>>>(a);
-    }
-  }
-  RBFFD_HIP(ctx, hipGetLastError());
-  if (cnt[0] > 0) {
-    int nd = 0;
-    RBFFD_HIP(ctx, hipMemcpyAsync(&nd, d_def, sizeof(int), hipMemcpyDeviceToHost, s));
-    RBFFD_HIP(ctx, hipStreamSynchronize(s));
-    if (nd > 0) {
-      WArgs f = a;
-      f.list = d_def + 1;
-      f.k_cap = 32;
-      f64 ? weights_wave_kernel<32, double><<<nd, 64, 0, s>>>(f) : weights_wave_kernel<32, float><<<nd, 64, 0, s>>>(f);
+        // systems of up to 32 unknowns: two per wavefront, then the stencils
+        // that kernel defers (a shape other than its partner's, a degenerate
+        // one) one per wavefront, persistent over their device-counted queue;
+        // or all one per wavefront
+        const WShape sh = kWaveShapes[shapes[0]];
+        if (sh.pair) {
+          WArgs p = a;
+          p.defer = d_def;
+          p.n_defer = &queue[Q_DEFER].y;
+          f64 ? launch_wave<32, double, 2>(p, (cnt[0] + 1) / 2, sh.persist, n_cu, s)
+              : launch_wave<32, float, 2>(p, (cnt[0] + 1) / 2, sh.persist, n_cu, s);
+          WArgs f = a;
+          f.list = d_def;
+          f.qinfo = queue + Q_DEFER;
+          f64 ? launch_wave<32, double, 1>(f, cnt[0], true, n_cu, s) : launch_wave<32, float, 1>(f, cnt[0], true, n_cu, s);
+        } else {
+          f64 ? launch_wave<32, double, 1>(a, cnt[0], sh.persist, n_cu, s)
+              : launch_wave<32, float, 1>(a, cnt[0], sh.persist, n_cu, s);
+        }
+      } else if (b <= 2) {  // systems of up to 64 unknowns: one wavefront each
+        const bool persist = kWaveShapes[shapes[b]].persist;
+        if (b == 1)
+          f64 ? launch_wave<48, double, 1>(a, cnt[b], persist, n_cu, s)
+              : launch_wave<48, float, 1>(a, cnt[b], persist, n_cu, s);
+        else
+          f64 ? launch_wave<64, double, 1>(a, cnt[b], persist, n_cu, s)
+              : launch_wave<64, float, 1>(a, cnt[b], persist, n_cu, s);
+      } else {  // one 256-thread workgroup per system
+        const unsigned g = grid_of(cnt[b], kBlockShapes[shapes[b]], n_cu);
+        const int rc = f64 ? launch_block<double>(ctx, a, a.k_cap, n_ops, g) : launch_block<float>(ctx, a, a.k_cap, n_ops, g);
+        if (rc) return rc;
+      }
       RBFFD_HIP(ctx, hipGetLastError());
     }
+    if (bucket_ev) RBFFD_HIP(ctx, hipEventRecord(bucket_ev[2 * b + 1], s));
   }
   // FP32 factorisation: the stencils whose refinement stalled are solved
-  // again in FP64 (the same kernels, over a list of them) and marked 3
-  if (precision == RBFFD_SOLVE_FP32_IR) {
+  // again in FP64 (the same kernels, over the stalled queues) and marked 3
+  if (!f64) {
     int *d_fl;
     RBFFD_WS(ctx, ws, ws.get(nc, &d_fl));
-    RBFFD_HIP(ctx, hipMemsetAsync(d_k, 0, 4 * sizeof(int), s));
     stalled_list_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, st->n_per, st->n_max, st->l_per, st->l_uniform, nc,
-                                                          d_fl, d_k);
-    RBFFD_HIP(ctx, hipGetLastError());
-    int hc[2];
-    RBFFD_HIP(ctx, hipMemcpyAsync(hc, d_k, sizeof(hc), hipMemcpyDeviceToHost, s));
-    RBFFD_HIP(ctx, hipStreamSynchronize(s));
-    if (hc[0] + hc[1] > 0) {
-      WArgs f = a;
-      f.max_iter = 3;  // the FP64 setting
-      if (hc[0] > 0) {
-        f.list = d_fl;
-        f.k_cap = 64;
-        weights_wave_kernel<64, double><<<hc[0], 64, 0, s>>>(f);
-      }
-      if (hc[1] > 0) {
-        f.list = d_fl + nc - hc[1];
-        f.k_cap = kc;
-        const size_t lds = sizeof(double) * (2 * static_cast<size_t>(n_ops) * kc + 4 * static_cast<size_t>(kc)) +
-                           sizeof(double) * static_cast<size_t>(kc) * (kc + n_ops);
-        if (lds > 156 * 1024) return rbffd_fail(ctx, RBFFD_EINVAL, "system size %d too large for LDS", kc);
-        RBFFD_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(&weights_kernel<double>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-        weights_kernel<double><<<hc[1], W_THREADS, lds, s>>>(f);
-      }
-      RBFFD_HIP(ctx, hipGetLastError());
-      if (hc[0] > 0) mark_fallback_kernel<<<grid_for(hc[0], 256), 256, 0, s>>>(st_out, d_fl, hc[0]);
-      if (hc[1] > 0)
-        mark_fallback_kernel<<<grid_for(hc[1], 256), 256, 0, s>>>(st_out, d_fl + nc - hc[1], hc[1]);
-      RBFFD_HIP(ctx, hipGetLastError());
+                                                          d_fl, queue + Q_STALL_LO, queue + Q_STALL_HI);
+    WArgs f = a;
+    f.max_iter = 3;  // the FP64 setting
+    f.list = d_fl;
+    if (n_small > 0) {
+      f.qinfo = queue + Q_STALL_LO;
+      f.k_cap = 64;
+      launch_wave<64, double, 1>(f, n_small, true, n_cu, s);
     }
+    if (n_large > 0) {
+      f.qinfo = queue + Q_STALL_HI;
+      f.k_cap = kc;
+      const int rc = launch_block<double>(ctx, f, kc, n_ops, grid_of(n_large, 2, n_cu));
+      if (rc) return rc;
+    }
+    mark_fallback_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, d_fl, nc, queue + Q_STALL_LO, queue + Q_STALL_HI);
+    RBFFD_HIP(ctx, hipGetLastError());
   }
-  RBFFD_HIP(ctx, hipMemsetAsync(d_k, 0, 4 * sizeof(int), s));
-  count_status_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, nc, d_k);
+  count_status_kernel<<<grid_for(nc, 256), 256, 0, s>>>(st_out, nc, d_cnt + C_STATUS);
   RBFFD_HIP(ctx, hipGetLastError());
   int hk[2];
-  RBFFD_HIP(ctx, hipMemcpyAsync(hk, d_k, sizeof(hk), hipMemcpyDeviceToHost, s));
+  RBFFD_HIP(ctx, hipMemcpyAsync(hk, d_cnt + C_STATUS, sizeof(hk), hipMemcpyDeviceToHost, s));
   RBFFD_HIP(ctx, hipStreamSynchronize(s));
   *n_bad = hk[1] > 0 ? -hk[1] : hk[0];
   return RBFFD_OK;
+}
+
+int weights_shape_count(int bucket) { return bucket >= 0 && bucket < NBUCKET ? shape_count(bucket) : 0; }
+
+int weights_tune(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, int n_ops, int precision,
+                 const int32_t *idx, double *w, int32_t *status, int32_t *n_bad, int32_t *shapes, double *ms) {
+  int forced[NBUCKET], best[NBUCKET], cur[NBUCKET];
+  double best_ms[NBUCKET];
+  for (int b = 0; b < NBUCKET; ++b) {
+    forced[b] = shapes ? shapes[b] : -1;
+    if (forced[b] >= shape_count(b))
+      return rbffd_fail(ctx, RBFFD_EINVAL, "shape %d of bucket %d outside 0..%d", forced[b], b, shape_count(b) - 1);
+    best[b] = forced[b] >= 0 ? forced[b] : ctx->wshape[b];
+    best_ms[b] = -1.0;
+  }
+  hipEvent_t ev[2 * NBUCKET] = {};
+  for (auto &e : ev) RBFFD_HIP(ctx, hipEventCreate(&e));
+  int rc = RBFFD_OK;
+  for (int sh = 0; sh < MAX_SHAPES && rc == RBFFD_OK; ++sh) {
+    bool any = false;
+    for (int b = 0; b < NBUCKET; ++b) {
+      const bool trial = forced[b] < 0 && sh < shape_count(b);
+      cur[b] = trial ? sh : best[b];
+      any = any || trial || (forced[b] >= 0 && sh == 0);
+    }
+    if (!any) continue;
+    Workspace ws;
+    rc = weights_run(ctx, st, ops, n_ops, precision, idx, w, status, n_bad, ws, cur, ev);
+    for (int b = 0; b < NBUCKET && rc == RBFFD_OK; ++b) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, ev[2 * b], ev[2 * b + 1]) != hipSuccess) continue;
+      if ((forced[b] < 0 && sh < shape_count(b)) || (forced[b] >= 0 && sh == 0)) {
+        if (best_ms[b] < 0.0 || t < best_ms[b]) {
+          best_ms[b] = t;
+          best[b] = cur[b];
+        }
+      }
+    }
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  for (int b = 0; b < NBUCKET; ++b) {
+    ctx->wshape[b] = best[b];
+    if (shapes) shapes[b] = best[b];
+    if (ms) ms[b] = best_ms[b];
+  }
+  // the outputs of the chosen shapes (every shape gives the same results)
+  Workspace ws;
+  return weights_run(ctx, st, ops, n_ops, precision, idx, w, status, n_bad, ws, best, nullptr);
 }

@@ -58,6 +58,8 @@ _lib.rbffd_sync.argtypes = [_vp]
 _lib.rbffd_knn.argtypes = [_vp, ctypes.POINTER(Stencils), _vp]
 _lib.rbffd_weights.argtypes = [_vp, ctypes.POINTER(Stencils), ctypes.POINTER(Op), ctypes.c_int,
                                ctypes.c_int, _vp, _vp, _vp]
+_lib.rbffd_weights_tune.argtypes = [_vp, ctypes.POINTER(Stencils), ctypes.POINTER(Op), ctypes.c_int,
+                                    ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_f64)]
 _lib.rbffd_weights_noalloc.argtypes = [_vp, ctypes.POINTER(Stencils), ctypes.POINTER(Op), ctypes.c_int,
                                        ctypes.c_int, _vp, _vp, _vp]
 _lib.rbffd_model_create.argtypes = [_vp, ctypes.POINTER(ModelDesc), ctypes.POINTER(_vp)]
@@ -87,16 +89,17 @@ _lib.rbffd_closure_destroy.argtypes = [_vp]
 _lib.rbffd_closure_params.argtypes = [_vp]
 _lib.rbffd_closure_params.restype = _vp
 _lib.rbffd_closure_forward.argtypes = [_vp, _vp, _vp, _vp]
+_lib.rbffd_closure_tune.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_f64)]
 _lib.rbffd_closure_gradient.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_f64)]
 _lib.rbffd_closure_train_step.argtypes = [_vp, _vp, _vp, _vp, _f64, ctypes.POINTER(_f64)]
 _lib.rbffd_closure_step.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_f64), _f64, _i64, ctypes.c_int,
                                     ctypes.POINTER(_i64)]
 
 EXPORTS = ["rbffd_create", "rbffd_destroy", "rbffd_last_error", "rbffd_sync", "rbffd_knn",
-           "rbffd_weights", "rbffd_weights_noalloc", "rbffd_model_create", "rbffd_model_destroy", "rbffd_ghost",
+           "rbffd_weights", "rbffd_weights_tune", "rbffd_weights_noalloc", "rbffd_model_create", "rbffd_model_destroy", "rbffd_ghost",
            "rbffd_rhs", "rbffd_step", "rbffd_model_bytes_per_node", "rbffd_model_profile",
            "rbffd_model_profile_read", "rbffd_stream_copy", "rbffd_mfma_probe", "rbffd_model_tune", "rbffd_closure_create",
-           "rbffd_closure_destroy", "rbffd_closure_params", "rbffd_closure_forward", "rbffd_closure_gradient",
+           "rbffd_closure_destroy", "rbffd_closure_params", "rbffd_closure_forward", "rbffd_closure_tune", "rbffd_closure_gradient",
            "rbffd_closure_train_step", "rbffd_closure_step"]
 
 
@@ -177,6 +180,8 @@ def rbffd_knn(ctx: Context, xy, n_max, period_x=0.0, centers=None, n_per=None, o
 
 
 NOALLOC_MAX_NODES = NOALLOC_MAX_CENTERS = 2097152
+WEIGHT_BUCKETS = 6
+WEIGHT_SHAPES = [4, 2, 2, 4, 4, 4]     # launch shapes per size bucket
 
 
 def rbffd_weights(ctx: Context, xy, ops, n_max, m=0, l=0, period_x=0.0, centers=None, n_per=None,
@@ -199,6 +204,19 @@ def rbffd_weights(ctx: Context, xy, ops, n_max, m=0, l=0, period_x=0.0, centers=
                                       _ptr(w, torch.float64, (len(ops), nc, n_max), "w"),
                                       _ptr(status, torch.int32, (nc,), "status")), allow=(ESINGULAR,))
     return idx, w, status, rc
+
+
+def rbffd_weights_tune(ctx: Context, xy, ops, n_max, shapes=None, **kw):
+    """rbffd_weights that also picks each size bucket's launch shape (kept in
+    the context for later calls). ``shapes``: per-bucket list, -1 = tune,
+    >= 0 = force. Returns (idx, w, status, rc, chosen shapes, ms per bucket)."""
+    sh = (_i32 * WEIGHT_BUCKETS)(*([-1] * WEIGHT_BUCKETS if shapes is None else shapes))
+    ms = (_f64 * WEIGHT_BUCKETS)()
+
+    def entry(h, st, op_arr, n_ops, prec, idx_out, w, status):
+        return _lib.rbffd_weights_tune(h, st, op_arr, n_ops, prec, idx_out, w, status, sh, ms)
+    idx, w, status, rc = rbffd_weights(ctx, xy, ops, n_max, _entry=entry, **kw)
+    return idx, w, status, rc, list(sh), list(ms)
 
 
 def rbffd_weights_noalloc(ctx: Context, xy, ops, n_max, out, **kw):
@@ -366,6 +384,14 @@ class Closure:
         out = torch.empty((self.model.Na, self.model.E, 4), dtype=torch.float32, device="cuda")
         self.ctx.check(_lib.rbffd_closure_forward(self.ctx.h, self.h, self.model._state(state), out.data_ptr()))
         return out
+
+    def tune(self, state, shape=-1):
+        """rbffd_closure_tune: (chosen launch shape, us per forward call);
+        ``shape`` >= 0 forces that shape."""
+        ch, us = ctypes.c_int(shape), _f64()
+        self.ctx.check(_lib.rbffd_closure_tune(self.ctx.h, self.h, self.model._state(state), ctypes.byref(ch),
+                                               ctypes.byref(us)))
+        return ch.value, us.value
 
     def gradient(self, state, target):
         g = torch.empty(CLOSURE_NPARAMS, dtype=torch.float32, device="cuda")

@@ -107,6 +107,26 @@ def test_closure_forward_and_gradient_parity(setup, act):
     assert np.all(g[OC.OW3 + 4 * OC.HID:OC.OB3] == 0.0)
 
 
+def test_closure_tuner_shapes_are_bit_identical(setup):
+    """Every launch shape of the fused forward kernel (tiles per wavefront,
+    wavefronts per block, occupancy) computes the same correction bit for
+    bit; the tuner keeps one of them."""
+    import torch
+    st = setup
+    say("closure tuner: every forward launch shape bit-identical")
+    p = OC.init_params(seed=5)
+    cl, _ = _closure(st, p, IN_SCALE, OUT_SCALE, OC.RELU)
+    s = torch.from_numpy(st["closed"].astype(np.float32)).cuda().contiguous()
+    ref = cl.forward(s)
+    for shape in range(5):
+        got, us = cl.tune(s, shape)
+        assert got == shape
+        assert torch.equal(cl.forward(s), ref), shape
+        say(f"   shape {shape}: {us:.1f} us per call")
+    chosen, us = cl.tune(s)
+    assert 0 <= chosen < 5 and torch.equal(cl.forward(s), ref)
+
+
 def test_closure_training_lowers_the_loss(setup):
     import torch
     st = setup

@@ -404,3 +404,37 @@ def test_knn_dense_cluster(R, ctx):
     n_per = rng.integers(1, 61, 60).astype(np.int32)
     samp = 400 + rng.choice(3000, 60, replace=False).astype(np.int32)
     _knn_case(R, ctx, xy, 60, 0.0, centers=samp, n_per=n_per)
+
+
+def test_weights_tuner_shapes_are_bit_identical(R, ctx):
+    """Every launch shape of every size bucket (persistent grids of 8-24
+    workgroups per compute unit or one per system; two systems per wavefront
+    or one for K <= 32) gives the same idx, weights and status bit for bit,
+    in both solve precisions; rbffd_weights_tune picks a shape per bucket and
+    later rbffd_weights calls, which use it, give the same results again."""
+    import torch
+    say("weights tuner: every shape of every bucket bit-identical (mixed 40x40 batch, FP64 and FP32+IR)")
+    cfg = weights_config(40, seed=5)
+    nd = cfg["nodes"]
+    xy = dev(nd.xy, torch.float64)
+    kw = dict(n_per=dev(cfg["n_per"], torch.int32), m_per=dev(cfg["m_per"], torch.int32),
+              l_per=dev(cfg["l_per"], torch.int32))
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.HYPERLAP, 0, 0)]
+    for prec in (R.SOLVE_FP64, R.SOLVE_FP32_IR):
+        ref = R.rbffd_weights(ctx, xy, ops, cfg["n_max"], precision=prec, **kw)
+        for s in range(max(R.WEIGHT_SHAPES)):
+            forced = [min(s, c - 1) for c in R.WEIGHT_SHAPES]
+            got = R.rbffd_weights_tune(ctx, xy, ops, cfg["n_max"], shapes=forced, precision=prec, **kw)
+            assert got[4] == forced
+            for a, b in zip(got[:3], ref[:3]):
+                assert torch.equal(a, b), (prec, forced)
+        idx, W, status, rc, chosen, ms = R.rbffd_weights_tune(ctx, xy, ops, cfg["n_max"], precision=prec, **kw)
+        say(f"   precision {prec}: tuned shapes {chosen}, bucket ms {['%.3f' % t for t in ms]}")
+        assert all(0 <= c < n for c, n in zip(chosen, R.WEIGHT_SHAPES))
+        after = R.rbffd_weights(ctx, xy, ops, cfg["n_max"], precision=prec, **kw)
+        for a, b in zip((idx, W, status) + after[:3], ref[:3] * 2):
+            assert torch.equal(a, b)
+    R.rbffd_weights_tune(ctx, xy, ops, cfg["n_max"], shapes=[0] * 6, **kw)   # back to the default shapes
+    with pytest.raises(R.RbffdError) as e:
+        R.rbffd_weights_tune(ctx, xy, ops, cfg["n_max"], shapes=[10, 0, 0, 0, 0, 0], **kw)
+    assert e.value.code == R.EINVAL
