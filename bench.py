@@ -375,6 +375,18 @@ def closure_leg(R, ctx, calls=20, members=256):
                      "steps: 4-stage RK4 of 256 members, corrected = plain + forward + correction")
 
 
+def closure_quality_leg(R, ctx, members=256, n_train=192):
+    """The learned closure's quality at the workload's 256 members: fine
+    (50 m) snapshots over 150 s, one-step targets, training on 192 members,
+    plain and corrected coarse (400 m) runs of the 64 held-out members,
+    theta' relative l2 against their fine runs at 30, 60, 120 and 150 s."""
+    from paper_1509_02615_amd import closure as CL
+    from workloads import closure_config
+    q = CL.quality_run(ctx, closure_config(n_members=members, n_train=n_train))
+    q["errors"] = {str(c): {"plain": e[0], "corrected": e[1]} for c, e in q["errors"].items()}
+    return q
+
+
 def closure_speedup(R, ctx, cc, params, nodef, members=64, seconds=30.0):
     """Cost of the corrected coarse run against the fine run it stands in
     for: the same members and the same simulated interval (30 s), each on
@@ -546,6 +558,8 @@ def main():
                          "JSON line")
     ap.add_argument("--ensemble", type=int, default=1, help="members of the --pmc-run model")
     ap.add_argument("--no-fullrun", action="store_true", help="skip the runs to t = 900 s (for profiling)")
+    ap.add_argument("--no-closure-quality", action="store_true",
+                    help="skip the 256-member closure training and held-out comparison (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the multi-GPU path is not built (see the sharding notes); "
@@ -634,6 +648,9 @@ def main():
         log(f"[bench] weights fp32+IR: {extras['weights_mixed_1M_fp32_ir']}")
         extras["closure_forward_256x2176"] = closure_leg(R, ctx)
         log(f"[bench] closure: {extras['closure_forward_256x2176']}")
+        if not args.no_closure_quality:
+            extras["closure_quality_256"] = closure_quality_leg(R, ctx)
+            log(f"[bench] closure quality: {extras['closure_quality_256']}")
         extras["device_peaks"] = device_peaks_leg(R, ctx)
         log(f"[bench] device peaks: {extras['device_peaks']}")
         extras["advection_64x64_fp64"] = advection_leg(R, P, ctx)

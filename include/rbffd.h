@@ -302,8 +302,10 @@ int rbffd_model_profile_read(rbffd_model *model, double *total_ms, int64_t *laun
  * (its ghost entries are overwritten), time every compiled launch shape of
  * the kernel (block size, slot unrolling, cached or non-temporal weight
  * loads) on a few evaluations of this model's data, and keep the fastest
- * for all later calls. Returns the shape index and its time per launch (us).
- * Synchronises. Transport models keep their single shape (chosen = -1). */
+ * for all later calls. Models of a multiple of 64 members also try
+ * traversing the nodes in Morton order of their coordinates (shape index + 6).
+ * Returns the shape index and its time per launch (us). Synchronises.
+ * Transport models keep their single shape (chosen = -1). */
 int rbffd_model_tune(rbffd_ctx *ctx, rbffd_model *model, void *state, int *chosen, double *best_us);
 
 /* ---- learned coarse closure (a per-node network on stencil-gathered fields) */

@@ -107,3 +107,44 @@ def rollout_errors(ctx, cmodel, closure, snaps, dt, checkpoints):
         ec = torch.linalg.norm(corr[:na, :, 2] - ref) / torch.linalg.norm(ref)
         res[int(c)] = (float(ep), float(ec))
     return res, fallbacks
+
+
+def quality_run(ctx, ccfg, n_steps=150, checkpoints=(30, 60, 120, 150), epochs=30, lr=1e-3, seed=0, log=None):
+    """The whole learned part on one closure workload: the fine ensemble's
+    snapshots, one-step correction targets, a relu network trained on the
+    first n_train members by the library's kernels, then plain and corrected
+    coarse runs of the held-out members against their fine runs. Returns the
+    theta' relative l2 errors {checkpoint: (plain, corrected)}, the number of
+    fallbacks, and timings."""
+    say = log or (lambda *a: None)
+    snaps, fine_s = fine_snapshots(ctx, ccfg, n_steps)
+    E, ntr = len(ccfg["amplitudes"]), ccfg["n_train"]
+    say(f"[closure] fine ensemble {E} x {ccfg['fine']['nodes'].n_active} nodes, {n_steps} s: {fine_s:.1f} s")
+    cm_all, xyiw = coarse_model(ctx, ccfg, E)
+    dt = ccfg["coarse"]["dt"]
+    tg = correction_targets(ctx, cm_all, snaps, dt)
+    in_scale = [float(snaps[..., c].std()) + 1e-12 for c in range(4)]
+    out_scale = [float(tg[:, :, :ntr, c].std()) + 1e-12 for c in range(4)]
+    cm_tr, _ = coarse_model(ctx, ccfg, ntr, xyiw)
+    nodef = torch.from_numpy(ccfg["node_feature"]).cuda()
+    from workloads.fields import closure_init_params
+    cl = R.Closure(ctx, cm_tr, torch.from_numpy(closure_init_params(seed)).cuda(), nodef, in_scale, out_scale,
+                   activation=R.ACT_RELU)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = train(ctx, cl, cm_tr, snaps[:, :, :ntr].contiguous(), tg[:, :, :ntr].contiguous(), out_scale,
+                   epochs=epochs, lr=lr, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    cm_te, _ = coarse_model(ctx, ccfg, E - ntr, xyiw)
+    cl_te = R.Closure(ctx, cm_te, cl.params(), nodef, in_scale, out_scale, activation=R.ACT_RELU)
+    res, fb = rollout_errors(ctx, cm_te, cl_te, snaps[:, :, ntr:].contiguous(), dt, list(checkpoints))
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    corr = to_full(cm_te, snaps[0, :, ntr:].contiguous())
+    cl_te.step(corr, 0.0, dt, n_steps, R.RK4)
+    torch.cuda.synchronize()
+    corrected_s = time.perf_counter() - w0
+    return dict(errors=res, fallbacks=fb, members=E, train_members=ntr, held_out=E - ntr, fine_run_s=fine_s,
+                train_s=train_s, corrected_run_s=corrected_s, loss_first=losses[0], loss_last=losses[-1],
+                in_scale=in_scale, out_scale=out_scale)

@@ -292,12 +292,15 @@ static int fail_model(rbffd_ctx *ctx, rbffd_model *m, int code, const char *msg)
   return rbffd_fail(ctx, code, "%s", msg);
 }
 
-// Traversal order of the member-wavefront stage kernel (ensembles of 64k
+// A traversal order for the member-wavefront stage kernel (ensembles of 64k
 // members, where a node's member vector is 1 KiB per 64 members): the active
 // nodes in Morton (Z) order of their coordinates, so that the nodes one XCD
 // works on at a time form a compact patch whose neighbours' member vectors
 // stay in its L2 instead of being fetched again for every stencil that
-// reaches them (row-major order spans several full rows per patch).
+// reaches them (row-major order spans several full rows per patch). The
+// tuner keeps it only where it is faster: it adds a dependent load before
+// each wavefront's first, and the kernel is bound by its vector
+// instructions rather than by those fetches.
 static int build_order(rbffd_ctx *ctx, rbffd_model *m, const double *xy_dev) {
   const int64_t na = m->Na;
   std::vector<double> xy(static_cast<size_t>(2 * na));

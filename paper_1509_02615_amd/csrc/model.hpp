@@ -65,7 +65,8 @@ struct rbffd_model {
   DevBuf rec;       // RecF64 / RecF32 / RecMW / RecBF16 [n - k0][Na], RecAdv [n][Na]
   DevBuf rec2;      // RecBF16X [n - k0][Na] (BF16 layout)
   DevBuf kind;      // uint8 [N]: KIND_* bits (0: interior)
-  DevBuf order;     // int32 [Na]: node traversal order of the member-wavefront stage kernel
+  DevBuf order;     // int32 [Na]: Morton traversal order of the member-wavefront stage kernel
+  int use_order = 0;  // traverse in `order` (chosen by the tuner) instead of node order
   DevBuf pibar;     // double [Na]
   double hv_coeff = 0.0, vel_period = 1.0;
   double c_p = 0, c_v = 0, R_d = 0, g = 0, theta_bar = 0, mu = 0, u_bar = 0;

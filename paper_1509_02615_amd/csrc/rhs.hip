@@ -747,7 +747,7 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.rec2 = m->rec2.p;
     a.kind = m->kind.as<uint8_t>();
     a.pibar = m->pibar.as<double>();
-    a.order = m->order.as<int>();
+    a.order = m->use_order ? m->order.as<int>() : nullptr;
     a.Na = m->Na;
     a.n = m->n - m->k0;
     a.E = m->E;
@@ -1020,31 +1020,38 @@ int model_tune(rbffd_ctx *ctx, rbffd_model *m, void *state, int *chosen, double 
   RBFFD_HIP(ctx, hipEventCreate(&e1));
   int rc = launch_ghost(ctx, m, state);
   double best = 1e300;
-  int best_s = default_shape(m->wdt);
+  int best_s = default_shape(m->wdt), best_o = 0;
   StageSpec sp{state, state, m->ya.p, 0.0, 0.0, 0.0, 0, 0, 0};
-  for (int sh = 0; sh < kNumShapes && rc == RBFFD_OK; ++sh) {
-    m->shape = sh;
-    rc = launch_stage(ctx, m, sp, 0.0, false, 0.0);  // warm-up
-    if (rc) break;
-    RBFFD_HIP(ctx, hipEventRecord(e0, ctx->stream));
-    constexpr int reps = 5;
-    for (int r = 0; r < reps && rc == RBFFD_OK; ++r) rc = launch_stage(ctx, m, sp, 0.0, false, 0.0);
-    RBFFD_HIP(ctx, hipEventRecord(e1, ctx->stream));
-    RBFFD_HIP(ctx, hipEventSynchronize(e1));
-    float ms = 0.0f;
-    RBFFD_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-    const double us = 1e3 * ms / reps;
-    if (us < best) {
-      best = us;
-      best_s = sh;
+  // member-wavefront models also try the Morton traversal
+  const int n_orders = m->order.p ? 2 : 1;
+  for (int o = 0; o < n_orders && rc == RBFFD_OK; ++o) {
+    m->use_order = o;
+    for (int sh = 0; sh < kNumShapes && rc == RBFFD_OK; ++sh) {
+      m->shape = sh;
+      rc = launch_stage(ctx, m, sp, 0.0, false, 0.0);  // warm-up
+      if (rc) break;
+      RBFFD_HIP(ctx, hipEventRecord(e0, ctx->stream));
+      constexpr int reps = 5;
+      for (int r = 0; r < reps && rc == RBFFD_OK; ++r) rc = launch_stage(ctx, m, sp, 0.0, false, 0.0);
+      RBFFD_HIP(ctx, hipEventRecord(e1, ctx->stream));
+      RBFFD_HIP(ctx, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      RBFFD_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1e3 * ms / reps;
+      if (us < best) {
+        best = us;
+        best_s = sh;
+        best_o = o;
+      }
     }
   }
+  m->use_order = best_o;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   m->shape = best_s;
   m->profile = saved_profile;
   drop_graphs(m);  // a captured graph holds the old shape
-  *chosen = best_s;
+  *chosen = best_s + kNumShapes * best_o;
   *best_us = best;
   return rc;
 }

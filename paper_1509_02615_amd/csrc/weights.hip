@@ -819,11 +819,13 @@ __device__ __forceinline__ float rl(float v, int l) {
 // Largest value over the wavefront (full exec mask): data-parallel
 // primitives within rows of 16 (quad permutes, half-mirror, mirror), then the
 // row broadcasts 15 and 31 carry the maximum to lane 63.
+// The moved value's "old" operand is 0, the identity of an unsigned maximum
+// (lanes a row mask leaves out keep it), so each step compiles to one
+// v_max_u32 with a DPP source operand.
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   auto step = [&](auto ctrl, auto rows) {
     const unsigned o = static_cast<unsigned>(
-        __builtin_amdgcn_update_dpp(static_cast<int>(v), static_cast<int>(v), decltype(ctrl)::value,
-                                    decltype(rows)::value, 0xF, false));
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(v), decltype(ctrl)::value, decltype(rows)::value, 0xF, false));
     v = max(v, o);
   };
   step(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});   // quad_perm 1,0,3,2
@@ -850,9 +852,8 @@ template <int H> __device__ __forceinline__ void group_max_key(unsigned v, unsig
     k0 = k1 = wave_max_u32(v);
   } else {
     auto step = [&](auto ctrl, auto rows) {
-      const unsigned o = static_cast<unsigned>(
-          __builtin_amdgcn_update_dpp(static_cast<int>(v), static_cast<int>(v), decltype(ctrl)::value,
-                                      decltype(rows)::value, 0xF, false));
+      const unsigned o = static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), decltype(ctrl)::value,
+                                                                           decltype(rows)::value, 0xF, false));
       v = max(v, o);
     };
     step(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});
@@ -1002,21 +1003,23 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
         v[g] = r.hi + (r.lo + (b.lo - acc[g].lo));
       }
     }
-    // forward substitution L y = P v: rows not yet pivot at step k
+    // forward substitution L y = P v: rows not yet pivot at step k. Every
+    // lane scales its value by its own 1 / pivot before the broadcast, so the
+    // value read from the pivot lane p_k of step k is already y_k / pivot_k
+    // (the same product as scaling after the broadcast) and the update takes
+    // it as a scalar operand
     for (int k = 0; k < K; ++k) {
       const int p0 = __builtin_amdgcn_readlane(R.pv, k), p1 = H == 1 ? p0 : __builtin_amdgcn_readlane(R.pv, 32 + k);
-      const double r = group_rl<H>(R.rpv, k, k, h);
       const double lk = R.mystep > k ? static_cast<double>(pick4<KC>(R.c0, R.c1, R.c2, R.c3, k)) : 0.0;
 #pragma unroll
-      for (int g = 0; g < G; ++g) v[g] = fma(-lk, group_rl<H>(v[g], p0, p1, h) * r, v[g]);
+      for (int g = 0; g < G; ++g) v[g] = fma(-lk, group_rl<H>(v[g] * R.rdg, p0, p1, h), v[g]);
     }
     // back substitution U d = y: rows pivoted before step k
     for (int k = K - 1; k >= 0; --k) {
       const int p0 = __builtin_amdgcn_readlane(R.pv, k), p1 = H == 1 ? p0 : __builtin_amdgcn_readlane(R.pv, 32 + k);
-      const double r = group_rl<H>(R.rpv, k, k, h);
       const double uk = R.mystep < k ? static_cast<double>(pick4<KC>(R.c0, R.c1, R.c2, R.c3, k)) : 0.0;
 #pragma unroll
-      for (int g = 0; g < G; ++g) v[g] = fma(-uk, group_rl<H>(v[g], p0, p1, h) * r, v[g]);
+      for (int g = 0; g < G; ++g) v[g] = fma(-uk, group_rl<H>(v[g] * R.rdg, p0, p1, h), v[g]);
     }
     // lane p_k holds y_k, so d_k = v * rdg there; lane k takes it
     double dm = 0.0, xm = 0.0;
@@ -1052,6 +1055,7 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
 template <int KC> constexpr int wave_occ() {
   return KC > 48 ? RBFFD_WAVE_OCC64 : KC > 32 ? RBFFD_WAVE_OCC48 : RBFFD_WAVE_OCC32;
 }
+
 
 // Stencils q and r have the same n, m and l (hence the same system shape).
 __device__ __forceinline__ bool same_shape(const WArgs &a, int q, int r) {

@@ -116,9 +116,11 @@ def _manufactured(nd):
 def test_manufactured_rhs_converges():
     """Eqs. uEq..piEq on a manufactured smooth state, away from the walls:
     the oracle's tendency approaches the exact one as h shrinks (every term
-    enters; a dropped term or wrong sign leaves an O(1) error)."""
+    enters; a dropped term or wrong sign leaves an O(1) error), at the order
+    of the polynomial degree, l = 4 (Section 4): measured 3.7-4.0 per field
+    from 800 m to 200 m columns, so a lost order fails too."""
     errs, hs = [], []
-    for nx, nz in ((64, 9), (128, 17)):
+    for nx, nz in ((64, 9), (128, 17), (256, 33)):
         nd = channel("hexagonal", nx, nz, -25600.0, 51200.0, 6400.0)
         cfg = _ns_config(nd, "mms", 1.0, "rk4")
         cfg["consts"] = dict(cfg["consts"], mu=1.0)
@@ -136,9 +138,9 @@ def test_manufactured_rhs_converges():
         errs.append(rel)
         hs.append(nd.h)
     errs = np.array(errs)
-    assert np.all(errs[-1] < 2e-3), errs
-    order = np.log(errs[0] / errs[1]) / np.log(hs[0] / hs[1])
-    assert np.all(order > 2.5), order
+    assert np.all(errs[-1] < 5e-5), errs
+    order = np.log(errs[-2] / errs[-1]) / np.log(hs[-2] / hs[-1])
+    assert np.all(order > 3.5), order
 
 
 def test_rk_orders():

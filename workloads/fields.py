@@ -92,3 +92,23 @@ def ensemble_amplitudes(n_members: int, seed: int = 1, low: float = -17.0, high:
     """Bubble temperature amplitudes drawn from U[low, high] K (PCG64 seed)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(low, high, n_members)
+
+
+def closure_init_params(seed: int = 0, out_rows: int = 4):
+    """Seeded initial parameters of the closure network in the C ABI's layout
+    (W1 [128][160], b1 [128], W2 [128][128], b2 [128], W3 [16][128], b3 [16]):
+    uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights with fan_in 149 for the
+    first layer (148 gathered values and one node feature) and 128 after,
+    zero biases, zero W3 rows beyond the 4 outputs (PCG64 seed)."""
+    hid, kin, nout = 128, 160, 16
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = hid * kin + hid + hid * hid + hid + nout * hid + nout
+    p = np.zeros(n)
+    ow2 = hid * kin + hid
+    ow3 = ow2 + hid * hid + hid
+    p[:hid * kin] = rng.uniform(-1, 1, hid * kin) / np.sqrt(149.0)
+    p[ow2:ow2 + hid * hid] = rng.uniform(-1, 1, hid * hid) / np.sqrt(hid)
+    w3 = np.zeros((nout, hid))
+    w3[:out_rows] = rng.uniform(-1, 1, (out_rows, hid)) / np.sqrt(hid)
+    p[ow3:ow3 + nout * hid] = w3.ravel()
+    return p.astype(np.float32)
