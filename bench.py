@@ -432,9 +432,11 @@ def cpu_oracle_weights(min_seconds=10.0):
     """The oracle's weights (extended-precision assembly, LU, refinement) on a
     bounded sample of the mixed 1M batch: 120 stencils (every 997th centre;
     their stencils found by the oracle's search beforehand, untimed), solved
-    repeatedly until min_seconds have passed; single thread. Also returns the
-    sample's oracle stencils and weights, against which the GPU weights legs
-    report their accuracy."""
+    repeatedly until min_seconds have passed, on one thread and then in one
+    process per core. The solves see only the sample's nodes (renumbered), so
+    that no call converts all 1M coordinates. Also returns the sample's
+    oracle stencils and weights, against which the GPU weights legs report
+    their accuracy."""
     import oracle as O
     from workloads import weights_config
     cfg = weights_config(1024)
@@ -442,19 +444,64 @@ def cpu_oracle_weights(min_seconds=10.0):
     sample = np.arange(0, nd.n_active, 997)[:120]
     stencils = [O.knn(nd.xy, [c], int(cfg["n_per"][c]), 0.0)[0] for c in sample]
     ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.HYPERLAP, 0, 0)]
-    done = 0
-    ref = {}
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < min_seconds:
-        for c, st in zip(sample, stencils):
-            W, _ = O.stencil_weights(nd.xy, st, int(c), int(cfg["m_per"][c]), int(cfg["l_per"][c]), ops, 0.0)
-            ref.setdefault(int(c), (st, W))
-            done += 1
-    el = time.perf_counter() - t0
-    res = dict(value=done / el, unit="stencils/s", cores=1, kind="oracle",
+    used = np.unique(np.concatenate([sample] + stencils))
+    local = lambda a: np.searchsorted(used, a)
+    job = (nd.xy[used], [(local(st), int(local(c)), int(cfg["m_per"][c]), int(cfg["l_per"][c]))
+                         for c, st in zip(sample, stencils)], ops)
+    ref = {int(c): (st, O.stencil_weights(*_solve_args(job, a))[0])
+           for a, (c, st) in enumerate(zip(sample, stencils))}
+    done, el = _oracle_weights_worker((job, min_seconds))
+    res = dict(value=done / el, unit="stencils/s", cores=1, kind="oracle", host=host_cpu(),
                sample=f"{done} solves of 120 stencils of the mixed 1M batch (every 997th centre), "
                       f"{el:.1f} s (numpy/scipy, single thread)")
+    res["all_cores"] = _all_cores(_oracle_weights_worker, job, min_seconds, 1, "stencils/s",
+                                  "the same 120 stencils")
     return res, ref
+
+
+def _solve_args(job, a):
+    """Arguments of the oracle's stencil_weights for stencil a of a job."""
+    xy, stencils, ops = job
+    st, c, m, l = stencils[a]
+    return xy, st, c, m, l, ops, 0.0
+
+
+def _oracle_weights_worker(args):
+    """One worker process of the all-cores weights baseline: the sample's
+    stencils solved by the oracle in turn for `seconds`; returns the number
+    of solves and the time taken."""
+    job, seconds = args
+    import oracle as O
+    with one_thread():
+        done, t0 = 0, time.perf_counter()
+        while True:
+            for a in range(len(job[1])):
+                O.stencil_weights(*_solve_args(job, a))
+                done += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return done, el
+
+
+def one_thread():
+    """Limits the BLAS/OpenMP pools of numpy and scipy to one thread, so an
+    oracle timing uses the cores it reports."""
+    from threadpoolctl import threadpool_limits
+    return threadpool_limits(1)
+
+
+def host_cpu():
+    """The host processor's model name and the cores this process may use."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name} ({len(os.sched_getaffinity(0))} cores available)"
 
 
 def sampled_weights_error(idx, W, ref):
@@ -486,54 +533,59 @@ def cpu_baseline(cfg, min_seconds=10.0):
     state = cfg["state0"].astype(np.float64)
     is_wall = np.zeros(len(rows), bool)
     reps = 0
-    t0 = time.perf_counter()
-    while True:
-        O.ns_tendency(state, rows, idx, Wo[0], Wo[1], Wo[2], Wo[3], nd.xy[rows, 1], is_wall,
-                      cfg["consts"], cfg["hv_coeff"])
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= min_seconds:
-            break
-    res = dict(value=len(rows) * reps / el, unit="node-updates/s", cores=1, kind="oracle",
+    with one_thread():
+        t0 = time.perf_counter()
+        while True:
+            O.ns_tendency(state, rows, idx, Wo[0], Wo[1], Wo[2], Wo[3], nd.xy[rows, 1], is_wall,
+                          cfg["consts"], cfg["hv_coeff"])
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= min_seconds:
+                break
+    res = dict(value=len(rows) * reps / el, unit="node-updates/s", cores=1, kind="oracle", host=host_cpu(),
                sample=f"one 2048-node row of the 2048x256 channel, {reps} FP64 RHS evaluations "
                       f"in {el:.1f} s (numpy, single thread)")
-    res["all_cores"] = _cpu_baseline_all_cores(state, rows, idx, Wo, nd.xy[rows, 1], is_wall, cfg, min_seconds)
+    job = (state, rows, idx, Wo, nd.xy[rows, 1], is_wall, cfg["consts"], cfg["hv_coeff"])
+    res["all_cores"] = _all_cores(_oracle_rhs_worker, job, min_seconds, len(rows), "node-updates/s",
+                                  "the same row")
     return res
 
 
 def _oracle_rhs_worker(args):
-    """One worker process of the all-cores baseline: the same oracle RHS on the
-    same row, repeated for `seconds`; returns the number of evaluations."""
-    state, rows, idx, Wo, z, is_wall, consts, hv, seconds = args
+    """One worker process of the all-cores RHS baseline: the oracle RHS on the
+    sample row, repeated for `seconds`; returns the number of evaluations and
+    the time taken."""
+    (state, rows, idx, Wo, z, is_wall, consts, hv), seconds = args
     import oracle as O
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        O.ns_tendency(state, rows, idx, Wo[0], Wo[1], Wo[2], Wo[3], z, is_wall, consts, hv)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            return reps, el
+    with one_thread():
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            O.ns_tendency(state, rows, idx, Wo[0], Wo[1], Wo[2], Wo[3], z, is_wall, consts, hv)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return reps, el
 
 
-def _cpu_baseline_all_cores(state, rows, idx, Wo, z, is_wall, cfg, seconds):
-    """The oracle on every host core it may use (at most 16): one process
-    each, started fresh (they never touch the GPU), all timed together."""
+def _all_cores(worker, job, seconds, units_per_rep, unit, what):
+    """An oracle worker on every host core it may use (at most 16): one
+    process each, started fresh (they never touch the GPU), all timed
+    together; `units_per_rep` converts a worker's repetitions to `unit`."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    args = (state, rows, idx, Wo, z, is_wall, cfg["consts"], cfg["hv_coeff"], seconds)
     try:
         with ProcessPoolExecutor(cores, mp_context=mp.get_context("spawn")) as ex:
             # a first round starts the workers (imports), the second is timed
-            list(ex.map(_oracle_rhs_worker, [args[:-1] + (0.0,)] * cores, timeout=300))
-            done = list(ex.map(_oracle_rhs_worker, [args] * cores, timeout=seconds + 300))
+            list(ex.map(worker, [(job, 0.0)] * cores, timeout=300))
+            done = list(ex.map(worker, [(job, seconds)] * cores, timeout=seconds + 300))
     except Exception as exc:  # a broken or slow pool leaves the single-thread figure alone
         print(f"[bench] all-cores oracle baseline skipped: {exc!r}", file=sys.stderr, flush=True)
         return None
     # each process times its own loop; the processes run at the same time
-    rate = sum(len(rows) * reps / el for reps, el in done)
-    return dict(value=rate, unit="node-updates/s", cores=cores, kind="oracle",
-                sample=f"the same row in {cores} processes at once, {sum(r for r, _ in done)} evaluations "
+    rate = sum(units_per_rep * reps / el for reps, el in done)
+    return dict(value=rate, unit=unit, cores=cores, kind="oracle",
+                sample=f"{what} in {cores} processes at once, {sum(r for r, _ in done)} repetitions "
                        f"over {max(el for _, el in done):.1f} s each")
 
 
@@ -557,6 +609,9 @@ def main():
                          "(and --ensemble) and 3 plain copies of 512 MiB (counter calibration); prints no "
                          "JSON line")
     ap.add_argument("--ensemble", type=int, default=1, help="members of the --pmc-run model")
+    ap.add_argument("--shape", type=int, default=-1,
+                    help="stage-kernel launch shape of the --pmc-run model (-1: tuned; with 64 members "
+                         "6-11 are 0-5 in Morton order)")
     ap.add_argument("--no-fullrun", action="store_true", help="skip the runs to t = 900 s (for profiling)")
     ap.add_argument("--no-closure-quality", action="store_true",
                     help="skip the 256-member closure training and held-out comparison (for profiling)")
@@ -618,7 +673,7 @@ def main():
         s0 = np.repeat(cfg["state0"][:, None, :], E, axis=1)
         state = P.to_dev(s0, torch.float64 if fdt == R.F64 else torch.float32)
         state = state.reshape(model.state_shape()).contiguous()
-        shape, _ = R.rbffd_model_tune(ctx, model, state)     # same launch shape as the timed region
+        shape, _ = R.rbffd_model_tune(ctx, model, state, args.shape)   # as in the timed region unless forced
         R.rbffd_step(ctx, model, state, 0.0, cfg["dt"], 2, R.RK4)
         src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -304,7 +304,9 @@ int rbffd_model_profile_read(rbffd_model *model, double *total_ms, int64_t *laun
  * loads) on a few evaluations of this model's data, and keep the fastest
  * for all later calls. Models of a multiple of 64 members also try
  * traversing the nodes in Morton order of their coordinates (shape index + 6).
- * Returns the shape index and its time per launch (us). Synchronises.
+ * *chosen on entry: -1 to time every shape, or one shape index to time and
+ * keep that one alone (EINVAL, nothing changed, if it is out of range); on
+ * return the shape kept and its time per launch (us). Synchronises.
  * Transport models keep their single shape (chosen = -1). */
 int rbffd_model_tune(rbffd_ctx *ctx, rbffd_model *model, void *state, int *chosen, double *best_us);
 

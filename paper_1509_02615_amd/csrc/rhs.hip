@@ -1013,30 +1013,37 @@ int model_tune(rbffd_ctx *ctx, rbffd_model *m, void *state, int *chosen, double 
     *best_us = 0.0;
     return RBFFD_OK;
   }
+  // member-wavefront models also try the Morton traversal
+  const int n_orders = m->order.p ? 2 : 1;
+  const int forced = *chosen;
+  if (forced < -1 || forced >= kNumShapes * n_orders)
+    return rbffd_fail(ctx, RBFFD_EINVAL, "model_tune: shape %d is not -1 or in [0, %d)", forced,
+                      kNumShapes * n_orders);
   const int saved_profile = m->profile;
   m->profile = 0;
-  hipEvent_t e0, e1;
-  RBFFD_HIP(ctx, hipEventCreate(&e0));
-  RBFFD_HIP(ctx, hipEventCreate(&e1));
-  int rc = launch_ghost(ctx, m, state);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = RBFFD_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = rbffd_fail(ctx, RBFFD_EDEVICE, "model_tune: hipEventCreate failed");
+  if (rc == RBFFD_OK) rc = launch_ghost(ctx, m, state);
   double best = 1e300;
   int best_s = default_shape(m->wdt), best_o = 0;
   StageSpec sp{state, state, m->ya.p, 0.0, 0.0, 0.0, 0, 0, 0};
-  // member-wavefront models also try the Morton traversal
-  const int n_orders = m->order.p ? 2 : 1;
   for (int o = 0; o < n_orders && rc == RBFFD_OK; ++o) {
     m->use_order = o;
     for (int sh = 0; sh < kNumShapes && rc == RBFFD_OK; ++sh) {
+      if (forced >= 0 && forced != sh + kNumShapes * o) continue;
       m->shape = sh;
       rc = launch_stage(ctx, m, sp, 0.0, false, 0.0);  // warm-up
       if (rc) break;
-      RBFFD_HIP(ctx, hipEventRecord(e0, ctx->stream));
-      constexpr int reps = 5;
-      for (int r = 0; r < reps && rc == RBFFD_OK; ++r) rc = launch_stage(ctx, m, sp, 0.0, false, 0.0);
-      RBFFD_HIP(ctx, hipEventRecord(e1, ctx->stream));
-      RBFFD_HIP(ctx, hipEventSynchronize(e1));
       float ms = 0.0f;
-      RBFFD_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+      constexpr int reps = 5;
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess) rc = rbffd_fail(ctx, RBFFD_EDEVICE, "hipEventRecord failed");
+      for (int r = 0; r < reps && rc == RBFFD_OK; ++r) rc = launch_stage(ctx, m, sp, 0.0, false, 0.0);
+      if (rc == RBFFD_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = rbffd_fail(ctx, RBFFD_EDEVICE, "model_tune: event timing failed");
+      if (rc) break;
       const double us = 1e3 * ms / reps;
       if (us < best) {
         best = us;
@@ -1046,8 +1053,8 @@ int model_tune(rbffd_ctx *ctx, rbffd_model *m, void *state, int *chosen, double 
     }
   }
   m->use_order = best_o;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   m->shape = best_s;
   m->profile = saved_profile;
   drop_graphs(m);  // a captured graph holds the old shape

@@ -5,10 +5,19 @@
 // entries of the solution of
 //     [Phi P; P^T 0] [w; v] = [L phi(|x - x_j|) at x_c ; L p_q(x_c)].
 // The repeated solve over all N centres is the O(n^3 N) preprocessing cost
-// the paper names; stencils are independent, so one workgroup solves one
-// stencil and a launch covers them all (mixed n, m, l in one launch).
+// the paper names. Stencils are independent, and a batch may mix n, m and l:
+// a counting pass bins them on the device by system size K = n + M into six
+// buckets (K <= 32, 48, 64, 80, 96, 128) and fills one work queue per bucket.
+// Each bucket has its own kernel, sized to its K: two systems per wavefront
+// (K <= 32; a stencil whose partner differs in shape is deferred to a second
+// queue and solved one per wavefront), one system per wavefront (K <= 64),
+// or one 256-thread workgroup per system (K <= 128). A kernel takes its
+// items from its queue either one per wavefront or workgroup, or in a
+// persistent loop over a grid sized to the device; which one, and whether
+// the smallest bucket pairs systems, is a per-bucket launch shape that
+// rbffd_weights_tune picks by timing. Every shape computes the same bits.
 //
-// Per workgroup:
+// Per system:
 //  1. offsets of the stencil nodes from the centre (minimum image in x),
 //     scaled by rho = the largest offset length;
 //  2. assembly of [A | B] in LDS (column-major), A = [Phi P; P^T 0] of size

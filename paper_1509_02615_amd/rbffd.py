@@ -305,10 +305,11 @@ def rbffd_rhs(ctx: Context, model: Model, t, state, tendency):
                              model._state(tendency, "tendency")))
 
 
-def rbffd_model_tune(ctx: Context, model: Model, state):
-    """Pick the fastest stage-kernel launch shape on this model's data;
-    returns (shape index, microseconds per launch)."""
-    ch, us = ctypes.c_int(), _f64()
+def rbffd_model_tune(ctx: Context, model: Model, state, shape=-1):
+    """Pick the fastest stage-kernel launch shape on this model's data (or
+    keep `shape` if it is not -1); returns (shape index, microseconds per
+    launch)."""
+    ch, us = ctypes.c_int(shape), _f64()
     ctx.check(_lib.rbffd_model_tune(ctx.h, model.h, model._state(state), ctypes.byref(ch), ctypes.byref(us)))
     return ch.value, us.value
 

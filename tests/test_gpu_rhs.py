@@ -569,6 +569,34 @@ def test_tuned_shape_gives_identical_results(R, ctx, fdt, wdt):
     assert torch.isfinite(s1).all()
 
 
+def test_every_forced_shape_and_morton_order_identical(R, ctx):
+    """A 64-member model has twelve launch shapes (six shapes, each in row
+    order and in Morton order of the coordinates): forcing each one in
+    turn gives the same tendency bit for bit, and a shape out of range is
+    refused without changing the kept one."""
+    import torch
+    E = 64
+    say(f"tune: every forced stage-kernel shape, E={E} (FP32), hexagonal 400 m")
+    cfg, om, idx, W, Ww = ns_case("hexagonal", 400.0)
+    gE = gpu_ns(R, ctx, cfg, idx, W, Ww, fdt=1, wdt=1, E=E)
+    states = [smooth_ns_state(cfg["nodes"], seed=60 + k).astype(np.float32) for k in range(E)]
+    sE = dev(np.stack(states, axis=1), torch.float32).contiguous()
+    ref = torch.empty_like(sE)
+    R.rbffd_rhs(ctx, gE, 0.0, sE, ref)
+    for shape in range(12):
+        got, us = R.rbffd_model_tune(ctx, gE, sE, shape)
+        assert got == shape and us > 0
+        out = torch.empty_like(sE)
+        R.rbffd_rhs(ctx, gE, 0.0, sE, out)
+        assert torch.equal(out, ref), shape
+    for bad in (12, -2):
+        with pytest.raises(R.RbffdError):
+            R.rbffd_model_tune(ctx, gE, sE, bad)
+    out = torch.empty_like(sE)
+    R.rbffd_rhs(ctx, gE, 0.0, sE, out)
+    assert torch.equal(out, ref)
+
+
 def test_measurement_helpers(R, ctx):
     """The streaming copy copies; the matrix-core probe rejects a short
     output, writes a finite value per thread and reports its flop count."""
