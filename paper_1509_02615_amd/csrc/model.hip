@@ -96,6 +96,18 @@ __global__ void repack_mw(const int *__restrict__ idx, const double *__restrict_
   rec[dst] = RecMW{w[src], w[plane + src], w[3 * plane + src], static_cast<float>(w[2 * plane + src]), idx[src]};
 }
 
+// Records of a traversal order: out[k][t] = rec[k][order[t]], copied in
+// 16-byte units (`units` per record), so that the traversal reads them in
+// sequence.
+__global__ void permute_records(const uint4 *__restrict__ rec, const int *__restrict__ order, int64_t na, int units,
+                                int64_t n_slots, uint4 *__restrict__ out) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_slots * na * units) return;
+  const int u = static_cast<int>(t % units);
+  const int64_t rest = t / units, li = rest % na, k = rest / na;
+  out[(k * na + li) * units + u] = rec[(k * na + order[li]) * units + u];
+}
+
 __device__ __forceinline__ uint16_t to_bf16(double v) {
   // round-to-nearest-even of the FP32 value to bfloat16 (finite inputs)
   float f = static_cast<float>(v);
@@ -297,10 +309,12 @@ static int fail_model(rbffd_ctx *ctx, rbffd_model *m, int code, const char *msg)
 // nodes in Morton (Z) order of their coordinates, so that the nodes one XCD
 // works on at a time form a compact patch whose neighbours' member vectors
 // stay in its L2 instead of being fetched again for every stencil that
-// reaches them (row-major order spans several full rows per patch). The
-// tuner keeps it only where it is faster: it adds a dependent load before
-// each wavefront's first, and the kernel is bound by its vector
-// instructions rather than by those fetches.
+// reaches them (row-major order spans several full rows per patch, and on
+// the 2048 x 256 channel at 64 members fetches a few times more bytes past
+// L2 than this order). FP32 ensemble
+// records are also kept in this order, so that the traversal reads them in
+// sequence. The tuner keeps the order only where it is faster: it adds a
+// dependent load before each wavefront's first.
 static int build_order(rbffd_ctx *ctx, rbffd_model *m, const double *xy_dev) {
   const int64_t na = m->Na;
   std::vector<double> xy(static_cast<size_t>(2 * na));
@@ -473,6 +487,14 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
   if (m->physics == RBFFD_PHYS_NS && m->E % 64 == 0) {
     const int rc = build_order(ctx, m, d->xy);
     if (rc) return fail_model(ctx, m, rc, "traversal order");
+    if (m->wide_rec) {  // the FP32 ensemble records once more, in that order
+      const int64_t slots = m->n - k0;
+      constexpr int units = sizeof(RecMW) / sizeof(uint4);
+      if (m->rec_order.alloc(sizeof(RecMW) * slots * na) != hipSuccess)
+        return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation (ordered records)");
+      permute_records<<<grid_for(slots * na * units, 256), 256, 0, s>>>(m->rec.as<uint4>(), m->order.as<int>(), na, units,
+                                                                         slots, m->rec_order.as<uint4>());
+    }
   }
   if (m->kind.alloc(m->N) != hipSuccess) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation");
   kind_kernel<<<grid_for(m->N, 256), 256, 0, s>>>(m->kind.as<uint8_t>(), m->N, na);

@@ -64,6 +64,7 @@ struct rbffd_model {
                           // centre-subtracted sums skip); the stream arrays hold slots k0..n-1
   DevBuf rec;       // RecF64 / RecF32 / RecMW / RecBF16 [n - k0][Na], RecAdv [n][Na]
   DevBuf rec2;      // RecBF16X [n - k0][Na] (BF16 layout)
+  DevBuf rec_order; // RecMW [n - k0][Na] in the Morton traversal's order (FP32 ensembles)
   DevBuf kind;      // uint8 [N]: KIND_* bits (0: interior)
   DevBuf order;     // int32 [Na]: Morton traversal order of the member-wavefront stage kernel
   int use_order = 0;  // traverse in `order` (chosen by the tuner) instead of node order

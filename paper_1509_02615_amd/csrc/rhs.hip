@@ -25,6 +25,8 @@
 // Launch geometry: 256-thread blocks, thread = (node, member); block ids are
 // remapped so that each of the 8 XCDs (which take block ids round-robin)
 // works on one contiguous node range and its L2 sees neighbouring gathers.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -153,6 +155,7 @@ struct NSArgs {
   const uint8_t *kind;
   const double *pibar;
   const int *order;   // member-wavefront mode: node of each wavefront-sized unit (or NULL)
+  const void *rec_t;  // with `order`, FP32 ensemble records in that order (or NULL)
   int64_t Na;
   int n, E;
   double c_p, rcv, g, theta_bar, mu, hv, dpibar, u_bar;
@@ -177,107 +180,139 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
   const int E = a.E;
   int64_t i = E == 1 ? t : t / E;
   const int e = static_cast<int>(t - i * E);  // the member
+  int64_t ri = i;  // column of the node's records: the node, or its place in the traversal
   if constexpr (MW) {  // a wave-uniform node, taken in the model's traversal order
     const int li = __builtin_amdgcn_readfirstlane(static_cast<int>(i));
     i = a.order ? a.order[li] : li;
+    ri = a.rec_t ? li : i;
   }
   const FT *ys = static_cast<const FT *>(a.ys);
   const F4<FT> own = load4(ys + (i * E + e) * 4);
-  FT sdx[4] = {0, 0, 0, 0}, sdz[4] = {0, 0, 0, 0}, slp[3] = {0, 0, 0};
-  double shv[4] = {0.0, 0.0, 0.0, 0.0};
-  // reduced-precision layouts: the divergence u_x + w_z in FP64, from exact
-  // differences and weights corrected towards FP64 (FP64 layout: sdx[0], sdz[1])
-  double sux = 0.0, swz = 0.0;
-  constexpr bool DIV64 = WDT != RBFFD_F64;
-  const double own_u = static_cast<double>(own.v[0]), own_w = static_cast<double>(own.v[1]);
   const int n = a.n;
   const int64_t Na = a.Na;
+  // the 15 stencil sums, in FP64 for the epilogue: Dx and Dz of the four
+  // fields, Lap of u, w, theta', Lap^k of all four; ux and wz the divergence
+  double gx[4], gz[4], gl[3], shv[4] = {0.0, 0.0, 0.0, 0.0}, ux, wz;
+  if constexpr (WDT == RBFFD_F32 && MW) {
+    // FP32 ensembles of a multiple of 64 members: the FP64 record (RecMW) is
+    // wave-uniform, and every sum is taken in FP64 from exact differences.
+    // The vector unit issues an FP64 multiply-add at the rate of an FP32 one
+    // (packed FP32 is not used), this path is bound by its vector
+    // instructions, and FP32 sums would need the FP64 weights converted
+    // per slot besides the FP64 Lap^k and divergence sums
+    const double o[4] = {own.v[0], own.v[1], own.v[2], own.v[3]};
+    double sx[4] = {0.0, 0.0, 0.0, 0.0}, sz[4] = {0.0, 0.0, 0.0, 0.0}, sl[3] = {0.0, 0.0, 0.0};
+    const RecMW *recs = static_cast<const RecMW *>(a.rec_t ? a.rec_t : a.rec);
 #pragma unroll SH::unroll
-  for (int k = 0; k < n; ++k) {
-    const int64_t s = static_cast<int64_t>(k) * Na + i;
-    int j;
-    FT wdx, wdz, wlp;
-    double whv, wdx64 = 0.0, wdz64 = 0.0;
-    int off;
-    if constexpr (WDT == RBFFD_F64) {
-      const double2 r0 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s);
-      const double2 r1 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s + 1);
-      off = load_off<NT, MW>(a.off16, s);
-      wdx = r0.x;
-      wdz = r0.y;
-      wlp = r1.x;
-      whv = r1.y;
-    } else if constexpr (WDT == RBFFD_F32 && MW) {  // RecMW: FP64 weights, full index inline
-      const RecMW r = reinterpret_cast<const RecMW *>(a.rec)[s];
-      off = 0;
-      wdx64 = r.dx;
-      wdz64 = r.dz;
-      wdx = static_cast<float>(r.dx);
-      wdz = static_cast<float>(r.dz);
-      wlp = r.lap;
-      whv = r.hv;
-      j = r.idx;
-    } else if constexpr (WDT == RBFFD_F32) {
-      const float4 r = stream_load4<NT>(reinterpret_cast<const float4 *>(a.rec) + s);
-      const uint32_t x = stream_load<NT>(a.aux32 + s);
-      off = static_cast<int16_t>(x >> 16);
-      wdx = r.x;
-      wdz = r.y;
-      wlp = r.z;
-      // corrections: bits 15-10 (Lap^k), 9-5 (Dx), 4-0 (Dz), signed
-      const int qh = static_cast<int>(x << 16) >> 26, qx = static_cast<int>(x << 22) >> 27,
-                qz = static_cast<int>(x << 27) >> 27;
-      const double hh = r.w, hx = r.x, hz = r.y;
-      whv = fma(hh, static_cast<double>(qh) * HV_Q_SCALE, hh);
-      wdx64 = fma(hx, static_cast<double>(qx) * D_Q_SCALE, hx);
-      wdz64 = fma(hz, static_cast<double>(qz) * D_Q_SCALE, hz);
-    } else {
-      const uint2 r = stream_load2u<NT>(reinterpret_cast<const uint2 *>(a.rec) + s);
-      const uint2 x = stream_load2u<NT>(reinterpret_cast<const uint2 *>(a.rec2) + s);
-      // RecBF16X: {float hv, int16 hvq, int8 dxq, int8 dzq}
-      const float bx = __uint_as_float(r.x << 16), bz = __uint_as_float(r.x & 0xffff0000u);
-      wdx = fmaf(bx, static_cast<float>(static_cast<int>(x.y << 8) >> 24) * BF_Q_SCALE, bx);
-      wdz = fmaf(bz, static_cast<float>(static_cast<int>(x.y) >> 24) * BF_Q_SCALE, bz);
-      wlp = __uint_as_float(r.y << 16);
-      off = static_cast<int16_t>(r.y >> 16);
-      const double hh = __uint_as_float(x.x);
-      whv = fma(hh, static_cast<double>(static_cast<int16_t>(x.y & 0xffffu)) * HV_Q16_SCALE, hh);
-      wdx64 = wdx;
-      wdz64 = wdz;
+    for (int k = 0; k < n; ++k) {
+      const RecMW r = recs[static_cast<int64_t>(k) * Na + ri];
+      // the neighbour's member vector: a wave-uniform base (scalar
+      // arithmetic) plus the lane's 16-byte offset
+      const FT *nb = ys + static_cast<int64_t>(r.idx) * (4 * E);
+      const F4<FT> f = load4(nb + 4 * static_cast<uint32_t>(e));
+      const double wl = r.lap;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double d = static_cast<double>(f.v[c]) - o[c];
+        sx[c] = fma(r.dx, d, sx[c]);
+        sz[c] = fma(r.dz, d, sz[c]);
+        if (c < 3) sl[c] = fma(wl, d, sl[c]);
+        shv[c] = fma(r.hv, d, shv[c]);
+      }
     }
-    if constexpr (!(WDT == RBFFD_F32 && MW)) {
+    for (int c = 0; c < 4; ++c) {
+      gx[c] = sx[c];
+      gz[c] = sz[c];
+      if (c < 3) gl[c] = sl[c];
+    }
+    ux = sx[0];
+    wz = sz[1];
+  } else {
+    FT sdx[4] = {0, 0, 0, 0}, sdz[4] = {0, 0, 0, 0}, slp[3] = {0, 0, 0};
+    // reduced-precision layouts: the divergence u_x + w_z in FP64, from exact
+    // differences and weights corrected towards FP64 (FP64 layout: sdx[0], sdz[1])
+    double sux = 0.0, swz = 0.0;
+    constexpr bool DIV64 = WDT != RBFFD_F64;
+    const double own_u = static_cast<double>(own.v[0]), own_w = static_cast<double>(own.v[1]);
+#pragma unroll SH::unroll
+    for (int k = 0; k < n; ++k) {
+      const int64_t s = static_cast<int64_t>(k) * Na + i;
+      int j;
+      FT wdx, wdz, wlp;
+      double whv, wdx64 = 0.0, wdz64 = 0.0;
+      int off;
+      if constexpr (WDT == RBFFD_F64) {
+        const double2 r0 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s);
+        const double2 r1 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s + 1);
+        off = load_off<NT, MW>(a.off16, s);
+        wdx = r0.x;
+        wdz = r0.y;
+        wlp = r1.x;
+        whv = r1.y;
+      } else if constexpr (WDT == RBFFD_F32) {
+        const float4 r = stream_load4<NT>(reinterpret_cast<const float4 *>(a.rec) + s);
+        const uint32_t x = stream_load<NT>(a.aux32 + s);
+        off = static_cast<int16_t>(x >> 16);
+        wdx = r.x;
+        wdz = r.y;
+        wlp = r.z;
+        // corrections: bits 15-10 (Lap^k), 9-5 (Dx), 4-0 (Dz), signed
+        const int qh = static_cast<int>(x << 16) >> 26, qx = static_cast<int>(x << 22) >> 27,
+                  qz = static_cast<int>(x << 27) >> 27;
+        const double hh = r.w, hx = r.x, hz = r.y;
+        whv = fma(hh, static_cast<double>(qh) * HV_Q_SCALE, hh);
+        wdx64 = fma(hx, static_cast<double>(qx) * D_Q_SCALE, hx);
+        wdz64 = fma(hz, static_cast<double>(qz) * D_Q_SCALE, hz);
+      } else {
+        const uint2 r = stream_load2u<NT>(reinterpret_cast<const uint2 *>(a.rec) + s);
+        const uint2 x = stream_load2u<NT>(reinterpret_cast<const uint2 *>(a.rec2) + s);
+        // RecBF16X: {float hv, int16 hvq, int8 dxq, int8 dzq}
+        const float bx = __uint_as_float(r.x << 16), bz = __uint_as_float(r.x & 0xffff0000u);
+        wdx = fmaf(bx, static_cast<float>(static_cast<int>(x.y << 8) >> 24) * BF_Q_SCALE, bx);
+        wdz = fmaf(bz, static_cast<float>(static_cast<int>(x.y) >> 24) * BF_Q_SCALE, bz);
+        wlp = __uint_as_float(r.y << 16);
+        off = static_cast<int16_t>(r.y >> 16);
+        const double hh = __uint_as_float(x.x);
+        whv = fma(hh, static_cast<double>(static_cast<int16_t>(x.y & 0xffffu)) * HV_Q16_SCALE, hh);
+        wdx64 = wdx;
+        wdz64 = wdz;
+      }
       if (__builtin_expect(off == OFF_FAR, 0))
         j = a.idx_t[s];  // a ghost neighbour
       else
         j = static_cast<int>(i) + off;
-    }
-    const F4<FT> f = load4(ys + (static_cast<int64_t>(j) * E + e) * 4);
+      const F4<FT> f = load4(ys + (static_cast<int64_t>(j) * E + e) * 4);
 #pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const FT d = f.v[c] - own.v[c];
+        if (!DIV64 || c != 0) sdx[c] = fma(wdx, d, sdx[c]);
+        if (!DIV64 || c != 1) sdz[c] = fma(wdz, d, sdz[c]);
+        if (c < 3) slp[c] = fma(wlp, d, slp[c]);
+        shv[c] = fma(whv, static_cast<double>(d), shv[c]);
+      }
+      if constexpr (DIV64) {
+        sux = fma(wdx64, static_cast<double>(f.v[0]) - own_u, sux);
+        swz = fma(wdz64, static_cast<double>(f.v[1]) - own_w, swz);
+      }
+    }
     for (int c = 0; c < 4; ++c) {
-      const FT d = f.v[c] - own.v[c];
-      if (!DIV64 || c != 0) sdx[c] = fma(wdx, d, sdx[c]);
-      if (!DIV64 || c != 1) sdz[c] = fma(wdz, d, sdz[c]);
-      if (c < 3) slp[c] = fma(wlp, d, slp[c]);
-      shv[c] = fma(whv, static_cast<double>(d), shv[c]);
+      gx[c] = static_cast<double>(sdx[c]);
+      gz[c] = static_cast<double>(sdz[c]);
+      if (c < 3) gl[c] = static_cast<double>(slp[c]);
     }
-    if constexpr (DIV64) {
-      sux = fma(wdx64, static_cast<double>(f.v[0]) - own_u, sux);
-      swz = fma(wdz64, static_cast<double>(f.v[1]) - own_w, swz);
-    }
+    ux = DIV64 ? sux : gx[0];
+    wz = DIV64 ? swz : gz[1];
   }
-  const double ux = DIV64 ? sux : static_cast<double>(sdx[0]);
-  const double wz = DIV64 ? swz : static_cast<double>(sdz[1]);
   // Eqs. uEq..piEq (perturbation form), evaluated in FP64; a uniform
   // background wind u_bar joins u in the advective terms
   const double u = own.v[0], w = own.v[1], th = own.v[2], pi = own.v[3];
   const double ua = u + a.u_bar;
   const double cp_th = a.c_p * (a.theta_bar + th);
   double f[4];
-  f[0] = -ua * ux - w * sdz[0] - cp_th * sdx[3] + a.mu * slp[0] + a.hv * shv[0];
-  f[1] = -ua * sdx[1] - w * wz - cp_th * sdz[3] + a.g * th / a.theta_bar + a.mu * slp[1] + a.hv * shv[1];
-  f[2] = -ua * sdx[2] - w * sdz[2] + a.mu * slp[2] + a.hv * shv[2];
-  f[3] = -ua * sdx[3] - w * (a.dpibar + static_cast<double>(sdz[3])) - a.rcv * (a.pibar[i] + pi) * (ux + wz) +
-         a.hv * shv[3];
+  f[0] = -ua * ux - w * gz[0] - cp_th * gx[3] + a.mu * gl[0] + a.hv * shv[0];
+  f[1] = -ua * gx[1] - w * wz - cp_th * gz[3] + a.g * th / a.theta_bar + a.mu * gl[1] + a.hv * shv[1];
+  f[2] = -ua * gx[2] - w * gz[2] + a.mu * gl[2] + a.hv * shv[2];
+  f[3] = -ua * gx[3] - w * (a.dpibar + gz[3]) - a.rcv * (a.pibar[i] + pi) * (ux + wz) + a.hv * shv[3];
   const uint8_t kd = a.kind[i];
   if (kd & KIND_ZWALL) f[1] = 0.0;  // w stays 0 on walls normal to z
   if (kd & KIND_XWALL) f[0] = 0.0;  // u stays 0 on walls normal to x
@@ -696,24 +731,37 @@ int launch_ghost(rbffd_ctx *ctx, rbffd_model *m, void *y) {
   return RBFFD_OK;
 }
 
+// One stage-kernel launch. With events (kernel timing), the launch goes
+// through hipExtLaunchKernel, which stamps them with the kernel's own start
+// and end, so the measured time leaves out the dispatch around it.
+template <class A>
+hipError_t launch_timed(void (*k)(A), unsigned grid, unsigned block, hipStream_t st, const A &a, hipEvent_t e0,
+                        hipEvent_t e1) {
+  if (e0) {
+    A copy = a;
+    void *args[] = {&copy};
+    return hipExtLaunchKernel(reinterpret_cast<const void *>(k), dim3(grid), dim3(block), args, 0, st, e0, e1, 0);
+  }
+  k<<<grid, block, 0, st>>>(a);
+  return hipGetLastError();
+}
+
 template <class FT, int WDT, int S>
-void launch_ns_one(int64_t cnt, hipStream_t st, const NSArgs &a) {
+hipError_t launch_ns_one(int64_t cnt, hipStream_t st, const NSArgs &a, hipEvent_t e0, hipEvent_t e1) {
   constexpr int B = StageShape<S>::block;
-  if (a.E % 64 == 0)
-    ns_stage_kernel<FT, WDT, S, true><<<grid_for(cnt, B), B, 0, st>>>(a);
-  else
-    ns_stage_kernel<FT, WDT, S, false><<<grid_for(cnt, B), B, 0, st>>>(a);
+  if (a.E % 64 == 0) return launch_timed(ns_stage_kernel<FT, WDT, S, true>, grid_for(cnt, B), B, st, a, e0, e1);
+  return launch_timed(ns_stage_kernel<FT, WDT, S, false>, grid_for(cnt, B), B, st, a, e0, e1);
 }
 
 template <class FT, int WDT>
-void launch_ns_shape(int shape, int64_t cnt, hipStream_t st, const NSArgs &a) {
+hipError_t launch_ns_shape(int shape, int64_t cnt, hipStream_t st, const NSArgs &a, hipEvent_t e0, hipEvent_t e1) {
   switch (shape) {
-    case 0: launch_ns_one<FT, WDT, 0>(cnt, st, a); break;
-    case 1: launch_ns_one<FT, WDT, 1>(cnt, st, a); break;
-    case 2: launch_ns_one<FT, WDT, 2>(cnt, st, a); break;
-    case 3: launch_ns_one<FT, WDT, 3>(cnt, st, a); break;
-    case 4: launch_ns_one<FT, WDT, 4>(cnt, st, a); break;
-    default: launch_ns_one<FT, WDT, 5>(cnt, st, a); break;
+    case 0: return launch_ns_one<FT, WDT, 0>(cnt, st, a, e0, e1);
+    case 1: return launch_ns_one<FT, WDT, 1>(cnt, st, a, e0, e1);
+    case 2: return launch_ns_one<FT, WDT, 2>(cnt, st, a, e0, e1);
+    case 3: return launch_ns_one<FT, WDT, 3>(cnt, st, a, e0, e1);
+    case 4: return launch_ns_one<FT, WDT, 4>(cnt, st, a, e0, e1);
+    default: return launch_ns_one<FT, WDT, 5>(cnt, st, a, e0, e1);
   }
 }
 
@@ -728,9 +776,11 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (m->profile) {
     RBFFD_HIP(ctx, hipEventCreate(&ev0));
-    RBFFD_HIP(ctx, hipEventCreate(&ev1));
+    if (hipEventCreate(&ev1) != hipSuccess) {
+      (void)hipEventDestroy(ev0);
+      return rbffd_fail(ctx, RBFFD_EDEVICE, "hipEventCreate failed");
+    }
     m->prof_events.push_back({ev0, ev1});
-    RBFFD_HIP(ctx, hipEventRecord(ev0, ctx->stream));
   }
   const int64_t cnt = m->Na * m->E;
   DevMisc *misc = m->dev_misc.as<DevMisc>();
@@ -748,6 +798,7 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.kind = m->kind.as<uint8_t>();
     a.pibar = m->pibar.as<double>();
     a.order = m->use_order ? m->order.as<int>() : nullptr;
+    a.rec_t = m->use_order ? m->rec_order.p : nullptr;
     a.Na = m->Na;
     a.n = m->n - m->k0;
     a.E = m->E;
@@ -767,11 +818,11 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.check = sp.check;
     const int shape = m->shape >= 0 ? m->shape : default_shape(m->wdt);
     if (m->fdt == RBFFD_F64)
-      launch_ns_shape<double, RBFFD_F64>(shape, cnt, ctx->stream, a);
+      RBFFD_HIP(ctx, (launch_ns_shape<double, RBFFD_F64>(shape, cnt, ctx->stream, a, ev0, ev1)));
     else if (m->wdt == RBFFD_F32)
-      launch_ns_shape<float, RBFFD_F32>(shape, cnt, ctx->stream, a);
+      RBFFD_HIP(ctx, (launch_ns_shape<float, RBFFD_F32>(shape, cnt, ctx->stream, a, ev0, ev1)));
     else
-      launch_ns_shape<float, RBFFD_BF16>(shape, cnt, ctx->stream, a);
+      RBFFD_HIP(ctx, (launch_ns_shape<float, RBFFD_BF16>(shape, cnt, ctx->stream, a, ev0, ev1)));
   } else {
     AdvArgs a{};
     a.ys = sp.ys;
@@ -799,12 +850,10 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
       a.mir_list = m->mirror_list.as<int>();
     }
     if (m->fdt == RBFFD_F64)
-      adv_stage_kernel<double><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(a);
+      RBFFD_HIP(ctx, launch_timed(adv_stage_kernel<double>, grid_for(cnt, RHS_BLOCK), RHS_BLOCK, ctx->stream, a, ev0, ev1));
     else
-      adv_stage_kernel<float><<<grid_for(cnt, RHS_BLOCK), RHS_BLOCK, 0, ctx->stream>>>(a);
+      RBFFD_HIP(ctx, launch_timed(adv_stage_kernel<float>, grid_for(cnt, RHS_BLOCK), RHS_BLOCK, ctx->stream, a, ev0, ev1));
   }
-  RBFFD_HIP(ctx, hipGetLastError());
-  if (ev1) RBFFD_HIP(ctx, hipEventRecord(ev1, ctx->stream));
   return RBFFD_OK;
 }
 
