@@ -55,9 +55,9 @@ def field_bytes_per_node_stage(tableau, fb, F=4, E=1):
 
 def measured_traffic(leg, bytes_per_launch):
     """HBM bytes per launch (GB) of the stage kernel of one bench leg (fp32,
-    fp64, bf16, ensemble64_fp32) from the committed counter passes, if the
-    kernel sources still hash as when counted and the algorithmic count is
-    the same."""
+    fp64, bf16, ensemble64_fp32_row, ensemble64_fp32_morton) from the
+    committed counter passes, if the kernel sources still hash as when
+    counted and the algorithmic count is the same."""
     import hashlib
     try:
         d = json.load(open(COUNTERS))
@@ -78,9 +78,12 @@ def leg_roofline(leg, res, n_active):
     HIP-event average launch duration, against the 8 TB/s HBM peak, with the
     counter-measured traffic where committed."""
     k_s = res["kernel_avg_ms"] / 1e3
+    counted = leg
+    if leg.startswith("ensemble"):   # the traversal the tuner kept: shapes 6-11 are Morton order
+        counted = f"{leg}_{'morton' if res.get('tuned_shape', 0) >= 6 else 'row'}"
     out = {"bound": "hbm", "achieved": res["bytes_per_launch"] / k_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": res["bytes_per_launch"] / k_s / 1e9 / HBM_PEAK_GBS,
-           "traffic": measured_traffic(leg, res["bytes_per_launch"]),
+           "traffic": measured_traffic(counted, res["bytes_per_launch"]),
            "traffic_unit": "GB per launch (HBM counters, calibrated)", "kernel": "ns_stage_kernel",
            "bytes_per_launch": res["bytes_per_launch"], "kernel_avg_ms": res["kernel_avg_ms"]}
     fixed = FIXED_BYTES_PER_NODE.get(leg)
@@ -341,6 +344,7 @@ def closure_leg(R, ctx, calls=20, members=256):
     cl = R.Closure(ctx, cm, params, nodef, [2.0, 2.0, 1.8, 3e-4], [1e-3, 1e-3, 7e-4, 3e-6],
                    activation=R.ACT_RELU)
     S = cm.Na * members
+    R.rbffd_model_tune(ctx, cm, state)    # the coarse steps in their tuned launch shape
     shape, tune_us = cl.tune(state)
     for _ in range(3):
         cl.forward(state)
@@ -402,6 +406,10 @@ def closure_speedup(R, ctx, cc, params, nodef, members=64, seconds=30.0):
     cm, _ = CL.coarse_model(ctx, cc, members)
     cs = CL.to_full(cm, CL.ensemble_state(cc["coarse"], amps)[:cm.Na])
     cl = R.Closure(ctx, cm, params, nodef, [2.0, 2.0, 1.8, 3e-4], [1e-3, 1e-3, 7e-4, 3e-6], activation=R.ACT_RELU)
+    # both runs in their tuned launch shapes
+    fine_shape, _ = R.rbffd_model_tune(ctx, fm, fs)
+    coarse_shape, _ = R.rbffd_model_tune(ctx, cm, cs)
+    cl.tune(cs)
 
     def timed(fn):
         torch.cuda.synchronize()
@@ -423,7 +431,8 @@ def closure_speedup(R, ctx, cc, params, nodef, members=64, seconds=30.0):
     cs.copy_(c0)
     plain_s = timed(lambda: R.rbffd_step(ctx, cm, cs, 0.0, cc["coarse"]["dt"], nc, R.RK4))
     return dict(members=members, simulated_s=seconds, fine_steps=nf, coarse_steps=nc, fine_run_s=fine_s,
-                corrected_run_s=corr_s, plain_coarse_run_s=plain_s, speedup_corrected_vs_fine=fine_s / corr_s)
+                corrected_run_s=corr_s, plain_coarse_run_s=plain_s, speedup_corrected_vs_fine=fine_s / corr_s,
+                fine_shape=fine_shape, coarse_shape=coarse_shape)
 
 
 def cpu_oracle_weights(min_seconds=10.0):

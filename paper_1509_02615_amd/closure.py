@@ -29,6 +29,7 @@ def fine_snapshots(ctx, ccfg, n_coarse_steps):
     xy, idx, W, Ww, _ = P.ns_weights(ctx, fine)
     model = P.ns_model(ctx, fine, idx, W, Ww, xy=xy, field_dtype=R.F32, weight_dtype=R.F32, ensemble=E)
     state = ensemble_state(fine, ccfg["amplitudes"])
+    R.rbffd_model_tune(ctx, model, state)  # launch shape only: the same bits in every shape
     fmap = torch.from_numpy(ccfg["fine_of_coarse"]).cuda()
     out = torch.empty((n_coarse_steps + 1, len(ccfg["fine_of_coarse"]), E, 4), dtype=torch.float32, device="cuda")
     out[0] = state[fmap]
