@@ -198,13 +198,15 @@ typedef struct {
   int32_t weight_dtype;   /* RBFFD_F64, RBFFD_F32 or RBFFD_BF16 storage of the weights
                              (closure weights stay FP64). F32: every weight as its FP32
                              rounding plus a small correction of Lap^k (within about
-                             2^-30 of FP64), Dx and Dz (about 2^-29). BF16: Dx and Dz as
-                             bfloat16 plus an 8-bit correction (about 2^-16), Lap as
-                             bfloat16, Lap^k as FP32 plus a 16-bit correction (about
-                             2^-40). With F32 and BF16 the hyperviscosity sums and the
-                             divergence u_x + w_z run in FP64 on the corrected
-                             weights, the other sums in FP32; Lap^k weights must lie
-                             in the FP32 normal range. F32/BF16 need field_dtype F32. */
+                             2^-30 of FP64), Dx and Dz (about 2^-29). BF16: Dx, Dz and
+                             Lap as bfloat16 plus an 8-bit correction (about 2^-16),
+                             Lap^k as FP32 plus an 8-bit correction (about 2^-32). With
+                             F32 and BF16 the hyperviscosity sums and the divergence
+                             u_x + w_z run in FP64 on the corrected weights, the other
+                             sums in FP32; ghost values are kept in FP64 beside the FP32
+                             state for the sums of the nodes next to walls; Lap^k
+                             weights must lie in the FP32 normal range. F32/BF16 need
+                             field_dtype F32. */
   int32_t n;              /* stencil length (row length of idx and w)                    */
   int64_t n_total;        /* N: all nodes including ghosts                               */
   int64_t n_active;       /* nodes 0..n_active-1 carry stencils and prognostic values;

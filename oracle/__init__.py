@@ -24,6 +24,6 @@ from .weights import (
     DX, DZ, LAP, HYPERLAP, DZZ, DXX, poly_exponents, phs_apply, poly_apply,
     stencil_weights, all_weights, op_order,
 )
-from .rhs import apply_dm, dm_matrix, advection_rhs, AdvectionModel, ghost_matrices, ghost_closure, ns_rhs, ns_tendency, NSModel
+from .rhs import apply_dm, dm_matrix, advection_rhs, AdvectionModel, ghost_matrices, ghost_closure, ns_rhs, ns_tendency, NSModel, WallRows
 from .timestep import rk4_step, wsrk3_step, integrate
 from .diagnostics import rel_l2, front_location, extrema, translating_fronts, bubble_height

@@ -90,7 +90,8 @@ def ghost_matrices(idx, rows_w, bnd_nodes, bnd_ghosts):
     """The ghost block W_G [R][R] (sparse) of one operator per boundary row:
     row r holds the weights ``rows_w[r]`` of the stencil of node
     ``bnd_nodes[r]`` at the ghost columns, column c being ghost
-    ``bnd_ghosts[c]``."""
+    ``bnd_ghosts[c]``. ``idx`` holds the stencils of at least those nodes
+    (``idx[bnd_nodes[r]]``)."""
     col = {int(g): c for c, g in enumerate(bnd_ghosts)}
     R = len(bnd_nodes)
     r_i, c_i, v = [], [], []
@@ -102,6 +103,37 @@ def ghost_matrices(idx, rows_w, bnd_nodes, bnd_ghosts):
                 c_i.append(c)
                 v.append(rows_w[r][k])
     return scipy.sparse.csc_matrix((v, (r_i, c_i)), shape=(R, R))
+
+
+@dataclass
+class WallRows:
+    """What the Section 5.2 ghost solve of a node set needs: its boundary
+    rows, their stencils and normal-derivative weights, and which nodes are
+    ghosts or wall nodes. The stencils of other nodes are not needed."""
+    idx: np.ndarray            # [n_active][n] stencils; only the rows of bnd_nodes are read
+    n_active: int
+    n_total: int
+    bnd_nodes: np.ndarray      # [R] boundary node of each boundary row
+    bnd_ghosts: np.ndarray     # [R] its ghost
+    bnd_normal: np.ndarray     # [R] 0: wall normal to z, 1: wall normal to x
+    bnd_d1: np.ndarray         # [R][n] first normal-derivative weights (Dz or Dx)
+    bnd_d2: np.ndarray         # [R][n] second normal-derivative weights (Dzz or Dxx)
+    consts: dict               # c_p, theta_bar, g
+
+    def __post_init__(self):
+        zn = (self.bnd_normal == 0)[:, None]
+        self.w_u = np.where(zn, self.bnd_d1, self.bnd_d2)      # du/dz, or d2u/dx2
+        self.w_w = np.where(zn, self.bnd_d2, self.bnd_d1)      # d2w/dz2, or dw/dx
+        mats = [ghost_matrices(self.idx, W, self.bnd_nodes, self.bnd_ghosts)
+                for W in (self.w_u, self.w_w, self.bnd_d1)]
+        self.lu = [scipy.sparse.linalg.splu(m) for m in mats] if len(self.bnd_nodes) else []
+        ghost = np.zeros(self.n_total, bool)
+        ghost[self.bnd_ghosts] = True
+        self.is_ghost = ghost
+        self.zwall = np.zeros(self.n_active, bool)
+        self.zwall[self.bnd_nodes[self.bnd_normal == 0]] = True
+        self.xwall = np.zeros(self.n_active, bool)
+        self.xwall[self.bnd_nodes[self.bnd_normal == 1]] = True
 
 
 @dataclass
@@ -123,44 +155,35 @@ class NSModel:
     hv_coeff: float
 
     def __post_init__(self):
-        zn = (self.bnd_normal == 0)[:, None]
-        self.w_u = np.where(zn, self.bnd_d1, self.bnd_d2)      # du/dz, or d2u/dx2
-        self.w_w = np.where(zn, self.bnd_d2, self.bnd_d1)      # d2w/dz2, or dw/dx
-        mats = [ghost_matrices(self.idx, W, self.bnd_nodes, self.bnd_ghosts)
-                for W in (self.w_u, self.w_w, self.bnd_d1)]
-        self.lu = [scipy.sparse.linalg.splu(m) for m in mats] if len(self.bnd_nodes) else []
-        ghost = np.zeros(self.z.shape[0], bool)
-        ghost[self.bnd_ghosts] = True
-        self.is_ghost = ghost
-        self.zwall = np.zeros(self.n_active, bool)
-        self.zwall[self.bnd_nodes[self.bnd_normal == 0]] = True
-        self.xwall = np.zeros(self.n_active, bool)
-        self.xwall[self.bnd_nodes[self.bnd_normal == 1]] = True
+        self.walls = WallRows(self.idx, self.n_active, self.z.shape[0], self.bnd_nodes, self.bnd_ghosts,
+                              self.bnd_normal, self.bnd_d1, self.bnd_d2, self.consts)
+        self.zwall, self.xwall = self.walls.zwall, self.walls.xwall
         # the same differentiation matrices as sparse products, for long runs
         n_tot = self.z.shape[0]
         self.D = [dm_matrix(self.idx, W, n_tot) for W in (self.w_dx, self.w_dz, self.w_lap, self.w_hv)]
 
 
-def ghost_closure(model: NSModel, state: np.ndarray) -> np.ndarray:
+def ghost_closure(model, state: np.ndarray) -> np.ndarray:
     """Return a copy of ``state`` [n_total][4] (u, w, theta', pi') with w = 0
     on walls normal to z, u = 0 on walls normal to x, and the ghost rows set
-    from the Section 5.2 solve."""
+    from the Section 5.2 solve. ``model`` is an NSModel or a WallRows."""
+    wr = model.walls if isinstance(model, NSModel) else model
     s = np.array(state, dtype=np.float64, copy=True)
-    if not len(model.bnd_nodes):
+    if not len(wr.bnd_nodes):
         return s
-    c = model.consts
-    s[np.nonzero(model.zwall)[0], 1] = 0.0
-    s[np.nonzero(model.xwall)[0], 0] = 0.0
-    nodes = model.bnd_nodes
-    rows = model.idx[nodes]                                  # [R][n]
-    keep = ~model.is_ghost[rows]                             # non-ghost entries
+    c = wr.consts
+    s[np.nonzero(wr.zwall)[0], 1] = 0.0
+    s[np.nonzero(wr.xwall)[0], 0] = 0.0
+    nodes = wr.bnd_nodes
+    rows = wr.idx[nodes]                                     # [R][n]
+    keep = ~wr.is_ghost[rows]                                # non-ghost entries
     th_b = s[nodes, 2]
-    bc_pi = np.where(model.bnd_normal == 0,
+    bc_pi = np.where(wr.bnd_normal == 0,
                      c["g"] * th_b / (c["c_p"] * c["theta_bar"] * (c["theta_bar"] + th_b)), 0.0)
-    for f, W, lu, bc in ((0, model.w_u, model.lu[0], 0.0), (1, model.w_w, model.lu[1], 0.0),
-                         (2, model.bnd_d1, model.lu[2], 0.0), (3, model.bnd_d1, model.lu[2], bc_pi)):
+    for f, W, lu, bc in ((0, wr.w_u, wr.lu[0], 0.0), (1, wr.w_w, wr.lu[1], 0.0),
+                         (2, wr.bnd_d1, wr.lu[2], 0.0), (3, wr.bnd_d1, wr.lu[2], bc_pi)):
         r = bc - apply_dm(rows, np.where(keep, W, 0.0), s[:, f])
-        s[model.bnd_ghosts, f] = lu.solve(r)
+        s[wr.bnd_ghosts, f] = lu.solve(r)
     return s
 
 

@@ -135,10 +135,12 @@ __global__ void repack_bf16(const int *__restrict__ idx, const double *__restric
   idx_t[static_cast<int64_t>(k) * na + i] = idx[src];
   if (k < k0) return;  // the centre slot: every centre-subtracted sum skips it
   const double wx = w[src], wz = w[plane + src], hv = w[3 * plane + src];
-  const uint16_t bx = to_bf16(wx), bz = to_bf16(wz);
-  rec[dst] = RecBF16{bx, bz, to_bf16(w[2 * plane + src]), nb_offset(idx[src], i)};
+  const double wl = w[2 * plane + src];
+  const uint16_t bx = to_bf16(wx), bz = to_bf16(wz), bl = to_bf16(wl);
+  rec[dst] = RecBF16{bx, bz, bl, nb_offset(idx[src], i)};
   const float hh = hv_hi(hv, bad);
-  rec2[dst] = RecBF16X{hh, static_cast<int16_t>(rel_q(hv, hh, 1.0 / HV_Q16_SCALE, 16)), bf_q(wx, bx), bf_q(wz, bz)};
+  rec2[dst] = RecBF16X{hh, static_cast<int8_t>(rel_q(hv, hh, 1.0 / HV_Q8_SCALE, 8)), bf_q(wl, bl), bf_q(wx, bx),
+                       bf_q(wz, bz)};
 }
 
 // Transport, flux form (Section 6.1): (D_x (U psi) + D_z (V psi))_i
@@ -181,6 +183,16 @@ __global__ void check_idx(const int *__restrict__ idx, int64_t count, int64_t n_
 __global__ void pibar_kernel(const double *__restrict__ xy, int64_t na, double gk, double *__restrict__ pb) {
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < na) pb[i] = 1.0 - gk * xy[2 * i + 1];
+}
+
+// KIND_REACH on every active node with a ghost (index >= na) in its stencil
+// (idx_t slot-major, [n][na]).
+__global__ void reach_kernel(const int *__restrict__ idx_t, int64_t na, int n, uint8_t *__restrict__ kind) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= na) return;
+  bool reach = false;
+  for (int k = 0; k < n; ++k) reach |= idx_t[static_cast<int64_t>(k) * na + i] >= na;
+  if (reach) kind[i] |= KIND_REACH;
 }
 
 __global__ void kind_kernel(uint8_t *__restrict__ kind, int64_t n_total, int64_t na) {
@@ -676,6 +688,9 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
          m->inv_off.alloc(sizeof(int64_t) * h_off.size()) == hipSuccess &&
          m->inv_val.alloc(sizeof(double) * h_val.size()) == hipSuccess &&
          m->gres.alloc(sizeof(double) * R * m->E * 4) == hipSuccess;
+    if (ok && m->fdt == RBFFD_F32 && m->N > na)
+      ok = m->ghrem.alloc(sizeof(float) * (m->N - na) * m->E * 4) == hipSuccess &&
+           hipMemset(m->ghrem.p, 0, m->ghrem.bytes) == hipSuccess;
     if (!ok) return fail_model(ctx, m, RBFFD_ENOMEM, "device allocation (closure)");
     ok = hipMemcpy(m->bnd_nodes.p, p_node.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(m->bnd_ghosts.p, p_ghost.data(), sizeof(int) * R, hipMemcpyHostToDevice) == hipSuccess &&
@@ -688,6 +703,8 @@ int model_create_impl(rbffd_ctx *ctx, const rbffd_model_desc *d, rbffd_model **o
          hipMemcpy(m->inv_val.p, h_val.data(), sizeof(double) * h_val.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(m->kind.p, h_kind.data(), static_cast<size_t>(m->N), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) return fail_model(ctx, m, RBFFD_EDEVICE, "closure upload");
+    reach_kernel<<<grid_for(na, 256), 256, 0, s>>>(m->idx_t.as<int>(), na, m->n, m->kind.as<uint8_t>());
+    if (hipGetLastError() != hipSuccess) return fail_model(ctx, m, RBFFD_EDEVICE, "node kinds");
   }
   // RK buffers
   const size_t sb = m->state_bytes();

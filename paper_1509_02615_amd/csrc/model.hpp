@@ -35,20 +35,21 @@ struct RecBF16 {     // BF16 Navier-Stokes: Dx, Dz, Lap (bfloat16 bits) and the 
   uint16_t dx, dz, lap;
   int16_t off;
 };
-struct RecBF16X {    // the BF16 layout's second stream: the Lap^k weight as FP32 hi and
-  float hv;          // a correction (hv (1 + hvq 2^-39), about 2^-40), and 8-bit
-  int16_t hvq;       // corrections of the Dx and Dz weights, each bf16 (1 + q 2^-15),
+struct RecBF16X {    // the BF16 layout's second stream: the Lap^k weight as FP32 hi with
+  float hv;          // an 8-bit correction (hv (1 + hvq 2^-31), about 2^-32), and 8-bit
+  int8_t hvq, lapq;  // corrections of the Lap, Dx and Dz weights, each bf16 (1 + q 2^-15),
   int8_t dxq, dzq;   // so that they keep about 16 significant bits
 };
-constexpr double HV_Q16_SCALE = 0x1p-39;
+constexpr double HV_Q8_SCALE = 0x1p-31;
 constexpr float BF_Q_SCALE = 0x1p-15f;
 struct RecAdv {      // transport: folded flux weights and Lap^k
   double adv, hv;
 };
 
 // Node kinds (bits): on a wall normal to z (w = 0), ghost, on a wall normal
-// to x (u = 0); a corner of a closed box carries both wall bits.
-constexpr uint8_t KIND_ZWALL = 1, KIND_GHOST = 2, KIND_XWALL = 4;
+// to x (u = 0); a corner of a closed box carries both wall bits. An active
+// node whose stencil holds a ghost also carries KIND_REACH.
+constexpr uint8_t KIND_ZWALL = 1, KIND_GHOST = 2, KIND_XWALL = 4, KIND_REACH = 8;
 
 struct rbffd_model {
   rbffd_ctx *ctx = nullptr;
@@ -85,6 +86,8 @@ struct rbffd_model {
   DevBuf inv_off;                  // int64 [3][R] offset of the window's values
   DevBuf inv_val;                  // double: window values
   DevBuf gres;                     // double [R][E][4] residuals
+  DevBuf ghrem;                    // float [N - Na][E][4]: the last closure's ghost values' FP64
+                                   // remainders past their FP32 rounding in the state (FP32 fields)
   // transport mirror ghosts
   int64_t n_mirror = 0;
   DevBuf mirror_src;               // int32 [N - Na]

@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 #include <cmath>
 
 #include "model.hpp"
@@ -139,6 +140,12 @@ __device__ __forceinline__ void store4(double *p, const double *v) {
   reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
   reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
 }
+// v - fl32(v) for each of four FP64 values, as FP32 (exact to about 2^-48 of v)
+__device__ __forceinline__ void store_remainder(float *p, const double *v) {
+  float r[4];
+  for (int c = 0; c < 4; ++c) r[c] = static_cast<float>(v[c] - static_cast<double>(static_cast<float>(v[c])));
+  *reinterpret_cast<float4 *>(p) = make_float4(r[0], r[1], r[2], r[3]);
+}
 
 __device__ __forceinline__ float bf16f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
 
@@ -156,6 +163,8 @@ struct NSArgs {
   const double *pibar;
   const int *order;   // member-wavefront mode: node of each wavefront-sized unit (or NULL)
   const void *rec_t;  // with `order`, FP32 ensemble records in that order (or NULL)
+  const float *ghrem; // FP32 fields: each ghost value's FP64 remainder past its FP32
+                      // rounding in the state, [N - Na][E][4] (or NULL)
   int64_t Na;
   int n, E;
   double c_p, rcv, g, theta_bar, mu, hv, dpibar, u_bar;
@@ -197,19 +206,38 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
     // FP32 ensembles of a multiple of 64 members: the FP64 record (RecMW) is
     // wave-uniform, and every sum is taken in FP64 from exact differences.
     // The vector unit issues an FP64 multiply-add at the rate of an FP32 one
-    // (packed FP32 is not used), this path is bound by its vector
-    // instructions, and FP32 sums would need the FP64 weights converted
-    // per slot besides the FP64 Lap^k and divergence sums
+    // (packed FP32 is not used), so FP64 sums cost no more and spare the
+    // per-slot conversions of FP64 weights to FP32
     const double o[4] = {own.v[0], own.v[1], own.v[2], own.v[3]};
     double sx[4] = {0.0, 0.0, 0.0, 0.0}, sz[4] = {0.0, 0.0, 0.0, 0.0}, sl[3] = {0.0, 0.0, 0.0};
-    const RecMW *recs = static_cast<const RecMW *>(a.rec_t ? a.rec_t : a.rec);
+    const RecMW *recs = static_cast<const RecMW *>(a.rec_t ? a.rec_t : a.rec) + ri;
+    // the neighbour's member vector: a wave-uniform base (scalar arithmetic)
+    // plus the lane's 16-byte offset
+    auto gather = [&](int j) { return load4(ys + static_cast<int64_t>(j) * (4 * E) + 4 * static_cast<uint32_t>(e)); };
+    if (a.ghrem && (a.kind[i] & KIND_REACH)) {
+      // a node next to a wall (wave-uniform): the ghost neighbours' closure
+      // values' FP64 remainders are added as well, as in the one-member path
+#pragma unroll 1
+      for (int k = 0; k < n; ++k) {
+        const RecMW r = recs[k * Na];
+        if (r.idx < Na) continue;
+        const float4 q4 = *reinterpret_cast<const float4 *>(a.ghrem + ((r.idx - Na) * E + e) * 4);
+        const float q[4] = {q4.x, q4.y, q4.z, q4.w};
+        const double wl = r.lap;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double d = q[c];
+          sx[c] = fma(r.dx, d, sx[c]);
+          sz[c] = fma(r.dz, d, sz[c]);
+          if (c < 3) sl[c] = fma(wl, d, sl[c]);
+          shv[c] = fma(r.hv, d, shv[c]);
+        }
+      }
+    }
 #pragma unroll SH::unroll
     for (int k = 0; k < n; ++k) {
-      const RecMW r = recs[static_cast<int64_t>(k) * Na + ri];
-      // the neighbour's member vector: a wave-uniform base (scalar
-      // arithmetic) plus the lane's 16-byte offset
-      const FT *nb = ys + static_cast<int64_t>(r.idx) * (4 * E);
-      const F4<FT> f = load4(nb + 4 * static_cast<uint32_t>(e));
+      const RecMW r = recs[k * Na];
+      const F4<FT> f = gather(r.idx);
       const double wl = r.lap;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -234,66 +262,103 @@ __global__ __launch_bounds__(StageShape<S>::block) void ns_stage_kernel(NSArgs a
     double sux = 0.0, swz = 0.0;
     constexpr bool DIV64 = WDT != RBFFD_F64;
     const double own_u = static_cast<double>(own.v[0]), own_w = static_cast<double>(own.v[1]);
-#pragma unroll SH::unroll
-    for (int k = 0; k < n; ++k) {
-      const int64_t s = static_cast<int64_t>(k) * Na + i;
+    // slot k's neighbour and weights (the weights corrected towards FP64
+    // for the FP64 sums)
+    struct Slot {
       int j;
       FT wdx, wdz, wlp;
-      double whv, wdx64 = 0.0, wdz64 = 0.0;
+      double whv, wdx64, wdz64;
+    };
+    auto slot = [&](int k) {
+      const int64_t s = static_cast<int64_t>(k) * Na + i;
+      Slot q{};
       int off;
       if constexpr (WDT == RBFFD_F64) {
         const double2 r0 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s);
         const double2 r1 = stream_load2<NT>(reinterpret_cast<const double2 *>(a.rec) + 2 * s + 1);
         off = load_off<NT, MW>(a.off16, s);
-        wdx = r0.x;
-        wdz = r0.y;
-        wlp = r1.x;
-        whv = r1.y;
+        q.wdx = r0.x;
+        q.wdz = r0.y;
+        q.wlp = r1.x;
+        q.whv = r1.y;
       } else if constexpr (WDT == RBFFD_F32) {
         const float4 r = stream_load4<NT>(reinterpret_cast<const float4 *>(a.rec) + s);
         const uint32_t x = stream_load<NT>(a.aux32 + s);
         off = static_cast<int16_t>(x >> 16);
-        wdx = r.x;
-        wdz = r.y;
-        wlp = r.z;
+        q.wdx = r.x;
+        q.wdz = r.y;
+        q.wlp = r.z;
         // corrections: bits 15-10 (Lap^k), 9-5 (Dx), 4-0 (Dz), signed
         const int qh = static_cast<int>(x << 16) >> 26, qx = static_cast<int>(x << 22) >> 27,
                   qz = static_cast<int>(x << 27) >> 27;
         const double hh = r.w, hx = r.x, hz = r.y;
-        whv = fma(hh, static_cast<double>(qh) * HV_Q_SCALE, hh);
-        wdx64 = fma(hx, static_cast<double>(qx) * D_Q_SCALE, hx);
-        wdz64 = fma(hz, static_cast<double>(qz) * D_Q_SCALE, hz);
+        q.whv = fma(hh, static_cast<double>(qh) * HV_Q_SCALE, hh);
+        q.wdx64 = fma(hx, static_cast<double>(qx) * D_Q_SCALE, hx);
+        q.wdz64 = fma(hz, static_cast<double>(qz) * D_Q_SCALE, hz);
       } else {
         const uint2 r = stream_load2u<NT>(reinterpret_cast<const uint2 *>(a.rec) + s);
         const uint2 x = stream_load2u<NT>(reinterpret_cast<const uint2 *>(a.rec2) + s);
-        // RecBF16X: {float hv, int16 hvq, int8 dxq, int8 dzq}
+        // RecBF16X: {float hv, int8 hvq, lapq, dxq, dzq}
         const float bx = __uint_as_float(r.x << 16), bz = __uint_as_float(r.x & 0xffff0000u);
-        wdx = fmaf(bx, static_cast<float>(static_cast<int>(x.y << 8) >> 24) * BF_Q_SCALE, bx);
-        wdz = fmaf(bz, static_cast<float>(static_cast<int>(x.y) >> 24) * BF_Q_SCALE, bz);
-        wlp = __uint_as_float(r.y << 16);
+        const float bl = __uint_as_float(r.y << 16);
+        q.wdx = fmaf(bx, static_cast<float>(static_cast<int>(x.y << 8) >> 24) * BF_Q_SCALE, bx);
+        q.wdz = fmaf(bz, static_cast<float>(static_cast<int>(x.y) >> 24) * BF_Q_SCALE, bz);
+        q.wlp = fmaf(bl, static_cast<float>(static_cast<int>(x.y << 16) >> 24) * BF_Q_SCALE, bl);
         off = static_cast<int16_t>(r.y >> 16);
         const double hh = __uint_as_float(x.x);
-        whv = fma(hh, static_cast<double>(static_cast<int16_t>(x.y & 0xffffu)) * HV_Q16_SCALE, hh);
-        wdx64 = wdx;
-        wdz64 = wdz;
+        q.whv = fma(hh, static_cast<double>(static_cast<int>(x.y << 24) >> 24) * HV_Q8_SCALE, hh);
+        q.wdx64 = q.wdx;
+        q.wdz64 = q.wdz;
       }
       if (__builtin_expect(off == OFF_FAR, 0))
-        j = a.idx_t[s];  // a ghost neighbour
+        q.j = a.idx_t[s];  // a neighbour beyond +-32767 (a ghost of the first rows)
       else
-        j = static_cast<int>(i) + off;
-      const F4<FT> f = load4(ys + (static_cast<int64_t>(j) * E + e) * 4);
+        q.j = static_cast<int>(i) + off;
+      return q;
+    };
+    // one slot's sums; `ghosts`: the model keeps its ghost values' FP64
+    // remainders (FP32 fields), and a ghost neighbour adds its remainder
+    // into every sum: the FP32 state holds the closure value rounded, and
+    // next to a wall that rounding is a large part of the stencil
+    // differences (which the Lap^k weights amplify)
+    auto step = [&](const Slot &q, auto ghosts) {
+      const F4<FT> f = load4(ys + (static_cast<int64_t>(q.j) * E + e) * 4);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const FT d = f.v[c] - own.v[c];
-        if (!DIV64 || c != 0) sdx[c] = fma(wdx, d, sdx[c]);
-        if (!DIV64 || c != 1) sdz[c] = fma(wdz, d, sdz[c]);
-        if (c < 3) slp[c] = fma(wlp, d, slp[c]);
-        shv[c] = fma(whv, static_cast<double>(d), shv[c]);
+        if (!DIV64 || c != 0) sdx[c] = fma(q.wdx, d, sdx[c]);
+        if (!DIV64 || c != 1) sdz[c] = fma(q.wdz, d, sdz[c]);
+        if (c < 3) slp[c] = fma(q.wlp, d, slp[c]);
+        shv[c] = fma(q.whv, static_cast<double>(d), shv[c]);
       }
       if constexpr (DIV64) {
-        sux = fma(wdx64, static_cast<double>(f.v[0]) - own_u, sux);
-        swz = fma(wdz64, static_cast<double>(f.v[1]) - own_w, swz);
+        sux = fma(q.wdx64, static_cast<double>(f.v[0]) - own_u, sux);
+        swz = fma(q.wdz64, static_cast<double>(f.v[1]) - own_w, swz);
       }
+      if constexpr (decltype(ghosts)::value && std::is_same<FT, float>::value) {
+        if (q.j >= Na) {
+          const float4 r4 = *reinterpret_cast<const float4 *>(a.ghrem + ((q.j - Na) * E + e) * 4);
+          const float r[4] = {r4.x, r4.y, r4.z, r4.w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (!DIV64 || c != 0) sdx[c] = fma(q.wdx, r[c], sdx[c]);
+            if (!DIV64 || c != 1) sdz[c] = fma(q.wdz, r[c], sdz[c]);
+            if (c < 3) slp[c] = fma(q.wlp, r[c], slp[c]);
+            shv[c] = fma(q.whv, static_cast<double>(r[c]), shv[c]);
+          }
+          if constexpr (DIV64) {
+            sux = fma(q.wdx64, static_cast<double>(r[0]), sux);
+            swz = fma(q.wdz64, static_cast<double>(r[1]), swz);
+          }
+        }
+      }
+    };
+    if (a.ghrem) {
+#pragma unroll SH::unroll
+      for (int k = 0; k < n; ++k) step(slot(k), std::true_type{});
+    } else {
+#pragma unroll SH::unroll
+      for (int k = 0; k < n; ++k) step(slot(k), std::false_type{});
     }
     for (int c = 0; c < 4; ++c) {
       gx[c] = static_cast<double>(sdx[c]);
@@ -405,7 +470,10 @@ struct GArgs {
   const int64_t *inv_off;  // window value offset per (matrix, row)
   const double *inv_val;
   double *gres;            // [R][E][4]
+  float *ghrem;            // FP32 fields: each ghost value's remainder past its FP32 rounding,
+                           // [N - Na][E][4] (or NULL)
   const uint8_t *kind;
+  int64_t Na;
   int R, n, E;
   int u_shared;                // 1: u's block equals theta prime's (no wall normal to x)
   double bc_scale, theta_bar;  // dpi/dz = bc_scale * th / (theta_bar + th) on walls normal to z
@@ -590,7 +658,10 @@ __global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_kernel(GArgs a) {
     apply_sum(a, wt, ww, wu, q + 64, t1, v);
   }
   for (int f = 0; f < 4; ++f) v[f] = wave_sum(v[f]);
-  if (lane == 0) store4(static_cast<FT *>(a.y) + go, v);
+  if (lane == 0) {
+    store4(static_cast<FT *>(a.y) + go, v);
+    if (a.ghrem) store_remainder(a.ghrem + go - a.Na * a.E * 4, v);
+  }
 }
 
 // Ensembles (E >= GHOST_MEMBER_LANES): the same two steps with one thread
@@ -651,7 +722,9 @@ __global__ __launch_bounds__(RHS_BLOCK) void ghost_apply_members_kernel(GArgs a)
       }
     }
   }
-  store4(static_cast<FT *>(a.y) + (static_cast<int64_t>(a.bnd_ghosts[row]) * a.E + e) * 4, v);
+  const int64_t go = (static_cast<int64_t>(a.bnd_ghosts[row]) * a.E + e) * 4;
+  store4(static_cast<FT *>(a.y) + go, v);
+  if (a.ghrem) store_remainder(a.ghrem + go - a.Na * a.E * 4, v);
 }
 
 __global__ void misc_init_kernel(DevMisc *m, double t0) {
@@ -700,6 +773,8 @@ int launch_ghost(rbffd_ctx *ctx, rbffd_model *m, void *y) {
   g.inv_off = m->inv_off.as<int64_t>();
   g.inv_val = m->inv_val.as<double>();
   g.gres = m->gres.as<double>();
+  g.ghrem = m->ghrem.as<float>();
+  g.Na = m->Na;
   g.kind = m->kind.as<uint8_t>();
   g.R = m->n_bnd;
   g.u_shared = m->u_shares_tp;
@@ -799,6 +874,7 @@ int launch_stage(rbffd_ctx *ctx, rbffd_model *m, const StageSpec &sp, double t_f
     a.pibar = m->pibar.as<double>();
     a.order = m->use_order ? m->order.as<int>() : nullptr;
     a.rec_t = m->use_order ? m->rec_order.p : nullptr;
+    a.ghrem = m->ghrem.as<float>();
     a.Na = m->Na;
     a.n = m->n - m->k0;
     a.E = m->E;

@@ -618,6 +618,77 @@ def test_measurement_helpers(R, ctx):
         assert bool(torch.isfinite(out).all())
 
 
+def test_full_size_wall_rows_match_the_oracle(R, ctx):
+    """2048 x 256 channel (2 x 2,048 wall rows): the tendency at 288 sampled
+    nodes of the three rows next to each wall, whose stencils reach the
+    ghosts, against the oracle with its own Section 5.2 ghost solve over
+    every boundary row: FP64 1e-12, FP32 1e-6 (FP32-representable inputs),
+    BF16 weights 2e-3, rel-l2 per field over the samples.
+
+    The oracle is handed the nodes of the 12 rows nearest each wall and all
+    ghosts, renumbered. That is the whole node set for these stencils: the
+    test checks that every oracle stencil's 37th neighbour is nearer than
+    the nearest node left out, so the stencils, weights and ghost values are
+    those of the full channel, and it checks the GPU stencils against them."""
+    import torch
+    from oracle.pipeline import ns_ops, wall_ops
+    from paper_1509_02615_amd import pipeline as P
+    say("full size: 2048x256 channel, sampled wall-adjacent rows against the oracle's ghost closure")
+    cfg = scale_config()
+    nd = cfg["nodes"]
+    na, nx, nz, n = nd.n_active, nd.nx, nd.nz, cfg["n"]
+    xy, idx, W, Ww, (st_a, st_w) = P.ns_weights(ctx, cfg)
+    assert int(st_a.abs().sum()) == 0 and int(st_w.abs().sum()) == 0
+    state = smooth_ns_state(nd, seed=8).astype(np.float32).astype(np.float64)
+    # the oracle's node set: the rows near the walls, then every ghost
+    row_of = np.arange(na) // nx
+    near = 12
+    sub_active = np.nonzero((row_of < near) | (row_of >= nz - near))[0]
+    sub = np.concatenate([sub_active, np.arange(na, nd.n_total)])
+    to_sub = np.full(nd.n_total, -1, np.int64)
+    to_sub[sub] = np.arange(len(sub))
+    oxy = nd.xy[sub]
+    assert np.all(nd.bnd_normal == 0)
+    bnd, ghosts = to_sub[nd.bnd_nodes], to_sub[nd.bnd_ghosts]
+    rng = np.random.default_rng(3)
+    samp_full = np.concatenate([r * nx + rng.choice(nx, 48, replace=False) for r in (0, 1, 2, nz - 3, nz - 2, nz - 1)])
+    samp = to_sub[samp_full]
+    idx_b = O.knn(oxy, bnd, n, nd.period_x)
+    idx_s = O.knn(oxy, samp, n, nd.period_x)
+    z_lo = nd.xy[:na][row_of == near][:, 1].min()
+    z_hi = nd.xy[:na][row_of == nz - near - 1][:, 1].max()
+    for centres, st in ((bnd, idx_b), (samp, idx_s)):
+        c, nb = oxy[centres], oxy[st]
+        dx = nb[:, :, 0] - c[:, None, 0]
+        dx -= nd.period_x * np.round(dx / nd.period_x)
+        radius = np.sqrt((dx ** 2 + (nb[:, :, 1] - c[:, None, 1]) ** 2).max(axis=1))
+        gap = np.minimum(np.abs(z_lo - c[:, 1]), np.abs(c[:, 1] - z_hi))
+        assert np.all(radius < 0.9 * gap)
+    gpu_idx = host(idx).astype(np.int64)
+    assert np.array_equal(to_sub[gpu_idx[samp_full]], idx_s)
+    assert np.array_equal(to_sub[gpu_idx[nd.bnd_nodes]], idx_b)
+    Wb, st_b = O.all_weights(oxy, idx_b, bnd, cfg["m"], cfg["l"], wall_ops(0), nd.period_x)
+    Ws, st_s = O.all_weights(oxy, idx_s, samp, cfg["m"], cfg["l"], ns_ops(cfg), nd.period_x)
+    assert st_b.sum() == 0 and st_s.sum() == 0
+    rows_idx = np.zeros((len(sub_active), n), np.int64)
+    rows_idx[bnd] = idx_b
+    walls = O.WallRows(rows_idx, len(sub_active), len(sub), bnd, ghosts, nd.bnd_normal, Wb[0], Wb[1], cfg["consts"])
+    closed = O.ghost_closure(walls, state[sub])
+    ref = O.ns_tendency(closed, samp, idx_s, Ws[0], Ws[1], Ws[2], Ws[3], oxy[samp, 1], walls.zwall[samp],
+                        cfg["consts"], cfg["hv_coeff"])
+    for fdt, wdt, dt, tol in ((0, 0, torch.float64, 1e-12), (1, 1, torch.float32, 1e-6),
+                              (1, 2, torch.float32, 2e-3)):
+        gm = P.ns_model(ctx, cfg, idx, W, Ww, xy=xy, field_dtype=fdt, weight_dtype=wdt)
+        s = dev(state, dt).reshape(gm.state_shape()).contiguous()
+        out = torch.empty_like(s)
+        R.rbffd_rhs(ctx, gm, 0.0, s, out)
+        got = host(out).reshape(-1, 4)[samp_full]
+        errs = [np.linalg.norm(got[:, f] - ref[:, f]) / np.linalg.norm(ref[:, f]) for f in range(4)]
+        say(f"   field dtype {fdt}, weight dtype {wdt}: rel-l2 per field over the wall-adjacent samples "
+            f"{['%.2e' % e for e in errs]}")
+        assert max(errs) <= tol
+
+
 def test_full_size_ghost_closure_holds_the_wall_conditions(R, ctx):
     """2048 x 256 channel (2 x 2,048 wall rows): after the ghost closure
     every wall row's own conditions hold to rounding with the model's wall

@@ -70,6 +70,50 @@ def test_ghost_closure_enforces_boundary_conditions(ns800):
     _check_boundary_conditions(*ns800)
 
 
+def test_wall_rows_alone_give_the_full_ghost_closure(ns800):
+    """The ghost solve (Section 5.2) needs only the boundary rows' stencils
+    and weights: a WallRows built on the nodes of the rows nearest the walls
+    plus the ghosts (renumbered) gives the same ghost values and the same
+    tendency at the rows next to the walls as the full model, bit for bit.
+    The full-size GPU comparison of the wall rows relies on this."""
+    from oracle.pipeline import ns_ops, wall_ops
+    cfg, model = ns800
+    nd = cfg["nodes"]
+    na, nx, nz = nd.n_active, nd.nx, nd.nz
+    rng = np.random.default_rng(2)
+    st = rng.standard_normal(cfg["state0"].shape) * np.array([10, 10, 5, 1e-3])
+    full, _ = O.ns_rhs(model, st)
+    closed_full = O.ghost_closure(model, st)
+    row = np.arange(na) // nx
+    near = 6
+    sub = np.concatenate([np.nonzero((row < near) | (row >= nz - near))[0], np.arange(na, nd.n_total)])
+    n_sub_active = int(np.sum((row < near) | (row >= nz - near)))
+    to_sub = np.full(nd.n_total, -1, np.int64)
+    to_sub[sub] = np.arange(len(sub))
+    xy = nd.xy[sub]
+    bnd, ghosts = to_sub[nd.bnd_nodes], to_sub[nd.bnd_ghosts]
+    idx_b = O.knn(xy, bnd, cfg["n"], nd.period_x)
+    assert np.array_equal(sub[idx_b], model.idx[nd.bnd_nodes])
+    Wb, _ = O.all_weights(xy, idx_b, bnd, cfg["m"], cfg["l"], wall_ops(0), nd.period_x)
+    rows_idx = np.zeros((n_sub_active, cfg["n"]), np.int64)
+    rows_idx[bnd] = idx_b
+    walls = O.WallRows(rows_idx, n_sub_active, len(sub), bnd, ghosts, nd.bnd_normal, Wb[0], Wb[1], cfg["consts"])
+    closed = O.ghost_closure(walls, st[sub])
+    assert np.array_equal(closed[ghosts], closed_full[nd.bnd_ghosts])
+    samp_full = np.concatenate([r * nx + np.arange(nx) for r in (0, 1, 2, nz - 3, nz - 2, nz - 1)])
+    samp = to_sub[samp_full]
+    idx_s = O.knn(xy, samp, cfg["n"], nd.period_x)
+    assert np.array_equal(sub[idx_s], model.idx[samp_full])
+    Ws, _ = O.all_weights(xy, idx_s, samp, cfg["m"], cfg["l"], ns_ops(cfg), nd.period_x)
+    got = O.ns_tendency(closed, samp, idx_s, Ws[0], Ws[1], Ws[2], Ws[3], xy[samp, 1], walls.zwall[samp],
+                        cfg["consts"], cfg["hv_coeff"])
+    ref = O.ns_tendency(closed_full, samp_full, model.idx[samp_full], model.w_dx[samp_full], model.w_dz[samp_full],
+                        model.w_lap[samp_full], model.w_hv[samp_full], nd.xy[samp_full, 1], model.zwall[samp_full],
+                        cfg["consts"], cfg["hv_coeff"])
+    assert np.array_equal(got, ref)
+    assert np.allclose(ref, full[samp_full], rtol=1e-12, atol=1e-12 * np.abs(full[samp_full]).max())
+
+
 def test_box_ghost_closure_enforces_all_four_walls(box500):
     """Section 6.5: in the closed box the bottom/top rows satisfy the
     conditions above and the lateral rows u = 0, d2u/dx2 = 0,
