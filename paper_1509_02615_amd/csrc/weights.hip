@@ -732,7 +732,7 @@ template <int KC, typename T> struct WaveShared {
   double pw[pw_cap(KC)][4];  // node t, power e at t (l + 1) + e: x^e (hi, lo), z^e (hi, lo)
   double xs[KC][4];          // current solution of the right-hand sides in flight
   double rps[KC];            // 1 / pivot of step k
-  T prow[KC];                // pivot row of the current step
+  T prow[KC], prow2[KC];     // pivot rows of the current pair of steps
   int perm[KC];              // pivot lane of step k
   int gl[MAX_OPS], kg[MAX_OPS];  // operators of the current group, their k
 };
@@ -929,6 +929,15 @@ __device__ __forceinline__ auto pick4(V c0, V c1, V c2, V c3, int k) {
   return r;
 }
 
+// Element e (dynamic) of chunk c, where c is a constant once the caller's
+// loops are unrolled: one indexed register read, no branch.
+template <typename V>
+__device__ __forceinline__ auto pickc(const V &c0, const V &c1, const V &c2, const V &c3, int c, int e) {
+  auto r = c == 0 ? c0[e] : c == 1 ? c1[e] : c == 2 ? c2[e] : c3[e];
+  asm volatile("" : "+v"(r));
+  return r;
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -1012,29 +1021,43 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
         v[g] = r.hi + (r.lo + (b.lo - acc[g].lo));
       }
     }
-    // forward substitution L y = P v: rows not yet pivot at step k. Every
-    // lane scales its value by its own 1 / pivot before the broadcast, so the
-    // value read from the pivot lane p_k of step k is already y_k / pivot_k
-    // (the same product as scaling after the broadcast) and the update takes
-    // it as a scalar operand
-    for (int k = 0; k < K; ++k) {
-      const int p0 = __builtin_amdgcn_readlane(R.pv, k), p1 = H == 1 ? p0 : __builtin_amdgcn_readlane(R.pv, 32 + k);
-      const double lk = R.mystep > k ? static_cast<double>(pick4<KC>(R.c0, R.c1, R.c2, R.c3, k)) : 0.0;
+    // Substitutions on w = v / own pivot: every row of the factors was scaled
+    // by its lane's 1 / pivot after the factorisation, so the value read from
+    // the pivot lane p_k of step k is y_k / pivot_k (forward) or d_k
+    // (backward) and enters each update as a scalar operand. The steps run
+    // in segments of 16 (one register chunk each, unrolled), so the entry of
+    // step k is an indexed read in a static chunk.
 #pragma unroll
-      for (int g = 0; g < G; ++g) v[g] = fma(-lk, group_rl<H>(v[g] * R.rdg, p0, p1, h), v[g]);
+    for (int g = 0; g < G; ++g) v[g] *= R.rdg;
+    // forward substitution L y = P v: rows not yet pivot at step k
+#pragma unroll
+    for (int sg = 0; sg < KC / 16; ++sg) {
+      const int kend = min(16 * sg + 16, K);
+      for (int k = 16 * sg; k < kend; ++k) {
+        const int p0 = __builtin_amdgcn_readlane(R.pv, k), p1 = H == 1 ? p0 : __builtin_amdgcn_readlane(R.pv, 32 + k);
+        const double e = static_cast<double>(pickc(R.c0, R.c1, R.c2, R.c3, sg, k & 15));
+        const double lk = R.mystep > k ? e : 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) v[g] = fma(-lk, group_rl<H>(v[g], p0, p1, h), v[g]);
+      }
     }
     // back substitution U d = y: rows pivoted before step k
-    for (int k = K - 1; k >= 0; --k) {
-      const int p0 = __builtin_amdgcn_readlane(R.pv, k), p1 = H == 1 ? p0 : __builtin_amdgcn_readlane(R.pv, 32 + k);
-      const double uk = R.mystep < k ? static_cast<double>(pick4<KC>(R.c0, R.c1, R.c2, R.c3, k)) : 0.0;
 #pragma unroll
-      for (int g = 0; g < G; ++g) v[g] = fma(-uk, group_rl<H>(v[g] * R.rdg, p0, p1, h), v[g]);
+    for (int sg = KC / 16 - 1; sg >= 0; --sg) {
+      const int kbeg = min(16 * sg + 15, K - 1);
+      for (int k = kbeg; k >= 16 * sg; --k) {
+        const int p0 = __builtin_amdgcn_readlane(R.pv, k), p1 = H == 1 ? p0 : __builtin_amdgcn_readlane(R.pv, 32 + k);
+        const double e = static_cast<double>(pickc(R.c0, R.c1, R.c2, R.c3, sg, k & 15));
+        const double uk = R.mystep < k ? e : 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) v[g] = fma(-uk, group_rl<H>(v[g], p0, p1, h), v[g]);
+      }
     }
-    // lane p_k holds y_k, so d_k = v * rdg there; lane k takes it
+    // lane p_k holds d_k; lane k takes it
     double dm = 0.0, xm = 0.0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const double dk = __shfl(v[g] * R.rdg, R.pv + (64 / H) * h, 64);
+      const double dk = __shfl(v[g], R.pv + (64 / H) * h, 64);
       const double d = lane < K && live ? dk : 0.0;
       x[g] += d;
       dm = fmax(dm, fabs(d));
@@ -1253,46 +1276,88 @@ __device__ __forceinline__ void wave_solve(const WArgs &a, WaveShared<KC, T> (&S
     }
     amax = group_max<H>(amax);
 
-    // 3. LU with partial pivoting, rows stay in their lanes
+    // 3. LU with partial pivoting, rows stay in their lanes, two steps per
+    // pass. Step k picks pivot row pa by column k; column k + 1 of every free
+    // row is brought up to date with that step alone (one multiply-add with
+    // row pa's entry, read from its lane), and step k + 1 picks pivot row pb
+    // by it. Both pivot rows go to LDS together (row pb as it stood before
+    // step k), and each free row takes both steps in one pass:
+    //   a_ij -= (l_ik - l_ik1 l_pb,k) a_pa,j + l_ik1 a_pb,j    (j >= k + 2)
+    // which equals step k followed by step k + 1. Column k keeps the entry
+    // eliminated at step k, and column k + 1 becomes the entry eliminated at
+    // step k + 1 (row pb's LDS entry there is l_pb,k a_pa,k+1, so the same
+    // pass gives a_i,k+1 - l_ik a_pa,k+1). The passes run in segments of 8
+    // columns: in segment s the two columns lie in chunk s / 2 and the
+    // columns still to update are those from 8 s on, so the register chunk
+    // and the blocks each pass reads and updates are static (the segment
+    // loop is unrolled); columns up to k take zero pivot-row entries, and
+    // columns >= K hold zeros in every row.
     bool fr = lane < K;  // not yet chosen as a pivot row
     int mystep = KC;     // elimination step at which this row became pivot
     double rdg = 0.0;    // 1 / own pivot
     double pmin = INFINITY;
-    for (int k = 0; k < K; ++k) {
-      const T ck = pick4<KC>(ar0, ar1, ar2, ar3, k);
-      // largest |a_ik| over the free rows, compared on 17 mantissa bits,
-      // ties to the highest lane; + 64 keeps free rows above the others
-      unsigned key = 0;
-      if (fr) key = ((__float_as_uint(static_cast<float>(fabs(static_cast<double>(ck)))) & ~63u) + 64u) | lane;
-      unsigned k0, k1;
-      group_max_key<H>(key, k0, k1);
-      const int p0 = __builtin_amdgcn_readfirstlane(static_cast<int>(k0 & 63u));
-      const int p1 = __builtin_amdgcn_readfirstlane(static_cast<int>(k1 & 63u));
-      const int p = h ? p1 : p0;
-      const T piv = group_rl<H>(ck, p0, p1, h);
-      pmin = fmin(pmin, fabs(static_cast<double>(piv)));
-      const T rp = recip(piv);
-      if (lane == p) {
-        fr = false;
-        mystep = k;
-        rdg = static_cast<double>(rp);
+    // largest |a_ik| over the free rows, compared on 17 mantissa bits, ties
+    // to the highest lane; + 64 keeps free rows above the others
+    auto pivot_key = [&](T v) {
+      return ((__float_as_uint(static_cast<float>(fabs(static_cast<double>(v)))) & ~63u) + 64u) | lane;
+    };
 #pragma unroll
-        for (int j0 = 0; j0 < KC; j0 += 8)
-          if (j0 + 8 > k + 1 && j0 < K) {
-#pragma unroll
-            for (int j = j0; j < j0 + 8; ++j) S.prow[j] = RBFFD_ROW_GET(j);
-          }
-      }
-      if (lane <= k) S.prow[lane] = T(0);  // columns up to k take no update
-      wave_sync_lds();
-      const T lm = fr ? ck * rp : T(0);
-#pragma unroll
-      for (int j0 = 0; j0 < KC; j0 += 8)
-        if (j0 + 8 > k + 1 && j0 < K) {
-#pragma unroll
-          for (int j = j0; j < j0 + 8; ++j) RBFFD_ROW_SET(j, fma(-lm, S.prow[j], RBFFD_ROW_GET(j)));
+    for (int sg = 0; sg < KC / 8; ++sg) {
+      const int kend = min(8 * sg + 8, K);
+      for (int k = 8 * sg; k < kend; k += 2) {
+        const bool two = k + 1 < K;
+        // step k
+        const T ck = pickc(ar0, ar1, ar2, ar3, sg / 2, k & 15);
+        unsigned k0, k1;
+        group_max_key<H>(fr ? pivot_key(ck) : 0u, k0, k1);
+        const int pa0 = __builtin_amdgcn_readfirstlane(static_cast<int>(k0 & 63u));
+        const int pa1 = __builtin_amdgcn_readfirstlane(static_cast<int>(k1 & 63u));
+        const int pa = h ? pa1 : pa0;
+        const T piva = group_rl<H>(ck, pa0, pa1, h);
+        pmin = fmin(pmin, fabs(static_cast<double>(piva)));
+        const T rpa = recip(piva);
+        if (lane == pa) {
+          fr = false;
+          mystep = k;
+          rdg = static_cast<double>(rpa);
         }
-      wave_sync_lds();
+        const T la = fr ? ck * rpa : T(0);
+        // column k + 1 after step k, and step k + 1
+        const T c1 = pickc(ar0, ar1, ar2, ar3, sg / 2, (k + 1) & 15);
+        const T ua = group_rl<H>(c1, pa0, pa1, h);
+        const T c1u = fma(-la, ua, c1);
+        group_max_key<H>(fr && two ? pivot_key(c1u) : 0u, k0, k1);
+        const int pb0 = __builtin_amdgcn_readfirstlane(static_cast<int>(k0 & 63u));
+        const int pb1 = __builtin_amdgcn_readfirstlane(static_cast<int>(k1 & 63u));
+        const int pb = h ? pb1 : pb0;
+        T lb = T(0), lab = T(0);
+        if (two) {
+          const T pivb = group_rl<H>(c1u, pb0, pb1, h);
+          pmin = fmin(pmin, fabs(static_cast<double>(pivb)));
+          const T rpb = recip(pivb);
+          if (lane == pb) {
+            fr = false;
+            mystep = k + 1;
+            rdg = static_cast<double>(rpb);
+          }
+          lb = fr ? c1u * rpb : T(0);
+          lab = group_rl<H>(la, pb0, pb1, h);
+        }
+        // both pivot rows to LDS in the same stores
+        if (lane == pa || (two && lane == pb)) {
+          T *dst = lane == pa ? S.prow : S.prow2;
+#pragma unroll
+          for (int j = 8 * sg; j < KC; ++j) dst[j] = RBFFD_ROW_GET(j);
+        }
+        if (lane <= k) S.prow[lane] = T(0);
+        if (lane < KC && (lane <= k + 1 || !two)) S.prow2[lane] = lane == k + 1 ? lab * ua : T(0);
+        wave_sync_lds();
+        const T ca = la - lb * lab;
+#pragma unroll
+        for (int j = 8 * sg; j < KC; ++j)
+          RBFFD_ROW_SET(j, fma(-ca, S.prow[j], fma(-lb, S.prow2[j], RBFFD_ROW_GET(j))));
+        wave_sync_lds();
+      }
     }
     // lane k: pivot lane and 1 / pivot of step k
     if (lane < K) {
@@ -1302,6 +1367,9 @@ __device__ __forceinline__ void wave_solve(const WArgs &a, WaveShared<KC, T> (&S
     wave_sync_lds();
     const int pv = lane < K ? S.perm[lane] : 0;
     const double rpv = lane < K ? S.rps[lane] : 0.0;
+    // each row scaled by its own 1 / pivot for the substitutions
+#pragma unroll
+    for (int j = 0; j < KC; ++j) RBFFD_ROW_SET(j, static_cast<T>(static_cast<double>(RBFFD_ROW_GET(j)) * rdg));
 
     // 4. right-hand sides four at a time: solve, then refine
     for (int g0 = 0; g0 < ng; g0 += 4) {
