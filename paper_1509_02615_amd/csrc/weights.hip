@@ -795,7 +795,11 @@ __device__ __forceinline__ double odd_pow(double r, double r2, int m) {
 // within about 2^-95: r^2 = s (1 + t) with s an FP64 number and t ~ 2^-52,
 // y = sqrt(s) within an ulp so that s - y^2 is exact, y^m in double-double
 // and (1 + t)^(m/2) to first order (the t^2 term is below 2^-100).
+// MC > 0: m = MC fixed at compile time (the power fully unrolled); MC = 0:
+// m at run time. Branch-free: coincident nodes (s = 0) give 0 by selection.
+template <int MC = 0>
 __device__ __forceinline__ dd phi_dd(const double (&a)[4], const double (&b)[4], int m) {
+  if constexpr (MC > 0) m = MC;
   dd dx = two_sum(a[0], -b[0]);
   dx.lo += a[1] - b[1];
   dd dz = two_sum(a[2], -b[2]);
@@ -805,14 +809,21 @@ __device__ __forceinline__ dd phi_dd(const double (&a)[4], const double (&b)[4],
   double slo = s.lo + (px.lo + pz.lo);
   slo = fma(dx.hi + dx.hi, dx.lo, slo);
   slo = fma(dz.hi + dz.hi, dz.lo, slo);
-  if (!(s.hi > 0.0)) return {0.0, 0.0};
+  const bool pos = s.hi > 0.0;
+  const double sh = pos ? s.hi : 1.0;
   double h;
-  const double y = sqrt_pos(s.hi, h);
-  const double t = (fma(-y, y, s.hi) + slo) * (4.0 * h * h);  // (2h)^2 ~ 1/s
+  const double y = sqrt_pos(sh, h);
+  const double t = (fma(-y, y, sh) + slo) * (4.0 * h * h);  // (2h)^2 ~ 1/s
   dd Y{y, 0.0};
   const dd y2 = two_prod(y, y);
-  for (int i = 1; i < m; i += 2) Y = dd_mulr(Y, y2);
-  return {Y.hi, fma(Y.hi * (0.5 * m), t, Y.lo)};
+  if constexpr (MC > 0) {
+#pragma unroll
+    for (int i = 1; i < MC; i += 2) Y = dd_mulr(Y, y2);
+  } else {
+    for (int i = 1; i < m; i += 2) Y = dd_mulr(Y, y2);
+  }
+  const double lo = fma(Y.hi * (0.5 * m), t, Y.lo);
+  return {pos ? Y.hi : 0.0, pos ? lo : 0.0};
 }
 
 __device__ __forceinline__ double rl(double v, int l) {
@@ -980,25 +991,32 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
     // residual b - A x in double-double, rounded to FP64 (b alone when x = 0)
     dd acc[G] = {};
     if (it > 0) {
-      for (int j = 0; j < n; ++j) {
-        const double oj[4] = {S.off[j][0], S.off[j][1], S.off[j][2], S.off[j][3]};
-        dd e{0.0, 0.0};
-        if (c.is_node) {
-          if (j != lane) e = phi_dd(own, oj, c.mg);
-        } else if (c.is_poly) {
+      // node columns: Phi for node rows (0 on the diagonal), the monomials of
+      // node j for polynomial rows; branch-free, with the power of r
+      // unrolled for the common orders
+      auto node_cols = [&](auto MC) {
+        for (int j = 0; j < n; ++j) {
+          const double oj[4] = {S.off[j][0], S.off[j][1], S.off[j][2], S.off[j][3]};
+          const dd ep = phi_dd<decltype(MC)::value>(own, oj, c.mg);
           const double *px = S.pw[j * P + c.poly_a], *pz = S.pw[j * P + c.poly_b];
-          e = dd_mulr(dd{px[0], px[1]}, dd{pz[2], pz[3]});
-        }
+          const dd em = dd_mulr(dd{px[0], px[1]}, dd{pz[2], pz[3]});
+          const dd e = c.is_node ? ep : (c.is_poly ? em : dd{0.0, 0.0});
 #pragma unroll
-        for (int g = 0; g < G; ++g) acc[g] = dd_acc(acc[g], e, S.xs[j][g]);
+          for (int g = 0; g < G; ++g) acc[g] = dd_acc(acc[g], e, S.xs[j][g]);
+        }
+      };
+      switch (c.mg) {
+        case 3: node_cols(std::integral_constant<int, 3>{}); break;
+        case 5: node_cols(std::integral_constant<int, 5>{}); break;
+        case 7: node_cols(std::integral_constant<int, 7>{}); break;
+        default: node_cols(std::integral_constant<int, 0>{}); break;
       }
+      // polynomial columns: the node row's own monomials
       int qa = 0, qb = 0;
       for (int j = n; j < K; ++j) {
-        dd e{0.0, 0.0};
-        if (c.is_node) {
-          const double *px = S.pw[c.own_pw + qa], *pz = S.pw[c.own_pw + qb];
-          e = dd_mulr(dd{px[0], px[1]}, dd{pz[2], pz[3]});
-        }
+        const double *px = S.pw[c.own_pw + qa], *pz = S.pw[c.own_pw + qb];
+        const dd em = dd_mulr(dd{px[0], px[1]}, dd{pz[2], pz[3]});
+        const dd e = c.is_node ? em : dd{0.0, 0.0};
 #pragma unroll
         for (int g = 0; g < G; ++g) acc[g] = dd_acc(acc[g], e, S.xs[j][g]);
         if (qa > 0) {
@@ -1248,19 +1266,28 @@ __device__ __forceinline__ void wave_solve(const WArgs &a, WaveShared<KC, T> (&S
       // loop instead of hoisted (and held in registers) across all groups
       int n = n_, K = K_, P = P_;
       asm volatile("" : "+s"(n), "+s"(K), "+s"(P));
-      int qa = 0, qb = 0;  // monomial of column j >= n, graded order
+      const int e = (mg - 1) / 2;  // r^m = r (r^2)^e
+      int qa = 0, qb = 0;            // monomial of column j >= n, graded order
+      // four columns at a time: loads and square roots first, then the
+      // powers (one loop over e for all four), then the selection per row
+      // kind; no branch on lanes
 #pragma unroll
-      for (int j = 0; j < KC; ++j) {
-        double v = 0.0;
-        if (j < K) {
+      for (int j0 = 0; j0 < KC; j0 += 4) {
+        double r[4], r2[4], mo[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + u;
           const int jn = j < n ? j : n - 1;
           const double ddx = own[0] - S.off[jn][0], ddz = own[2] - S.off[jn][2];
-          const double r2 = ddx * ddx + ddz * ddz;
-          const double phi = r2 > 0.0 ? odd_pow(sqrt_pos(r2), r2, mg) : 0.0;
-          const double mono_j = S.pw[jn * P + poly_a][0] * S.pw[jn * P + poly_b][2];
-          const double mono_i = S.pw[own_pw + qa][0] * S.pw[own_pw + qb][2];
-          v = j < n ? (is_node ? phi : (is_poly ? mono_j : 0.0)) : (is_node ? mono_i : 0.0);
-          if (j >= n) {
+          const double s2 = ddx * ddx + ddz * ddz;
+          const bool pos = s2 > 0.0;
+          const double y = sqrt_pos(pos ? s2 : 1.0);
+          r[u] = pos ? y : 0.0;
+          r2[u] = s2;
+          if (j < n) {  // wave-uniform: polynomial rows take the monomials of node j
+            mo[u] = S.pw[jn * P + poly_a][0] * S.pw[jn * P + poly_b][2];
+          } else {      // node rows take their own monomial of column j
+            mo[u] = S.pw[own_pw + qa][0] * S.pw[own_pw + qb][2];
             if (qa > 0) {
               --qa;
               ++qb;
@@ -1270,8 +1297,17 @@ __device__ __forceinline__ void wave_solve(const WArgs &a, WaveShared<KC, T> (&S
             }
           }
         }
-        RBFFD_ROW_SET(j, static_cast<T>(v));
-        amax = fmax(amax, fabs(v));
+        for (int t = 0; t < e; ++t) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) r[u] *= r2[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + u;
+          const double v = j < K ? (j < n ? (is_node ? r[u] : (is_poly ? mo[u] : 0.0)) : (is_node ? mo[u] : 0.0)) : 0.0;
+          RBFFD_ROW_SET(j, static_cast<T>(v));
+          amax = fmax(amax, fabs(v));
+        }
       }
     }
     amax = group_max<H>(amax);
