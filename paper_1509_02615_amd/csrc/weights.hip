@@ -20,11 +20,14 @@
 // Per system:
 //  1. offsets of the stencil nodes from the centre (minimum image in x),
 //     scaled by rho = the largest offset length;
-//  2. assembly of [A | B] in LDS (column-major), A = [Phi P; P^T 0] of size
-//     K = n + M, B = one right-hand side per operator of this PHS order
-//     (Section 5.3, Eq. eqn:laplacian for Laplacian^k of r^m);
-//  3. LU with partial pivoting of [A | B] (FP64, or FP32 for the
-//     mixed-precision variant);
+//  2. assembly of A = [Phi P; P^T 0] of size K = n + M and of B = one
+//     right-hand side per operator of this PHS order (Section 5.3, Eq.
+//     eqn:laplacian for Laplacian^k of r^m): [A | B] column-major in LDS in
+//     the workgroup kernel, row i of A in lane i's registers in the
+//     wavefront kernels;
+//  3. LU with partial pivoting (FP64, or FP32 for the mixed-precision
+//     variant); the wavefront kernels move no rows and take two steps per
+//     pass (both pivot rows broadcast together, one rank-2 update);
 //  4. back substitution, then iterative refinement: residual b - A x with A
 //     and b formed in double-double arithmetic from the FP64 node
 //     coordinates (so the refinement converges to the solution of the exact
