@@ -530,7 +530,10 @@ def sampled_weights_error(idx, W, ref):
 def cpu_baseline(cfg, min_seconds=10.0):
     """The oracle's RHS on a bounded sample: one 2048-node row of the same
     channel (row 128), stencils and weights from the oracle (untimed), then
-    repeated evaluations of Eqs. uEq..piEq for at least min_seconds."""
+    repeated evaluations of Eqs. uEq..piEq for at least min_seconds. The
+    evaluation is the oracle's own full-model path (ns_rhs): the four
+    differentiation matrices as sparse products (the sample rows' DMs, built
+    untimed), then the pointwise physics."""
     import oracle as O
     nd = cfg["nodes"]
     rows = np.arange(128 * nd.nx, 129 * nd.nx)
@@ -538,36 +541,30 @@ def cpu_baseline(cfg, min_seconds=10.0):
     idx = O.knn(nd.xy, rows, cfg["n"], nd.period_x)
     Wo, _ = O.all_weights(nd.xy, idx, rows, cfg["m"], cfg["l"], ops, nd.period_x)
     state = cfg["state0"].astype(np.float64)
+    D = [O.dm_matrix(idx, W, state.shape[0]) for W in Wo]
     is_wall = np.zeros(len(rows), bool)
-    reps = 0
-    with one_thread():
-        t0 = time.perf_counter()
-        while True:
-            O.ns_tendency(state, rows, idx, Wo[0], Wo[1], Wo[2], Wo[3], nd.xy[rows, 1], is_wall,
-                          cfg["consts"], cfg["hv_coeff"])
-            reps += 1
-            el = time.perf_counter() - t0
-            if el >= min_seconds:
-                break
+    job = (state, rows, idx, Wo, D, nd.xy[rows, 1], is_wall, cfg["consts"], cfg["hv_coeff"])
+    reps, el = _oracle_rhs_worker((job, min_seconds))
     res = dict(value=len(rows) * reps / el, unit="node-updates/s", cores=1, kind="oracle", host=host_cpu(),
                sample=f"one 2048-node row of the 2048x256 channel, {reps} FP64 RHS evaluations "
-                      f"in {el:.1f} s (numpy, single thread)")
-    job = (state, rows, idx, Wo, nd.xy[rows, 1], is_wall, cfg["consts"], cfg["hv_coeff"])
+                      f"in {el:.1f} s (numpy and scipy sparse products, single thread)")
     res["all_cores"] = _all_cores(_oracle_rhs_worker, job, min_seconds, len(rows), "node-updates/s",
                                   "the same row")
     return res
 
 
 def _oracle_rhs_worker(args):
-    """One worker process of the all-cores RHS baseline: the oracle RHS on the
-    sample row, repeated for `seconds`; returns the number of evaluations and
-    the time taken."""
-    (state, rows, idx, Wo, z, is_wall, consts, hv), seconds = args
+    """The oracle RHS on the sample row (sparse products of the four
+    differentiation matrices, then Eqs. uEq..piEq), repeated for `seconds`
+    on one thread; returns the number of evaluations and the time taken.
+    Also one worker process of the all-cores baseline."""
+    (state, rows, idx, Wo, D, z, is_wall, consts, hv), seconds = args
     import oracle as O
     with one_thread():
         reps, t0 = 0, time.perf_counter()
         while True:
-            O.ns_tendency(state, rows, idx, Wo[0], Wo[1], Wo[2], Wo[3], z, is_wall, consts, hv)
+            O.ns_tendency(state, rows, idx, Wo[0], Wo[1], Wo[2], Wo[3], z, is_wall, consts, hv,
+                          derivs=[Dm @ state for Dm in D])
             reps += 1
             el = time.perf_counter() - t0
             if el >= seconds:
