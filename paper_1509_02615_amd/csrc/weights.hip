@@ -734,7 +734,6 @@ template <int KC, typename T> struct WaveShared {
   double off[KC][4];         // scaled node offsets: x hi, x lo, z hi, z lo
   double pw[pw_cap(KC)][4];  // node t, power e at t (l + 1) + e: x^e (hi, lo), z^e (hi, lo)
   double xs[KC][4];          // current solution of the right-hand sides in flight
-  double rps[KC];            // 1 / pivot of step k
   T prow[KC], prow2[KC];     // pivot rows of the current pair of steps
   int perm[KC];              // pivot lane of step k
   int gl[MAX_OPS], kg[MAX_OPS];  // operators of the current group, their k
@@ -786,13 +785,6 @@ __device__ __forceinline__ double recip(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 __device__ __forceinline__ float recip(float x) { return 1.0f / x; }
-
-// r^m for odd m >= 1 from r and r^2
-__device__ __forceinline__ double odd_pow(double r, double r2, int m) {
-  double v = r;
-  for (int i = 1; i < m; i += 2) v *= r2;
-  return v;
-}
 
 // |a - b|^m for distinct nodes, offsets in double-double, relative error
 // within about 2^-95: r^2 = s (1 + t) with s an FP64 number and t ~ 2^-52,
@@ -921,28 +913,6 @@ template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_t
       ar3[(j) & 15] = (x);    \
   } while (0)
 
-// Element k (wave-uniform) of a row: one indexed register read in the chunk
-// holding k; the empty asm keeps the chunk choice a branch.
-template <int KC, typename V>
-__device__ __forceinline__ auto pick4(V c0, V c1, V c2, V c3, int k) {
-  const int e = k & 15;
-  auto r = c0[0];
-  if (k < 16) {
-    r = c0[e];
-    asm volatile("" : "+v"(r));
-  } else if (KC <= 32 || k < 32) {
-    r = c1[e];
-    asm volatile("" : "+v"(r));
-  } else if (KC <= 48 || k < 48) {
-    r = c2[e];
-    asm volatile("" : "+v"(r));
-  } else {
-    r = c3[e];
-    asm volatile("" : "+v"(r));
-  }
-  return r;
-}
-
 // Element e (dynamic) of chunk c, where c is a constant once the caller's
 // loops are unrolled: one indexed register read, no branch.
 template <typename V>
@@ -964,7 +934,6 @@ template <int KC, typename T> struct WaveRows {
   typename Vec16<T>::type c0, c1, c2, c3;
   int mystep;   // step at which this row was pivot
   int pv;       // lane k: pivot lane of step k
-  double rpv;   // lane k: 1 / pivot of step k
   double rdg;   // 1 / own pivot
 };
 struct WaveCtx {
@@ -1398,14 +1367,10 @@ __device__ __forceinline__ void wave_solve(const WArgs &a, WaveShared<KC, T> (&S
         wave_sync_lds();
       }
     }
-    // lane k: pivot lane and 1 / pivot of step k
-    if (lane < K) {
-      S.perm[mystep] = lane;
-      S.rps[mystep] = rdg;
-    }
+    // lane k: pivot lane of step k
+    if (lane < K) S.perm[mystep] = lane;
     wave_sync_lds();
     const int pv = lane < K ? S.perm[lane] : 0;
-    const double rpv = lane < K ? S.rps[lane] : 0.0;
     // each row scaled by its own 1 / pivot for the substitutions
 #pragma unroll
     for (int j = 0; j < KC; ++j) RBFFD_ROW_SET(j, static_cast<T>(static_cast<double>(RBFFD_ROW_GET(j)) * rdg));
@@ -1415,7 +1380,7 @@ __device__ __forceinline__ void wave_solve(const WArgs &a, WaveShared<KC, T> (&S
       const int G = min(4, ng - g0);
       double x[4] = {0.0, 0.0, 0.0, 0.0};  // lane k: unknown k
       bool converged = false;
-      const WaveRows<KC, T> rows{ar0, ar1, ar2, ar3, mystep, pv, rpv, rdg};
+      const WaveRows<KC, T> rows{ar0, ar1, ar2, ar3, mystep, pv, rdg};
       const WaveCtx wc{lane, n, K, mg, P, own_pw, poly_a, poly_b, is_node, is_poly, ex, ez};
       switch (G) {
         case 1: wave_refine<KC, 1, T, H>(a, S, rows, wc, g0, x, converged, h); break;
