@@ -1064,12 +1064,15 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
   }
 }
 
-// wavefronts per SIMD the register budget is fitted to
+// wavefronts per SIMD the register budget is fitted to (measured: at
+// KC = 48 three per SIMD, spilling a few values of the set-up and refinement
+// code, beat two by about 2%; at KC = 64 three triple the time, and at
+// KC = 32 four are slower than three)
 #ifndef RBFFD_WAVE_OCC64
 #define RBFFD_WAVE_OCC64 2
 #endif
 #ifndef RBFFD_WAVE_OCC48
-#define RBFFD_WAVE_OCC48 2
+#define RBFFD_WAVE_OCC48 3
 #endif
 #ifndef RBFFD_WAVE_OCC32
 #define RBFFD_WAVE_OCC32 3
