@@ -705,15 +705,16 @@ __global__ __launch_bounds__(W_THREADS) __attribute__((amdgpu_waves_per_eu(4))) 
 // ---- one wavefront per system, rows in registers (K <= 64) ----
 //
 // Lane i holds row i of A = [Phi P; P^T 0] in registers; column loops are
-// unrolled over a compile-time capacity KC (in guarded chunks of 8), so row
-// entries have static register indices, and column k of the running step is
-// fetched with a uniform switch. Partial pivoting moves no data: the lane
-// that supplies the pivot of step k leaves the active set and its row, row k
-// of U, is broadcast through LDS. A lane eliminated at step k keeps the
-// eliminated entry in column k (no later step touches it), so its multiplier
-// is that entry times 1 / pivot_k, applied in the substitutions. The
-// right-hand sides are solved after the factorisation, four at a time, so
-// registers hold one row and not [A | B].
+// unrolled over a compile-time capacity KC, so row entries have static
+// register indices, and the column of a running step is one indexed register
+// read in a chunk that the unrolled segment loops make static. Partial
+// pivoting moves no data: the lane that supplies the pivot of step k leaves
+// the active set and its row, row k of U, is broadcast through LDS (two
+// steps per pass). A lane eliminated at step k keeps the eliminated entry in
+// column k (no later step touches it), so its multiplier is that entry times
+// 1 / pivot_k, applied in the substitutions. The right-hand sides are solved
+// after the factorisation, four at a time, so registers hold one row and not
+// [A | B].
 //
 // Iterative refinement evaluates the residual b - A x row by row with A and
 // b in double-double: lane i runs over the columns j with node j's offsets
