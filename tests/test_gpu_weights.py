@@ -206,6 +206,33 @@ def test_weights_parity_parameter_sweep(R, ctx):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_weights_parity_small_systems(R, ctx, precision):
+    """The smallest systems, K = 3..21 (polynomial degree 0..3 with n from M
+    to a few nodes more), odd and even K mixed in one batch: the wavefront
+    kernels' elimination takes two steps per pass, and an odd K ends on a
+    single step. Every combination is well posed at every centre of this
+    node set (cubics on exactly n = M = 10 scattered nodes are not: near
+    the edges some of those stencils are singular, so the cubic systems
+    here take 11 nodes), and each operator's weights are non-zero."""
+    say("weights: K = 3..21, m = 3..7, l = 0..3, mixed in one batch")
+    nd = jittered_square(16, seed=7)
+    combos = [(3, 0, 2), (3, 0, 3), (5, 0, 4), (3, 1, 4), (3, 1, 5), (5, 1, 6), (5, 2, 6), (5, 2, 7),
+              (7, 2, 9), (7, 3, 11)]
+    # interior centres: on the square's edges the nodes are collinear, and a
+    # two- or three-node stencil there has exactly zero weights for one
+    # derivative
+    x, z = nd.xy[:nd.n_active, 0], nd.xy[:nd.n_active, 1]
+    centers = np.flatnonzero((x > 0.2) & (x < 0.8) & (z > 0.2) & (z < 0.8))
+    pick = np.arange(len(centers)) % len(combos)
+    m_per = np.array([combos[p][0] for p in pick], np.int32)
+    l_per = np.array([combos[p][1] for p in pick], np.int32)
+    n_per = np.array([combos[p][2] for p in pick], np.int32)
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0)]
+    _weights_parity(R, ctx, nd.xy, ops, int(n_per.max()), 0, 0, 0.0, centers, n_per=n_per, m_per=m_per,
+                    l_per=l_per, precision=precision)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_two_systems_per_wavefront(R, ctx, precision):
     """Systems of up to 32 unknowns run two per wavefront, and the two share
     n, m and l; a stencil whose partner has another shape is solved on its
