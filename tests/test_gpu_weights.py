@@ -232,6 +232,36 @@ def test_weights_parity_small_systems(R, ctx, precision):
                     l_per=l_per, precision=precision)
 
 
+def test_singular_stencils_match_the_oracle(R, ctx):
+    """Cubics on exactly n = M = 10 scattered nodes: near the edges of the
+    node set some of these stencils are singular (the nodes do not determine
+    a cubic). The GPU flags exactly the stencils the oracle flags (status 1;
+    bit-exact, integer), and the others agree with the oracle's weights."""
+    import torch
+    say("weights: r^7 + cubics on n = M = 10 nodes, singular stencils flagged as by the oracle")
+    nd = jittered_square(12, seed=7)
+    N = nd.n_active
+    ops = [(O.DX, 0, 0), (O.DZ, 0, 0), (O.LAP, 0, 0)]
+    idx, W, status, rc = R.rbffd_weights(ctx, dev(nd.xy, torch.float64), ops, 10, 7, 3)
+    idx, W, status = host(idx), host(W), host(status)
+    want = np.zeros(N, np.int32)
+    worst = 0.0
+    for c in range(N):
+        st = O.knn(nd.xy, [c], 10, 0.0)[0]
+        assert np.array_equal(idx[c], st)
+        Wo, so = O.stencil_weights(nd.xy, st, c, 7, 3, ops, 0.0)
+        want[c] = so
+        if so == 0:
+            for o in range(len(ops)):
+                err = np.linalg.norm(W[o, c] - Wo[o]) / np.linalg.norm(Wo[o])
+                worst = max(worst, err)
+                assert err <= TOL_W, (c, o, err)
+    assert 0 < int(np.count_nonzero(want)) < N  # the node set has both kinds
+    assert np.array_equal(status, want)
+    assert rc == R.ESINGULAR
+    say(f"   {int(np.count_nonzero(want))} singular of {N}; worst relative error of the others {worst:.2e}")
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_two_systems_per_wavefront(R, ctx, precision):
     """Systems of up to 32 unknowns run two per wavefront, and the two share
