@@ -395,16 +395,30 @@ __global__ void loss_kernel(const float *__restrict__ Y, const float *__restrict
   if (threadIdx.x == 0) atomicAdd(loss, red[0] / (4.0 * static_cast<double>(S)));
 }
 
-// grad[c] += sum_s D[s][c] over a chunk of samples (bias gradients).
+// grad[c] += sum_s D[s][c] over a chunk of samples (bias gradients). A block
+// is COLSUM_SLICES x 128 threads: each column's chunk is summed in that many
+// interleaved slices (independent loads in flight), the slices are added in
+// LDS, and one atomic per column and block goes to grad.
+constexpr int COLSUM_SLICES = 8;
 template <class T>
-__global__ void colsum_kernel(const T *__restrict__ D, int ldd, int64_t S, int Cn, int64_t chunk,
-                              float *__restrict__ grad) {
-  const int c = threadIdx.x;
-  if (c >= Cn) return;
-  const int64_t b = static_cast<int64_t>(blockIdx.x) * chunk, e = min(S, b + chunk);
+__global__ __launch_bounds__(128 * COLSUM_SLICES) void colsum_kernel(const T *__restrict__ D, int ldd, int64_t S,
+                                                                    int Cn, int64_t chunk, float *__restrict__ grad) {
+  __shared__ float part[COLSUM_SLICES][128];
+  const int c = static_cast<int>(threadIdx.x) & 127, sl = static_cast<int>(threadIdx.x) >> 7;
   float acc = 0.0f;
-  for (int64_t s = b; s < e; ++s) acc += static_cast<float>(D[s * ldd + c]);
-  atomicAdd(grad + c, acc);
+  if (c < Cn) {
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * chunk, e = min(S, b + chunk);
+#pragma unroll 8
+    for (int64_t s = b + sl; s < e; s += COLSUM_SLICES) acc += static_cast<float>(D[s * ldd + c]);
+  }
+  part[sl][c] = acc;
+  __syncthreads();
+  if (sl == 0 && c < Cn) {
+    float t = 0.0f;
+#pragma unroll
+    for (int q = 0; q < COLSUM_SLICES; ++q) t += part[q][c];
+    atomicAdd(grad + c, t);
+  }
 }
 
 // BF16 copies of the weights (and the transposed W2, W3 the backward pass uses).
@@ -560,9 +574,9 @@ int backward(rbffd_ctx *ctx, rbffd_closure *cl, const float *T, int64_t S) {
                       g + OW3, HID);
   const int64_t cch = 2048;
   const unsigned nb = static_cast<unsigned>((S + cch - 1) / cch);
-  colsum_kernel<__bf16><<<nb, HID, 0, s>>>(cp<__bf16>(cl->dH1), HID, S, HID, cch, g + OB1);
-  colsum_kernel<__bf16><<<nb, HID, 0, s>>>(cp<__bf16>(cl->dH2), HID, S, HID, cch, g + OB2);
-  colsum_kernel<float><<<nb, HID, 0, s>>>(cp<float>(cl->dY32), 4, S, 4, cch, g + OB3);
+  colsum_kernel<__bf16><<<nb, 128 * COLSUM_SLICES, 0, s>>>(cp<__bf16>(cl->dH1), HID, S, HID, cch, g + OB1);
+  colsum_kernel<__bf16><<<nb, 128 * COLSUM_SLICES, 0, s>>>(cp<__bf16>(cl->dH2), HID, S, HID, cch, g + OB2);
+  colsum_kernel<float><<<nb, 128 * COLSUM_SLICES, 0, s>>>(cp<float>(cl->dY32), 4, S, 4, cch, g + OB3);
   RBFFD_HIP(ctx, hipGetLastError());
   return RBFFD_OK;
 }
