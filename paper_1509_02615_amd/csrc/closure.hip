@@ -344,24 +344,35 @@ __global__ void features_kernel(const float *__restrict__ y, const int *__restri
   for (int c = 0; c < 4; ++c) o[c] = static_cast<__bf16>(v[c]);
 }
 
-// out[c][s] = in[s][c] for s < S, 0 for S <= s < Sp; 32x32 tiles through LDS.
-template <class T>
-__global__ void transpose_kernel(const T *__restrict__ in, int ldi, int64_t S, int Cn, __bf16 *__restrict__ out,
-                                 int64_t Sp) {
-  __shared__ float tile[32][33];
-  const int64_t s0 = static_cast<int64_t>(blockIdx.x) * 32;
-  const int c0 = blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  for (int r = ty; r < 32; r += 8) {
+// out[c][s] = in[s][c] for s < S, 0 for S <= s < Sp (Cn, ldi and Sp multiples
+// of 8); 64x64 tiles through LDS, with 16-byte loads along c and 16-byte
+// stores along s.
+__global__ __launch_bounds__(256) void transpose_kernel(const __bf16 *__restrict__ in, int ldi, int64_t S, int Cn,
+                                                        __bf16 *__restrict__ out, int64_t Sp) {
+  __shared__ __attribute__((aligned(16))) __bf16 tile[64][72];  // [s][c]; 144-byte rows
+  const int64_t s0 = static_cast<int64_t>(blockIdx.x) * 64;
+  const int c0 = blockIdx.y * 64;
+  for (int v = threadIdx.x; v < 512; v += 256) {  // 64 rows x 8 vectors of 8
+    const int r = v >> 3, cv = (v & 7) * 8;
     const int64_t s = s0 + r;
-    const int c = c0 + tx;
-    tile[r][tx] = (s < S && c < Cn) ? static_cast<float>(in[s * ldi + c]) : 0.0f;
+    const int c = c0 + cv;
+    bf8v x;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = static_cast<__bf16>(0.0f);
+    if (s < S && c < Cn) x = *reinterpret_cast<const bf8v *>(in + s * ldi + c);
+    *reinterpret_cast<bf8v *>(&tile[r][cv]) = x;
   }
   __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int c = c0 + r;
-    const int64_t s = s0 + tx;
-    if (c < Cn && s < Sp) out[static_cast<int64_t>(c) * Sp + s] = static_cast<__bf16>(tile[tx][r]);
+  for (int v = threadIdx.x; v < 512; v += 256) {  // 64 columns x 8 vectors of 8 samples
+    const int cr = v >> 3, sv = (v & 7) * 8;
+    const int c = c0 + cr;
+    const int64_t s = s0 + sv;
+    if (c < Cn && s < Sp) {
+      bf8v y;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) y[q] = tile[sv + q][cr];
+      *reinterpret_cast<bf8v *>(out + static_cast<int64_t>(c) * Sp + s) = y;
+    }
   }
 }
 
@@ -555,8 +566,8 @@ int backward(rbffd_ctx *ctx, rbffd_closure *cl, const float *T, int64_t S) {
                     cp<__bf16>(cl->H1), HID, cl->dH1.p, HID, cl->act);
   // transposes for the weight gradients (contraction over samples)
   auto tr = [&](const __bf16 *in, int ldi, int Cn, DevBuf &out) {
-    dim3 grid(static_cast<unsigned>(Sp / 32), (Cn + 31) / 32);
-    transpose_kernel<__bf16><<<grid, 256, 0, s>>>(in, ldi, S, Cn, out.as<__bf16>(), Sp);
+    dim3 grid(static_cast<unsigned>((Sp + 63) / 64), (Cn + 63) / 64);
+    transpose_kernel<<<grid, 256, 0, s>>>(in, ldi, S, Cn, out.as<__bf16>(), Sp);
   };
   tr(cp<__bf16>(cl->X), KIN, KIN, cl->XT);
   tr(cp<__bf16>(cl->H1), HID, HID, cl->H1T);
