@@ -576,7 +576,7 @@ int backward(rbffd_ctx *ctx, rbffd_closure *cl, const float *T, int64_t S) {
   tr(cp<__bf16>(cl->dH2), HID, HID, cl->dH2T);
   tr(cp<__bf16>(cl->dY), 32, NOUT, cl->dYT);
   const int Ki = static_cast<int>(Sp);
-  const int chunk = 4096;
+  const int chunk = 1024;
   gemm<EPI_ATOMIC, 10>(s, cp<__bf16>(cl->dH1T), Ki, cp<__bf16>(cl->XT), Ki, HID, Ki, chunk, nullptr, nullptr, 0,
                        g + OW1, KIN);
   gemm<EPI_ATOMIC, 8>(s, cp<__bf16>(cl->dH2T), Ki, cp<__bf16>(cl->H1T), Ki, HID, Ki, chunk, nullptr, nullptr, 0,
