@@ -948,12 +948,31 @@ struct WaveCtx {
 // system's lanes ends with unknown k in x[g]. With two systems per
 // wavefront (H = 2, group h), a system that has converged keeps its
 // solution while the other one refines.
+//
+// FP32 factors contract the error by only about cond 2^-24 per pass, so
+// they take several passes. The first ones form the residual in plain FP64
+// against the FP64 matrix that was rounded for the factorisation (the
+// same entries, so the error still contracts, down to about cond 2^-53);
+// the double-double passes start once a correction is below 2^-24 |x| or
+// stops contracting, for the whole wavefront at once, and only they may
+// end the refinement. The right-hand sides are then evaluated once.
 template <int KC, int G, typename T, int H>
 __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S, const WaveRows<KC, T> R,
                                             const WaveCtx &c, int g0, double (&x)[4], bool &converged, int h) {
+  constexpr bool F32 = std::is_same<T, float>::value;
   const int lane = c.lane, n = c.n, K = c.K, P = c.P;
   const double own[4] = {c.ex.hi, c.ex.lo, c.ez.hi, c.ez.lo};
   double dprev = 0.0;  // previous correction (the plain solution after the first pass)
+  dd bc[G];            // FP32 factors: the right-hand sides, kept over the passes
+  if constexpr (F32) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int o = __builtin_amdgcn_readfirstlane(S.gl[g0 + g]);
+      bc[g] = lane < K ? rhs_dd_at(lane, n, c.mg, a.ops[o], __builtin_amdgcn_readfirstlane(S.kg[g0 + g]), c.ex, c.ez)
+                       : dd{0.0, 0.0};
+    }
+  }
+  bool plain = F32;  // FP64 residuals (wave-uniform)
   for (int it = 0; it <= a.max_iter; ++it) {
     if constexpr (H == 1) {
       if (converged) break;
@@ -961,9 +980,37 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
       if (__ballot(!converged) == 0) break;
     }
     const bool live = !converged;
+    const bool plain_pass = plain && it > 0;
     // residual b - A x in double-double, rounded to FP64 (b alone when x = 0)
     dd acc[G] = {};
-    if (it > 0) {
+    if (plain_pass) {
+      // the FP64 entries of the assembly: r^m = r (r^2)^((m-1)/2)
+      const int e = (c.mg - 1) / 2;
+      for (int j = 0; j < n; ++j) {
+        const double ddx = own[0] - S.off[j][0], ddz = own[2] - S.off[j][2];
+        const double s2 = ddx * ddx + ddz * ddz;
+        const bool pos = s2 > 0.0;
+        double r = sqrt_pos(pos ? s2 : 1.0);
+        for (int t = 0; t < e; ++t) r *= s2;
+        const double em = S.pw[j * P + c.poly_a][0] * S.pw[j * P + c.poly_b][2];
+        const double ev = c.is_node ? (pos ? r : 0.0) : (c.is_poly ? em : 0.0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g].hi = fma(ev, S.xs[j][g], acc[g].hi);
+      }
+      int qa = 0, qb = 0;
+      for (int j = n; j < K; ++j) {
+        const double ev = c.is_node ? S.pw[c.own_pw + qa][0] * S.pw[c.own_pw + qb][2] : 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g].hi = fma(ev, S.xs[j][g], acc[g].hi);
+        if (qa > 0) {
+          --qa;
+          ++qb;
+        } else {
+          qa = qb + 1;
+          qb = 0;
+        }
+      }
+    } else if (it > 0) {
       // node columns: Phi for node rows (0 on the diagonal), the monomials of
       // node j for polynomial rows; branch-free, with the power of r
       // unrolled for the common orders
@@ -1006,8 +1053,13 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
     for (int g = 0; g < G; ++g) {
       v[g] = 0.0;
       if (lane < K) {
-        const int o = __builtin_amdgcn_readfirstlane(S.gl[g0 + g]);
-        const dd b = rhs_dd_at(lane, n, c.mg, a.ops[o], __builtin_amdgcn_readfirstlane(S.kg[g0 + g]), c.ex, c.ez);
+        dd b;
+        if constexpr (F32) {
+          b = bc[g];
+        } else {
+          const int o = __builtin_amdgcn_readfirstlane(S.gl[g0 + g]);
+          b = rhs_dd_at(lane, n, c.mg, a.ops[o], __builtin_amdgcn_readfirstlane(S.kg[g0 + g]), c.ex, c.ez);
+        }
         const dd r = two_sum(b.hi, -acc[g].hi);
         v[g] = r.hi + (r.lo + (b.lo - acc[g].lo));
       }
@@ -1058,17 +1110,21 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
     wave_sync_lds();
     dm = group_max<H>(dm);
     xm = group_max<H>(xm);
+    if (plain_pass && __ballot(live && (dm <= 0x1p-24 * xm || dm > 0.5 * dprev)) != 0) plain = false;
     if (live) {
-      converged = it == 0 ? dm <= 0x1p-48 * xm : refined(dm, xm, dprev);
+      if (!plain_pass) converged = it == 0 ? dm <= 0x1p-48 * xm : refined(dm, xm, dprev);
       dprev = dm;
     }
   }
 }
 
-// wavefronts per SIMD the register budget is fitted to (measured: at
-// KC = 48 three per SIMD, spilling a few values of the set-up and refinement
-// code, beat two by about 2%; at KC = 64 three triple the time, and at
-// KC = 32 four are slower than three)
+// wavefronts per SIMD the register budget is fitted to (measured: with FP64
+// factors, at KC = 48 three per SIMD, spilling a few values of the set-up
+// and refinement code, beat two by about 2%; at KC = 64 three triple the
+// time, and at KC = 32 two and four are slower than three. FP32 factors
+// take half the registers for the row: three per SIMD at KC = 64 beat two
+// by 16%, four at KC = 48 beat three by 7%, and four at KC = 32 gain
+// nothing)
 #ifndef RBFFD_WAVE_OCC64
 #define RBFFD_WAVE_OCC64 2
 #endif
@@ -1078,8 +1134,19 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
 #ifndef RBFFD_WAVE_OCC32
 #define RBFFD_WAVE_OCC32 3
 #endif
-template <int KC> constexpr int wave_occ() {
-  return KC > 48 ? RBFFD_WAVE_OCC64 : KC > 32 ? RBFFD_WAVE_OCC48 : RBFFD_WAVE_OCC32;
+#ifndef RBFFD_WAVE_OCC64F
+#define RBFFD_WAVE_OCC64F 3
+#endif
+#ifndef RBFFD_WAVE_OCC48F
+#define RBFFD_WAVE_OCC48F 4
+#endif
+#ifndef RBFFD_WAVE_OCC32F
+#define RBFFD_WAVE_OCC32F 3
+#endif
+template <int KC, typename T = double> constexpr int wave_occ() {
+  return std::is_same<T, float>::value
+             ? (KC > 48 ? RBFFD_WAVE_OCC64F : KC > 32 ? RBFFD_WAVE_OCC48F : RBFFD_WAVE_OCC32F)
+             : (KC > 48 ? RBFFD_WAVE_OCC64 : KC > 32 ? RBFFD_WAVE_OCC48 : RBFFD_WAVE_OCC32);
 }
 
 
@@ -1425,7 +1492,7 @@ __device__ __forceinline__ void wave_solve(const WArgs &a, WaveShared<KC, T> (&S
 // stencil, go to a.defer for the one-system kernel. The wavefront drains its
 // share of the launch's queue (items of H systems).
 template <int KC, typename T, int H = 1, bool PERSIST = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC>()))) void weights_wave_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(wave_occ<KC, T>()))) void weights_wave_kernel(
     WArgs a) {
   __shared__ WaveShared<KC, T> SS[H];
   QueueView qv = queue_view(a);
@@ -1638,7 +1705,7 @@ inline unsigned grid_of(int64_t items, int per_cu, int n_cu) {
 template <int KC, typename T, int H>
 void launch_wave(const WArgs &a, int64_t items, bool persist, int n_cu, hipStream_t s) {
   if (persist)
-    weights_wave_kernel<KC, T, H, true><<<grid_of(items, 4 * wave_occ<KC>(), n_cu), 64, 0, s>>>(a);
+    weights_wave_kernel<KC, T, H, true><<<grid_of(items, 4 * wave_occ<KC, T>(), n_cu), 64, 0, s>>>(a);
   else
     weights_wave_kernel<KC, T, H, false><<<grid_of(items, 0, n_cu), 64, 0, s>>>(a);
 }
