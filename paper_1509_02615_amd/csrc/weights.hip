@@ -955,16 +955,19 @@ struct WaveCtx {
 // same entries, so the error still contracts, down to about cond 2^-53);
 // the double-double passes start once a correction is below 2^-24 |x| or
 // stops contracting, for the whole wavefront at once, and only they may
-// end the refinement. The right-hand sides are then evaluated once.
+// end the refinement. The right-hand sides are then evaluated once, and so
+// are they with FP64 factors at KC = 48 (measured: 4% faster there; at
+// KC = 32 and 64 the extra registers cost more than the second evaluation).
 template <int KC, int G, typename T, int H>
 __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S, const WaveRows<KC, T> R,
                                             const WaveCtx &c, int g0, double (&x)[4], bool &converged, int h) {
   constexpr bool F32 = std::is_same<T, float>::value;
+  constexpr bool KEEP_B = F32 || KC == 48;
   const int lane = c.lane, n = c.n, K = c.K, P = c.P;
   const double own[4] = {c.ex.hi, c.ex.lo, c.ez.hi, c.ez.lo};
   double dprev = 0.0;  // previous correction (the plain solution after the first pass)
-  dd bc[G];            // FP32 factors: the right-hand sides, kept over the passes
-  if constexpr (F32) {
+  dd bc[G];            // the right-hand sides, kept over the passes (KEEP_B)
+  if constexpr (KEEP_B) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int o = __builtin_amdgcn_readfirstlane(S.gl[g0 + g]);
@@ -1054,7 +1057,7 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
       v[g] = 0.0;
       if (lane < K) {
         dd b;
-        if constexpr (F32) {
+        if constexpr (KEEP_B) {
           b = bc[g];
         } else {
           const int o = __builtin_amdgcn_readfirstlane(S.gl[g0 + g]);
