@@ -954,8 +954,10 @@ struct WaveCtx {
 // against the FP64 matrix that was rounded for the factorisation (the
 // same entries, so the error still contracts, down to about cond 2^-53);
 // the double-double passes start once a correction is below 2^-24 |x| or
-// stops contracting, for the whole wavefront at once, and only they may
-// end the refinement. The right-hand sides are then evaluated once, and so
+// stops contracting, and only they may end the refinement. The switch is
+// each system's own, so a system's passes do not depend on its partner in
+// the wavefront (the two halves branch apart only in a pass where one has
+// switched and the other not). The right-hand sides are then evaluated once, and so
 // are they with FP64 factors at KC = 48 (measured: 4% faster there; at
 // KC = 32 and 64 the extra registers cost more than the second evaluation).
 template <int KC, int G, typename T, int H>
@@ -975,7 +977,7 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
                        : dd{0.0, 0.0};
     }
   }
-  bool plain = F32;  // FP64 residuals (wave-uniform)
+  bool plain = F32;  // FP64 residuals (uniform over the system's lanes)
   for (int it = 0; it <= a.max_iter; ++it) {
     if constexpr (H == 1) {
       if (converged) break;
@@ -1113,7 +1115,7 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
     wave_sync_lds();
     dm = group_max<H>(dm);
     xm = group_max<H>(xm);
-    if (plain_pass && __ballot(live && (dm <= 0x1p-24 * xm || dm > 0.5 * dprev)) != 0) plain = false;
+    if (plain_pass && live && (dm <= 0x1p-24 * xm || dm > 0.5 * dprev)) plain = false;
     if (live) {
       if (!plain_pass) converged = it == 0 ? dm <= 0x1p-48 * xm : refined(dm, xm, dprev);
       dprev = dm;
