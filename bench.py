@@ -604,8 +604,11 @@ def main():
     ap.add_argument("--closure-only", action="store_true",
                     help="run only the learned-closure leg and print its result (for profiling)")
     ap.add_argument("--weights-only", action="store_true",
-                    help="run only the mixed 1M-stencil weights batch (FP64) once and print its result "
-                         "(for profiling)")
+                    help="run only the mixed 1M-stencil weights batch once (after one tuning call) and print "
+                         "its result (for profiling)")
+    ap.add_argument("--weights-precision", default="fp64", choices=["fp64", "fp32_ir"],
+                    help="solve precision of --weights-only: FP64, or the FP32 factorisation with FP64 "
+                         "refinement")
     ap.add_argument("--fullrun-only", action="store_true",
                     help="run only the FP64/FP32/BF16 runs to t = 900 s and print their comparison")
     ap.add_argument("--pmc-run", action="store_true",
@@ -648,7 +651,8 @@ def main():
         return
     if args.weights_only:
         from workloads import weights_config
-        print(json.dumps(weights_leg(R, ctx, weights_config(1024), R.SOLVE_FP64)), flush=True)
+        prec = R.SOLVE_FP64 if args.weights_precision == "fp64" else R.SOLVE_FP32_IR
+        print(json.dumps(weights_leg(R, ctx, weights_config(1024), prec)), flush=True)
         return
     cfg = scale_config()
     nd = cfg["nodes"]
