@@ -959,9 +959,10 @@ struct WaveCtx {
 // stops contracting, and only they may end the refinement. The switch is
 // each system's own, so a system's passes do not depend on its partner in
 // the wavefront (the two halves branch apart only in a pass where one has
-// switched and the other not). The right-hand sides are then evaluated once, and so
-// are they with FP64 factors at KC = 48 (measured: 4% faster there; at
-// KC = 32 and 64 the extra registers cost more than the second evaluation).
+// switched and the other not). The right-hand sides are then evaluated
+// once, and so are they with FP64 factors at KC = 48 (measured: 4% faster
+// there; at KC = 32 and 64 the extra registers cost more than the second
+// evaluation).
 template <int KC, int G, typename T, int H>
 __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S, const WaveRows<KC, T> R,
                                             const WaveCtx &c, int g0, double (&x)[4], bool &converged, int h) {
@@ -988,7 +989,8 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
     }
     const bool live = !converged;
     const bool plain_pass = plain && it > 0;
-    // residual b - A x in double-double, rounded to FP64 (b alone when x = 0)
+    // residual b - A x in double-double (A x in plain FP64 in a plain
+    // pass), rounded to FP64 (b alone when x = 0)
     dd acc[G] = {};
     if (plain_pass) {
       // the FP64 entries of the assembly: r^m = r (r^2)^((m-1)/2)
