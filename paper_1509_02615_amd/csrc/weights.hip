@@ -1078,19 +1078,23 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
     // the pivot lane p_k of step k is y_k / pivot_k (forward) or d_k
     // (backward) and enters each update as a scalar operand. The steps run
     // in segments of 16 (one register chunk each, unrolled), so the entry of
-    // step k is an indexed read in a static chunk.
+    // step k is an indexed read in a static chunk. They run in the factors'
+    // precision: with FP32 factors the correction is only good to about
+    // cond 2^-24 whatever the arithmetic, and FP32 halves the broadcasts and
+    // needs no widening of the factors (the residual and x stay FP64).
+    T w[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) v[g] *= R.rdg;
+    for (int g = 0; g < G; ++g) w[g] = static_cast<T>(v[g] * R.rdg);
     // forward substitution L y = P v: rows not yet pivot at step k
 #pragma unroll
     for (int sg = 0; sg < KC / 16; ++sg) {
       const int kend = min(16 * sg + 16, K);
       for (int k = 16 * sg; k < kend; ++k) {
         const int p0 = __builtin_amdgcn_readlane(R.pv, k), p1 = H == 1 ? p0 : __builtin_amdgcn_readlane(R.pv, 32 + k);
-        const double e = static_cast<double>(pickc(R.c0, R.c1, R.c2, R.c3, sg, k & 15));
-        const double lk = R.mystep > k ? e : 0.0;
+        const T e = pickc(R.c0, R.c1, R.c2, R.c3, sg, k & 15);
+        const T lk = R.mystep > k ? e : T(0);
 #pragma unroll
-        for (int g = 0; g < G; ++g) v[g] = fma(-lk, group_rl<H>(v[g], p0, p1, h), v[g]);
+        for (int g = 0; g < G; ++g) w[g] = fma(-lk, group_rl<H>(w[g], p0, p1, h), w[g]);
       }
     }
     // back substitution U d = y: rows pivoted before step k
@@ -1099,17 +1103,17 @@ __device__ __forceinline__ void wave_refine(const WArgs &a, WaveShared<KC, T> &S
       const int kbeg = min(16 * sg + 15, K - 1);
       for (int k = kbeg; k >= 16 * sg; --k) {
         const int p0 = __builtin_amdgcn_readlane(R.pv, k), p1 = H == 1 ? p0 : __builtin_amdgcn_readlane(R.pv, 32 + k);
-        const double e = static_cast<double>(pickc(R.c0, R.c1, R.c2, R.c3, sg, k & 15));
-        const double uk = R.mystep < k ? e : 0.0;
+        const T e = pickc(R.c0, R.c1, R.c2, R.c3, sg, k & 15);
+        const T uk = R.mystep < k ? e : T(0);
 #pragma unroll
-        for (int g = 0; g < G; ++g) v[g] = fma(-uk, group_rl<H>(v[g], p0, p1, h), v[g]);
+        for (int g = 0; g < G; ++g) w[g] = fma(-uk, group_rl<H>(w[g], p0, p1, h), w[g]);
       }
     }
     // lane p_k holds d_k; lane k takes it
     double dm = 0.0, xm = 0.0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const double dk = __shfl(v[g], R.pv + (64 / H) * h, 64);
+      const double dk = static_cast<double>(__shfl(w[g], R.pv + (64 / H) * h, 64));
       const double d = lane < K && live ? dk : 0.0;
       x[g] += d;
       dm = fmax(dm, fabs(d));
