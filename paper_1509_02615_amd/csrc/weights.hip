@@ -35,7 +35,8 @@
 //     stencils differs by ~5e-10), correction through the same factors,
 //     until the correction is at rounding level (with FP32 factors the
 //     wavefront kernels take their first passes with plain FP64 residuals
-//     of the FP64 matrix, and double-double ones from there on);
+//     of the FP64 matrix, and double-double ones from there on, and solve
+//     for the corrections in FP32);
 //  5. rescaling by rho^-q (q = derivative order) and the padded row write.
 //
 // FP64 matrix cores on gfx950 have the same peak as the FP64 vector ALUs,
