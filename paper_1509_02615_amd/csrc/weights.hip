@@ -34,9 +34,9 @@
 //     system, not of its FP64 rounding, which for one-sided degree-5
 //     stencils differs by ~5e-10), correction through the same factors,
 //     until the correction is at rounding level (with FP32 factors the
-//     wavefront kernels take their first passes with plain FP64 residuals
-//     of the FP64 matrix, and double-double ones from there on, and solve
-//     for the corrections in FP32);
+//     first passes take plain FP64 residuals of the FP64 matrix, and
+//     double-double ones from there on; the wavefront kernels solve for
+//     the corrections in FP32);
 //  5. rescaling by rho^-q (q = derivative order) and the padded row write.
 //
 // FP64 matrix cores on gfx950 have the same peak as the FP64 vector ALUs,
@@ -362,7 +362,7 @@ template <typename T> __device__ void block_solve(const WArgs &a, double *smem, 
   double *ze = xi + kc;                    // [kc] scaled z offsets (FP64)
   double *xl = ze + kc;                    // [kc] low parts of the double-double x offsets
   double *zl = xl + kc;                    // [kc] low parts of the double-double z offsets
-  __shared__ double s_red[4];  // rho, converged flag, max |x|, previous correction
+  __shared__ double s_red[5];  // rho, converged flag, max |x|, previous correction, FP64-residual flag
   __shared__ int s_piv[128];
   __shared__ int s_gl[MAX_OPS], s_kg[MAX_OPS];  // operators of the current group, their k
   __shared__ int s_flag, s_pivrow;
@@ -583,8 +583,13 @@ template <typename T> __device__ void block_solve(const WArgs &a, double *smem, 
       __syncthreads();
     }
 
-    // 5. iterative refinement with double-double residuals
+    // 5. iterative refinement with double-double residuals (with FP32
+    // factors the first passes take the FP64 entries of the assembly, as in
+    // the wavefront kernels: until a correction is below 2^-24 |x| or stops
+    // contracting, and without ending the refinement)
     bool converged = false;
+    constexpr bool F32 = std::is_same<T, float>::value;
+    bool plain = F32;  // uniform over the workgroup
     if (tid == 0) s_red[3] = -1.0;  // no previous correction yet
     for (int it = 0; it < a.max_iter && !converged; ++it) {
       // r = b - A x in double-double: 4 lanes per row, partial sums over j,
@@ -597,7 +602,7 @@ template <typename T> __device__ void block_solve(const WArgs &a, double *smem, 
 #pragma unroll
           for (int g = 0; g < 4; ++g) acc[g] = dd{0.0, 0.0};
           for (int j = part; j < K; j += 4) {
-            const dd aij = sys_entry_dd(i, j, n, mg, xi, xl, ze, zl);
+            const dd aij = plain ? dd{sys_entry(i, j, n, mg, xi, ze), 0.0} : sys_entry_dd(i, j, n, mg, xi, xl, ze, zl);
 #pragma unroll
             for (int g = 0; g < 4; ++g)
               if (g0 + g < ng) acc[g] = dd_add_terms(acc[g], dd_mul_d(aij, xs[(g0 + g) * kc + j]));
@@ -660,12 +665,15 @@ template <typename T> __device__ void block_solve(const WArgs &a, double *smem, 
         dmax = wave_max(dmax);
         xmax = wave_max(xmax);
         if (tid == 0) {
-          s_red[1] = refined(dmax, xmax, s_red[3] >= 0.0 ? s_red[3] : xmax) ? 1.0 : 0.0;
+          const double dprev = s_red[3] >= 0.0 ? s_red[3] : xmax;
+          s_red[1] = !plain && refined(dmax, xmax, dprev) ? 1.0 : 0.0;
+          s_red[4] = plain && !(dmax <= 0x1p-24 * xmax || dmax > 0.5 * dprev) ? 1.0 : 0.0;
           s_red[3] = dmax;
         }
       }
       __syncthreads();
       converged = s_red[1] != 0.0;
+      plain = F32 && s_red[4] != 0.0;
       __syncthreads();
     }
 
