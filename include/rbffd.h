@@ -157,9 +157,10 @@ int rbffd_weights(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops,
  * per wavefront or one; shapes never change a system's arithmetic, so every
  * shape gives bit-identical results. This call computes the same outputs as
  * rbffd_weights; for every bucket whose shapes[b] is -1 it runs each of the
- * bucket's shapes (the batch is solved once per shape), times the bucket's
- * launches with HIP events and keeps the fastest in the context for later
- * rbffd_weights calls; shapes[b] >= 0 forces that shape (0 is the default).
+ * bucket's shapes twice (the batch is solved twice per shape), times the
+ * bucket's launches with HIP events and keeps the fastest in the context for
+ * later rbffd_weights calls; shapes[b] >= 0 forces that shape (0 is the
+ * default).
  * shapes (host, [RBFFD_WEIGHT_BUCKETS], in/out, or NULL = tune all) returns
  * the chosen shapes, bucket_ms (host or NULL) the chosen shapes' times.
  * Shape counts: 4 for bucket 0 (two systems per wavefront with one wavefront

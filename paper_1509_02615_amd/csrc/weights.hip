@@ -1906,7 +1906,10 @@ int weights_tune(rbffd_ctx *ctx, const rbffd_stencils *st, const rbffd_op *ops, 
   hipEvent_t ev[2 * NBUCKET] = {};
   for (auto &e : ev) RBFFD_HIP(ctx, hipEventCreate(&e));
   int rc = RBFFD_OK;
-  for (int sh = 0; sh < MAX_SHAPES && rc == RBFFD_OK; ++sh) {
+  // every shape twice, the faster time kept: the first launch of the first
+  // shape also pays for cold caches and code loading
+  for (int trial_sh = 0; trial_sh < 2 * MAX_SHAPES && rc == RBFFD_OK; ++trial_sh) {
+    const int sh = trial_sh % MAX_SHAPES;
     bool any = false;
     for (int b = 0; b < NBUCKET; ++b) {
       const bool trial = forced[b] < 0 && sh < shape_count(b);
